@@ -1,0 +1,434 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: numbers
+printed in the paper, closed forms, library routines, brute force on tiny
+inputs, invariances and finite differences.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as npleg
+
+import oracle as O
+from paper_2107_08119_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+H = O.hyper()  # r_c 5/4 A, n_max 8/4, l_max 4, 30 neurons
+
+
+def _rand_rotation(rng):
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q @ np.diag(np.sign(np.diag(r)))
+    return q
+
+
+# ------------------------------------------------------------------ sizes
+def test_model_sizes_match_paper():
+    rows = np.loadtxt(os.path.join(GOLDEN, "nep_model_sizes.txt"), dtype=int)
+    for nr, na, lmax, nneu, ndes, npar in rows:
+        h = O.hyper(5.0, 5.0, nr, na, lmax, nneu)
+        assert O.n_des(h) == ndes
+        assert O.n_par(h) == npar
+    assert O.n_des(H) == 29 and O.n_par(H) == 931
+
+
+# ------------------------------------------------------- special functions
+@pytest.mark.parametrize("t", [0.0, 0.3, 1.1, 2.0, math.pi - 1e-3])
+def test_chebyshev_closed_forms(t):
+    T, U = O.chebyshev(math.cos(t), 12)
+    for n in range(13):
+        assert T[n] == pytest.approx(math.cos(n * t), abs=1e-12)
+        if math.sin(t) > 1e-6:
+            assert U[n] == pytest.approx(math.sin((n + 1) * t) / math.sin(t), abs=1e-9)
+
+
+def test_chebyshev_derivative_is_n_U():
+    x, h = 0.37, 1e-6
+    Tp, _ = O.chebyshev(x + h, 10)
+    Tm, _ = O.chebyshev(x - h, 10)
+    _, U = O.chebyshev(x, 10)
+    for n in range(1, 11):
+        assert (Tp[n] - Tm[n]) / (2 * h) == pytest.approx(n * U[n - 1], rel=1e-7)
+
+
+def test_radial_basis_special_values():
+    rc = 5.0
+    g0, _ = O.radial_basis(1e-12, rc, 8)
+    np.testing.assert_allclose(g0, 1.0, atol=1e-12)  # g_n(0) = 1 for all n
+    g, dg = O.radial_basis(rc, rc, 8)
+    np.testing.assert_allclose(g, 0.0, atol=1e-15)
+    np.testing.assert_allclose(dg, 0.0, atol=1e-12)
+    for r in np.linspace(0.1, 4.9, 23):
+        g, _ = O.radial_basis(r, rc, 8)
+        fc = 0.5 * (1 + math.cos(math.pi * r / rc))
+        assert g[0] == pytest.approx(fc, rel=1e-13)
+        assert g[1] == pytest.approx((r / rc - 1) ** 2 * fc, rel=1e-12)
+        assert np.all(g >= -1e-15) and np.all(g <= 1 + 1e-15)  # positive, bounded
+    g, _ = O.radial_basis(5.2, rc, 8)
+    np.testing.assert_array_equal(g, 0.0)
+
+
+def test_radial_basis_derivative_fd():
+    h = 1e-6
+    for rc in (4.0, 5.0):
+        for r in np.linspace(0.5, rc - 0.05, 11):
+            gp, _ = O.radial_basis(r + h, rc, 8)
+            gm, _ = O.radial_basis(r - h, rc, 8)
+            _, dg = O.radial_basis(r, rc, 8)
+            np.testing.assert_allclose((gp - gm) / (2 * h), dg, atol=2e-8)
+
+
+def test_legendre_against_numpy():
+    for c in np.linspace(-1, 1, 17):
+        P, dP = O.legendre(c, 6)
+        for l in range(7):
+            coef = np.zeros(l + 1)
+            coef[l] = 1
+            assert P[l] == pytest.approx(npleg.legval(c, coef), abs=1e-13)
+            assert dP[l] == pytest.approx(npleg.legval(c, npleg.legder(coef)), abs=1e-12)
+    P, _ = O.legendre(1.0, 6)
+    np.testing.assert_allclose(P, 1.0)
+
+
+# --------------------------------------------------------------- neighbours
+def _brute_neighbors(pos, box, rc, nimg=3):
+    out = []
+    rng_ = range(-nimg, nimg + 1)
+    for i in range(len(pos)):
+        lst = []
+        for j in range(len(pos)):
+            for n0 in rng_:
+                for n1 in rng_:
+                    for n2 in rng_:
+                        if i == j and n0 == n1 == n2 == 0:
+                            continue
+                        d = []
+                        for c in range(3):
+                            sh = (n0 * box[0, c] + n1 * box[1, c]) + n2 * box[2, c]
+                            d.append((pos[j, c] - pos[i, c]) + sh)
+                        if (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2] < rc * rc:
+                            lst.append((j, n0, n1, n2))
+        out.append(sorted(lst))
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_neighbors_brute_force_small_triclinic(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 9))
+    box = np.diag(rng.uniform(4.0, 7.0, 3)) + rng.uniform(-1.0, 1.0, (3, 3)) * (1 - np.eye(3))
+    pos = rng.random((n, 3)) @ box + rng.standard_normal((n, 3)) * 0.3  # some outside the cell
+    rc = 5.5
+    assert O.neighbors(pos, box, rc) == _brute_neighbors(pos, box, rc)
+
+
+def test_neighbors_diamond_shell_counts():
+    pos, box = I.diamond_supercell(3, 3, 3)
+    for rc, m in ((4.0, 16), (4.5, 16), (5.0, 28), (5.5, 34)):
+        lists = O.neighbors(pos, box, rc)
+        assert all(len(l) == m for l in lists)
+
+
+def test_neighbors_symmetric_pairs():
+    pos, box = I.parity_cell(0)
+    lists = O.neighbors(pos, box, 5.5)
+    sets = [set(l) for l in lists]
+    for i, l in enumerate(lists):
+        for (j, a, b, c) in l:
+            assert (i, -a, -b, -c) in sets[j]
+
+
+# --------------------------------------------------------------- descriptor
+def _cluster(points, box_len=60.0):
+    """Atoms near the centre of a large cubic box (no periodic neighbours)."""
+    pos = np.asarray(points, dtype=np.float64) + box_len / 2
+    return pos, np.eye(3) * box_len
+
+
+def test_descriptor_single_neighbor():
+    pos, box = _cluster([[0, 0, 0], [2.3, 0.4, -0.2]])
+    q = O.nep_eval(H, np.zeros(O.n_par(H)), pos, box, want_q=True)["q"][0]
+    r = math.sqrt(2.3 ** 2 + 0.4 ** 2 + 0.2 ** 2)
+    gR, _ = O.radial_basis(r, 5.0, 8)
+    gA, _ = O.radial_basis(r, 4.0, 4)
+    np.testing.assert_allclose(q[:9], gR, rtol=1e-12)
+    for n in range(5):
+        for l in range(1, 5):
+            assert q[9 + 4 * n + (l - 1)] == pytest.approx(gA[n] ** 2, rel=1e-12)
+
+
+def test_descriptor_two_neighbors_brute_force():
+    a = np.array([2.1, 0.3, 0.5])
+    b = np.array([-0.7, 2.6, -1.1])
+    pos, box = _cluster([[0, 0, 0], a, b])
+    q = O.nep_eval(H, np.zeros(O.n_par(H)), pos, box, want_q=True)["q"][0]
+    ra, rb = np.linalg.norm(a), np.linalg.norm(b)
+    cos = a @ b / (ra * rb)
+    ga, _ = O.radial_basis(ra, 4.0, 4)
+    gb, _ = O.radial_basis(rb, 4.0, 4)
+    for n in range(5):
+        for l in range(1, 5):
+            coef = np.zeros(l + 1)
+            coef[l] = 1
+            expect = ga[n] ** 2 + gb[n] ** 2 + 2 * ga[n] * gb[n] * npleg.legval(cos, coef)
+            assert q[9 + 4 * n + (l - 1)] == pytest.approx(expect, rel=1e-12)
+
+
+def test_angular_descriptor_addition_theorem():
+    """q_nl = 4 pi/(2l+1) sum_m |sum_j g_n(r_ij) Y_lm(r_ij)|^2 (scipy harmonics)."""
+    from scipy.special import sph_harm_y
+
+    pos, box = I.parity_cell(0)
+    out = O.nep_eval(H, np.zeros(O.n_par(H)), pos, box, want_q=True, sel=[0, 5, 100])
+    for k, i in enumerate([0, 5, 100]):
+        lst = O.neighbors(pos, box, 4.0)[i]
+        d = np.array([pos[j] + np.array(n) @ box - pos[i] for (j, *n) in lst])
+        r = np.linalg.norm(d, axis=1)
+        theta = np.arccos(np.clip(d[:, 2] / r, -1, 1))
+        phi = np.arctan2(d[:, 1], d[:, 0])
+        g = np.array([O.radial_basis(x, 4.0, 4)[0] for x in r])
+        for n in range(5):
+            for l in range(1, 5):
+                tot = 0.0
+                for m in range(-l, l + 1):
+                    c = np.sum(g[:, n] * sph_harm_y(l, m, theta, phi))
+                    tot += abs(c) ** 2
+                tot *= 4 * math.pi / (2 * l + 1)
+                assert out["q"][k, 9 + 4 * n + l - 1] == pytest.approx(tot, rel=1e-10, abs=1e-12)
+
+
+def test_perfect_diamond_symmetry():
+    pos, box = I.diamond_supercell(3, 3, 3)
+    z = I.random_parameters(O.n_par(H), 1)
+    out = O.nep_eval(H, z, pos, box, want_q=True)
+    np.testing.assert_allclose(out["U"], out["U"][0], rtol=1e-12)
+    assert np.abs(out["F"]).max() < 1e-10
+    W = out["W"].sum(0)
+    assert np.abs(W - np.diag(np.diag(W))).max() < 1e-9
+    np.testing.assert_allclose(np.diag(W), W[0, 0], rtol=1e-10)
+    q = out["q"][0]
+    # cubic site symmetry removes l = 1, 2; l = 3 (tetrahedral) and l = 4 survive
+    for n in range(5):
+        assert abs(q[9 + 4 * n + 0]) < 1e-12 and abs(q[9 + 4 * n + 1]) < 1e-12
+    assert q[9 + 2] > 0 and q[9 + 3] > 0
+    # radial components from the shell structure: 4 at a sqrt(3)/4, 12 at a/sqrt(2), 12 at a sqrt(11)/4
+    a = I.DIAMOND_SI_A
+    shells = [(4, a * math.sqrt(3) / 4), (12, a / math.sqrt(2)), (12, a * math.sqrt(11) / 4)]
+    fc = lambda r: 0.5 * (1 + math.cos(math.pi * r / 5.0))
+    assert q[0] == pytest.approx(sum(c * fc(r) for c, r in shells), rel=1e-12)
+    assert q[1] == pytest.approx(sum(c * (r / 5 - 1) ** 2 * fc(r) for c, r in shells), rel=1e-12)
+
+
+# ------------------------------------------------------ energy, forces, virial
+@pytest.fixture(scope="module")
+def small_cell():
+    pos, box = I.diamond_supercell(2, 2, 2)
+    rng = np.random.default_rng(7)
+    pos = pos + rng.standard_normal(pos.shape) * 0.1
+    z = I.random_parameters(O.n_par(H), 1)
+    return pos, box, z
+
+
+def test_invariance_rotation_translation_permutation(small_cell):
+    pos, box, z = small_cell
+    rng = np.random.default_rng(3)
+    ref = O.nep_eval(H, z, pos, box, want_q=True)
+    R = _rand_rotation(rng) * -1.0  # includes inversion
+    perm = rng.permutation(len(pos))
+    pos2 = (pos @ R.T + rng.standard_normal(3))[perm]
+    box2 = box @ R.T
+    out = O.nep_eval(H, z, pos2, box2, want_q=True)
+    np.testing.assert_allclose(out["q"], ref["q"][perm], rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(out["U"], ref["U"][perm], rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(out["F"], ref["F"][perm] @ R.T, atol=1e-11)
+    np.testing.assert_allclose(out["W"], R @ ref["W"][perm] @ R.T, atol=1e-10)
+
+
+def test_forces_finite_difference(small_cell):
+    pos, box, z = small_cell
+    out = O.nep_eval(H, z, pos, box)
+    h = 1e-4
+    for i in (0, 9, 33):
+        for c in range(3):
+            p = pos.copy()
+            p[i, c] += h
+            ep = O.nep_eval(H, z, p, box)["U"].sum()
+            p[i, c] -= 2 * h
+            em = O.nep_eval(H, z, p, box)["U"].sum()
+            assert -(ep - em) / (2 * h) == pytest.approx(out["F"][i, c], rel=1e-6, abs=1e-9)
+
+
+def test_net_force_and_torque_vanish():
+    rng = np.random.default_rng(11)
+    pts = rng.uniform(-3.5, 3.5, (14, 3))
+    pos, box = _cluster(pts)
+    z = I.random_parameters(O.n_par(H), 2)
+    out = O.nep_eval(H, z, pos, box)
+    np.testing.assert_allclose(out["F"].sum(0), 0.0, atol=1e-12)
+    torque = np.cross(pos - pos.mean(0), out["F"]).sum(0)
+    np.testing.assert_allclose(torque, 0.0, atol=1e-11)
+    # cluster virial: sum_i W_i = sum_i r_i (x) F_i
+    W = out["W"].sum(0)
+    np.testing.assert_allclose(W, np.einsum("ia,ib->ab", pos, out["F"]), atol=1e-10)
+
+
+def test_virial_strain_derivative(small_cell):
+    pos, box, z = small_cell
+    out = O.nep_eval(H, z, pos, box)
+    Wi = out["W"]
+    W = Wi.sum(0)
+    np.testing.assert_allclose(W, W.T, atol=1e-11)
+    assert np.abs(Wi - Wi.transpose(0, 2, 1)).max() > 1e-4  # per-atom virial not symmetric
+    h = 1e-5
+    fd = np.zeros((3, 3))
+    for a in range(3):
+        for b in range(3):
+            D = np.eye(3)
+            D[a, b] += h
+            ep = O.nep_eval(H, z, pos @ D, box @ D)["U"].sum()
+            D[a, b] -= 2 * h
+            em = O.nep_eval(H, z, pos @ D, box @ D)["U"].sum()
+            fd[a, b] = -(ep - em) / (2 * h)
+    np.testing.assert_allclose(W, fd.T, atol=1e-7)
+
+
+def test_heat_current_uniform_velocity_and_linearity(small_cell):
+    pos, box, z = small_cell
+    u = np.array([0.003, -0.001, 0.002])
+    out = O.nep_eval(H, z, pos, box, vel=np.tile(u, (len(pos), 1)))
+    W = out["W"].sum(0)
+    np.testing.assert_allclose(out["J"].sum(0), W @ u, atol=1e-13)
+    rng = np.random.default_rng(5)
+    v1, v2 = rng.standard_normal((2, len(pos), 3)) * 0.01
+    j1 = O.nep_eval(H, z, pos, box, vel=v1)["J"]
+    j2 = O.nep_eval(H, z, pos, box, vel=v2)["J"]
+    j12 = O.nep_eval(H, z, pos, box, vel=2 * v1 - v2)["J"]
+    np.testing.assert_allclose(j12, 2 * j1 - j2, atol=1e-13)
+
+
+def test_subset_evaluation_matches_full(small_cell):
+    pos, box, z = small_cell
+    full = O.nep_eval(H, z, pos, box)
+    sel = [3, 40, 17]
+    part = O.nep_eval(H, z, pos, box, sel=sel)
+    for key in ("U", "F", "W", "J"):
+        np.testing.assert_array_equal(part[key], full[key][sel])
+
+
+# ---------------------------------------------------------------------- MD
+def test_velocity_verlet_energy_error_scales_as_dt_squared():
+    pos, box = I.diamond_supercell(2, 2, 2)
+    rng = np.random.default_rng(8)
+    pos = pos + rng.standard_normal(pos.shape) * 0.03
+    vel = I.maxwell_boltzmann(len(pos), 300.0, 9)
+    z = I.random_parameters(O.n_par(H), 1)
+    spans = []
+    for dt, n in ((1.0, 100), (0.5, 200)):
+        th, _, _ = O.md_nve(H, z, pos, box, vel, I.MASS_SI, dt, n)
+        e = th[:, 0] + th[:, 1]
+        spans.append(e.max() - e.min())
+    ratio = spans[0] / spans[1]
+    assert 3.0 < ratio < 5.5, ratio
+
+
+def test_velocity_verlet_free_particles():
+    """No neighbours: positions advance by v t exactly (up to rounding)."""
+    pos, box = _cluster([[0, 0, 0], [8, 0, 0]])
+    vel = np.array([[0.01, 0.0, -0.02], [0.0, 0.005, 0.0]])
+    z = I.random_parameters(O.n_par(H), 1)
+    th, p, v = O.md_nve(H, z, pos, box, vel, I.MASS_SI, 1.0, 10)
+    np.testing.assert_allclose(p, pos + 10 * vel, atol=1e-12)
+    np.testing.assert_allclose(v, vel, atol=1e-15)
+
+
+# -------------------------------------------------------------------- loss
+@pytest.fixture(scope="module")
+def tiny_set():
+    return I.labelled_set(6, 8, 40, seed=21)
+
+
+def test_loss_zero_when_targets_are_own_predictions(tiny_set):
+    ds = tiny_set
+    z = I.random_parameters(O.n_par(H), 3)
+    e, f, w = [], [], []
+    off = 0
+    for s, n in enumerate(ds.n_atoms):
+        out = O.nep_eval(H, z, ds.pos[off:off + n], ds.boxes[s].reshape(3, 3))
+        e.append(out["U"].sum())
+        f.append(out["F"])
+        W = out["W"].sum(0)
+        w.append([W[a, b] for a, b in I.VIRIAL_COMPONENTS])
+        off += n
+    own = I.LabelledSet(ds.n_atoms, ds.boxes, ds.pos, np.array(e), np.concatenate(f),
+                        np.array(w), ds.has_virial)
+    out = O.loss(H, z, own)
+    assert out[1] < 1e-13 and out[2] < 1e-13 and out[3] < 1e-13
+    zd = z.astype(np.float64)
+    assert out[4] == pytest.approx(np.abs(zd).mean(), rel=1e-12)
+    assert out[5] == pytest.approx(math.sqrt((zd ** 2).mean()), rel=1e-12)
+    assert out[0] == pytest.approx(0.05 * out[4] + 0.05 * out[5], rel=1e-12)
+    # shift every per-atom energy by delta, every force by c, every per-atom virial by v
+    delta, c, v = 0.013, np.array([0.02, -0.01, 0.03]), 0.004
+    shifted = I.LabelledSet(ds.n_atoms, ds.boxes, ds.pos, own.energy + delta * ds.n_atoms,
+                            own.forces + c, own.virial + v * ds.n_atoms[:, None], ds.has_virial)
+    out = O.loss(H, z, shifted)
+    assert out[1] == pytest.approx(delta, rel=1e-9)
+    assert out[2] == pytest.approx(np.linalg.norm(c) / math.sqrt(3), rel=1e-9)
+    assert out[3] == pytest.approx(v, rel=1e-9)
+    # structures without virials drop out of L_v
+    hv = ds.has_virial.copy()
+    hv[:3] = 0
+    part = I.LabelledSet(ds.n_atoms, ds.boxes, ds.pos, shifted.energy, shifted.forces,
+                         shifted.virial + 0.1 * (np.arange(6) < 3)[:, None], hv)
+    assert O.loss(H, z, part)[3] == pytest.approx(v, rel=1e-9)
+
+
+# -------------------------------------------------------------------- SNES
+def test_philox_known_answers():
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(x, 16) for x in line.split()]
+        np.testing.assert_array_equal(O.philox4x32_10(v[0:4], v[4:6]), np.array(v[6:10], np.uint32))
+
+
+def test_snes_noise_is_standard_normal():
+    m = np.zeros(1000, np.float32)
+    s = np.ones(1000, np.float32)
+    r, z = O.snes_sample(m, s, seed=12345, gen=0, n_pop=200)
+    x = r.astype(np.float64).ravel()
+    assert abs(x.mean()) < 0.01 and abs(x.var() - 1) < 0.01
+    assert abs(np.mean(x ** 4) - 3) < 0.05  # Gaussian kurtosis
+    np.testing.assert_array_equal(r, z)
+    r2, _ = O.snes_sample(m, s, seed=12345, gen=1, n_pop=200)
+    assert np.corrcoef(r.ravel(), r2.ravel())[0, 1] < 0.01
+
+
+def test_snes_utilities():
+    for n_pop in (4, 10, 50):
+        u = O.snes_utilities(n_pop)
+        assert abs(u.sum()) < 1e-14
+        assert np.all(np.diff(u) <= 1e-15)
+        positive = math.floor(n_pop / 2 + 1 - 1e-12)  # ranks with ln(P/2+1) > ln k
+        np.testing.assert_allclose(u[positive:], -1.0 / n_pop)
+        assert u[positive - 1] > -1.0 / n_pop
+
+
+def test_snes_order_is_stable():
+    order = O.snes_order([3.0, 1.0, 2.0, 1.0, 0.5])
+    np.testing.assert_array_equal(order, [4, 1, 3, 2, 0])
+
+
+def test_snes_minimises_a_quadratic():
+    n_par, n_pop = 40, 20
+    rng = np.random.default_rng(0)
+    m = rng.uniform(-0.5, 0.5, n_par).astype(np.float32)
+    s = np.full(n_par, 0.1, np.float32)
+    f0 = float(np.sum(m.astype(np.float64) ** 2))
+    for gen in range(600):
+        r, z = O.snes_sample(m, s, seed=7, gen=gen, n_pop=n_pop)
+        losses = np.sum(z.astype(np.float64) ** 2, axis=1)
+        m, s = O.snes_update(m, s, r, losses)
+    assert float(np.sum(m.astype(np.float64) ** 2)) < 1e-4 * f0
