@@ -1,0 +1,188 @@
+"""Throughput of the NEP molecular-dynamics hot path on one MI355X.
+
+One step = one velocity-Verlet NVE step of the whole path: half-kick and
+drift, neighbour-list rebuild every 10 steps (amortised), descriptor, network
+and partial forces (pass 1), scatter-free gather of forces, per-atom virials
+and heat currents with the second half-kick and thermo sums (pass 2).
+
+Workload: 64,000-atom silicon diamond (20x20x20 conventional cells,
+a = 5.43 A), Maxwell-Boltzmann velocities at 300 K, dt = 1 fs, skin 0.5 A,
+NEP 29-30-1 (r_c 5/4 A, Chebyshev 0-8 / 0-4, Legendre 1-4), float32
+arithmetic with float64 positions, velocities and totals.  The paper's speed
+test (Sec. III D: bulk Si, 8000 atoms, 100 NVT steps) is the analogue.
+
+Prints ONE JSON line with the metric, a roofline for the dominant kernel
+(event-timed inside the timed region on the library's stream) and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "atom-steps/s (NEP MD, 64k–512k atoms) + SNES gen/s, vs plain path at 1e-5 rel err"
+PEAK_FP32_TFLOPS = 157.3  # MI355X published dense FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic float32 work of the descriptor/network/partial-force kernel,
+# counted from its arithmetic (a fused multiply-add counts 2, a square root,
+# reciprocal or exponential 1):
+#   every list slot (geometry in both loops)                   29
+#   every pair inside r_c^R (radial basis, sum, derivative)   227
+#   every pair inside r_c^A (basis, harmonics, moments,
+#                            partial force)                   1257
+#   every atom (angular invariants, 30-neuron network with
+#               derivative, moment scaling)                   4246
+FLOP_SLOT, FLOP_RADIAL, FLOP_ANGULAR, FLOP_ATOM = 29, 227, 1257, 4246
+# Algorithmic HBM bytes of the same kernel per atom: own position 24, counts 8,
+# list 4 per slot, partial force written 16 per slot, site energy 4.
+BYTE_ATOM, BYTE_SLOT = 36, 20
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--cells", type=int, default=20, help="diamond cells per edge")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def pair_counts(pos, box, rc):
+    """Mean number of neighbours within rc (periodic orthorhombic box)."""
+    from scipy.spatial import cKDTree
+    L = np.diag(box)
+    tree = cKDTree(np.mod(pos, L), boxsize=L)
+    return 2.0 * len(tree.query_pairs(rc, output_type="ndarray")) / len(pos)
+
+
+def cpu_baseline(h_np, z, pos, box, vel, mass, dt, target_s):
+    """The FP64 oracle as it stands: velocity-Verlet steps of the same system."""
+    import oracle as O
+    h = O.hyper(h_np.rc_radial, h_np.rc_angular, h_np.n_max_radial, h_np.n_max_angular,
+                h_np.l_max, h_np.n_neuron)
+    # one evaluation sizes the sample; the oracle's MD step costs two evaluations
+    # of the first step and one per later step
+    t0 = time.perf_counter()
+    O.nep_eval(h, z, pos, box)
+    t_eval = time.perf_counter() - t0
+    steps = int(max(1, min(20, target_s / max(t_eval, 1e-9) - 1)))
+    t0 = time.perf_counter()
+    O.md_nve(h, z, pos, box, vel, mass, dt, steps)
+    t = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": len(pos) * steps / t, "unit": "atom-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d velocity-Verlet steps of the same %d-atom system by the FP64 oracle "
+                      "(plain C, literal angular double sum, OpenMP %d threads), %.1f s"
+                      % (steps, len(pos), threads, t)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; this build has no multi-GPU path (--gpus %d refused)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2107_08119_amd import inputs as I
+    from paper_2107_08119_amd import nep
+
+    n_cells = args.cells
+    pos, box = I.diamond_supercell(n_cells, n_cells, n_cells)
+    n = len(pos)
+    vel = I.maxwell_boltzmann(n, 300.0, seed=2)
+    h = nep.hyper()
+    z = I.random_parameters(nep.num_params(h), seed=1)
+    dt, rebuild, skin, cap, mass = 1.0, 10, 0.5, 96, I.MASS_SI
+
+    ctx = nep.Context(0)
+    ctx.load_params(h, z)
+    p, v = nep.soa(pos), nep.soa(vel)
+    ctx.build_neighbors(p, box, skin=skin, max_neighbors=cap)
+    thermo = torch.empty((max(args.steps, args.warmup, 1), 5), dtype=torch.float64,
+                         device="cuda")
+    if args.warmup:
+        ctx.md_step(args.warmup, dt, rebuild, mass, p, v, thermo)
+    ctx.synchronize()
+    nb = ctx.get_neighbors()
+    mean_slots = float(nb["cnt_radial"].double().mean())
+    # timed region
+    nep.set_timing(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.md_step(args.steps, dt, rebuild, mass, p, v, thermo)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.synchronize()
+    kt = nep.get_timing(ctx)
+    nep.set_timing(ctx, False)
+    th = thermo[: args.steps].cpu().numpy()
+    e_tot = th[:, 0] + th[:, 1]
+
+    pos_end = nep.aos(p)
+    nr = 0.5 * (pair_counts(pos, box, h.rc_radial) + pair_counts(pos_end, box, h.rc_radial))
+    na = 0.5 * (pair_counts(pos, box, h.rc_angular) + pair_counts(pos_end, box, h.rc_angular))
+    flop_atom = FLOP_SLOT * mean_slots + FLOP_RADIAL * nr + FLOP_ANGULAR * na + FLOP_ATOM
+    ms_partials, launches = kt["partials"]
+    avg_s = ms_partials / 1e3 / max(launches, 1)
+    achieved = flop_atom * n / avg_s / 1e12
+    value = n * args.steps / elapsed
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "NEP NVE velocity-Verlet MD, Si diamond %dx%dx%d cells (%d atoms), "
+                        "dt 1 fs, rebuild every %d steps, skin %.1f A, NEP 29-30-1 "
+                        "(r_c 5/4 A), random parameters N(0, 0.1^2)" % (
+                            n_cells, n_cells, n_cells, n, rebuild, skin),
+            "atoms": n, "dt_fs": dt, "rebuild_every": rebuild, "skin_A": skin,
+            "neighbours_radial": nr, "neighbours_angular": na, "list_slots": mean_slots,
+        },
+        "roofline": {
+            "kernel": "k_partials (descriptor, network, partial forces)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None,
+            "flop_per_atom": flop_atom,
+            "avg_launch_us": avg_s * 1e6,
+            "launches": launches,
+            "algorithmic_GBps": (BYTE_ATOM + BYTE_SLOT * mean_slots) * n / avg_s / 1e9,
+        },
+        "kernel_ms": {k: val[0] for k, val in kt.items()},
+        "kernel_launches": {k: val[1] for k, val in kt.items()},
+        "energy_drift_meV_per_atom": float((e_tot.max() - e_tot.min()) / n * 1e3),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(h, z, pos, box, vel, mass, dt, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * nep.h -- C ABI of libnep, the MI355X (gfx950) implementation of the hot
+ * path of the neuroevolution potential (NEP) of Fan et al., arXiv 2107.08119:
+ * per-atom Chebyshev radial and Legendre angular descriptors, a one-hidden-
+ * layer tanh network, analytic partial forces, and from them forces, full
+ * per-atom virials and heat currents, velocity-Verlet molecular dynamics and
+ * the separable-NES population loss.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Plain C types only; no exception crosses the ABI.  Every call returns a
+ *    nep_status; nep_last_error() gives a message for the last failure.
+ *  - Array arguments are owned by the caller.  Names ending in _dev are
+ *    device pointers (HBM of the context's device); names ending in _host
+ *    are host pointers.  The library never frees caller memory.
+ *  - The context owns its neighbour lists, partial forces and scratch; it
+ *    never touches caller buffers outside a call's documented outputs.
+ *  - Work is enqueued on the HIP stream given to nep_create (borrowed, not
+ *    owned).  Calls return after argument checks, before the device work
+ *    completes, except where stated.  Device-side failures (neighbour
+ *    capacity, image range, non-finite energy) are latched in the context
+ *    and reported by nep_synchronize() and by the next call that checks them.
+ *  - Units: Angstrom, fs, amu, eV.  Forces in eV/A, virials in eV, heat
+ *    currents in eV A/fs, velocities in A/fs.
+ *  - Atom arrays are structure-of-arrays: positions and velocities are
+ *    float64 [3][N] (all x, then all y, then all z); forces [3][N] float32;
+ *    per-atom virials [9][N] float32 with component (a,b) at row 3a+b;
+ *    heat currents [3][N] float32.
+ *  - A box is 9 float64 host values: the three cell vectors as rows, so that
+ *    a lattice translation is n0*a + n1*b + n2*c.
+ *  - Pair displacement convention r_ij = r_j - r_i (paper, Sec. II A).
+ */
+#ifndef NEP_H_
+#define NEP_H_
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nep_ctx_s* nep_ctx;
+typedef struct nep_dataset_s* nep_dataset;
+
+typedef enum {
+  NEP_OK = 0,
+  NEP_EINVAL = 1,      /* bad argument (null pointer, size, layout)            */
+  NEP_ESTATE = 2,      /* call order: parameters or neighbour list missing     */
+  NEP_ENOMEM = 3,      /* device allocation failed                            */
+  NEP_EOVERFLOW = 4,   /* an atom has more neighbours than max_neighbors      */
+  NEP_ENONFINITE = 5,  /* a non-finite energy or force was produced           */
+  NEP_EDEVICE = 6,     /* a HIP runtime call failed                           */
+  NEP_ENOTIMPL = 7,    /* hyperparameters without a compiled kernel variant   */
+  NEP_EIMAGE = 8       /* a pair needs a lattice image beyond +-3 cells       */
+} nep_status;
+
+/* Hyperparameters of Table nep-hyper (Sec. III B): radial and angular cutoffs
+ * r_c^R, r_c^A (A), Chebyshev orders n_max^R, n_max^A (n = 0..n_max), Legendre
+ * order l_max (l = 1..l_max) and hidden neurons N_neu.  The descriptor has
+ * N_des = (n_max^R+1) + (n_max^A+1) l_max components (Eq. N_des) and the
+ * network N_par = (N_des+2) N_neu + 1 parameters (Eq. N_par).  Requires
+ * 0 < rc_angular <= rc_radial.  Compiled variants: (n_max^R, n_max^A, l_max,
+ * N_neu) = (8, 4, 4, 30); other values return NEP_ENOTIMPL. */
+typedef struct {
+  double rc_radial, rc_angular;
+  int n_max_radial, n_max_angular, l_max, n_neuron;
+} nep_hyper;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t, or NULL for the null stream).  *out is set on success. */
+nep_status nep_create(nep_ctx* out, int device, void* hip_stream);
+
+/* Free everything the context owns.  Waits for its stream first.  NULL is ok. */
+void nep_destroy(nep_ctx ctx);
+
+/* Message of the last failure of a call on this context ("" if none).  The
+ * string is owned by the context and valid until its next call. */
+const char* nep_last_error(nep_ctx ctx);
+
+/* Replace the stream used by later calls (borrowed). */
+nep_status nep_set_stream(nep_ctx ctx, void* hip_stream);
+
+/* Wait for all enqueued work; return the first latched device error
+ * (NEP_EOVERFLOW, NEP_EIMAGE, NEP_ENONFINITE) and clear it, else NEP_OK. */
+nep_status nep_synchronize(nep_ctx ctx);
+
+/* N_des and N_par of a hyperparameter set (Eqs. N_des, N_par); 0 if invalid. */
+int nep_num_descriptors(const nep_hyper* hyper);
+int nep_num_params(const nep_hyper* hyper);
+
+/* ------------------------------------------------------------- the model */
+
+/* Copy the parameter vector z (host, float32, n_par values) to the device.
+ * Layout (Sec. II D): w1 [N_neu][N_des] row-major (w1[mu][nu] is the weight
+ * from descriptor component nu to neuron mu), b1 [N_neu], w2 [N_neu], b2.
+ * Descriptor order nu: radial n = 0..n_max^R, then angular components
+ * (n, l) at N_R + n*l_max + (l-1).  Site energy
+ *   U_i = sum_mu w2[mu] tanh(sum_nu w1[mu][nu] q_nu - b1[mu]) - b2
+ * (Eqs. nn1, nn2).  NEP_EINVAL unless n_par == nep_num_params(hyper).
+ * Synchronous with respect to the host buffer. */
+nep_status nep_load_params(nep_ctx ctx, const nep_hyper* hyper, const float* z_host, int n_par);
+
+/* ------------------------------------------------------------ neighbours */
+
+/* Build the neighbour list of a periodic system of n_atoms atoms at pos_dev
+ * ([3][N] float64).  An entry (j, n) of atom i is kept iff
+ *   |r_j + n.H - r_i|^2 < (rc_radial + skin)^2
+ * with the displacement and its squared norm evaluated in float64 as
+ *   d_c = (x_jc - x_ic) + ((n0*H_0c + n1*H_1c) + n2*H_2c),
+ *   |d|^2 = (d_x*d_x + d_y*d_y) + d_z*d_z          (no fused multiply-add),
+ * and (j, n) != (i, 0) -- the paper's site environment within a cutoff
+ * (Sec. II A).  Entries with |d|^2 < (rc_angular + skin)^2 come first in
+ * each atom's list.  Every lattice image is a separate entry, so boxes
+ * thinner than twice the cutoff are handled; images beyond +-3 cells latch
+ * NEP_EIMAGE.  max_neighbors bounds the list length (more latches
+ * NEP_EOVERFLOW).  n_atoms must be below 2^23.  Requires loaded parameters. */
+nep_status nep_build_neighbors(nep_ctx ctx, int n_atoms, const double* pos_dev,
+                               const double* box_host, double skin, int max_neighbors);
+
+/* Copy the current list to caller device buffers (for inspection):
+ * cnt_radial_dev, cnt_angular_dev [N] int32; nbr_dev [max_neighbors][N] int32
+ * holding j; img_dev [max_neighbors][N][3] int32 holding (n0, n1, n2)
+ * (slot s of atom i at (s*N + i)*3); rev_dev [max_neighbors][N] int32 holding
+ * the slot of the reverse entry (i, -n) in atom j's list.  Entries at
+ * s >= cnt are unspecified.  Any pointer may be NULL. */
+nep_status nep_get_neighbors(nep_ctx ctx, int* cnt_radial_dev, int* cnt_angular_dev,
+                             int* nbr_dev, int* img_dev, int* rev_dev);
+
+/* ------------------------------------------------------------ evaluation */
+
+/* One force evaluation of the system last passed to nep_build_neighbors
+ * (same n_atoms and box; positions may have moved by less than skin/2).
+ * Computes, per Sec. II A-D:
+ *   U_i (site energy), F_i = sum_j (dU_i/dr_ij - dU_j/dr_ji),
+ *   W_i = sum_j r_ij (x) dU_j/dr_ji (full 3x3, Eq. Wi), J_i = W_i . v_i,
+ * in float32 arithmetic with float64 positions and float64 totals.
+ * Outputs (any may be NULL except F_dev): U_dev [N], F_dev [3][N],
+ * W_dev [9][N], J_dev [3][N] (needs vel_dev [3][N] float64), totals_dev
+ * [13] float64 = (sum U, sum W (9, row-major), sum J (3)). */
+nep_status nep_compute(nep_ctx ctx, const double* pos_dev, const double* vel_dev, float* U_dev,
+                       float* F_dev, float* W_dev, float* J_dev, double* totals_dev);
+
+/* n_steps of velocity-Verlet NVE for atoms of mass mass_amu:
+ *   v += dt/2 F/m;  r += dt v;  (rebuild the list every rebuild_every steps,
+ *   first wrapping positions into the box);  F = F(r);  v += dt/2 F/m.
+ * pos_dev, vel_dev: [3][N] float64, updated in place.  thermo_dev
+ * [n_steps][5] float64 receives per step (E_pot, E_kin, sum J_x, J_y, J_z)
+ * evaluated with the end-of-step velocities.  W_dev [9][N] / J_dev [3][N]
+ * (float32, may be NULL) receive the per-atom virial and heat current of the
+ * last step.  Requires a prior nep_build_neighbors for this system (its skin
+ * and max_neighbors are reused).  Forces of the starting positions are
+ * computed first unless the previous call was nep_md_step on the same
+ * buffers. */
+nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every,
+                       double mass_amu, double* pos_dev, double* vel_dev, double* thermo_dev,
+                       float* W_dev, float* J_dev);
+
+/* ----------------------------------------------------------- measurement */
+
+/* Kernel timing for benchmarks.  While enabled, every launch of the force
+ * passes, the neighbour-list build and the integrator is bracketed by a pair
+ * of HIP events recorded on the context's stream.  Disabled by default. */
+nep_status nep_set_timing(nep_ctx ctx, int enable);
+
+/* Waits for the stream, then returns per kernel class the summed event time
+ * in milliseconds (ms_out[4]) and the number of launches (launches_out[4])
+ * since timing was enabled or last read, and resets both.  Classes:
+ * 0 descriptor/network/partial forces, 1 force/virial/heat-current gather,
+ * 2 neighbour-list build, 3 integrator kick-drift. */
+nep_status nep_get_timing(nep_ctx ctx, double* ms_out, int* launches_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEP_H_ */

@@ -128,6 +128,17 @@ def legendre(c: float, lmax: int):
 
 
 # -------------------------------------------------------------- neighbours
+def neighbor_arrays(pos, box, rc: float, cap: int = 256):
+    """Counts [N], atom indices [N, cap] and images [N, cap, 3] (unspecified order)."""
+    pos = _d(pos)
+    N = len(pos)
+    cnt = np.zeros(max(N, 1), np.int32)
+    jl = np.zeros(max(N, 1) * cap, np.int32)
+    img = np.zeros(max(N, 1) * cap * 3, np.int32)
+    _check(lib().or_neighbors(N, pos, _d(box), rc, cap, cnt, jl, img))
+    return cnt[:N], jl.reshape(-1, cap)[:N], img.reshape(-1, cap, 3)[:N]
+
+
 def neighbors(pos, box, rc: float, cap: int = 256):
     """Per atom: sorted list of (j, n0, n1, n2) with 0 < |r_j + n.H - r_i| < rc."""
     pos = _d(pos)

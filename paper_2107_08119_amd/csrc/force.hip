@@ -1,0 +1,560 @@
+// Force evaluation on gfx950: descriptor -> network -> partial forces (pass 1)
+// and the scatter-free gather of forces, virials and heat currents (pass 2).
+//
+// Pass 1 works on L consecutive lanes per atom.  The lanes split the atom's
+// neighbour slots, accumulate partial descriptor sums, and combine them with
+// DPP lane permutations, so every lane ends with the full descriptor.  The
+// angular descriptor (Eq. qinl) is evaluated in the factorised form that the
+// addition theorem gives (paper, text after Eq. N_des): with real harmonics
+// Yhat_lm normalised so that sum_m Yhat_lm(u) Yhat_lm(v) = P_l(u.v),
+//   q_nl = sum_j sum_k g_n(r_ij) g_n(r_ik) P_l(cos theta_ijk) = sum_m c_nlm^2,
+//   c_nlm = sum_j g_n(r_ij) Yhat_lm(r_ij / r_ij),
+// which costs O(M) per atom instead of O(M^2) and equals the double sum
+// (j = k terms included) up to rounding.  The partial force (Sec. II D) is
+//   dU_i/dr_ij = sum_n dU/dq_n g_n'(r) u
+//              + sum_lm [ B_lm Yhat_lm(u) u + A_lm (grad Yhat_lm - u (u.grad Yhat_lm)) / r ],
+// with a_nlm = 2 dU/dq_nl c_nlm, A_lm = sum_n a_nlm g_n(r), B_lm = sum_n a_nlm g_n'(r).
+//
+// Pass 2 computes, per atom, F_i = sum_j (p_ij - p_ji), W_i = sum_j r_ij (x) p_ji
+// and J_i = W_i v_i (Sec. II A-B), reading p_ji through the reverse-slot
+// index instead of scattering, so no atomics touch forces and the result is
+// reproducible bit for bit.  Totals are summed in float64 per block and
+// combined in block order by the last block to finish.
+#include "nep_internal.h"
+
+namespace nep {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr float kPi = 3.14159265358979323846f;
+
+// ----------------------------------------------------------- lane groups
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over aligned groups of L consecutive lanes; every lane gets the sum.
+// quad_perm [1,0,3,2] and [2,3,0,1] pair lanes within quads, row_half_mirror
+// pairs the two quads of an 8-lane half row, row_mirror the two halves of a row.
+template <int L>
+__device__ __forceinline__ float group_sum(float v) {
+  static_assert(L == 1 || L == 2 || L == 4 || L == 8 || L == 16, "group size");
+  if constexpr (L >= 2) v += dpp<0xB1>(v);
+  if constexpr (L >= 4) v += dpp<0x4E>(v);
+  if constexpr (L >= 8) v += dpp<0x141>(v);
+  if constexpr (L >= 16) v += dpp<0x140>(v);
+  return v;
+}
+
+// ------------------------------------------------------------ radial basis
+// sin y and cos y for |y| <= pi/2 from their Taylor series through y^13 and
+// y^14 (truncation below 1e-9, under float32 rounding).
+__device__ __forceinline__ void sincos_quarter_turn(float y, float& s, float& c) {
+  const float y2 = y * y;
+  s = y * (1.f + y2 * (-1.f / 6.f +
+                       y2 * (1.f / 120.f +
+                             y2 * (-1.f / 5040.f +
+                                   y2 * (1.f / 362880.f +
+                                         y2 * (-1.f / 39916800.f + y2 * (1.f / 6227020800.f)))))));
+  c = 1.f + y2 * (-0.5f +
+                  y2 * (1.f / 24.f +
+                        y2 * (-1.f / 720.f +
+                              y2 * (1.f / 40320.f +
+                                    y2 * (-1.f / 3628800.f +
+                                          y2 * (1.f / 479001600.f + y2 * (-1.f / 87178291200.f)))))));
+}
+
+// g_n(r) = (T_n(x) + 1)/2 f_c(r), x = 2 (r/r_c - 1)^2 - 1, n = 0..NB-1 (Eq. g_n),
+// with f_c = (1 + cos(pi r/r_c))/2; and g_n'(r) via dT_n/dx = n U_{n-1}(x)
+// (Appendix A).  Requires r < r_c.
+template <int NB, bool DERIV>
+__device__ __forceinline__ void radial_basis(float r, float rc_inv, float* g, float* dg) {
+  const float t = r * rc_inv;
+  float sy, cy;
+  sincos_quarter_turn(kPi * (t - 0.5f), sy, cy);  // cos(pi t) = -sin(pi (t - 1/2))
+  const float fc = 0.5f * (1.f - sy);
+  const float dfc = -0.5f * kPi * rc_inv * cy;  // -(pi/2r_c) sin(pi t)
+  const float tm1 = t - 1.f;
+  const float x = 2.f * tm1 * tm1 - 1.f;
+  const float dxdr = 4.f * tm1 * rc_inv;
+  float T[NB], U[NB];
+  T[0] = 1.f;
+  U[0] = 1.f;
+  if constexpr (NB > 1) {
+    T[1] = x;
+    U[1] = 2.f * x;
+  }
+#pragma unroll
+  for (int n = 2; n < NB; ++n) {
+    T[n] = 2.f * x * T[n - 1] - T[n - 2];
+    U[n] = 2.f * x * U[n - 1] - U[n - 2];
+  }
+#pragma unroll
+  for (int n = 0; n < NB; ++n) {
+    const float h = 0.5f * (T[n] + 1.f);
+    g[n] = h * fc;
+    if constexpr (DERIV) {
+      const float dT = n == 0 ? 0.f : (float)n * U[n - 1];
+      dg[n] = 0.5f * dT * dxdr * fc + h * dfc;
+    }
+  }
+}
+
+// ------------------------------------------------------- angular harmonics
+// Real harmonics for l = 1..4 scaled by sqrt(4 pi/(2l+1)) so that
+// sum_m Y_lm(u) Y_lm(v) = P_l(u.v) for unit u, v, written as polynomials in
+// (x, y, z) = u together with their gradients in R^3.  Entry idx = l^2-1+(m+l).
+#define NEP_S3 1.7320508075688772f
+#define NEP_S5 2.2360679774997897f
+#define NEP_S6 2.4494897427831781f
+#define NEP_S10 3.1622776601683795f
+#define NEP_S15 3.8729833462074170f
+#define NEP_S35 5.9160797830996160f
+#define NEP_S70 8.3666002653407555f
+#define NEP_YLM_TABLE(X)                                                                        \
+  X(0, x, 1.f, 0.f, 0.f)                                                                        \
+  X(1, y, 0.f, 1.f, 0.f)                                                                        \
+  X(2, z, 0.f, 0.f, 1.f)                                                                        \
+  X(3, NEP_S3 * xy, NEP_S3 * y, NEP_S3 * x, 0.f)                                                \
+  X(4, NEP_S3 * yz, 0.f, NEP_S3 * z, NEP_S3 * y)                                                \
+  X(5, 0.5f * (3.f * zz - 1.f), 0.f, 0.f, 3.f * z)                                              \
+  X(6, NEP_S3 * xz, NEP_S3 * z, 0.f, NEP_S3 * x)                                                \
+  X(7, 0.5f * NEP_S3 * (xx - yy), NEP_S3 * x, -NEP_S3 * y, 0.f)                                 \
+  X(8, 0.25f * NEP_S10 * y * (3.f * xx - yy), 1.5f * NEP_S10 * xy, 0.75f * NEP_S10 * (xx - yy), \
+    0.f)                                                                                        \
+  X(9, NEP_S15 * xyz, NEP_S15 * yz, NEP_S15 * xz, NEP_S15 * xy)                                 \
+  X(10, 0.25f * NEP_S6 * y * (5.f * zz - 1.f), 0.f, 0.25f * NEP_S6 * (5.f * zz - 1.f),          \
+    2.5f * NEP_S6 * yz)                                                                         \
+  X(11, 0.5f * z * (5.f * zz - 3.f), 0.f, 0.f, 0.5f * (15.f * zz - 3.f))                        \
+  X(12, 0.25f * NEP_S6 * x * (5.f * zz - 1.f), 0.25f * NEP_S6 * (5.f * zz - 1.f), 0.f,          \
+    2.5f * NEP_S6 * xz)                                                                         \
+  X(13, 0.5f * NEP_S15 * z * (xx - yy), NEP_S15 * xz, -NEP_S15 * yz,                            \
+    0.5f * NEP_S15 * (xx - yy))                                                                 \
+  X(14, 0.25f * NEP_S10 * x * (xx - 3.f * yy), 0.75f * NEP_S10 * (xx - yy),                     \
+    -1.5f * NEP_S10 * xy, 0.f)                                                                  \
+  X(15, 0.5f * NEP_S35 * xy * (xx - yy), 0.5f * NEP_S35 * y * (3.f * xx - yy),                  \
+    0.5f * NEP_S35 * x * (xx - 3.f * yy), 0.f)                                                  \
+  X(16, 0.25f * NEP_S70 * yz * (3.f * xx - yy), 1.5f * NEP_S70 * xyz,                           \
+    0.75f * NEP_S70 * z * (xx - yy), 0.25f * NEP_S70 * y * (3.f * xx - yy))                     \
+  X(17, 0.5f * NEP_S5 * xy * (7.f * zz - 1.f), 0.5f * NEP_S5 * y * (7.f * zz - 1.f),            \
+    0.5f * NEP_S5 * x * (7.f * zz - 1.f), 7.f * NEP_S5 * xyz)                                   \
+  X(18, 0.25f * NEP_S10 * yz * (7.f * zz - 3.f), 0.f, 0.25f * NEP_S10 * z * (7.f * zz - 3.f),   \
+    0.25f * NEP_S10 * y * (21.f * zz - 3.f))                                                    \
+  X(19, 0.125f * (35.f * zz * zz - 30.f * zz + 3.f), 0.f, 0.f, 0.125f * z * (140.f * zz - 60.f)) \
+  X(20, 0.25f * NEP_S10 * xz * (7.f * zz - 3.f), 0.25f * NEP_S10 * z * (7.f * zz - 3.f), 0.f,   \
+    0.25f * NEP_S10 * x * (21.f * zz - 3.f))                                                    \
+  X(21, 0.25f * NEP_S5 * (xx - yy) * (7.f * zz - 1.f), 0.5f * NEP_S5 * x * (7.f * zz - 1.f),    \
+    -0.5f * NEP_S5 * y * (7.f * zz - 1.f), 3.5f * NEP_S5 * z * (xx - yy))                       \
+  X(22, 0.25f * NEP_S70 * xz * (xx - 3.f * yy), 0.75f * NEP_S70 * z * (xx - yy),                \
+    -1.5f * NEP_S70 * xyz, 0.25f * NEP_S70 * x * (xx - 3.f * yy))                               \
+  X(23, 0.125f * NEP_S35 * (xx * xx - 6.f * xx * yy + yy * yy),                                 \
+    0.5f * NEP_S35 * x * (xx - 3.f * yy), 0.5f * NEP_S35 * y * (yy - 3.f * xx), 0.f)
+
+// r_ij = r_j + n.H - r_i formed in float64, rounded to float32.
+__device__ __forceinline__ void displacement(uint32_t e, const double* __restrict__ pos, int n,
+                                             double xi, double yi, double zi, const Box& b,
+                                             int& j, float& dx, float& dy, float& dz) {
+  j = (int)(e & kAtomMask);
+  int n0, n1, n2;
+  unpack_image(e, n0, n1, n2);
+  const double a0 = (double)n0, a1 = (double)n1, a2 = (double)n2;
+  dx = (float)((pos[j] - xi) + (a0 * b.h[0] + a1 * b.h[3] + a2 * b.h[6]));
+  dy = (float)((pos[n + j] - yi) + (a0 * b.h[1] + a1 * b.h[4] + a2 * b.h[7]));
+  dz = (float)((pos[2 * n + j] - zi) + (a0 * b.h[2] + a1 * b.h[5] + a2 * b.h[8]));
+}
+
+// ------------------------------------------------------------------ pass 1
+template <int NR, int NA, int LMAX, int NNEU, int L>
+__global__ __launch_bounds__(kBlock) void k_partials(
+    int n, const double* __restrict__ pos, const uint32_t* __restrict__ nl,
+    const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, Box box,
+    const float* __restrict__ zpar, float rc_r, float rc_a, float4* __restrict__ p,
+    float* __restrict__ U) {
+  constexpr int NLM = (LMAX + 1) * (LMAX + 1) - 1;
+  constexpr int NDES = NR + NA * LMAX;
+  constexpr int NPAR = (NDES + 2) * NNEU + 1;
+  __shared__ float sz[NPAR];
+  for (int t = threadIdx.x; t < NPAR; t += blockDim.x) sz[t] = zpar[t];
+  __syncthreads();
+
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / L;
+  const int lane = gid % L;
+  const bool active = i < n;
+  const int ii = active ? i : 0;
+  const int cr = active ? cnt_r[i] : 0;
+  const int ca = active ? cnt_a[i] : 0;
+  const double xi = pos[ii], yi = pos[n + ii], zi = pos[2 * n + ii];
+  const float rcr_inv = 1.f / rc_r, rca_inv = 1.f / rc_a;
+
+  float q[NDES];
+  float c[NA][NLM];
+#pragma unroll
+  for (int v = 0; v < NDES; ++v) q[v] = 0.f;
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int m = 0; m < NLM; ++m) c[a][m] = 0.f;
+
+  // descriptor sums over this lane's share of the neighbour slots
+  for (int s = lane; s < cr; s += L) {
+    int j;
+    float dx, dy, dz;
+    displacement(nl[(size_t)s * n + i], pos, n, xi, yi, zi, box, j, dx, dy, dz);
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * rinv;
+    if (r < rc_r) {
+      float g[NR];
+      radial_basis<NR, false>(r, rcr_inv, g, nullptr);
+#pragma unroll
+      for (int a = 0; a < NR; ++a) q[a] += g[a];
+    }
+    if (s < ca && r < rc_a) {
+      float g[NA];
+      radial_basis<NA, false>(r, rca_inv, g, nullptr);
+      const float x = dx * rinv, y = dy * rinv, z = dz * rinv;
+      const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+      const float xyz = xy * z;
+      (void)xyz;
+#define NEP_ACC(idx, YV, GX, GY, GZ)                    \
+  if constexpr ((idx) < NLM) {                          \
+    const float yv = (YV);                              \
+    _Pragma("unroll") for (int a = 0; a < NA; ++a) c[a][idx] += g[a] * yv; \
+  }
+      NEP_YLM_TABLE(NEP_ACC)
+#undef NEP_ACC
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NR; ++a) q[a] = group_sum<L>(q[a]);
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int m = 0; m < NLM; ++m) c[a][m] = group_sum<L>(c[a][m]);
+  // angular components q_nl = sum_m c_nlm^2
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int l = 1; l <= LMAX; ++l) {
+      float s2 = 0.f;
+#pragma unroll
+      for (int m = 0; m < 2 * l + 1; ++m) s2 += c[a][l * l - 1 + m] * c[a][l * l - 1 + m];
+      q[NR + a * LMAX + (l - 1)] = s2;
+    }
+
+  // network (Eqs. nn1, nn2) and dU/dq; the neurons are split over the lanes
+  const float* w1 = sz;
+  const float* b1 = sz + NNEU * NDES;
+  const float* w2 = b1 + NNEU;
+  const float b2 = w2[NNEU];
+  float dq[NDES];
+#pragma unroll
+  for (int v = 0; v < NDES; ++v) dq[v] = 0.f;
+  float u = 0.f;
+  for (int mu = lane; mu < NNEU; mu += L) {
+    float act = -b1[mu];
+#pragma unroll
+    for (int v = 0; v < NDES; ++v) act += w1[mu * NDES + v] * q[v];
+    // tanh and its derivative 1 - tanh^2 from e = exp(-2|a|) (no cancellation)
+    const float ea = __expf(-2.f * fabsf(act));
+    const float inv = __builtin_amdgcn_rcpf(1.f + ea);
+    const float th = copysignf((1.f - ea) * inv, act);
+    const float sech2 = 4.f * ea * inv * inv;
+    u += w2[mu] * th;
+    const float gmu = w2[mu] * sech2;
+#pragma unroll
+    for (int v = 0; v < NDES; ++v) dq[v] += gmu * w1[mu * NDES + v];
+  }
+  u = group_sum<L>(u) - b2;
+#pragma unroll
+  for (int v = 0; v < NDES; ++v) dq[v] = group_sum<L>(dq[v]);
+  if (active && lane == 0) U[i] = u;
+
+  // a_nlm = 2 dU/dq_nl c_nlm, stored in place of c
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int l = 1; l <= LMAX; ++l) {
+      const float f = 2.f * dq[NR + a * LMAX + (l - 1)];
+#pragma unroll
+      for (int m = 0; m < 2 * l + 1; ++m) c[a][l * l - 1 + m] *= f;
+    }
+
+  // partial forces p_ij = dU_i/dr_ij for this lane's slots
+  for (int s = lane; s < cr; s += L) {
+    int j;
+    float dx, dy, dz;
+    displacement(nl[(size_t)s * n + i], pos, n, xi, yi, zi, box, j, dx, dy, dz);
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * rinv;
+    const float x = dx * rinv, y = dy * rinv, z = dz * rinv;
+    float px = 0.f, py = 0.f, pz = 0.f;
+    if (r < rc_r) {
+      float g[NR], dg[NR];
+      radial_basis<NR, true>(r, rcr_inv, g, dg);
+      float f = 0.f;
+#pragma unroll
+      for (int a = 0; a < NR; ++a) f += dq[a] * dg[a];
+      px += f * x;
+      py += f * y;
+      pz += f * z;
+    }
+    if (s < ca && r < rc_a) {
+      float g[NA], dg[NA];
+      radial_basis<NA, true>(r, rca_inv, g, dg);
+      const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+      const float xyz = xy * z;
+      (void)xyz;
+      float sb = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+#define NEP_PF(idx, YV, GX, GY, GZ)                 \
+  if constexpr ((idx) < NLM) {                      \
+    float A = 0.f, B = 0.f;                         \
+    _Pragma("unroll") for (int a = 0; a < NA; ++a) { \
+      A += c[a][idx] * g[a];                        \
+      B += c[a][idx] * dg[a];                       \
+    }                                               \
+    sb += B * (YV);                                 \
+    gx += A * (GX);                                 \
+    gy += A * (GY);                                 \
+    gz += A * (GZ);                                 \
+  }
+      NEP_YLM_TABLE(NEP_PF)
+#undef NEP_PF
+      const float ug = x * gx + y * gy + z * gz;
+      px += sb * x + (gx - x * ug) * rinv;
+      py += sb * y + (gy - y * ug) * rinv;
+      pz += sb * z + (gz - z * ug) * rinv;
+    }
+    p[(size_t)s * n + i] = make_float4(px, py, pz, 0.f);
+  }
+}
+
+// ------------------------------------------------------------------ pass 2
+// Sum of NQ doubles over a block in a fixed order: shuffle tree inside each
+// wave, then waves in index order.  The result is valid in threads < NQ
+// (thread q holds quantity q).
+template <int NQ>
+__device__ __forceinline__ double block_sum(double (&v)[NQ], double (&sw)[kBlock / 64][NQ]) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+  const int wave = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sw[wave][q] = v[q];
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x < NQ)
+    for (int w = 0; w < kBlock / 64; ++w) s += sw[w][threadIdx.x];
+  return s;
+}
+
+// Deterministic sum of NQ per-thread doubles over the grid: every block
+// writes its sums; the last block to finish re-reads all block sums (each
+// thread a strided subset, in block order) and reduces them the same way.
+// Returns true in the last block, where threads < NQ hold the totals in `tot`.
+template <int NQ>
+__device__ bool grid_sum(double (&v)[NQ], double* __restrict__ partials,
+                         unsigned* __restrict__ ticket, double& tot) {
+  __shared__ double sw[kBlock / 64][NQ];
+  __shared__ bool last;
+  const double s = block_sum<NQ>(v, sw);
+  if (threadIdx.x < NQ) partials[(size_t)blockIdx.x * NQ + threadIdx.x] = s;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  const volatile double* vp = partials;
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] += vp[(size_t)b * NQ + q];
+  __syncthreads();  // sw is reused
+  tot = block_sum<NQ>(acc, sw);
+  if (threadIdx.x == 0) *ticket = 0u;
+  return true;
+}
+
+// MODE 0: evaluation -> out[13] = (sum U, sum W_ab (9), sum J (3)).
+// MODE 1: velocity-Verlet second half-kick v += kick F, then
+//         out[5] = (E_pot, E_kin, sum J) with the kicked velocities.
+template <int L, int MODE>
+__global__ __launch_bounds__(kBlock) void k_gather(
+    int n, const double* __restrict__ pos, double* __restrict__ vel,
+    const uint32_t* __restrict__ nl, const int* __restrict__ cnt_r, const int* __restrict__ rev,
+    const float4* __restrict__ p, const float* __restrict__ U, Box box, float* __restrict__ U_out,
+    float* __restrict__ F, float* __restrict__ W, float* __restrict__ J, double kick,
+    double ekin_factor, double* __restrict__ partials, unsigned* __restrict__ ticket,
+    double* __restrict__ out, int* __restrict__ flags) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / L;
+  const int lane = gid % L;
+  const bool active = i < n;
+  const int ii = active ? i : 0;
+  const int cr = active ? cnt_r[i] : 0;
+  const double xi = pos[ii], yi = pos[n + ii], zi = pos[2 * n + ii];
+  float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+  float w[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) w[k] = 0.f;
+  for (int s = lane; s < cr; s += L) {
+    const size_t idx = (size_t)s * n + i;
+    int j;
+    float dx, dy, dz;
+    displacement(nl[idx], pos, n, xi, yi, zi, box, j, dx, dy, dz);
+    const float4 pij = p[idx];
+    const float4 pji = p[(size_t)rev[idx] * n + j];
+    f0 += pij.x - pji.x;
+    f1 += pij.y - pji.y;
+    f2 += pij.z - pji.z;
+    w[0] += dx * pji.x;
+    w[1] += dx * pji.y;
+    w[2] += dx * pji.z;
+    w[3] += dy * pji.x;
+    w[4] += dy * pji.y;
+    w[5] += dy * pji.z;
+    w[6] += dz * pji.x;
+    w[7] += dz * pji.y;
+    w[8] += dz * pji.z;
+  }
+  f0 = group_sum<L>(f0);
+  f1 = group_sum<L>(f1);
+  f2 = group_sum<L>(f2);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) w[k] = group_sum<L>(w[k]);
+
+  constexpr int NQ = MODE == 0 ? 13 : 5;
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+  if (active && lane == 0) {
+    F[i] = f0;
+    F[n + i] = f1;
+    F[2 * n + i] = f2;
+    const float ui = U[i];
+    if (U_out) U_out[i] = ui;
+    if (W)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) W[(size_t)k * n + i] = w[k];
+    double vx = 0.0, vy = 0.0, vz = 0.0;
+    if (vel) {
+      vx = vel[i];
+      vy = vel[n + i];
+      vz = vel[2 * n + i];
+      if constexpr (MODE == 1) {
+        vx += kick * (double)f0;
+        vy += kick * (double)f1;
+        vz += kick * (double)f2;
+        vel[i] = vx;
+        vel[n + i] = vy;
+        vel[2 * n + i] = vz;
+      }
+    }
+    const double j0 = (double)w[0] * vx + (double)w[1] * vy + (double)w[2] * vz;
+    const double j1 = (double)w[3] * vx + (double)w[4] * vy + (double)w[5] * vz;
+    const double j2 = (double)w[6] * vx + (double)w[7] * vy + (double)w[8] * vz;
+    if (J) {
+      J[i] = (float)j0;
+      J[n + i] = (float)j1;
+      J[2 * n + i] = (float)j2;
+    }
+    v[0] = (double)ui;
+    if constexpr (MODE == 0) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v[1 + k] = (double)w[k];
+      v[10] = j0;
+      v[11] = j1;
+      v[12] = j2;
+    } else {
+      v[1] = ekin_factor * (vx * vx + vy * vy + vz * vz);
+      v[2] = j0;
+      v[3] = j1;
+      v[4] = j2;
+    }
+  }
+  double tot = 0.0;
+  if (grid_sum<NQ>(v, partials, ticket, tot) && threadIdx.x < NQ) {
+    out[threadIdx.x] = tot;
+    if (!isfinite(tot)) flags[kFlagNonFinite] = 1;
+  }
+}
+
+__global__ void k_kick_drift(int n, double* __restrict__ pos, double* __restrict__ vel,
+                             const float* __restrict__ F, double kick, double dt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * n) return;
+  const double v = vel[t] + kick * (double)F[t];
+  vel[t] = v;
+  pos[t] += dt * v;
+}
+
+__global__ void k_zero_d(double* __restrict__ a, int m) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) a[t] = 0.0;
+}
+
+constexpr int kLanes = 4;  // lanes per atom
+
+inline bool is_default_variant(const nep_hyper& h) {
+  return h.n_max_radial == 8 && h.n_max_angular == 4 && h.l_max == 4 && h.n_neuron == 30;
+}
+
+inline unsigned blocks_for(size_t work, int block) { return (unsigned)((work + block - 1) / block); }
+
+}  // namespace
+
+bool have_force_variant(const nep_hyper& h) { return is_default_variant(h); }
+
+size_t gather_blocks(int n) { return blocks_for((size_t)n * kLanes, kBlock); }
+
+hipError_t launch_partials(nep_ctx ctx, const double* pos) {
+  const System& s = ctx->sys;
+  if (s.n == 0) return hipSuccess;
+  const unsigned nb = blocks_for((size_t)s.n * kLanes, kBlock);
+  k_partials<9, 5, 4, 30, kLanes><<<nb, kBlock, 0, ctx->stream>>>(
+      s.n, pos, s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr, s.box, ctx->z.ptr,
+      (float)ctx->hyper.rc_radial, (float)ctx->hyper.rc_angular, ctx->p.ptr, ctx->U.ptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_out, float* F_out,
+                         float* W_out, float* J_out, double* out, int mode, double kick,
+                         double mass) {
+  const System& s = ctx->sys;
+  if (s.n == 0) {
+    if (out) k_zero_d<<<1, 64, 0, ctx->stream>>>(out, mode == 0 ? 13 : 5);
+    return hipGetLastError();
+  }
+  const unsigned nb = blocks_for((size_t)s.n * kLanes, kBlock);
+  const double ekin_factor = 0.5 * mass / kAccel;
+  if (mode == 0) {
+    k_gather<kLanes, 0><<<nb, kBlock, 0, ctx->stream>>>(
+        s.n, pos, vel, s.nl.ptr, s.cnt_r.ptr, s.rev.ptr, ctx->p.ptr, ctx->U.ptr, s.box, U_out,
+        F_out, W_out, J_out, kick, ekin_factor, ctx->partials.ptr, ctx->ticket.ptr, out,
+        ctx->flags.ptr);
+  } else {
+    k_gather<kLanes, 1><<<nb, kBlock, 0, ctx->stream>>>(
+        s.n, pos, vel, s.nl.ptr, s.cnt_r.ptr, s.rev.ptr, ctx->p.ptr, ctx->U.ptr, s.box, U_out,
+        F_out, W_out, J_out, kick, ekin_factor, ctx->partials.ptr, ctx->ticket.ptr, out,
+        ctx->flags.ptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_kick_drift(nep_ctx ctx, double* pos, double* vel, double kick, double dt) {
+  const int n = ctx->sys.n;
+  if (n == 0) return hipSuccess;
+  k_kick_drift<<<blocks_for((size_t)3 * n, kBlock), kBlock, 0, ctx->stream>>>(n, pos, vel,
+                                                                             ctx->F.ptr, kick, dt);
+  return hipGetLastError();
+}
+
+}  // namespace nep

@@ -1,0 +1,350 @@
+// C ABI entry points of libnep: argument checks, state, buffer management and
+// launch sequencing.  The arithmetic lives in the kernels.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "nep_internal.h"
+
+namespace nep {
+
+nep_status fail(nep_ctx ctx, nep_status code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+nep_status check_hip(nep_ctx ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return NEP_OK;
+  return fail(ctx, e == hipErrorOutOfMemory ? NEP_ENOMEM : NEP_EDEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+int n_des_of(const nep_hyper& h) {
+  return (h.n_max_radial + 1) + (h.n_max_angular + 1) * h.l_max;
+}
+
+bool hyper_valid(const nep_hyper* h) {
+  return h && std::isfinite(h->rc_radial) && std::isfinite(h->rc_angular) && h->rc_angular > 0 &&
+         h->rc_angular <= h->rc_radial && h->n_max_radial >= 0 && h->n_max_angular >= 0 &&
+         h->l_max >= 1 && h->l_max <= 4 && h->n_neuron >= 1 && h->n_max_radial < 64 &&
+         h->n_max_angular < 64 && h->n_neuron <= 4096;
+}
+
+// Make the context's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// Buffers whose size follows the system: partial forces, energies, forces,
+// block partial sums.
+nep_status size_system_buffers(nep_ctx ctx) {
+  const System& s = ctx->sys;
+  hipError_t e;
+  if ((e = ctx->p.ensure((size_t)s.cap * s.n)) != hipSuccess ||
+      (e = ctx->U.ensure((size_t)s.n)) != hipSuccess ||
+      (e = ctx->F.ensure((size_t)3 * s.n)) != hipSuccess ||
+      (e = ctx->partials.ensure(gather_blocks(s.n) * 16 + 16)) != hipSuccess)
+    return check_hip(ctx, e, "allocating system buffers");
+  return NEP_OK;
+}
+
+}  // namespace
+}  // namespace nep
+
+using namespace nep;
+
+extern "C" {
+
+nep_status nep_create(nep_ctx* out, int device, void* hip_stream) {
+  if (!out) return NEP_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NEP_EINVAL;
+  DeviceGuard guard(device);
+  nep_ctx ctx = new (std::nothrow) nep_ctx_s();
+  if (!ctx) return NEP_ENOMEM;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  hipError_t e;
+  if ((e = ctx->flags.ensure(kNumFlags)) != hipSuccess || (e = ctx->ticket.ensure(1)) != hipSuccess ||
+      (e = ctx->totals.ensure(16)) != hipSuccess ||
+      (e = hipMemset(ctx->flags.ptr, 0, sizeof(int) * kNumFlags)) != hipSuccess ||
+      (e = hipMemset(ctx->ticket.ptr, 0, sizeof(unsigned))) != hipSuccess) {
+    nep_destroy(ctx);
+    return e == hipErrorOutOfMemory ? NEP_ENOMEM : NEP_EDEVICE;
+  }
+  *out = ctx;
+  return NEP_OK;
+}
+
+void nep_destroy(nep_ctx ctx) {
+  if (!ctx) return;
+  DeviceGuard guard(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->sys.release();
+  ctx->z.release();
+  ctx->p.release();
+  ctx->U.release();
+  ctx->F.release();
+  ctx->partials.release();
+  ctx->totals.release();
+  ctx->ticket.release();
+  ctx->flags.release();
+  delete ctx;
+}
+
+const char* nep_last_error(nep_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+nep_status nep_set_stream(nep_ctx ctx, void* hip_stream) {
+  if (!ctx) return NEP_EINVAL;
+  ctx->stream = (hipStream_t)hip_stream;
+  return NEP_OK;
+}
+
+nep_status nep_synchronize(nep_ctx ctx) {
+  if (!ctx) return NEP_EINVAL;
+  DeviceGuard guard(ctx->device);
+  nep_status st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "synchronizing");
+  if (st != NEP_OK) return st;
+  int h[kNumFlags];
+  st = check_hip(ctx, hipMemcpy(h, ctx->flags.ptr, sizeof(h), hipMemcpyDeviceToHost),
+                 "reading device flags");
+  if (st != NEP_OK) return st;
+  if (h[0] | h[1] | h[2] | h[3]) {
+    st = check_hip(ctx, hipMemset(ctx->flags.ptr, 0, sizeof(h)), "clearing device flags");
+    if (st != NEP_OK) return st;
+  }
+  if (h[kFlagOverflow]) return fail(ctx, NEP_EOVERFLOW, "an atom has more than max_neighbors neighbours");
+  if (h[kFlagImage]) return fail(ctx, NEP_EIMAGE, "a neighbour needs a lattice image beyond +-3 cells");
+  if (h[kFlagReverse]) return fail(ctx, NEP_EDEVICE, "neighbour list is not symmetric");
+  if (h[kFlagNonFinite]) return fail(ctx, NEP_ENONFINITE, "non-finite energy, virial or heat current");
+  return NEP_OK;
+}
+
+int nep_num_descriptors(const nep_hyper* hyper) {
+  return hyper_valid(hyper) ? n_des_of(*hyper) : 0;
+}
+
+int nep_num_params(const nep_hyper* hyper) {
+  return hyper_valid(hyper) ? (n_des_of(*hyper) + 2) * hyper->n_neuron + 1 : 0;
+}
+
+nep_status nep_load_params(nep_ctx ctx, const nep_hyper* hyper, const float* z_host, int n_par) {
+  if (!ctx) return NEP_EINVAL;
+  if (!hyper_valid(hyper)) return fail(ctx, NEP_EINVAL, "invalid hyperparameters");
+  if (!z_host) return fail(ctx, NEP_EINVAL, "z_host is NULL");
+  const int want = nep_num_params(hyper);
+  if (n_par != want)
+    return fail(ctx, NEP_EINVAL,
+                "n_par is " + std::to_string(n_par) + ", expected (N_des+2)*N_neu+1 = " +
+                    std::to_string(want));
+  if (!have_force_variant(*hyper))
+    return fail(ctx, NEP_ENOTIMPL, "no compiled kernel for these descriptor/network sizes");
+  if (ctx->have_list && (hyper->rc_radial != ctx->hyper.rc_radial ||
+                         hyper->rc_angular != ctx->hyper.rc_angular))
+    ctx->have_list = false;  // list cutoffs change with the model
+  DeviceGuard guard(ctx->device);
+  nep_status st = check_hip(ctx, ctx->z.ensure(n_par), "allocating parameters");
+  if (st != NEP_OK) return st;
+  st = check_hip(ctx,
+                 hipMemcpyAsync(ctx->z.ptr, z_host, sizeof(float) * n_par, hipMemcpyHostToDevice,
+                                ctx->stream),
+                 "copying parameters");
+  if (st != NEP_OK) return st;
+  st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "copying parameters");
+  if (st != NEP_OK) return st;
+  ctx->hyper = *hyper;
+  ctx->n_des = n_des_of(*hyper);
+  ctx->n_par = n_par;
+  ctx->have_params = true;
+  ctx->md_forces_valid = false;
+  return NEP_OK;
+}
+
+nep_status nep_build_neighbors(nep_ctx ctx, int n_atoms, const double* pos_dev,
+                               const double* box_host, double skin, int max_neighbors) {
+  if (!ctx) return NEP_EINVAL;
+  if (!ctx->have_params) return fail(ctx, NEP_ESTATE, "nep_load_params must come first");
+  if (n_atoms < 0 || n_atoms > kMaxAtoms)
+    return fail(ctx, NEP_EINVAL, "n_atoms must be in [0, 2^23)");
+  if (n_atoms > 0 && !pos_dev) return fail(ctx, NEP_EINVAL, "pos_dev is NULL");
+  if (!box_host) return fail(ctx, NEP_EINVAL, "box_host is NULL");
+  if (!(skin >= 0.0) || !std::isfinite(skin)) return fail(ctx, NEP_EINVAL, "skin must be >= 0");
+  if (max_neighbors < 1 || (size_t)max_neighbors * (size_t)(n_atoms > 0 ? n_atoms : 1) > (1ull << 40))
+    return fail(ctx, NEP_EINVAL, "max_neighbors must be >= 1");
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(box_host[k])) return fail(ctx, NEP_EINVAL, "box has non-finite entries");
+  System& s = ctx->sys;
+  System probe;
+  prepare_system_geometry(probe, box_host, ctx->hyper.rc_radial, ctx->hyper.rc_angular, skin);
+  const double det = probe.box.h[0] * (probe.box.h[4] * probe.box.h[8] - probe.box.h[5] * probe.box.h[7]) -
+                     probe.box.h[1] * (probe.box.h[3] * probe.box.h[8] - probe.box.h[5] * probe.box.h[6]) +
+                     probe.box.h[2] * (probe.box.h[3] * probe.box.h[7] - probe.box.h[4] * probe.box.h[6]);
+  if (!(std::fabs(det) > 0.0)) return fail(ctx, NEP_EINVAL, "box is singular");
+  if (!probe.use_cells && (probe.kimg[0] > 2 || probe.kimg[1] > 2 || probe.kimg[2] > 2))
+    return fail(ctx, NEP_EINVAL, "box thinner than half the list cutoff along a cell vector");
+  DeviceGuard guard(ctx->device);
+  for (int k = 0; k < 9; ++k) s.box.h[k] = probe.box.h[k];
+  for (int k = 0; k < 9; ++k) s.box.hinv[k] = probe.box.hinv[k];
+  s.skin = probe.skin;
+  s.rc_list_r = probe.rc_list_r;
+  s.rc_list_a = probe.rc_list_a;
+  s.use_cells = probe.use_cells;
+  for (int a = 0; a < 3; ++a) {
+    s.nc[a] = probe.nc[a];
+    s.kimg[a] = probe.kimg[a];
+  }
+  s.n = n_atoms;
+  s.cap = max_neighbors;
+  ctx->have_list = false;
+  ctx->md_forces_valid = false;
+  nep_status st = size_system_buffers(ctx);
+  if (st != NEP_OK) return st;
+  if (n_atoms > 0) {
+    st = build_neighbors(ctx, pos_dev, false);
+    if (st != NEP_OK) return st;
+  }
+  ctx->have_list = true;
+  ctx->steps_since_rebuild = 0;
+  return NEP_OK;
+}
+
+nep_status nep_get_neighbors(nep_ctx ctx, int* cnt_radial_dev, int* cnt_angular_dev, int* nbr_dev,
+                             int* img_dev, int* rev_dev) {
+  if (!ctx) return NEP_EINVAL;
+  if (!ctx->have_list) return fail(ctx, NEP_ESTATE, "no neighbour list");
+  const System& s = ctx->sys;
+  if (s.n == 0) return NEP_OK;
+  DeviceGuard guard(ctx->device);
+  const size_t ncap = (size_t)s.n * s.cap;
+  hipError_t e = hipSuccess;
+  if (cnt_radial_dev && e == hipSuccess)
+    e = hipMemcpyAsync(cnt_radial_dev, s.cnt_r.ptr, sizeof(int) * s.n, hipMemcpyDeviceToDevice, ctx->stream);
+  if (cnt_angular_dev && e == hipSuccess)
+    e = hipMemcpyAsync(cnt_angular_dev, s.cnt_a.ptr, sizeof(int) * s.n, hipMemcpyDeviceToDevice, ctx->stream);
+  if (rev_dev && e == hipSuccess)
+    e = hipMemcpyAsync(rev_dev, s.rev.ptr, sizeof(int) * ncap, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e != hipSuccess) return check_hip(ctx, e, "copying neighbour list");
+  if (nbr_dev || img_dev) {
+    e = unpack_neighbors(ctx, nbr_dev, img_dev);
+    if (e != hipSuccess) return check_hip(ctx, e, "unpacking neighbour list");
+  }
+  return NEP_OK;
+}
+
+nep_status nep_compute(nep_ctx ctx, const double* pos_dev, const double* vel_dev, float* U_dev,
+                       float* F_dev, float* W_dev, float* J_dev, double* totals_dev) {
+  if (!ctx) return NEP_EINVAL;
+  if (!ctx->have_params || !ctx->have_list)
+    return fail(ctx, NEP_ESTATE, "nep_load_params and nep_build_neighbors must come first");
+  if (ctx->sys.n > 0 && (!pos_dev || !F_dev))
+    return fail(ctx, NEP_EINVAL, "pos_dev and F_dev are required");
+  if (J_dev && !vel_dev) return fail(ctx, NEP_EINVAL, "J_dev needs vel_dev");
+  DeviceGuard guard(ctx->device);
+  ctx->md_forces_valid = false;
+  hipError_t e = timed(ctx, 0, [&] { return launch_partials(ctx, pos_dev); });
+  if (e == hipSuccess)
+    e = timed(ctx, 1, [&] {
+      return launch_gather(ctx, pos_dev, const_cast<double*>(vel_dev), U_dev, F_dev, W_dev,
+                           J_dev, totals_dev ? totals_dev : ctx->totals.ptr, 0, 0.0, 1.0);
+    });
+  return check_hip(ctx, e, "launching force kernels");
+}
+
+nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every,
+                       double mass_amu, double* pos_dev, double* vel_dev, double* thermo_dev,
+                       float* W_dev, float* J_dev) {
+  if (!ctx) return NEP_EINVAL;
+  if (!ctx->have_params || !ctx->have_list)
+    return fail(ctx, NEP_ESTATE, "nep_load_params and nep_build_neighbors must come first");
+  if (n_steps < 0) return fail(ctx, NEP_EINVAL, "n_steps must be >= 0");
+  if (!(dt_fs > 0.0) || !std::isfinite(dt_fs)) return fail(ctx, NEP_EINVAL, "dt must be > 0");
+  if (rebuild_every < 1) return fail(ctx, NEP_EINVAL, "rebuild_every must be >= 1");
+  if (!(mass_amu > 0.0) || !std::isfinite(mass_amu)) return fail(ctx, NEP_EINVAL, "mass must be > 0");
+  if (n_steps == 0) return NEP_OK;
+  if (ctx->sys.n > 0 && (!pos_dev || !vel_dev)) return fail(ctx, NEP_EINVAL, "pos/vel are required");
+  if (!thermo_dev) return fail(ctx, NEP_EINVAL, "thermo_dev is required");
+  DeviceGuard guard(ctx->device);
+  const double kick = 0.5 * dt_fs * kAccel / mass_amu;
+  hipError_t e = hipSuccess;
+  if (!(ctx->md_forces_valid && ctx->md_pos == pos_dev && ctx->md_vel == vel_dev)) {
+    e = timed(ctx, 0, [&] { return launch_partials(ctx, pos_dev); });
+    if (e == hipSuccess)
+      e = timed(ctx, 1, [&] {
+        return launch_gather(ctx, pos_dev, nullptr, nullptr, ctx->F.ptr, nullptr, nullptr,
+                             ctx->totals.ptr, 0, 0.0, mass_amu);
+      });
+    if (e != hipSuccess) return check_hip(ctx, e, "launching force kernels");
+  }
+  ctx->md_forces_valid = false;
+  for (int step = 0; step < n_steps; ++step) {
+    e = timed(ctx, 3, [&] { return launch_kick_drift(ctx, pos_dev, vel_dev, kick, dt_fs); });
+    if (e != hipSuccess) return check_hip(ctx, e, "launching integrator");
+    if (++ctx->steps_since_rebuild >= rebuild_every) {
+      if (ctx->sys.n > 0) {
+        nep_status st = NEP_OK;
+        e = timed(ctx, 2, [&] {
+          st = build_neighbors(ctx, pos_dev, true);
+          return st == NEP_OK ? hipSuccess : hipErrorUnknown;
+        });
+        if (st != NEP_OK) return st;
+        if (e != hipSuccess) return check_hip(ctx, e, "timing neighbour build");
+      }
+      ctx->steps_since_rebuild = 0;
+    }
+    e = timed(ctx, 0, [&] { return launch_partials(ctx, pos_dev); });
+    const bool last = step == n_steps - 1;
+    if (e == hipSuccess)
+      e = timed(ctx, 1, [&] {
+        return launch_gather(ctx, pos_dev, vel_dev, nullptr, ctx->F.ptr, last ? W_dev : nullptr,
+                             last ? J_dev : nullptr, thermo_dev + (size_t)5 * step, 1, kick,
+                             mass_amu);
+      });
+    if (e != hipSuccess) return check_hip(ctx, e, "launching force kernels");
+  }
+  ctx->md_forces_valid = true;
+  ctx->md_pos = pos_dev;
+  ctx->md_vel = vel_dev;
+  return NEP_OK;
+}
+
+nep_status nep_set_timing(nep_ctx ctx, int enable) {
+  if (!ctx) return NEP_EINVAL;
+  ctx->timer.on = enable != 0;
+  for (int c = 0; c < KernelTimer::kClasses; ++c) ctx->timer.used[c] = 0;
+  return NEP_OK;
+}
+
+nep_status nep_get_timing(nep_ctx ctx, double* ms_out, int* launches_out) {
+  if (!ctx || !ms_out || !launches_out) return NEP_EINVAL;
+  DeviceGuard guard(ctx->device);
+  nep_status st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "synchronizing");
+  if (st != NEP_OK) return st;
+  KernelTimer& t = ctx->timer;
+  for (int c = 0; c < KernelTimer::kClasses; ++c) {
+    double tot = 0.0;
+    for (size_t k = 0; k < t.used[c]; ++k) {
+      float ms = 0.f;
+      st = check_hip(ctx, hipEventElapsedTime(&ms, t.start[c][k], t.stop[c][k]), "reading events");
+      if (st != NEP_OK) return st;
+      tot += ms;
+    }
+    ms_out[c] = tot;
+    launches_out[c] = (int)t.used[c];
+    t.used[c] = 0;
+  }
+  return NEP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,201 @@
+// Internal declarations of libnep (gfx950).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nep.h"
+
+namespace nep {
+
+// A periodic cell: rows of h are the cell vectors; hinv is its inverse, so
+// fractional coordinates are s = r . hinv (row vector times matrix).
+struct Box {
+  double h[9];
+  double hinv[9];
+};
+
+// Packed neighbour entry: atom index in the low 23 bits, lattice image code
+// (n0+3) + 7 (n1+3) + 49 (n2+3) in the high 9 bits.
+constexpr int kAtomBits = 23;
+constexpr uint32_t kAtomMask = (1u << kAtomBits) - 1u;
+constexpr int kMaxAtoms = (1 << kAtomBits) - 1;
+
+__host__ __device__ inline uint32_t pack_entry(int j, int n0, int n1, int n2) {
+  return (uint32_t)j | ((uint32_t)((n0 + 3) + 7 * (n1 + 3) + 49 * (n2 + 3)) << kAtomBits);
+}
+__host__ __device__ inline void unpack_image(uint32_t e, int& n0, int& n1, int& n2) {
+  int code = (int)(e >> kAtomBits);
+  n0 = code % 7 - 3;
+  n1 = (code / 7) % 7 - 3;
+  n2 = code / 49 - 3;
+}
+
+// A device array owned by the context that only grows.
+template <class T>
+struct DevBuf {
+  T* ptr = nullptr;
+  size_t size = 0;
+  hipError_t ensure(size_t need) {
+    if (ptr && need <= size) return hipSuccess;
+    if (ptr) {
+      hipError_t e = hipFree(ptr);
+      ptr = nullptr;
+      size = 0;
+      if (e != hipSuccess) return e;
+    }
+    size_t n = need > 0 ? need : 1;
+    hipError_t e = hipMalloc((void**)&ptr, n * sizeof(T));
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      return e;
+    }
+    size = n;
+    return hipSuccess;
+  }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    size = 0;
+  }
+};
+
+// Device error flags latched by kernels.
+enum Flag { kFlagOverflow = 0, kFlagImage = 1, kFlagNonFinite = 2, kFlagReverse = 3, kNumFlags = 4 };
+
+// 1 eV/A acting on 1 amu, in A/fs^2; and 1 amu A^2/fs^2 in eV.
+constexpr double kAccel = 1.602176634e-19 / 1.66053906660e-27 * 1.0e-10;
+
+// Neighbour-list state of one system (a single periodic box).
+struct System {
+  int n = 0;             // atoms
+  int cap = 0;           // slots per atom (max_neighbors)
+  Box box{};
+  double skin = 0.0;
+  double rc_list_r = 0, rc_list_a = 0;  // rc + skin
+  bool use_cells = false;
+  int nc[3] = {1, 1, 1};
+  int kimg[3] = {0, 0, 0};  // image range for the all-pairs builder
+  // device arrays (owned by the context)
+  DevBuf<uint32_t> nl;     // [cap][n]
+  DevBuf<int> cnt_r;       // [n]
+  DevBuf<int> cnt_a;       // [n]
+  DevBuf<int> rev;         // [cap][n]
+  DevBuf<int> wrap;        // [3][n] integer cell offsets of the raw positions
+  DevBuf<int> cell_of;     // [n]
+  DevBuf<int> cell_cnt;    // [ncell]
+  DevBuf<int> cell_start;  // [ncell+1]
+  DevBuf<int> cell_fill;   // [ncell]
+  DevBuf<int> cell_atoms;  // [n]
+  void release() {
+    nl.release();
+    cnt_r.release();
+    cnt_a.release();
+    rev.release();
+    wrap.release();
+    cell_of.release();
+    cell_cnt.release();
+    cell_start.release();
+    cell_fill.release();
+    cell_atoms.release();
+  }
+};
+
+// Event pairs bracketing kernel launches, per kernel class.
+struct KernelTimer {
+  static constexpr int kClasses = 4;
+  bool on = false;
+  std::vector<hipEvent_t> start[kClasses], stop[kClasses];
+  size_t used[kClasses] = {0, 0, 0, 0};
+  ~KernelTimer() {
+    for (int c = 0; c < kClasses; ++c) {
+      for (hipEvent_t e : start[c]) (void)hipEventDestroy(e);
+      for (hipEvent_t e : stop[c]) (void)hipEventDestroy(e);
+    }
+  }
+};
+
+}  // namespace nep
+
+struct nep_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // model
+  bool have_params = false;
+  nep_hyper hyper{};
+  int n_des = 0, n_par = 0;
+  nep::DevBuf<float> z;  // [n_par]
+  // system
+  bool have_list = false;
+  nep::System sys;
+  nep::DevBuf<float4> p;          // partial forces dU_i/dr_ij, [cap][n]
+  nep::DevBuf<float> U;           // [n]
+  nep::DevBuf<float> F;           // [3][n]
+  nep::DevBuf<double> partials;   // [blocks][16] block sums
+  nep::DevBuf<double> totals;     // [16]
+  nep::DevBuf<unsigned> ticket;   // [1]
+  nep::DevBuf<int> flags;         // [kNumFlags]
+  // molecular dynamics state
+  bool md_forces_valid = false;
+  const double* md_pos = nullptr;
+  const double* md_vel = nullptr;
+  int steps_since_rebuild = 0;
+  nep::KernelTimer timer;
+};
+
+namespace nep {
+
+// neighbours.hip
+nep_status build_neighbors(nep_ctx ctx, const double* pos, bool wrap_in_place);
+void prepare_system_geometry(System& s, const double* box_host, double rc_r, double rc_a,
+                             double skin);
+// Expand packed entries to atom indices [cap][n] and images [cap][n][3].
+hipError_t unpack_neighbors(nep_ctx ctx, int* nbr, int* img);
+
+// force.hip
+bool have_force_variant(const nep_hyper& h);
+// pass 1: descriptor, network, partial forces; pass 2: scatter-free gather.
+hipError_t launch_partials(nep_ctx ctx, const double* pos);
+// mode 0: plain evaluation (totals = E, W(9), J(3)); mode 1: velocity-Verlet
+// second half-kick fused (vel updated, thermo row written).
+hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_out, float* F_out,
+                         float* W_out, float* J_out, double* out, int mode, double kick,
+                         double mass);
+size_t gather_blocks(int n);
+hipError_t launch_kick_drift(nep_ctx ctx, double* pos, double* vel, double kick, double dt);
+
+// Run `launch` between two timing events of class `cls` when timing is on.
+template <class Fn>
+hipError_t timed(nep_ctx ctx, int cls, Fn&& launch) {
+  KernelTimer& t = ctx->timer;
+  if (!t.on) return launch();
+  if (t.used[cls] == t.start[cls].size()) {
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return e;
+    }
+    t.start[cls].push_back(a);
+    t.stop[cls].push_back(b);
+  }
+  const size_t k = t.used[cls]++;
+  hipError_t e = hipEventRecord(t.start[cls][k], ctx->stream);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  return hipEventRecord(t.stop[cls][k], ctx->stream);
+}
+
+// helpers (nep_api.hip)
+nep_status fail(nep_ctx ctx, nep_status code, const std::string& msg);
+nep_status check_hip(nep_ctx ctx, hipError_t e, const char* what);
+
+}  // namespace nep

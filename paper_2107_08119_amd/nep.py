@@ -1,0 +1,234 @@
+"""Thin Python binding of libnep (the C ABI declared in include/nep.h).
+
+Only argument marshalling happens here: torch tensors provide device memory
+and the current HIP stream, every step of the computation runs in the HIP
+kernels of libnep.so.  The library must be built (``__graft_entry__.build()``
+or ``python -m paper_2107_08119_amd.build``); nothing falls back to the CPU.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnep.so")
+
+NEP_OK, NEP_EINVAL, NEP_ESTATE, NEP_ENOMEM, NEP_EOVERFLOW = 0, 1, 2, 3, 4
+NEP_ENONFINITE, NEP_EDEVICE, NEP_ENOTIMPL, NEP_EIMAGE = 5, 6, 7, 8
+STATUS_NAMES = {0: "NEP_OK", 1: "NEP_EINVAL", 2: "NEP_ESTATE", 3: "NEP_ENOMEM",
+                4: "NEP_EOVERFLOW", 5: "NEP_ENONFINITE", 6: "NEP_EDEVICE", 7: "NEP_ENOTIMPL",
+                8: "NEP_EIMAGE"}
+
+EXPORTED = [
+    "nep_create", "nep_destroy", "nep_last_error", "nep_set_stream", "nep_synchronize",
+    "nep_num_descriptors", "nep_num_params", "nep_load_params", "nep_build_neighbors",
+    "nep_get_neighbors", "nep_compute", "nep_md_step", "nep_set_timing", "nep_get_timing",
+]
+
+
+class NepError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), message))
+        self.status = status
+
+
+class Hyper(C.Structure):
+    """nep_hyper: cutoffs (A), Chebyshev orders, Legendre order, hidden neurons."""
+    _fields_ = [("rc_radial", C.c_double), ("rc_angular", C.c_double),
+                ("n_max_radial", C.c_int), ("n_max_angular", C.c_int),
+                ("l_max", C.c_int), ("n_neuron", C.c_int)]
+
+
+def hyper(rc_radial=5.0, rc_angular=4.0, n_max_radial=8, n_max_angular=4, l_max=4,
+          n_neuron=30) -> Hyper:
+    return Hyper(rc_radial, rc_angular, n_max_radial, n_max_angular, l_max, n_neuron)
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libnep.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError("libnep.so is not built: run __graft_entry__.build()")
+        L = C.CDLL(_LIB_PATH)
+        vp, ip, dp, fp = C.c_void_p, C.c_int, C.c_double, C.c_void_p
+        H = C.POINTER(Hyper)
+        L.nep_create.argtypes = [C.POINTER(vp), ip, vp]
+        L.nep_destroy.argtypes = [vp]
+        L.nep_destroy.restype = None
+        L.nep_last_error.argtypes = [vp]
+        L.nep_last_error.restype = C.c_char_p
+        L.nep_set_stream.argtypes = [vp, vp]
+        L.nep_synchronize.argtypes = [vp]
+        L.nep_num_descriptors.argtypes = [H]
+        L.nep_num_params.argtypes = [H]
+        L.nep_load_params.argtypes = [vp, H, vp, ip]
+        L.nep_build_neighbors.argtypes = [vp, ip, vp, C.POINTER(C.c_double), dp, ip]
+        L.nep_get_neighbors.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.nep_compute.argtypes = [vp, vp, vp, vp, fp, vp, vp, vp]
+        L.nep_md_step.argtypes = [vp, ip, dp, ip, dp, vp, vp, vp, vp, vp]
+        L.nep_set_timing.argtypes = [vp, ip]
+        L.nep_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+        for name in EXPORTED:
+            if name not in ("nep_destroy", "nep_last_error", "nep_num_descriptors",
+                            "nep_num_params"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _require(t, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, shape, tuple(t.shape)))
+    return t
+
+
+def num_params(h: Hyper) -> int:
+    return lib().nep_num_params(C.byref(h))
+
+
+def num_descriptors(h: Hyper) -> int:
+    return lib().nep_num_descriptors(C.byref(h))
+
+
+class Context:
+    """A libnep context bound to one device and the current torch stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self._lib = lib()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = self._lib.nep_create(C.byref(h), device, C.c_void_p(stream.cuda_stream))
+        if st != NEP_OK:
+            raise NepError(st, "nep_create failed")
+        self._h = h
+        self.n = 0
+        self.cap = 0
+        self.hyper = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.nep_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != NEP_OK:
+            raise NepError(st, self._lib.nep_last_error(self._h).decode())
+
+    # -- C ABI calls ---------------------------------------------------------
+    def synchronize(self):
+        self._check(self._lib.nep_synchronize(self._h))
+
+    def load_params(self, h: Hyper, z) -> None:
+        z = np.ascontiguousarray(z, dtype=np.float32)
+        self._check(self._lib.nep_load_params(self._h, C.byref(h), z.ctypes.data, len(z)))
+        self.hyper = h
+
+    def build_neighbors(self, pos: torch.Tensor, box, skin: float = 0.5,
+                        max_neighbors: int = 64) -> None:
+        n = pos.shape[1] if pos.dim() == 2 else 0
+        _require(pos, torch.float64, (3, n), "pos")
+        b = np.ascontiguousarray(box, dtype=np.float64).reshape(9)
+        self._check(self._lib.nep_build_neighbors(
+            self._h, n, _ptr(pos), b.ctypes.data_as(C.POINTER(C.c_double)), skin, max_neighbors))
+        self.n, self.cap = n, max_neighbors  # cap > 0 marks a built list
+
+    def get_neighbors(self) -> dict:
+        dev = torch.device("cuda", self.device)
+        n, cap = self.n, self.cap
+        out = {
+            "cnt_radial": torch.zeros(n, dtype=torch.int32, device=dev),
+            "cnt_angular": torch.zeros(n, dtype=torch.int32, device=dev),
+            "nbr": torch.zeros((cap, n), dtype=torch.int32, device=dev),
+            "img": torch.zeros((cap, n, 3), dtype=torch.int32, device=dev),
+            "rev": torch.zeros((cap, n), dtype=torch.int32, device=dev),
+        }
+        self._check(self._lib.nep_get_neighbors(
+            self._h, _ptr(out["cnt_radial"]), _ptr(out["cnt_angular"]), _ptr(out["nbr"]),
+            _ptr(out["img"]), _ptr(out["rev"])))
+        return out
+
+    def compute(self, pos: torch.Tensor, vel: torch.Tensor | None = None, *, U: bool = True,
+                W: bool = True, J: bool | None = None, out: dict | None = None) -> dict:
+        n = self.n
+        dev = torch.device("cuda", self.device)
+        _require(pos, torch.float64, (3, n) if self.cap else None, "pos")
+        if vel is not None:
+            _require(vel, torch.float64, (3, n), "vel")
+        if J is None:
+            J = vel is not None
+        if out is None:
+            out = {"F": torch.empty((3, n), dtype=torch.float32, device=dev),
+                   "totals": torch.empty(13, dtype=torch.float64, device=dev)}
+            if U:
+                out["U"] = torch.empty(n, dtype=torch.float32, device=dev)
+            if W:
+                out["W"] = torch.empty((9, n), dtype=torch.float32, device=dev)
+            if J:
+                out["J"] = torch.empty((3, n), dtype=torch.float32, device=dev)
+        self._check(self._lib.nep_compute(
+            self._h, _ptr(pos), _ptr(vel), _ptr(out.get("U")), _ptr(out["F"]),
+            _ptr(out.get("W")), _ptr(out.get("J")), _ptr(out.get("totals"))))
+        return out
+
+    def md_step(self, n_steps: int, dt: float, rebuild_every: int, mass: float,
+                pos: torch.Tensor, vel: torch.Tensor, thermo: torch.Tensor | None = None,
+                W: torch.Tensor | None = None, J: torch.Tensor | None = None) -> torch.Tensor:
+        n = self.n
+        _require(pos, torch.float64, (3, n), "pos")
+        _require(vel, torch.float64, (3, n), "vel")
+        if thermo is None:
+            thermo = torch.empty((max(n_steps, 1), 5), dtype=torch.float64, device=pos.device)
+        self._check(self._lib.nep_md_step(self._h, n_steps, dt, rebuild_every, mass, _ptr(pos),
+                                          _ptr(vel), _ptr(thermo), _ptr(W), _ptr(J)))
+        return thermo
+
+
+KERNEL_CLASSES = ("partials", "gather", "neighbors", "integrator")
+
+
+def set_timing(ctx: "Context", enable: bool) -> None:
+    ctx._check(ctx._lib.nep_set_timing(ctx._h, 1 if enable else 0))
+
+
+def get_timing(ctx: "Context") -> dict:
+    """{class: (milliseconds, launches)} since timing was enabled or last read."""
+    ms = (C.c_double * 4)()
+    cnt = (C.c_int * 4)()
+    ctx._check(ctx._lib.nep_get_timing(ctx._h, ms, cnt))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+
+def soa(x: np.ndarray, device: int = 0) -> torch.Tensor:
+    """[N, 3] host array -> [3, N] contiguous float64 device tensor."""
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, np.float64).T)).to(
+        torch.device("cuda", device))
+
+
+def aos(t: torch.Tensor) -> np.ndarray:
+    """[k, N] device tensor -> [N, k] host array."""
+    return t.detach().cpu().numpy().T.copy()

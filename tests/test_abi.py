@@ -1,0 +1,44 @@
+"""The C-ABI library loads and exports every symbol include/nep.h declares (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2107_08119_amd", "libnep.so")
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "nep.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:nep|snes)_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for required in ("nep_load_params", "nep_build_neighbors", "nep_compute", "nep_md_step"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libnep.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libnep.so not built")
+def test_host_only_calls():
+    from paper_2107_08119_amd import nep
+    h = nep.hyper()
+    assert nep.num_descriptors(h) == 29
+    assert nep.num_params(h) == 931
+    assert nep.num_params(nep.hyper(5.0, 5.0, 15, 15, 4, 50)) == 4101
+    bad = nep.hyper(4.0, 5.0)  # angular cutoff beyond the radial one
+    assert nep.num_params(bad) == 0
+    # context creation without a visible device fails cleanly
+    import torch
+    if not torch.cuda.is_available():
+        out = ctypes.c_void_p()
+        assert nep.lib().nep_create(ctypes.byref(out), 0, None) == nep.NEP_EINVAL
