@@ -169,6 +169,13 @@ nep_status nep_set_timing(nep_ctx ctx, int enable);
  * 2 neighbour-list build, 3 integrator kick-drift. */
 nep_status nep_get_timing(nep_ctx ctx, double* ms_out, int* launches_out);
 
+/* Enqueue `reps` back-to-back launches of the descriptor/network/partial-
+ * force kernel on the current system at pos_dev (each launch recomputes the
+ * same outputs) between one pair of HIP events on the context's stream, wait
+ * for them, and return the mean duration of one launch in milliseconds.
+ * Needs loaded parameters and a neighbour list; 1 <= reps <= 100000. */
+nep_status nep_time_partials(nep_ctx ctx, const double* pos_dev, int reps, double* ms_per_launch);
+
 #ifdef __cplusplus
 }
 #endif

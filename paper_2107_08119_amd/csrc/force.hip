@@ -15,11 +15,13 @@
 //              + sum_lm [ B_lm Yhat_lm(u) u + A_lm (grad Yhat_lm - u (u.grad Yhat_lm)) / r ],
 // with a_nlm = 2 dU/dq_nl c_nlm, A_lm = sum_n a_nlm g_n(r), B_lm = sum_n a_nlm g_n'(r).
 //
-// Pass 2 computes, per atom, F_i = sum_j (p_ij - p_ji), W_i = sum_j r_ij (x) p_ji
-// and J_i = W_i v_i (Sec. II A-B), reading p_ji through the reverse-slot
-// index instead of scattering, so no atomics touch forces and the result is
-// reproducible bit for bit.  Totals are summed in float64 per block and
-// combined in block order by the last block to finish.
+// Pass 1 also sums the atom's own partials, sum_j p_ij, and stores every p_ij
+// in the reverse slot of atom j's list (each slot is written exactly once).
+// Pass 2 then computes, per atom, F_i = sum_j p_ij - sum_j p_ji,
+// W_i = sum_j r_ij (x) p_ji and J_i = W_i v_i (Sec. II A-B) from coalesced
+// reads of its own slots; no atomics touch forces and the result is
+// reproducible bit for bit.  Totals are summed in float64 per block and the
+// block sums are added in block order by a one-block kernel.
 #include "nep_internal.h"
 
 namespace nep {
@@ -166,12 +168,15 @@ __device__ __forceinline__ void displacement(uint32_t e, const double* __restric
 }
 
 // ------------------------------------------------------------------ pass 1
+// Outputs: U[i]; fown[c*n + i] = sum_j dU_i/dr_ij (component c); and every
+// partial force dU_i/dr_ij written to the reverse slot, pin[t*n + j] with
+// t = rev[s*n + i], where atom j finds it as its incoming partial dU_i/dr_ij.
 template <int NR, int NA, int LMAX, int NNEU, int L>
 __global__ __launch_bounds__(kBlock) void k_partials(
     int n, const double* __restrict__ pos, const uint32_t* __restrict__ nl,
-    const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, Box box,
-    const float* __restrict__ zpar, float rc_r, float rc_a, float4* __restrict__ p,
-    float* __restrict__ U) {
+    const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, const int* __restrict__ rev,
+    Box box, const float* __restrict__ zpar, float rc_r, float rc_a, float4* __restrict__ pin,
+    float* __restrict__ fown, float* __restrict__ U) {
   constexpr int NLM = (LMAX + 1) * (LMAX + 1) - 1;
   constexpr int NDES = NR + NA * LMAX;
   constexpr int NPAR = (NDES + 2) * NNEU + 1;
@@ -284,10 +289,12 @@ __global__ __launch_bounds__(kBlock) void k_partials(
     }
 
   // partial forces p_ij = dU_i/dr_ij for this lane's slots
+  float fx = 0.f, fy = 0.f, fz = 0.f;
   for (int s = lane; s < cr; s += L) {
     int j;
     float dx, dy, dz;
-    displacement(nl[(size_t)s * n + i], pos, n, xi, yi, zi, box, j, dx, dy, dz);
+    const size_t idx = (size_t)s * n + i;
+    displacement(nl[idx], pos, n, xi, yi, zi, box, j, dx, dy, dz);
     const float r2 = dx * dx + dy * dy + dz * dz;
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * rinv;
@@ -329,7 +336,18 @@ __global__ __launch_bounds__(kBlock) void k_partials(
       py += sb * y + (gy - y * ug) * rinv;
       pz += sb * z + (gz - z * ug) * rinv;
     }
-    p[(size_t)s * n + i] = make_float4(px, py, pz, 0.f);
+    fx += px;
+    fy += py;
+    fz += pz;
+    pin[(size_t)rev[idx] * n + j] = make_float4(px, py, pz, 0.f);
+  }
+  fx = group_sum<L>(fx);
+  fy = group_sum<L>(fy);
+  fz = group_sum<L>(fz);
+  if (active && lane == 0) {
+    fown[i] = fx;
+    fown[n + i] = fy;
+    fown[2 * n + i] = fz;
   }
 }
 
@@ -353,34 +371,32 @@ __device__ __forceinline__ double block_sum(double (&v)[NQ], double (&sw)[kBlock
   return s;
 }
 
-// Deterministic sum of NQ per-thread doubles over the grid: every block
-// writes its sums; the last block to finish re-reads all block sums (each
-// thread a strided subset, in block order) and reduces them the same way.
-// Returns true in the last block, where threads < NQ hold the totals in `tot`.
+// Per-block sums of NQ doubles, written to partials[block][NQ]; a second
+// kernel adds the blocks in order (no device-scope fence in the hot kernel).
 template <int NQ>
-__device__ bool grid_sum(double (&v)[NQ], double* __restrict__ partials,
-                         unsigned* __restrict__ ticket, double& tot) {
+__device__ __forceinline__ void block_partials(double (&v)[NQ], double* __restrict__ partials) {
   __shared__ double sw[kBlock / 64][NQ];
-  __shared__ bool last;
   const double s = block_sum<NQ>(v, sw);
   if (threadIdx.x < NQ) partials[(size_t)blockIdx.x * NQ + threadIdx.x] = s;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  const volatile double* vp = partials;
+}
+
+// One block: out[q] = sum over blocks b (in order of b) of partials[b][q].
+template <int NQ>
+__global__ __launch_bounds__(kBlock) void k_finalize(int nblocks, const double* __restrict__ partials,
+                                                      double* __restrict__ out,
+                                                      int* __restrict__ flags) {
+  __shared__ double sw[kBlock / 64][NQ];
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] += vp[(size_t)b * NQ + q];
-  __syncthreads();  // sw is reused
-  tot = block_sum<NQ>(acc, sw);
-  if (threadIdx.x == 0) *ticket = 0u;
-  return true;
+    for (int q = 0; q < NQ; ++q) acc[q] += partials[(size_t)b * NQ + q];
+  const double tot = block_sum<NQ>(acc, sw);
+  if (threadIdx.x < NQ) {
+    out[threadIdx.x] = tot;
+    if (!isfinite(tot)) flags[kFlagNonFinite] = 1;
+  }
 }
 
 // MODE 0: evaluation -> out[13] = (sum U, sum W_ab (9), sum J (3)).
@@ -389,11 +405,11 @@ __device__ bool grid_sum(double (&v)[NQ], double* __restrict__ partials,
 template <int L, int MODE>
 __global__ __launch_bounds__(kBlock) void k_gather(
     int n, const double* __restrict__ pos, double* __restrict__ vel,
-    const uint32_t* __restrict__ nl, const int* __restrict__ cnt_r, const int* __restrict__ rev,
-    const float4* __restrict__ p, const float* __restrict__ U, Box box, float* __restrict__ U_out,
+    const uint32_t* __restrict__ nl, const int* __restrict__ cnt_r,
+    const float4* __restrict__ pin, const float* __restrict__ fown, const float* __restrict__ U,
+    Box box, float* __restrict__ U_out,
     float* __restrict__ F, float* __restrict__ W, float* __restrict__ J, double kick,
-    double ekin_factor, double* __restrict__ partials, unsigned* __restrict__ ticket,
-    double* __restrict__ out, int* __restrict__ flags) {
+    double ekin_factor, double* __restrict__ partials) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gid / L;
   const int lane = gid % L;
@@ -410,11 +426,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     int j;
     float dx, dy, dz;
     displacement(nl[idx], pos, n, xi, yi, zi, box, j, dx, dy, dz);
-    const float4 pij = p[idx];
-    const float4 pji = p[(size_t)rev[idx] * n + j];
-    f0 += pij.x - pji.x;
-    f1 += pij.y - pji.y;
-    f2 += pij.z - pji.z;
+    const float4 pji = pin[idx];
+    f0 -= pji.x;
+    f1 -= pji.y;
+    f2 -= pji.z;
     w[0] += dx * pji.x;
     w[1] += dx * pji.y;
     w[2] += dx * pji.z;
@@ -425,9 +440,9 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     w[7] += dz * pji.y;
     w[8] += dz * pji.z;
   }
-  f0 = group_sum<L>(f0);
-  f1 = group_sum<L>(f1);
-  f2 = group_sum<L>(f2);
+  f0 = group_sum<L>(f0) + (active ? fown[i] : 0.f);
+  f1 = group_sum<L>(f1) + (active ? fown[n + i] : 0.f);
+  f2 = group_sum<L>(f2) + (active ? fown[2 * n + i] : 0.f);
 #pragma unroll
   for (int k = 0; k < 9; ++k) w[k] = group_sum<L>(w[k]);
 
@@ -480,11 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(
       v[4] = j2;
     }
   }
-  double tot = 0.0;
-  if (grid_sum<NQ>(v, partials, ticket, tot) && threadIdx.x < NQ) {
-    out[threadIdx.x] = tot;
-    if (!isfinite(tot)) flags[kFlagNonFinite] = 1;
-  }
+  block_partials<NQ>(v, partials);
 }
 
 __global__ void k_kick_drift(int n, double* __restrict__ pos, double* __restrict__ vel,
@@ -519,9 +530,11 @@ hipError_t launch_partials(nep_ctx ctx, const double* pos) {
   const System& s = ctx->sys;
   if (s.n == 0) return hipSuccess;
   const unsigned nb = blocks_for((size_t)s.n * kLanes, kBlock);
-  k_partials<9, 5, 4, 30, kLanes><<<nb, kBlock, 0, ctx->stream>>>(
-      s.n, pos, s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr, s.box, ctx->z.ptr,
-      (float)ctx->hyper.rc_radial, (float)ctx->hyper.rc_angular, ctx->p.ptr, ctx->U.ptr);
+  launch_kernel(ctx, true, true, k_partials<9, 5, 4, 30, kLanes>, dim3(nb), dim3(kBlock), s.n,
+                pos, (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr, (const int*)s.cnt_a.ptr,
+                (const int*)s.rev.ptr, s.box, (const float*)ctx->z.ptr,
+                (float)ctx->hyper.rc_radial, (float)ctx->hyper.rc_angular, ctx->p.ptr,
+                ctx->fown.ptr, ctx->U.ptr);
   return hipGetLastError();
 }
 
@@ -530,21 +543,28 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
                          double mass) {
   const System& s = ctx->sys;
   if (s.n == 0) {
-    if (out) k_zero_d<<<1, 64, 0, ctx->stream>>>(out, mode == 0 ? 13 : 5);
+    if (out) launch_kernel(ctx, true, true, k_zero_d, dim3(1), dim3(64), out, mode == 0 ? 13 : 5);
     return hipGetLastError();
   }
   const unsigned nb = blocks_for((size_t)s.n * kLanes, kBlock);
   const double ekin_factor = 0.5 * mass / kAccel;
+  const uint32_t* nl = s.nl.ptr;
+  const int* cnt = s.cnt_r.ptr;
+  const float4* p = ctx->p.ptr;
+  const float* fown = ctx->fown.ptr;
+  const float* U = ctx->U.ptr;
   if (mode == 0) {
-    k_gather<kLanes, 0><<<nb, kBlock, 0, ctx->stream>>>(
-        s.n, pos, vel, s.nl.ptr, s.cnt_r.ptr, s.rev.ptr, ctx->p.ptr, ctx->U.ptr, s.box, U_out,
-        F_out, W_out, J_out, kick, ekin_factor, ctx->partials.ptr, ctx->ticket.ptr, out,
-        ctx->flags.ptr);
+    launch_kernel(ctx, true, false, k_gather<kLanes, 0>, dim3(nb), dim3(kBlock), s.n, pos, vel, nl,
+                  cnt, p, fown, U, s.box, U_out, F_out, W_out, J_out, kick, ekin_factor,
+                  ctx->partials.ptr);
+    launch_kernel(ctx, false, true, k_finalize<13>, dim3(1), dim3(kBlock), (int)nb,
+                  (const double*)ctx->partials.ptr, out, ctx->flags.ptr);
   } else {
-    k_gather<kLanes, 1><<<nb, kBlock, 0, ctx->stream>>>(
-        s.n, pos, vel, s.nl.ptr, s.cnt_r.ptr, s.rev.ptr, ctx->p.ptr, ctx->U.ptr, s.box, U_out,
-        F_out, W_out, J_out, kick, ekin_factor, ctx->partials.ptr, ctx->ticket.ptr, out,
-        ctx->flags.ptr);
+    launch_kernel(ctx, true, false, k_gather<kLanes, 1>, dim3(nb), dim3(kBlock), s.n, pos, vel, nl,
+                  cnt, p, fown, U, s.box, U_out, F_out, W_out, J_out, kick, ekin_factor,
+                  ctx->partials.ptr);
+    launch_kernel(ctx, false, true, k_finalize<5>, dim3(1), dim3(kBlock), (int)nb,
+                  (const double*)ctx->partials.ptr, out, ctx->flags.ptr);
   }
   return hipGetLastError();
 }
@@ -552,8 +572,8 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
 hipError_t launch_kick_drift(nep_ctx ctx, double* pos, double* vel, double kick, double dt) {
   const int n = ctx->sys.n;
   if (n == 0) return hipSuccess;
-  k_kick_drift<<<blocks_for((size_t)3 * n, kBlock), kBlock, 0, ctx->stream>>>(n, pos, vel,
-                                                                             ctx->F.ptr, kick, dt);
+  launch_kernel(ctx, true, true, k_kick_drift, dim3(blocks_for((size_t)3 * n, kBlock)),
+                dim3(kBlock), n, pos, vel, (const float*)ctx->F.ptr, kick, dt);
   return hipGetLastError();
 }
 

@@ -39,6 +39,17 @@ __device__ __forceinline__ double pair_r2(const double* __restrict__ pos, int n,
   return (dx * dx + dy * dy) + dz * dz;
 }
 
+// The same expression with the neighbour position already loaded.
+__device__ __forceinline__ double pair_r2_at(double xj, double yj, double zj, double xi, double yi,
+                                             double zi, int n0, int n1, int n2, const Box& b) {
+#pragma clang fp contract(off)
+  const double a0 = (double)n0, a1 = (double)n1, a2 = (double)n2;
+  double dx = (xj - xi) + ((a0 * b.h[0] + a1 * b.h[3]) + a2 * b.h[6]);
+  double dy = (yj - yi) + ((a0 * b.h[1] + a1 * b.h[4]) + a2 * b.h[7]);
+  double dz = (zj - zi) + ((a0 * b.h[2] + a1 * b.h[5]) + a2 * b.h[8]);
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
 __global__ void k_zero(int* __restrict__ a, int m) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < m) a[t] = 0;
@@ -129,62 +140,128 @@ __global__ void k_sort_cells(int ncell, const int* __restrict__ start, int* __re
   }
 }
 
-// One thread per atom: scan the 27 surrounding cells twice, first keeping the
-// angular-range entries, then the remaining radial-range entries.
-__global__ void k_build_cells(int n, int cap, const double* __restrict__ pos, Box box, int nc0,
-                              int nc1, int nc2, const int* __restrict__ wrap,
-                              const int* __restrict__ cell_of, const int* __restrict__ start,
-                              const int* __restrict__ members, double rc2_r, double rc2_a,
-                              uint32_t* __restrict__ nl, int* __restrict__ cnt_r,
-                              int* __restrict__ cnt_a, int* __restrict__ flags) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Copy every atom into its cell-ordered slot: position, index and packed
+// cell offsets, so that the candidates of a cell are contiguous in memory.
+__global__ void k_records(int n, const double* __restrict__ pos, const int* __restrict__ wrap,
+                          const int* __restrict__ members, CellRec* __restrict__ rec,
+                          int* __restrict__ flags) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int j = members[t];
+  const int w0 = wrap[j], w1 = wrap[n + j], w2 = wrap[2 * n + j];
+  if (w0 < -127 || w0 > 127 || w1 < -127 || w1 > 127 || w2 < -127 || w2 > 127)
+    flags[kFlagImage] = 1;
+  CellRec r;
+  r.x = pos[j];
+  r.y = pos[n + j];
+  r.z = pos[2 * n + j];
+  r.j = j;
+  r.w = (w0 & 0xFF) | ((w1 & 0xFF) << 8) | ((w2 & 0xFF) << 16);
+  rec[t] = r;
+}
+
+// G lanes per atom (G = 32) scan the 27 surrounding cells twice, first
+// keeping the angular-range entries, then the remaining radial-range entries.
+// The candidates of the 27 cells are numbered consecutively (cell order, then
+// member order) and the G lanes test G consecutive candidates at a time; a
+// ballot and a population count give each kept entry the slot a serial scan
+// would give it, so the order does not depend on G.
+template <int G>
+__global__ __launch_bounds__(256) void k_build_cells(
+    int n, int cap, const double* __restrict__ pos, Box box, int nc0, int nc1, int nc2,
+    const int* __restrict__ wrap, const int* __restrict__ cell_of, const int* __restrict__ start,
+    const CellRec* __restrict__ rec, double rc2_r, double rc2_a, uint32_t* __restrict__ nl,
+    int* __restrict__ cnt_r, int* __restrict__ cnt_a, int* __restrict__ flags) {
+  static_assert(G >= 27 && G <= 64 && 256 % G == 0, "a group covers the 27 cells");
+  __shared__ int s_off[256 / G][28];   // first candidate number of each cell
+  __shared__ int s_first[256 / G][27]; // first member slot of each cell
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int grp = threadIdx.x / G;
+  const int k = gid % G;
+  const int i = gid / G;
+  const bool active = i < n;
+  const int shift = (threadIdx.x & 63) - k;  // first lane of the group within its wave
+  const unsigned long long below = (1ull << k) - 1ull;
+  const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+  const int ii = active ? i : 0;
+  const int cell = cell_of[ii];
+  const int c0 = cell % nc0, c1 = (cell / nc0) % nc1, c2 = cell / (nc0 * nc1);
+  // lane k < 27 looks up neighbour cell k (offsets o2, o1, o0 in -1..1, o0 fastest)
+  int my_cnt = 0;
+  if (k < 27) {
+    int d0 = c0 + k % 3 - 1, d1 = c1 + (k / 3) % 3 - 1, d2 = c2 + k / 9 - 1;
+    d0 -= (d0 < 0 ? -1 : (d0 >= nc0 ? 1 : 0)) * nc0;
+    d1 -= (d1 < 0 ? -1 : (d1 >= nc1 ? 1 : 0)) * nc1;
+    d2 -= (d2 < 0 ? -1 : (d2 >= nc2 ? 1 : 0)) * nc2;
+    const int cc = (d2 * nc1 + d1) * nc0 + d0;
+    const int b = start[cc];
+    my_cnt = start[cc + 1] - b;
+    s_first[grp][k] = b;
+  }
+  // exclusive prefix of the 27 counts (serial over the group's first lane)
+  __syncthreads();
+  if (k < 27) s_off[grp][k + 1] = my_cnt;
+  __syncthreads();
+  if (k == 0) {
+    s_off[grp][0] = 0;
+    for (int q = 1; q <= 27; ++q) s_off[grp][q] += s_off[grp][q - 1];
+  }
+  __syncthreads();
+  if (!active) return;  // whole groups leave together
+  const int total = s_off[grp][27];
   const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
   const int wi0 = wrap[i], wi1 = wrap[n + i], wi2 = wrap[2 * n + i];
-  const int cell = cell_of[i];
-  const int c0 = cell % nc0, c1 = (cell / nc0) % nc1, c2 = cell / (nc0 * nc1);
   int count = 0;
   bool overflow = false, bad_image = false;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int o2 = -1; o2 <= 1; ++o2) {
-      int d2 = c2 + o2;
-      const int m2 = d2 < 0 ? -1 : (d2 >= nc2 ? 1 : 0);
-      d2 -= m2 * nc2;
-      for (int o1 = -1; o1 <= 1; ++o1) {
-        int d1 = c1 + o1;
-        const int m1 = d1 < 0 ? -1 : (d1 >= nc1 ? 1 : 0);
-        d1 -= m1 * nc1;
-        for (int o0 = -1; o0 <= 1; ++o0) {
-          int d0 = c0 + o0;
-          const int m0 = d0 < 0 ? -1 : (d0 >= nc0 ? 1 : 0);
-          d0 -= m0 * nc0;
-          const int cc = (d2 * nc1 + d1) * nc0 + d0;
-          for (int t = start[cc]; t < start[cc + 1]; ++t) {
-            const int j = members[t];
-            const int n0 = m0 + wi0 - wrap[j];
-            const int n1 = m1 + wi1 - wrap[n + j];
-            const int n2 = m2 + wi2 - wrap[2 * n + j];
-            if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
-            const double r2 = pair_r2(pos, n, j, xi, yi, zi, n0, n1, n2, box);
-            const bool in_a = r2 < rc2_a;
-            const bool keep = pass == 0 ? in_a : (!in_a && r2 < rc2_r);
-            if (!keep) continue;
-            if (n0 < -3 || n0 > 3 || n1 < -3 || n1 > 3 || n2 < -3 || n2 > 3) {
-              bad_image = true;
-              continue;
-            }
-            if (count < cap)
-              nl[(size_t)count * n + i] = pack_entry(j, n0, n1, n2);
-            else
-              overflow = true;
-            ++count;
+    for (int base = 0; base < total; base += G) {
+      const int c = base + k;
+      bool keep = false;
+      uint32_t entry = 0;
+      if (c < total) {
+        int lo = 0, hi = 27;  // the cell q that holds candidate c: off[q] <= c < off[q+1]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_off[grp][mid] <= c)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        const int q = lo;
+        const int o0 = q % 3 - 1, o1 = (q / 3) % 3 - 1, o2 = q / 9 - 1;
+        const int e0 = c0 + o0, e1 = c1 + o1, e2 = c2 + o2;
+        const int m0 = e0 < 0 ? -1 : (e0 >= nc0 ? 1 : 0);
+        const int m1 = e1 < 0 ? -1 : (e1 >= nc1 ? 1 : 0);
+        const int m2 = e2 < 0 ? -1 : (e2 >= nc2 ? 1 : 0);
+        const CellRec rc = rec[s_first[grp][q] + (c - s_off[grp][q])];
+        const int j = rc.j;
+        const int n0 = m0 + wi0 - (int)(signed char)(rc.w & 0xFF);
+        const int n1 = m1 + wi1 - (int)(signed char)((rc.w >> 8) & 0xFF);
+        const int n2 = m2 + wi2 - (int)(signed char)((rc.w >> 16) & 0xFF);
+        if (!(j == i && n0 == 0 && n1 == 0 && n2 == 0)) {
+          const double r2 = pair_r2_at(rc.x, rc.y, rc.z, xi, yi, zi, n0, n1, n2, box);
+          const bool in_a = r2 < rc2_a;
+          keep = pass == 0 ? in_a : (!in_a && r2 < rc2_r);
+          if (keep && (n0 < -3 || n0 > 3 || n1 < -3 || n1 > 3 || n2 < -3 || n2 > 3)) {
+            bad_image = true;
+            keep = false;
           }
+          entry = pack_entry(j, n0, n1, n2);
         }
       }
+      const unsigned long long ball = (__ballot(keep) >> shift) & gmask;
+      if (keep) {
+        const int slot = count + __popcll(ball & below);
+        if (slot < cap)
+          nl[(size_t)slot * n + i] = entry;
+        else
+          overflow = true;
+      }
+      count += __popcll(ball);
     }
-    if (pass == 0) cnt_a[i] = min(count, cap);
+    if (pass == 0 && k == 0) cnt_a[i] = min(count, cap);
   }
-  cnt_r[i] = min(count, cap);
+  if (k == 0) cnt_r[i] = min(count, cap);
   if (overflow) flags[kFlagOverflow] = 1;
   if (bad_image) flags[kFlagImage] = 1;
 }
@@ -193,8 +270,9 @@ __global__ void k_build_cells(int n, int cap, const double* __restrict__ pos, Bo
 // wrapped frame (boxes thinner than three cut-off widths).
 __global__ void k_build_all_pairs(int n, int cap, const double* __restrict__ pos, Box box, int k0,
                                   int k1, int k2, const int* __restrict__ wrap, double rc2_r,
-                                  double rc2_a, uint32_t* __restrict__ nl, int* __restrict__ cnt_r,
-                                  int* __restrict__ cnt_a, int* __restrict__ flags) {
+                                  double rc2_a, uint32_t* __restrict__ nl,
+                                  int* __restrict__ cnt_r, int* __restrict__ cnt_a,
+                                  int* __restrict__ flags) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
@@ -232,10 +310,12 @@ __global__ void k_build_all_pairs(int n, int cap, const double* __restrict__ pos
 }
 
 // Slot of the reverse entry (i, -n) in atom j's list, for every entry (j, n)
-// of atom i.  One thread per (slot, atom).
+// of atom i.  One thread per (slot, atom).  |r_ji| = |r_ij| exactly, so the
+// reverse entry lies in the same part (angular prefix or radial rest) of j's
+// list and only that part is searched.
 __global__ void k_reverse(int n, int cap, const uint32_t* __restrict__ nl,
-                          const int* __restrict__ cnt_r, int* __restrict__ rev,
-                          int* __restrict__ flags) {
+                          const int* __restrict__ cnt_r, const int* __restrict__ cnt_a,
+                          int* __restrict__ rev, int* __restrict__ flags) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)n * cap) return;
   const int i = (int)(idx % (size_t)n);
@@ -246,9 +326,11 @@ __global__ void k_reverse(int n, int cap, const uint32_t* __restrict__ nl,
   int n0, n1, n2;
   unpack_image(e, n0, n1, n2);
   const uint32_t target = pack_entry(i, -n0, -n1, -n2);
-  const int cj = cnt_r[j];
+  const bool angular = s < cnt_a[i];
+  const int t0 = angular ? 0 : cnt_a[j];
+  const int t1 = angular ? cnt_a[j] : cnt_r[j];
   int found = -1;
-  for (int t = 0; t < cj; ++t) {
+  for (int t = t0; t < t1; ++t) {
     if (nl[(size_t)t * n + j] == target) {
       found = t;
       break;
@@ -329,7 +411,6 @@ void prepare_system_geometry(System& s, const double* H, double rc_r, double rc_
 nep_status build_neighbors(nep_ctx ctx, const double* pos_c, bool wrap_in_place) {
   System& s = ctx->sys;
   const int n = s.n;
-  hipStream_t st = ctx->stream;
   double* pos = const_cast<double*>(pos_c);  // written only when wrap_in_place
   hipError_t e = hipSuccess;
   const size_t ncap = (size_t)n * s.cap;
@@ -339,37 +420,48 @@ nep_status build_neighbors(nep_ctx ctx, const double* pos_c, bool wrap_in_place)
     return check_hip(ctx, e, "allocating neighbour lists");
   const double rc2_r = s.rc_list_r * s.rc_list_r;
   const double rc2_a = s.rc_list_a * s.rc_list_a;
+  const dim3 blk(kBlock);
   if (s.use_cells) {
     const int ncell = s.nc[0] * s.nc[1] * s.nc[2];
     if ((e = s.cell_of.ensure(n)) != hipSuccess || (e = s.cell_cnt.ensure(ncell)) != hipSuccess ||
         (e = s.cell_start.ensure((size_t)ncell + 1)) != hipSuccess ||
         (e = s.cell_fill.ensure(ncell)) != hipSuccess ||
-        (e = s.cell_atoms.ensure(n)) != hipSuccess)
+        (e = s.cell_atoms.ensure(n)) != hipSuccess || (e = s.cell_rec.ensure(n)) != hipSuccess)
       return check_hip(ctx, e, "allocating cell lists");
-    k_zero<<<blocks_for(ncell, kBlock), kBlock, 0, st>>>(s.cell_cnt.ptr, ncell);
-    k_zero<<<blocks_for(ncell, kBlock), kBlock, 0, st>>>(s.cell_fill.ptr, ncell);
-    k_bin<<<blocks_for(n, kBlock), kBlock, 0, st>>>(n, pos, s.box, s.nc[0], s.nc[1], s.nc[2], 1,
-                                                    wrap_in_place ? 1 : 0, s.wrap.ptr,
-                                                    s.cell_of.ptr, s.cell_cnt.ptr);
-    k_scan<<<1, 1024, 0, st>>>(ncell, s.cell_cnt.ptr, s.cell_start.ptr);
-    k_fill<<<blocks_for(n, kBlock), kBlock, 0, st>>>(n, s.cell_of.ptr, s.cell_start.ptr,
-                                                     s.cell_fill.ptr, s.cell_atoms.ptr);
-    k_sort_cells<<<blocks_for(ncell, kBlock), kBlock, 0, st>>>(ncell, s.cell_start.ptr,
-                                                               s.cell_atoms.ptr);
-    k_build_cells<<<blocks_for(n, kBlock), kBlock, 0, st>>>(
-        n, s.cap, pos, s.box, s.nc[0], s.nc[1], s.nc[2], s.wrap.ptr, s.cell_of.ptr,
-        s.cell_start.ptr, s.cell_atoms.ptr, rc2_r, rc2_a, s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr,
-        ctx->flags.ptr);
+    launch_kernel(ctx, true, false, k_zero, dim3(blocks_for(ncell, kBlock)), blk, s.cell_cnt.ptr,
+                  ncell);
+    launch_kernel(ctx, false, false, k_zero, dim3(blocks_for(ncell, kBlock)), blk,
+                  s.cell_fill.ptr, ncell);
+    launch_kernel(ctx, false, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, pos, s.box,
+                  s.nc[0], s.nc[1], s.nc[2], 1, wrap_in_place ? 1 : 0, s.wrap.ptr, s.cell_of.ptr,
+                  s.cell_cnt.ptr);
+    launch_kernel(ctx, false, false, k_scan, dim3(1), dim3(1024), ncell,
+                  (const int*)s.cell_cnt.ptr, s.cell_start.ptr);
+    launch_kernel(ctx, false, false, k_fill, dim3(blocks_for(n, kBlock)), blk, n,
+                  (const int*)s.cell_of.ptr, (const int*)s.cell_start.ptr, s.cell_fill.ptr,
+                  s.cell_atoms.ptr);
+    launch_kernel(ctx, false, false, k_sort_cells, dim3(blocks_for(ncell, kBlock)), blk, ncell,
+                  (const int*)s.cell_start.ptr, s.cell_atoms.ptr);
+    launch_kernel(ctx, false, false, k_records, dim3(blocks_for(n, kBlock)), blk, n,
+                  (const double*)pos, (const int*)s.wrap.ptr, (const int*)s.cell_atoms.ptr,
+                  s.cell_rec.ptr, ctx->flags.ptr);
+    constexpr int G = 32;
+    launch_kernel(ctx, false, false, k_build_cells<G>, dim3(blocks_for((size_t)n * G, kBlock)),
+                  blk, n, s.cap, (const double*)pos, s.box, s.nc[0], s.nc[1], s.nc[2],
+                  (const int*)s.wrap.ptr, (const int*)s.cell_of.ptr,
+                  (const int*)s.cell_start.ptr, (const CellRec*)s.cell_rec.ptr, rc2_r, rc2_a,
+                  s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr, ctx->flags.ptr);
   } else {
-    k_bin<<<blocks_for(n, kBlock), kBlock, 0, st>>>(n, pos, s.box, 1, 1, 1, 0,
-                                                    wrap_in_place ? 1 : 0, s.wrap.ptr, nullptr,
-                                                    nullptr);
-    k_build_all_pairs<<<blocks_for(n, 64), 64, 0, st>>>(
-        n, s.cap, pos, s.box, s.kimg[0], s.kimg[1], s.kimg[2], s.wrap.ptr, rc2_r, rc2_a, s.nl.ptr,
-        s.cnt_r.ptr, s.cnt_a.ptr, ctx->flags.ptr);
+    launch_kernel(ctx, true, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, pos, s.box, 1, 1,
+                  1, 0, wrap_in_place ? 1 : 0, s.wrap.ptr, (int*)nullptr, (int*)nullptr);
+    launch_kernel(ctx, false, false, k_build_all_pairs, dim3(blocks_for(n, 64)), dim3(64), n,
+                  s.cap, (const double*)pos, s.box, s.kimg[0], s.kimg[1], s.kimg[2],
+                  (const int*)s.wrap.ptr, rc2_r, rc2_a, s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr,
+                  ctx->flags.ptr);
   }
-  k_reverse<<<blocks_for(ncap, kBlock), kBlock, 0, st>>>(n, s.cap, s.nl.ptr, s.cnt_r.ptr,
-                                                         s.rev.ptr, ctx->flags.ptr);
+  launch_kernel(ctx, false, true, k_reverse, dim3(blocks_for(ncap, kBlock)), blk, n, s.cap,
+                (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr, (const int*)s.cnt_a.ptr,
+                s.rev.ptr, ctx->flags.ptr);
   return check_hip(ctx, hipGetLastError(), "launching neighbour kernels");
 }
 

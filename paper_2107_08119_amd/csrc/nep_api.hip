@@ -53,6 +53,7 @@ nep_status size_system_buffers(nep_ctx ctx) {
   hipError_t e;
   if ((e = ctx->p.ensure((size_t)s.cap * s.n)) != hipSuccess ||
       (e = ctx->U.ensure((size_t)s.n)) != hipSuccess ||
+      (e = ctx->fown.ensure((size_t)3 * s.n)) != hipSuccess ||
       (e = ctx->F.ensure((size_t)3 * s.n)) != hipSuccess ||
       (e = ctx->partials.ensure(gather_blocks(s.n) * 16 + 16)) != hipSuccess)
     return check_hip(ctx, e, "allocating system buffers");
@@ -77,10 +78,8 @@ nep_status nep_create(nep_ctx* out, int device, void* hip_stream) {
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
   hipError_t e;
-  if ((e = ctx->flags.ensure(kNumFlags)) != hipSuccess || (e = ctx->ticket.ensure(1)) != hipSuccess ||
-      (e = ctx->totals.ensure(16)) != hipSuccess ||
-      (e = hipMemset(ctx->flags.ptr, 0, sizeof(int) * kNumFlags)) != hipSuccess ||
-      (e = hipMemset(ctx->ticket.ptr, 0, sizeof(unsigned))) != hipSuccess) {
+  if ((e = ctx->flags.ensure(kNumFlags)) != hipSuccess || (e = ctx->totals.ensure(16)) != hipSuccess ||
+      (e = hipMemset(ctx->flags.ptr, 0, sizeof(int) * kNumFlags)) != hipSuccess) {
     nep_destroy(ctx);
     return e == hipErrorOutOfMemory ? NEP_ENOMEM : NEP_EDEVICE;
   }
@@ -95,11 +94,11 @@ void nep_destroy(nep_ctx ctx) {
   ctx->sys.release();
   ctx->z.release();
   ctx->p.release();
+  ctx->fown.release();
   ctx->U.release();
   ctx->F.release();
   ctx->partials.release();
   ctx->totals.release();
-  ctx->ticket.release();
   ctx->flags.release();
   delete ctx;
 }
@@ -344,6 +343,30 @@ nep_status nep_get_timing(nep_ctx ctx, double* ms_out, int* launches_out) {
     launches_out[c] = (int)t.used[c];
     t.used[c] = 0;
   }
+  return NEP_OK;
+}
+
+nep_status nep_time_partials(nep_ctx ctx, const double* pos_dev, int reps, double* ms_per_launch) {
+  if (!ctx || !ms_per_launch) return NEP_EINVAL;
+  if (!ctx->have_params || !ctx->have_list)
+    return fail(ctx, NEP_ESTATE, "nep_load_params and nep_build_neighbors must come first");
+  if (reps < 1 || reps > 100000) return fail(ctx, NEP_EINVAL, "reps must be in [1, 100000]");
+  if (ctx->sys.n > 0 && !pos_dev) return fail(ctx, NEP_EINVAL, "pos_dev is NULL");
+  DeviceGuard guard(ctx->device);
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_partials(ctx, pos_dev);
+  if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (e != hipSuccess) return check_hip(ctx, e, "timing the partial-force kernel");
+  *ms_per_launch = (double)ms / reps;
+  ctx->md_forces_valid = false;  // the partial forces were recomputed
   return NEP_OK;
 }
 

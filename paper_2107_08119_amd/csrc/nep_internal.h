@@ -1,6 +1,7 @@
 // Internal declarations of libnep (gfx950).  Not part of the C ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -70,6 +71,14 @@ enum Flag { kFlagOverflow = 0, kFlagImage = 1, kFlagNonFinite = 2, kFlagReverse 
 // 1 eV/A acting on 1 amu, in A/fs^2; and 1 amu A^2/fs^2 in eV.
 constexpr double kAccel = 1.602176634e-19 / 1.66053906660e-27 * 1.0e-10;
 
+// An atom as a neighbour candidate, stored in cell order: float64 position,
+// index, and integer cell offsets of the raw position packed as 3 x int8.
+struct alignas(32) CellRec {
+  double x, y, z;
+  int j;
+  int w;
+};
+
 // Neighbour-list state of one system (a single periodic box).
 struct System {
   int n = 0;             // atoms
@@ -91,6 +100,7 @@ struct System {
   DevBuf<int> cell_start;  // [ncell+1]
   DevBuf<int> cell_fill;   // [ncell]
   DevBuf<int> cell_atoms;  // [n]
+  DevBuf<CellRec> cell_rec;  // [n] positions and offsets in cell order
   void release() {
     nl.release();
     cnt_r.release();
@@ -102,6 +112,7 @@ struct System {
     cell_start.release();
     cell_fill.release();
     cell_atoms.release();
+    cell_rec.release();
   }
 };
 
@@ -133,12 +144,12 @@ struct nep_ctx_s {
   // system
   bool have_list = false;
   nep::System sys;
-  nep::DevBuf<float4> p;          // partial forces dU_i/dr_ij, [cap][n]
+  nep::DevBuf<float4> p;          // incoming partial forces dU_j/dr_ji at i's slots, [cap][n]
+  nep::DevBuf<float> fown;        // sum_j dU_i/dr_ij, [3][n]
   nep::DevBuf<float> U;           // [n]
   nep::DevBuf<float> F;           // [3][n]
   nep::DevBuf<double> partials;   // [blocks][16] block sums
   nep::DevBuf<double> totals;     // [16]
-  nep::DevBuf<unsigned> ticket;   // [1]
   nep::DevBuf<int> flags;         // [kNumFlags]
   // molecular dynamics state
   bool md_forces_valid = false;
@@ -146,6 +157,8 @@ struct nep_ctx_s {
   const double* md_vel = nullptr;
   int steps_since_rebuild = 0;
   nep::KernelTimer timer;
+  // events of the kernel class being launched (set by nep::timed)
+  hipEvent_t ev_first = nullptr, ev_last = nullptr;
 };
 
 namespace nep {
@@ -169,7 +182,22 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
 size_t gather_blocks(int n);
 hipError_t launch_kick_drift(nep_ctx ctx, double* pos, double* vel, double kick, double dt);
 
-// Run `launch` between two timing events of class `cls` when timing is on.
+// Launch a kernel on the context's stream.  When a timed kernel class is
+// being launched, its first kernel carries the start event and its last
+// kernel the stop event in the dispatch itself (no extra packets).
+template <typename F, typename... Args>
+inline void launch_kernel(nep_ctx ctx, bool first, bool last, F kernel, dim3 grid, dim3 block,
+                          Args... args) {
+  hipEvent_t a = first ? ctx->ev_first : nullptr;
+  hipEvent_t b = last ? ctx->ev_last : nullptr;
+  if (a || b)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, ctx->stream, a, b, 0, args...);
+  else
+    kernel<<<grid, block, 0, ctx->stream>>>(args...);
+}
+
+// Run `launch` (which enqueues the kernels of class `cls`) with that class's
+// timing events attached when timing is on.
 template <class Fn>
 hipError_t timed(nep_ctx ctx, int cls, Fn&& launch) {
   KernelTimer& t = ctx->timer;
@@ -187,11 +215,11 @@ hipError_t timed(nep_ctx ctx, int cls, Fn&& launch) {
     t.stop[cls].push_back(b);
   }
   const size_t k = t.used[cls]++;
-  hipError_t e = hipEventRecord(t.start[cls][k], ctx->stream);
-  if (e != hipSuccess) return e;
-  e = launch();
-  if (e != hipSuccess) return e;
-  return hipEventRecord(t.stop[cls][k], ctx->stream);
+  ctx->ev_first = t.start[cls][k];
+  ctx->ev_last = t.stop[cls][k];
+  hipError_t e = launch();
+  ctx->ev_first = ctx->ev_last = nullptr;
+  return e;
 }
 
 // helpers (nep_api.hip)

@@ -25,6 +25,7 @@ EXPORTED = [
     "nep_create", "nep_destroy", "nep_last_error", "nep_set_stream", "nep_synchronize",
     "nep_num_descriptors", "nep_num_params", "nep_load_params", "nep_build_neighbors",
     "nep_get_neighbors", "nep_compute", "nep_md_step", "nep_set_timing", "nep_get_timing",
+    "nep_time_partials",
 ]
 
 
@@ -74,6 +75,7 @@ def lib() -> C.CDLL:
         L.nep_md_step.argtypes = [vp, ip, dp, ip, dp, vp, vp, vp, vp, vp]
         L.nep_set_timing.argtypes = [vp, ip]
         L.nep_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+        L.nep_time_partials.argtypes = [vp, vp, ip, C.POINTER(C.c_double)]
         for name in EXPORTED:
             if name not in ("nep_destroy", "nep_last_error", "nep_num_descriptors",
                             "nep_num_params"):
@@ -221,6 +223,13 @@ def get_timing(ctx: "Context") -> dict:
     cnt = (C.c_int * 4)()
     ctx._check(ctx._lib.nep_get_timing(ctx._h, ms, cnt))
     return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+
+def time_partials(ctx: "Context", pos: torch.Tensor, reps: int = 200) -> float:
+    """Mean milliseconds of one descriptor/network/partial-force launch."""
+    ms = C.c_double()
+    ctx._check(ctx._lib.nep_time_partials(ctx._h, _ptr(pos), reps, C.byref(ms)))
+    return ms.value
 
 
 def soa(x: np.ndarray, device: int = 0) -> torch.Tensor:
