@@ -58,7 +58,77 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--no-snes", action="store_true", help="skip the SNES generation rate")
+    ap.add_argument("--snes-structures", type=int, default=1000)
+    ap.add_argument("--snes-generations", type=int, default=20)
     return ap.parse_args()
+
+
+def snes_rate(args, ctx, nep, I, torch):
+    """SNES generations/s on 1000 SW-labelled Si structures of 8-256 atoms,
+    population 50, and the plain per-structure GPU path as the yardstick."""
+    h = nep.hyper()
+    n_par = nep.num_params(h)
+    ls = I.labelled_set(args.snes_structures, 8, 256, seed=4)
+    ds = ctx.dataset_create(ls, max_neighbors=64)
+    n_pop, seed, lam = 50, 5, (1.0, 1.0, 1.0, 0.05, 0.05)
+    rng = np.random.default_rng(seed)
+    m = torch.from_numpy(rng.uniform(-0.5, 0.5, n_par).astype(np.float32)).cuda()
+    s = torch.full((n_par,), 0.1, dtype=torch.float32, device="cuda")
+    r = torch.empty((n_pop, n_par), dtype=torch.float32, device="cuda")
+    Z = torch.empty_like(r)
+    loss = torch.empty((n_pop, 6), dtype=torch.float64, device="cuda")
+
+    def generation(g):
+        ctx.snes_sample(m, s, seed, g, n_pop, r, Z)
+        ctx.eval_population(ds, Z, lam, loss)
+        ctx.snes_update(m, s, r, loss)
+
+    for g in range(2):
+        generation(g)
+    ctx.synchronize()
+    G = args.snes_generations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(2, 2 + G):
+        generation(g)
+    torch.cuda.synchronize()
+    t_gen = (time.perf_counter() - t0) / G
+    ctx.synchronize()
+    best = float(loss[:, 0].min())
+    # plain path: per individual, per structure nep_build_neighbors + nep_compute,
+    # loss assembled on the host; timed on two individuals, scaled to the population
+    Zh = Z.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(ls.n_atoms)])
+    pos_dev = [nep.soa(ls.pos[off[k]:off[k + 1]]) for k in range(len(ls.n_atoms))]
+    boxes = [ls.boxes[k].reshape(3, 3) for k in range(len(ls.n_atoms))]
+    pctx = nep.Context(0)
+    n_plain = 2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_plain):
+        pctx.load_params(h, Zh[k])
+        e = []
+        for st in range(len(ls.n_atoms)):
+            pctx.build_neighbors(pos_dev[st], boxes[st], skin=0.0, max_neighbors=64)
+            out = pctx.compute(pos_dev[st], W=True, U=False)
+            e.append((out["totals"], out["F"]))
+        [(t.cpu(), f.cpu()) for t, f in e]
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / n_plain * n_pop
+    return {
+        "workload": "SNES, population %d x %d SW-labelled Si structures (8-256 atoms, "
+                    "%d atoms), NEP 29-30-1, loss E+F+V+L1+L2" % (n_pop, len(ls.n_atoms),
+                                                                 int(ls.n_atoms.sum())),
+        "gen_per_s": 1.0 / t_gen,
+        "ms_per_gen": t_gen * 1e3,
+        "generations": G,
+        "best_loss_last_gen": best,
+        "plain_per_structure_gen_per_s": 1.0 / t_plain,
+        "plain_path": "host loop of nep_build_neighbors + nep_compute per (structure, "
+                      "individual), timed on %d individuals and scaled to %d" % (n_plain, n_pop),
+        "speedup_vs_plain": t_plain / t_gen,
+    }
 
 
 def pair_counts(pos, box, rc):
@@ -186,6 +256,8 @@ def main():
             k: (val[0] * 1e3 / val[1] if val[1] else None) for k, val in kt.items()},
         "energy_drift_meV_per_atom": float((e_tot.max() - e_tot.min()) / n * 1e3),
     }
+    if not args.no_snes:
+        line["snes"] = snes_rate(args, ctx, nep, I, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(h, z, pos, box, vel, mass, dt, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -155,6 +155,64 @@ nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every
                        double mass_amu, double* pos_dev, double* vel_dev, double* thermo_dev,
                        float* W_dev, float* J_dev);
 
+/* ---------------------------------------------------- training (SNES) */
+
+/* Copy a training set to the device and build its neighbour lists once
+ * (Sec. II E; small structures are concatenated into one system, Sec. II F).
+ * n_struct periodic cells; structure s has n_atoms_host[s] >= 1 atoms whose
+ * positions follow those of structure s-1 in pos_host ([sum N][3] float64,
+ * A), with cell vectors boxes_host[s] (9 float64, rows).  Targets: total
+ * energy energy_host[s] (eV), forces forces_host ([sum N][3], eV/A), total
+ * virial virial_host[s] (6 float64: xx yy zz xy yz zx, eV) used only when
+ * has_virial_host[s] != 0.  Positions are wrapped into their cells on the
+ * device.  Every lattice image within rc_radial (no skin) is a neighbour;
+ * more than max_neighbors returns NEP_EOVERFLOW, cells thinner than half the
+ * radial cutoff NEP_EINVAL.  Uses the hyperparameters of the last
+ * nep_load_params.  All host arrays are read before the call returns;
+ * *out owns device copies until nep_dataset_destroy. */
+nep_status nep_dataset_create(nep_ctx ctx, int n_struct, const int* n_atoms_host,
+                              const double* boxes_host, const double* pos_host,
+                              const double* energy_host, const double* forces_host,
+                              const double* virial_host, const unsigned char* has_virial_host,
+                              int max_neighbors, nep_dataset* out);
+
+/* Free a dataset (waits for its context's stream).  NULL is ok. */
+void nep_dataset_destroy(nep_dataset ds);
+
+/* Loss of n_pop parameter vectors (Eq. loss): Z_dev [n_pop][N_par] float32
+ * on the device (layout as in nep_load_params); lambda_host = (lambda_e,
+ * lambda_f, lambda_v, lambda_1, lambda_2).  Writes loss_dev [n_pop][6]
+ * float64 = (L, L_e, L_f, L_v, L_1, L_2) with
+ *   L_e = sqrt(mean_s ((U_s - E_s)/N_s)^2),
+ *   L_f = sqrt(sum_i |F_i - F_i^tar|^2 / (3 N)),
+ *   L_v = sqrt(sum_{s with virial} sum_6 ((W_s - W_s^tar)/N_s)^2 / (6 N_v)),
+ *   L_1 = mean |z|,  L_2 = sqrt(mean z^2),
+ * where U_s and W_s = sum_i W_i are the NEP energy and virial of structure s.
+ * All individuals are evaluated by the same launches; sums are float64 in a
+ * fixed order.  The dataset must belong to ctx and match its hyperparameters. */
+nep_status snes_eval_population(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z_dev,
+                                const double* lambda_host, double* loss_dev);
+
+/* Draw the population of generation `generation` (Sec. II E 2, step 2a):
+ * r_dev [n_pop][n_par] standard normal (float32) and Z_dev = m + s . r
+ * (float32, rounded from float64), with m_dev, s_dev [n_par] float32.  Noise
+ * for individual k, parameters 4b..4b+3: Philox-4x32-10 (Salmon et al.,
+ * SC'11) of counter (b, k, generation, 0) and key (seed low 32 bits, seed
+ * high 32 bits), uniforms u = (x + 1/2) 2^-32, Box-Muller on (u0, u1) and
+ * (u2, u3) in float64. */
+nep_status snes_sample(nep_ctx ctx, int n_par, int n_pop, const float* m_dev, const float* s_dev,
+                       unsigned long long seed, int generation, float* r_dev, float* Z_dev);
+
+/* SNES update (Sec. II E 2, steps 2b-2d): rank individuals by loss_dev[k*6]
+ * (ascending; NaN ranks last; ties by index), rank utilities
+ * u_k = max(0, ln(P/2+1) - ln k) / sum_j max(0, ln(P/2+1) - ln j) - 1/P,
+ * grad_m = sum_k u_k r_k, grad_s = sum_k u_k (r_k^2 - 1) summed in rank order
+ * in float64, then m += eta_m s . grad_m and s *= exp(eta_s/2 grad_s) in
+ * float64, stored as float32 in place.  eta_m <= 0 selects 1 and eta_s <= 0
+ * selects (3 + ln n_par) / (5 sqrt(n_par)).  1 <= n_pop <= 1024. */
+nep_status snes_update(nep_ctx ctx, int n_par, int n_pop, float* m_dev, float* s_dev,
+                       const float* r_dev, const double* loss_dev, double eta_m, double eta_s);
+
 /* ----------------------------------------------------------- measurement */
 
 /* Kernel timing for benchmarks.  While enabled, every launch of the force

@@ -16,38 +16,13 @@
 #include <algorithm>
 #include <cmath>
 
-#include "nep_internal.h"
+#include "nep_device.h"
 
 namespace nep {
 namespace {
 
-constexpr int kBlock = 256;
-
 __device__ __forceinline__ void fractional(const Box& b, const double r[3], double s[3]) {
   for (int a = 0; a < 3; ++a) s[a] = r[0] * b.hinv[a] + r[1] * b.hinv[3 + a] + r[2] * b.hinv[6 + a];
-}
-
-// |r_j + n.H - r_i|^2 in the documented evaluation order.
-__device__ __forceinline__ double pair_r2(const double* __restrict__ pos, int n, int j, double xi,
-                                          double yi, double zi, int n0, int n1, int n2,
-                                          const Box& b) {
-#pragma clang fp contract(off)
-  const double a0 = (double)n0, a1 = (double)n1, a2 = (double)n2;
-  double dx = (pos[j] - xi) + ((a0 * b.h[0] + a1 * b.h[3]) + a2 * b.h[6]);
-  double dy = (pos[n + j] - yi) + ((a0 * b.h[1] + a1 * b.h[4]) + a2 * b.h[7]);
-  double dz = (pos[2 * n + j] - zi) + ((a0 * b.h[2] + a1 * b.h[5]) + a2 * b.h[8]);
-  return (dx * dx + dy * dy) + dz * dz;
-}
-
-// The same expression with the neighbour position already loaded.
-__device__ __forceinline__ double pair_r2_at(double xj, double yj, double zj, double xi, double yi,
-                                             double zi, int n0, int n1, int n2, const Box& b) {
-#pragma clang fp contract(off)
-  const double a0 = (double)n0, a1 = (double)n1, a2 = (double)n2;
-  double dx = (xj - xi) + ((a0 * b.h[0] + a1 * b.h[3]) + a2 * b.h[6]);
-  double dy = (yj - yi) + ((a0 * b.h[1] + a1 * b.h[4]) + a2 * b.h[7]);
-  double dz = (zj - zi) + ((a0 * b.h[2] + a1 * b.h[5]) + a2 * b.h[8]);
-  return (dx * dx + dy * dy) + dz * dz;
 }
 
 __global__ void k_zero(int* __restrict__ a, int m) {
@@ -239,7 +214,7 @@ __global__ __launch_bounds__(256) void k_build_cells(
         const int n1 = m1 + wi1 - (int)(signed char)((rc.w >> 8) & 0xFF);
         const int n2 = m2 + wi2 - (int)(signed char)((rc.w >> 16) & 0xFF);
         if (!(j == i && n0 == 0 && n1 == 0 && n2 == 0)) {
-          const double r2 = pair_r2_at(rc.x, rc.y, rc.z, xi, yi, zi, n0, n1, n2, box);
+          const double r2 = list_r2(rc.x, rc.y, rc.z, xi, yi, zi, n0, n1, n2, box.h);
           const bool in_a = r2 < rc2_a;
           keep = pass == 0 ? in_a : (!in_a && r2 < rc2_r);
           if (keep && (n0 < -3 || n0 > 3 || n1 < -3 || n1 > 3 || n2 < -3 || n2 > 3)) {
@@ -287,7 +262,7 @@ __global__ void k_build_all_pairs(int n, int cap, const double* __restrict__ pos
           for (int m2 = -k2; m2 <= k2; ++m2) {
             const int n0 = m0 + wi0 - wj0, n1 = m1 + wi1 - wj1, n2 = m2 + wi2 - wj2;
             if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
-            const double r2 = pair_r2(pos, n, j, xi, yi, zi, n0, n1, n2, box);
+            const double r2 = list_r2(pos[j], pos[n + j], pos[2 * n + j], xi, yi, zi, n0, n1, n2, box.h);
             const bool in_a = r2 < rc2_a;
             const bool keep = pass == 0 ? in_a : (!in_a && r2 < rc2_r);
             if (!keep) continue;
@@ -361,6 +336,14 @@ __global__ void k_unpack(int n, int cap, const uint32_t* __restrict__ nl, int* _
 inline unsigned blocks_for(size_t work, int block) { return (unsigned)((work + block - 1) / block); }
 
 }  // namespace
+
+void launch_reverse(nep_ctx ctx, int n, int cap, const uint32_t* nl, const int* cnt_r,
+                    const int* cnt_a, int* rev) {
+  const size_t ncap = (size_t)n * cap;
+  if (ncap == 0) return;
+  launch_kernel(ctx, false, false, k_reverse, dim3(blocks_for(ncap, kBlock)), dim3(kBlock), n, cap,
+                nl, cnt_r, cnt_a, rev, ctx->flags.ptr);
+}
 
 hipError_t unpack_neighbors(nep_ctx ctx, int* nbr, int* img) {
   const System& s = ctx->sys;

@@ -33,19 +33,6 @@ bool hyper_valid(const nep_hyper* h) {
          h->n_max_angular < 64 && h->n_neuron <= 4096;
 }
 
-// Make the context's device current for the duration of a call.
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
 // Buffers whose size follows the system: partial forces, energies, forces,
 // block partial sums.
 nep_status size_system_buffers(nep_ctx ctx) {

@@ -161,6 +161,32 @@ struct nep_ctx_s {
   hipEvent_t ev_first = nullptr, ev_last = nullptr;
 };
 
+// A training set on the device (structures concatenated).
+struct nep_dataset_s {
+  nep_ctx ctx = nullptr;
+  int S = 0, N = 0, cap = 0;
+  int n_virial = 0;
+  double rc_r = 0, rc_a = 0;  // cutoffs the lists were built for
+  nep::DevBuf<double> pos;     // [3][N] wrapped
+  nep::DevBuf<double> boxes;   // [S][9]
+  nep::DevBuf<double> boxinv;  // [S][9]
+  nep::DevBuf<int> struct_of;  // [N]
+  nep::DevBuf<int> off;        // [S+1]
+  nep::DevBuf<int> kimg;       // [S][3]
+  nep::DevBuf<double> e_tar;   // [S]
+  nep::DevBuf<double> f_tar;   // [3][N]
+  nep::DevBuf<double> w_tar;   // [S][6]
+  nep::DevBuf<int> has_v;      // [S]
+  nep::DevBuf<uint32_t> nl;    // [cap][N]
+  nep::DevBuf<int> cnt_r, cnt_a, rev, wrap;
+  // population workspace
+  nep::DevBuf<float4> pin;          // [pop][cap][N]
+  nep::DevBuf<float> fown;          // [pop][3][N]
+  nep::DevBuf<float> U;             // [pop][N]
+  nep::DevBuf<double> atom_terms;   // [pop][8][N]
+  nep::DevBuf<double> struct_sq;    // [pop][S][3]
+};
+
 namespace nep {
 
 // neighbours.hip
@@ -169,6 +195,9 @@ void prepare_system_geometry(System& s, const double* box_host, double rc_r, dou
                              double skin);
 // Expand packed entries to atom indices [cap][n] and images [cap][n][3].
 hipError_t unpack_neighbors(nep_ctx ctx, int* nbr, int* img);
+// Reverse slots of a list (any system, global atom indices).
+void launch_reverse(nep_ctx ctx, int n, int cap, const uint32_t* nl, const int* cnt_r,
+                    const int* cnt_a, int* rev);
 
 // force.hip
 bool have_force_variant(const nep_hyper& h);
@@ -181,6 +210,8 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
                          double mass);
 size_t gather_blocks(int n);
 hipError_t launch_kick_drift(nep_ctx ctx, double* pos, double* vel, double kick, double dt);
+// pass 1 over a dataset for n_pop parameter vectors Z [n_pop][n_par].
+hipError_t launch_partials_population(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z);
 
 // Launch a kernel on the context's stream.  When a timed kernel class is
 // being launched, its first kernel carries the start event and its last
@@ -221,6 +252,19 @@ hipError_t timed(nep_ctx ctx, int cls, Fn&& launch) {
   ctx->ev_first = ctx->ev_last = nullptr;
   return e;
 }
+
+// Make the context's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
 
 // helpers (nep_api.hip)
 nep_status fail(nep_ctx ctx, nep_status code, const std::string& msg);

@@ -1,0 +1,597 @@
+// Training-set evaluation for the separable natural evolution strategy on
+// gfx950 (paper, Sec. II E): the loss of a whole population of parameter
+// vectors over many small periodic structures, and the SNES sampling and
+// update steps.
+//
+// Structures are concatenated into one system (as the paper does, Sec. II F)
+// with a cell per structure.  Their neighbour lists are built once, when the
+// dataset is created.  One launch of the partial-force kernel evaluates every
+// (atom, individual) pair; a population gather turns the partials into per-
+// atom loss terms; float64 sums over each structure and then over structures
+// give the loss components of each individual, in a fixed order.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nep_device.h"
+
+namespace nep {
+namespace {
+
+inline unsigned blocks_for(size_t work, int block) { return (unsigned)((work + block - 1) / block); }
+
+constexpr int kLanes = 4;  // lanes per atom in the population gather (as in pass 1)
+
+// ------------------------------------------------------- dataset lists
+
+// Wrap every position into its structure's cell; record the integer offsets
+// that remain after rounding (normally zero).
+__global__ void k_ds_wrap(int N, double* __restrict__ pos, const double* __restrict__ boxes,
+                          const double* __restrict__ boxinv, const int* __restrict__ struct_of,
+                          int* __restrict__ wrap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double* H = boxes + 9 * (size_t)struct_of[i];
+  const double* Hi = boxinv + 9 * (size_t)struct_of[i];
+  double r[3] = {pos[i], pos[N + i], pos[2 * N + i]};
+  int w[3];
+  for (int a = 0; a < 3; ++a) w[a] = (int)floor(r[0] * Hi[a] + r[1] * Hi[3 + a] + r[2] * Hi[6 + a]);
+  for (int c = 0; c < 3; ++c) {
+    r[c] -= ((double)w[0] * H[c] + (double)w[1] * H[3 + c]) + (double)w[2] * H[6 + c];
+    pos[c * N + i] = r[c];
+  }
+  for (int a = 0; a < 3; ++a)
+    wrap[a * N + i] = (int)floor(r[0] * Hi[a] + r[1] * Hi[3 + a] + r[2] * Hi[6 + a]);
+}
+
+// One wave per atom: every atom j of the same structure and every image m in
+// [-K, K]^3 of the wrapped frame, numbered in (j, m0, m1, m2) order; 64 such
+// candidates are tested at a time and a ballot keeps the serial order.  The
+// angular-range entries come first (first pass), then the rest.
+__global__ __launch_bounds__(256) void k_ds_build(
+    int N, int cap, const double* __restrict__ pos, const double* __restrict__ boxes,
+    const int* __restrict__ struct_of, const int* __restrict__ off, const int* __restrict__ kimg,
+    const int* __restrict__ wrap, double rc2_r, double rc2_a, uint32_t* __restrict__ nl,
+    int* __restrict__ cnt_r, int* __restrict__ cnt_a, int* __restrict__ flags) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / 64;
+  const int k = gid % 64;
+  if (i >= N) return;  // whole waves leave together
+  const unsigned long long below = (1ull << k) - 1ull;
+  const int s = struct_of[i];
+  const double* H = boxes + 9 * (size_t)s;
+  const int j0 = off[s], nj = off[s + 1] - off[s];
+  const int K0 = kimg[3 * s], K1 = kimg[3 * s + 1], K2 = kimg[3 * s + 2];
+  const int w1n = 2 * K1 + 1, w2n = 2 * K2 + 1;
+  const int nimg = (2 * K0 + 1) * w1n * w2n;
+  const int total = nj * nimg;
+  const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
+  const int wi0 = wrap[i], wi1 = wrap[N + i], wi2 = wrap[2 * N + i];
+  int count = 0;
+  bool overflow = false, bad_image = false;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int base = 0; base < total; base += 64) {
+      const int c = base + k;
+      bool keep = false;
+      uint32_t entry = 0;
+      if (c < total) {
+        const int j = j0 + c / nimg;
+        const int mi = c % nimg;
+        const int m0 = mi / (w1n * w2n) - K0;
+        const int m1 = (mi / w2n) % w1n - K1;
+        const int m2 = mi % w2n - K2;
+        const int n0 = m0 + wi0 - wrap[j], n1 = m1 + wi1 - wrap[N + j], n2 = m2 + wi2 - wrap[2 * N + j];
+        if (!(j == i && n0 == 0 && n1 == 0 && n2 == 0)) {
+          const double r2 =
+              list_r2(pos[j], pos[N + j], pos[2 * N + j], xi, yi, zi, n0, n1, n2, H);
+          const bool in_a = r2 < rc2_a;
+          keep = pass == 0 ? in_a : (!in_a && r2 < rc2_r);
+          if (keep && (n0 < -3 || n0 > 3 || n1 < -3 || n1 > 3 || n2 < -3 || n2 > 3)) {
+            bad_image = true;
+            keep = false;
+          }
+          entry = pack_entry(j, n0, n1, n2);
+        }
+      }
+      const unsigned long long ball = __ballot(keep);
+      if (keep) {
+        const int slot = count + __popcll(ball & below);
+        if (slot < cap)
+          nl[(size_t)slot * N + i] = entry;
+        else
+          overflow = true;
+      }
+      count += __popcll(ball);
+    }
+    if (pass == 0 && k == 0) cnt_a[i] = min(count, cap);
+  }
+  if (k == 0) cnt_r[i] = min(count, cap);
+  if (overflow) flags[kFlagOverflow] = 1;
+  if (bad_image) flags[kFlagImage] = 1;
+}
+
+// ------------------------------------------------- population loss terms
+
+// Per (atom, individual k = blockIdx.y): F_i = sum_j p_ij - sum_j p_ji and
+// W_i = sum_j r_ij (x) p_ji from the individual's partials, then the per-atom
+// loss terms (U_i, |F_i - F_i^tar|^2, W_i xx yy zz xy yz zx) in float64 at
+// terms[(8k + q) N + i].
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_ds_gather(
+    int N, int cap, const double* __restrict__ pos, const double* __restrict__ boxes,
+    const int* __restrict__ struct_of, const uint32_t* __restrict__ nl,
+    const int* __restrict__ cnt_r, const float4* __restrict__ pin, const float* __restrict__ fown,
+    const float* __restrict__ U, const double* __restrict__ f_tar, double* __restrict__ terms) {
+  const size_t pk = blockIdx.y;
+  pin += pk * (size_t)cap * N;
+  fown += pk * 3 * (size_t)N;
+  U += pk * (size_t)N;
+  terms += pk * 8 * (size_t)N;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / L;
+  const int lane = gid % L;
+  const bool active = i < N;
+  const int ii = active ? i : 0;
+  const int cr = active ? cnt_r[i] : 0;
+  const double xi = pos[ii], yi = pos[N + ii], zi = pos[2 * N + ii];
+  const double* H = boxes + 9 * (size_t)struct_of[ii];
+  float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+  float w[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) w[q] = 0.f;
+  for (int s = lane; s < cr; s += L) {
+    const size_t idx = (size_t)s * N + i;
+    int j;
+    float dx, dy, dz;
+    displacement(nl[idx], pos, N, xi, yi, zi, H, j, dx, dy, dz);
+    const float4 pji = pin[idx];
+    f0 -= pji.x;
+    f1 -= pji.y;
+    f2 -= pji.z;
+    w[0] += dx * pji.x;
+    w[1] += dx * pji.y;
+    w[2] += dx * pji.z;
+    w[3] += dy * pji.x;
+    w[4] += dy * pji.y;
+    w[5] += dy * pji.z;
+    w[6] += dz * pji.x;
+    w[7] += dz * pji.y;
+    w[8] += dz * pji.z;
+  }
+  f0 = group_sum<L>(f0);
+  f1 = group_sum<L>(f1);
+  f2 = group_sum<L>(f2);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) w[q] = group_sum<L>(w[q]);
+  if (active && lane == 0) {
+    const double F0 = (double)(f0 + fown[i]) - f_tar[i];
+    const double F1 = (double)(f1 + fown[N + i]) - f_tar[N + i];
+    const double F2 = (double)(f2 + fown[2 * N + i]) - f_tar[2 * N + i];
+    terms[i] = (double)U[i];
+    terms[(size_t)N + i] = F0 * F0 + F1 * F1 + F2 * F2;
+    terms[2 * (size_t)N + i] = (double)w[0];  // xx
+    terms[3 * (size_t)N + i] = (double)w[4];  // yy
+    terms[4 * (size_t)N + i] = (double)w[8];  // zz
+    terms[5 * (size_t)N + i] = (double)w[1];  // xy
+    terms[6 * (size_t)N + i] = (double)w[5];  // yz
+    terms[7 * (size_t)N + i] = (double)w[6];  // zx
+  }
+}
+
+// Per (structure s = blockIdx.x, individual k = blockIdx.y): sums of the
+// per-atom terms over the structure, then sq[(k S + s) 3 + (0, 1, 2)] =
+// (((U_s - E_s)/N_s)^2, sum_i |dF_i|^2, sum_6 ((W_s - W_s^tar)/N_s)^2 or 0).
+__global__ __launch_bounds__(kBlock) void k_ds_struct(
+    int N, int S, const int* __restrict__ off, const double* __restrict__ terms,
+    const double* __restrict__ e_tar, const double* __restrict__ w_tar,
+    const int* __restrict__ has_v, double* __restrict__ sq) {
+  __shared__ double sw[kBlock / 64][8];
+  __shared__ double tot[8];
+  const int s = blockIdx.x;
+  const size_t pk = blockIdx.y;
+  const double* t = terms + pk * 8 * (size_t)N;
+  const int a0 = off[s], a1 = off[s + 1];
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] += t[(size_t)q * N + a];
+  const double v = block_sum<8>(acc, sw);
+  if (threadIdx.x < 8) tot[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double ns = (double)(a1 - a0);
+    const double de = (tot[0] - e_tar[s]) / ns;
+    double dv = 0.0;
+    if (has_v[s])
+      for (int c = 0; c < 6; ++c) {
+        const double d = (tot[2 + c] - w_tar[6 * s + c]) / ns;
+        dv += d * d;
+      }
+    double* o = sq + (pk * S + s) * 3;
+    o[0] = de * de;
+    o[1] = tot[1];
+    o[2] = dv;
+  }
+}
+
+// Per individual k = blockIdx.x: loss[k][6] = (L, L_e, L_f, L_v, L_1, L_2).
+__global__ __launch_bounds__(kBlock) void k_ds_loss(int S, int N, int n_virial, int n_par,
+                                                    const double* __restrict__ sq,
+                                                    const float* __restrict__ Z, double le,
+                                                    double lf, double lv, double l1, double l2,
+                                                    double* __restrict__ loss) {
+  __shared__ double sw[kBlock / 64][5];
+  __shared__ double tot[5];
+  const size_t pk = blockIdx.x;
+  const double* q = sq + pk * 3 * (size_t)S;
+  const float* z = Z + pk * (size_t)n_par;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int s = threadIdx.x; s < S; s += blockDim.x) {
+    acc[0] += q[3 * s];
+    acc[1] += q[3 * s + 1];
+    acc[2] += q[3 * s + 2];
+  }
+  for (int v = threadIdx.x; v < n_par; v += blockDim.x) {
+    const double x = (double)z[v];
+    acc[3] += fabs(x);
+    acc[4] += x * x;
+  }
+  const double v = block_sum<5>(acc, sw);
+  if (threadIdx.x < 5) tot[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double Le = sqrt(tot[0] / S);
+    const double Lf = sqrt(tot[1] / (3.0 * N));
+    const double Lv = n_virial > 0 ? sqrt(tot[2] / (6.0 * n_virial)) : 0.0;
+    const double L1 = tot[3] / n_par;
+    const double L2 = sqrt(tot[4] / n_par);
+    double* o = loss + 6 * pk;
+    o[0] = le * Le + lf * Lf + lv * Lv + l1 * L1 + l2 * L2;
+    o[1] = Le;
+    o[2] = Lf;
+    o[3] = Lv;
+    o[4] = L1;
+    o[5] = L2;
+  }
+}
+
+// ------------------------------------------------------- SNES steps
+
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each round
+// multiplies words 0 and 2 by 0xD2511F53 and 0xCD9E8D57, mixes the high
+// halves with words 1 and 3 and the key; the key advances by 0x9E3779B9 and
+// 0xBB67AE85 between rounds.
+__device__ __forceinline__ void philox(uint32_t (&x)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t a = (uint64_t)0xD2511F53u * x[0];
+    const uint64_t b = (uint64_t)0xCD9E8D57u * x[2];
+    const uint32_t n0 = (uint32_t)(b >> 32) ^ x[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(a >> 32) ^ x[3] ^ k1;
+    x[0] = n0;
+    x[1] = (uint32_t)b;
+    x[2] = n2;
+    x[3] = (uint32_t)a;
+  }
+}
+
+__global__ void k_snes_sample(int n_par, const float* __restrict__ m, const float* __restrict__ s,
+                              uint32_t key0, uint32_t key1, uint32_t gen, float* __restrict__ r,
+                              float* __restrict__ Z) {
+#pragma clang fp contract(off)
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (4 * b >= n_par) return;
+  uint32_t x[4] = {(uint32_t)b, (uint32_t)k, gen, 0u};
+  philox(x, key0, key1);
+  double u[4];
+  for (int t = 0; t < 4; ++t) u[t] = ((double)x[t] + 0.5) * (1.0 / 4294967296.0);
+  const double twopi = 6.28318530717958647692;
+  const double rad0 = sqrt(-2.0 * log(u[0])), rad1 = sqrt(-2.0 * log(u[2]));
+  const double nrm[4] = {rad0 * cos(twopi * u[1]), rad0 * sin(twopi * u[1]),
+                         rad1 * cos(twopi * u[3]), rad1 * sin(twopi * u[3])};
+  for (int t = 0; t < 4; ++t) {
+    const int v = 4 * b + t;
+    if (v >= n_par) break;
+    const float rv = (float)nrm[t];
+    r[(size_t)k * n_par + v] = rv;
+    Z[(size_t)k * n_par + v] = (float)((double)m[v] + (double)s[v] * (double)rv);
+  }
+}
+
+// Every block ranks the population itself (P <= 1024), then updates its
+// share of the parameters.
+__global__ __launch_bounds__(kBlock) void k_snes_update(int n_par, int n_pop, float* __restrict__ m,
+                                                        float* __restrict__ s,
+                                                        const float* __restrict__ r,
+                                                        const double* __restrict__ loss,
+                                                        double eta_m, double eta_s) {
+#pragma clang fp contract(off)
+  __shared__ int order[1024];
+  __shared__ double util[1024];
+  for (int k = threadIdx.x; k < n_pop; k += blockDim.x) {
+    const double lk = loss[6 * k];
+    const double key = lk != lk ? INFINITY : lk;
+    int rank = 0;
+    for (int j = 0; j < n_pop; ++j) {
+      const double lj = loss[6 * j];
+      const double kj = lj != lj ? INFINITY : lj;
+      rank += (kj < key || (kj == key && j < k)) ? 1 : 0;
+    }
+    order[rank] = k;
+  }
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    const double top = log(n_pop / 2.0 + 1.0);
+    for (int k = 1; k <= n_pop; ++k) {
+      const double v = top - log((double)k);
+      util[k - 1] = v > 0.0 ? v : 0.0;
+      tot += util[k - 1];
+    }
+    for (int k = 0; k < n_pop; ++k) util[k] = util[k] / tot - 1.0 / n_pop;
+  }
+  __syncthreads();
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_par) return;
+  double gm = 0.0, gs = 0.0;
+  for (int rank = 0; rank < n_pop; ++rank) {
+    const double rv = (double)r[(size_t)order[rank] * n_par + v];
+    gm += util[rank] * rv;
+    gs += util[rank] * (rv * rv - 1.0);
+  }
+  const double sv = (double)s[v];
+  m[v] = (float)((double)m[v] + eta_m * sv * gm);
+  s[v] = (float)(sv * exp(0.5 * eta_s * gs));
+}
+
+void invert_box(const double* H, double* Hi) {
+  const double a = H[0], b = H[1], c = H[2], d = H[3], e = H[4], f = H[5], g = H[6], h = H[7],
+               k = H[8];
+  const double det = a * (e * k - f * h) - b * (d * k - f * g) + c * (d * h - e * g);
+  Hi[0] = (e * k - f * h) / det;
+  Hi[1] = (c * h - b * k) / det;
+  Hi[2] = (b * f - c * e) / det;
+  Hi[3] = (f * g - d * k) / det;
+  Hi[4] = (a * k - c * g) / det;
+  Hi[5] = (c * d - a * f) / det;
+  Hi[6] = (d * h - e * g) / det;
+  Hi[7] = (b * g - a * h) / det;
+  Hi[8] = (a * e - b * d) / det;
+}
+
+}  // namespace
+}  // namespace nep
+
+using namespace nep;
+
+extern "C" {
+
+nep_status nep_dataset_create(nep_ctx ctx, int n_struct, const int* n_atoms_host,
+                              const double* boxes_host, const double* pos_host,
+                              const double* energy_host, const double* forces_host,
+                              const double* virial_host, const unsigned char* has_virial_host,
+                              int max_neighbors, nep_dataset* out) {
+  if (!ctx || !out) return NEP_EINVAL;
+  *out = nullptr;
+  if (!ctx->have_params) return fail(ctx, NEP_ESTATE, "nep_load_params must come first");
+  if (n_struct < 1) return fail(ctx, NEP_EINVAL, "n_struct must be >= 1");
+  if (!n_atoms_host || !boxes_host || !pos_host || !energy_host || !forces_host || !virial_host ||
+      !has_virial_host)
+    return fail(ctx, NEP_EINVAL, "a host array is NULL");
+  if (max_neighbors < 1) return fail(ctx, NEP_EINVAL, "max_neighbors must be >= 1");
+  long long total = 0;
+  for (int s = 0; s < n_struct; ++s) {
+    if (n_atoms_host[s] < 1) return fail(ctx, NEP_EINVAL, "every structure needs >= 1 atom");
+    total += n_atoms_host[s];
+  }
+  if (total > kMaxAtoms) return fail(ctx, NEP_EINVAL, "more than 2^23 - 1 atoms in total");
+  const int N = (int)total, S = n_struct;
+  const double rc_r = ctx->hyper.rc_radial, rc_a = ctx->hyper.rc_angular;
+  std::vector<double> hinv((size_t)9 * S);
+  std::vector<int> kimg((size_t)3 * S), off((size_t)S + 1), sof(N);
+  std::vector<double> posT((size_t)3 * N), ftT((size_t)3 * N);
+  std::vector<int> hv(S);
+  int n_virial = 0;
+  off[0] = 0;
+  for (int s = 0; s < S; ++s) {
+    const double* H = boxes_host + 9 * (size_t)s;
+    for (int q = 0; q < 9; ++q)
+      if (!std::isfinite(H[q])) return fail(ctx, NEP_EINVAL, "box has non-finite entries");
+    invert_box(H, &hinv[9 * (size_t)s]);
+    System probe;
+    prepare_system_geometry(probe, H, rc_r, rc_a, 0.0);
+    for (int a = 0; a < 3; ++a) {
+      kimg[3 * s + a] = probe.kimg[a];
+      if (probe.kimg[a] > 2 || !std::isfinite(hinv[9 * (size_t)s]))
+        return fail(ctx, NEP_EINVAL,
+                    "structure " + std::to_string(s) + ": cell thinner than half the cutoff");
+    }
+    off[s + 1] = off[s] + n_atoms_host[s];
+    for (int a = off[s]; a < off[s + 1]; ++a) sof[a] = s;
+    hv[s] = has_virial_host[s] ? 1 : 0;
+    n_virial += hv[s];
+  }
+  for (int a = 0; a < N; ++a)
+    for (int c = 0; c < 3; ++c) {
+      posT[(size_t)c * N + a] = pos_host[3 * (size_t)a + c];
+      ftT[(size_t)c * N + a] = forces_host[3 * (size_t)a + c];
+    }
+  nep_dataset ds = new (std::nothrow) nep_dataset_s();
+  if (!ds) return fail(ctx, NEP_ENOMEM, "dataset");
+  ds->ctx = ctx;
+  ds->S = S;
+  ds->N = N;
+  ds->cap = max_neighbors;
+  ds->n_virial = n_virial;
+  ds->rc_r = rc_r;
+  ds->rc_a = rc_a;
+  DeviceGuard guard(ctx->device);
+  hipError_t e = hipSuccess;
+  const size_t ncap = (size_t)N * max_neighbors;
+  if (e == hipSuccess) e = ds->pos.ensure((size_t)3 * N);
+  if (e == hipSuccess) e = ds->boxes.ensure((size_t)9 * S);
+  if (e == hipSuccess) e = ds->boxinv.ensure((size_t)9 * S);
+  if (e == hipSuccess) e = ds->struct_of.ensure(N);
+  if (e == hipSuccess) e = ds->off.ensure((size_t)S + 1);
+  if (e == hipSuccess) e = ds->kimg.ensure((size_t)3 * S);
+  if (e == hipSuccess) e = ds->e_tar.ensure(S);
+  if (e == hipSuccess) e = ds->f_tar.ensure((size_t)3 * N);
+  if (e == hipSuccess) e = ds->w_tar.ensure((size_t)6 * S);
+  if (e == hipSuccess) e = ds->has_v.ensure(S);
+  if (e == hipSuccess) e = ds->nl.ensure(ncap);
+  if (e == hipSuccess) e = ds->rev.ensure(ncap);
+  if (e == hipSuccess) e = ds->cnt_r.ensure(N);
+  if (e == hipSuccess) e = ds->cnt_a.ensure(N);
+  if (e == hipSuccess) e = ds->wrap.ensure((size_t)3 * N);
+  hipStream_t st = ctx->stream;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  up(ds->pos.ptr, posT.data(), sizeof(double) * 3 * N);
+  up(ds->boxes.ptr, boxes_host, sizeof(double) * 9 * S);
+  up(ds->boxinv.ptr, hinv.data(), sizeof(double) * 9 * S);
+  up(ds->struct_of.ptr, sof.data(), sizeof(int) * N);
+  up(ds->off.ptr, off.data(), sizeof(int) * (S + 1));
+  up(ds->kimg.ptr, kimg.data(), sizeof(int) * 3 * S);
+  up(ds->e_tar.ptr, energy_host, sizeof(double) * S);
+  up(ds->f_tar.ptr, ftT.data(), sizeof(double) * 3 * N);
+  up(ds->w_tar.ptr, virial_host, sizeof(double) * 6 * S);
+  up(ds->has_v.ptr, hv.data(), sizeof(int) * S);
+  if (e == hipSuccess) {
+    k_ds_wrap<<<blocks_for(N, kBlock), kBlock, 0, st>>>(N, ds->pos.ptr, ds->boxes.ptr,
+                                                        ds->boxinv.ptr, ds->struct_of.ptr,
+                                                        ds->wrap.ptr);
+    const double rl = rc_r, ra = rc_a;
+    k_ds_build<<<blocks_for((size_t)N * 64, 256), 256, 0, st>>>(
+        N, max_neighbors, ds->pos.ptr, ds->boxes.ptr, ds->struct_of.ptr, ds->off.ptr,
+        ds->kimg.ptr, ds->wrap.ptr, rl * rl, ra * ra, ds->nl.ptr, ds->cnt_r.ptr, ds->cnt_a.ptr,
+        ctx->flags.ptr);
+    launch_reverse(ctx, N, max_neighbors, ds->nl.ptr, ds->cnt_r.ptr, ds->cnt_a.ptr, ds->rev.ptr);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    nep_dataset_destroy(ds);
+    return check_hip(ctx, e, "creating the dataset");
+  }
+  // the host buffers above are read by the copies: wait before returning
+  nep_status stt = nep_synchronize(ctx);
+  if (stt != NEP_OK) {
+    nep_dataset_destroy(ds);
+    return stt;
+  }
+  *out = ds;
+  return NEP_OK;
+}
+
+void nep_dataset_destroy(nep_dataset ds) {
+  if (!ds) return;
+  DeviceGuard guard(ds->ctx->device);
+  (void)hipStreamSynchronize(ds->ctx->stream);
+  ds->pos.release();
+  ds->boxes.release();
+  ds->boxinv.release();
+  ds->struct_of.release();
+  ds->off.release();
+  ds->kimg.release();
+  ds->e_tar.release();
+  ds->f_tar.release();
+  ds->w_tar.release();
+  ds->has_v.release();
+  ds->nl.release();
+  ds->cnt_r.release();
+  ds->cnt_a.release();
+  ds->rev.release();
+  ds->wrap.release();
+  ds->pin.release();
+  ds->fown.release();
+  ds->U.release();
+  ds->atom_terms.release();
+  ds->struct_sq.release();
+  delete ds;
+}
+
+nep_status snes_eval_population(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z_dev,
+                                const double* lambda_host, double* loss_dev) {
+  if (!ctx) return NEP_EINVAL;
+  if (!ds || ds->ctx != ctx) return fail(ctx, NEP_EINVAL, "dataset belongs to another context");
+  if (!ctx->have_params) return fail(ctx, NEP_ESTATE, "nep_load_params must come first");
+  if (ds->rc_r != ctx->hyper.rc_radial || ds->rc_a != ctx->hyper.rc_angular)
+    return fail(ctx, NEP_ESTATE, "dataset lists were built for other cutoffs");
+  if (n_pop < 1 || n_pop > 65535) return fail(ctx, NEP_EINVAL, "n_pop must be in [1, 65535]");
+  if (!Z_dev || !lambda_host || !loss_dev) return fail(ctx, NEP_EINVAL, "NULL argument");
+  const int N = ds->N, S = ds->S;
+  DeviceGuard guard(ctx->device);
+  hipError_t e = ds->pin.ensure((size_t)n_pop * ds->cap * N);
+  if (e == hipSuccess) e = ds->fown.ensure((size_t)n_pop * 3 * N);
+  if (e == hipSuccess) e = ds->U.ensure((size_t)n_pop * N);
+  if (e == hipSuccess) e = ds->atom_terms.ensure((size_t)n_pop * 8 * N);
+  if (e == hipSuccess) e = ds->struct_sq.ensure((size_t)n_pop * 3 * S);
+  if (e != hipSuccess) return check_hip(ctx, e, "allocating population workspace");
+  e = timed(ctx, 0, [&] { return launch_partials_population(ctx, ds, n_pop, Z_dev); });
+  if (e == hipSuccess)
+    e = timed(ctx, 1, [&] {
+      launch_kernel(ctx, true, false, k_ds_gather<kLanes>,
+                    dim3(blocks_for((size_t)N * kLanes, kBlock), n_pop), dim3(kBlock), N, ds->cap,
+                    (const double*)ds->pos.ptr, (const double*)ds->boxes.ptr,
+                    (const int*)ds->struct_of.ptr, (const uint32_t*)ds->nl.ptr,
+                    (const int*)ds->cnt_r.ptr, (const float4*)ds->pin.ptr,
+                    (const float*)ds->fown.ptr, (const float*)ds->U.ptr,
+                    (const double*)ds->f_tar.ptr, ds->atom_terms.ptr);
+      launch_kernel(ctx, false, false, k_ds_struct, dim3(S, n_pop), dim3(kBlock), N, S,
+                    (const int*)ds->off.ptr, (const double*)ds->atom_terms.ptr,
+                    (const double*)ds->e_tar.ptr, (const double*)ds->w_tar.ptr,
+                    (const int*)ds->has_v.ptr, ds->struct_sq.ptr);
+      launch_kernel(ctx, false, true, k_ds_loss, dim3(n_pop), dim3(kBlock), S, N, ds->n_virial,
+                    ctx->n_par, (const double*)ds->struct_sq.ptr, Z_dev, lambda_host[0],
+                    lambda_host[1], lambda_host[2], lambda_host[3], lambda_host[4], loss_dev);
+      return hipGetLastError();
+    });
+  return check_hip(ctx, e, "launching population kernels");
+}
+
+nep_status snes_sample(nep_ctx ctx, int n_par, int n_pop, const float* m_dev, const float* s_dev,
+                       unsigned long long seed, int generation, float* r_dev, float* Z_dev) {
+  if (!ctx) return NEP_EINVAL;
+  if (n_par < 1 || n_pop < 1 || n_pop > 65535)
+    return fail(ctx, NEP_EINVAL, "n_par >= 1 and 1 <= n_pop <= 65535 required");
+  if (generation < 0) return fail(ctx, NEP_EINVAL, "generation must be >= 0");
+  if (!m_dev || !s_dev || !r_dev || !Z_dev) return fail(ctx, NEP_EINVAL, "NULL argument");
+  DeviceGuard guard(ctx->device);
+  hipError_t e = hipSuccess;
+  {
+    const int nb = (n_par + 3) / 4;
+    launch_kernel(ctx, true, true, k_snes_sample, dim3(blocks_for(nb, kBlock), n_pop),
+                  dim3(kBlock), n_par, m_dev, s_dev, (uint32_t)(seed & 0xFFFFFFFFull),
+                  (uint32_t)(seed >> 32), (uint32_t)generation, r_dev, Z_dev);
+    e = hipGetLastError();
+  }
+  return check_hip(ctx, e, "launching the SNES sampler");
+}
+
+nep_status snes_update(nep_ctx ctx, int n_par, int n_pop, float* m_dev, float* s_dev,
+                       const float* r_dev, const double* loss_dev, double eta_m, double eta_s) {
+  if (!ctx) return NEP_EINVAL;
+  if (n_par < 1 || n_pop < 1 || n_pop > 1024)
+    return fail(ctx, NEP_EINVAL, "n_par >= 1 and 1 <= n_pop <= 1024 required");
+  if (!m_dev || !s_dev || !r_dev || !loss_dev) return fail(ctx, NEP_EINVAL, "NULL argument");
+  if (!(eta_m > 0.0)) eta_m = 1.0;
+  if (!(eta_s > 0.0)) eta_s = (3.0 + std::log((double)n_par)) / (5.0 * std::sqrt((double)n_par));
+  DeviceGuard guard(ctx->device);
+  hipError_t e = hipSuccess;
+  {
+    launch_kernel(ctx, true, true, k_snes_update, dim3(blocks_for(n_par, kBlock)), dim3(kBlock),
+                  n_par, n_pop, m_dev, s_dev, r_dev, loss_dev, eta_m, eta_s);
+    e = hipGetLastError();
+  }
+  return check_hip(ctx, e, "launching the SNES update");
+}
+
+}  // extern "C"

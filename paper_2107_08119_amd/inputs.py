@@ -325,16 +325,16 @@ def stillinger_weber(pos: np.ndarray, box: np.ndarray):
     # three-body: for each centre i, unordered pairs (j, k) of its neighbours
     order = np.argsort(ii, kind="stable")
     ii, jj, d, r, u = ii[order], jj[order], d[order], r[order], u[order]
-    starts = np.searchsorted(ii, np.arange(n + 1))
-    a_list, b_list = [], []
-    for i in range(n):
-        s0, s1 = starts[i], starts[i + 1]
-        m = s1 - s0
-        if m < 2:
-            continue
-        aa, bb = np.triu_indices(m, k=1)
-        a_list.append(aa + s0)
-        b_list.append(bb + s0)
+    # all (a, b) with a < b inside each centre's group of consecutive pairs
+    same = []
+    for gap in range(1, len(ii)):
+        first = np.arange(len(ii) - gap)
+        hit = ii[first] == ii[first + gap]
+        if not np.any(hit):
+            break
+        same.append((first[hit], first[hit] + gap))
+    a_list = [x[0] for x in same]
+    b_list = [x[1] for x in same]
     energy3 = 0.0
     if a_list:
         A = np.concatenate(a_list)

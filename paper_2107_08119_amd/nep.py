@@ -25,7 +25,8 @@ EXPORTED = [
     "nep_create", "nep_destroy", "nep_last_error", "nep_set_stream", "nep_synchronize",
     "nep_num_descriptors", "nep_num_params", "nep_load_params", "nep_build_neighbors",
     "nep_get_neighbors", "nep_compute", "nep_md_step", "nep_set_timing", "nep_get_timing",
-    "nep_time_partials",
+    "nep_time_partials", "nep_dataset_create", "nep_dataset_destroy", "snes_eval_population",
+    "snes_sample", "snes_update",
 ]
 
 
@@ -76,9 +77,15 @@ def lib() -> C.CDLL:
         L.nep_set_timing.argtypes = [vp, ip]
         L.nep_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.nep_time_partials.argtypes = [vp, vp, ip, C.POINTER(C.c_double)]
+        L.nep_dataset_create.argtypes = [vp, ip, vp, vp, vp, vp, vp, vp, vp, ip, C.POINTER(vp)]
+        L.nep_dataset_destroy.argtypes = [vp]
+        L.nep_dataset_destroy.restype = None
+        L.snes_eval_population.argtypes = [vp, vp, ip, vp, vp, vp]
+        L.snes_sample.argtypes = [vp, ip, ip, vp, vp, C.c_ulonglong, ip, vp, vp]
+        L.snes_update.argtypes = [vp, ip, ip, vp, vp, vp, vp, dp, dp]
         for name in EXPORTED:
             if name not in ("nep_destroy", "nep_last_error", "nep_num_descriptors",
-                            "nep_num_params"):
+                            "nep_num_params", "nep_dataset_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -197,6 +204,52 @@ class Context:
             _ptr(out.get("W")), _ptr(out.get("J")), _ptr(out.get("totals"))))
         return out
 
+    # -- training ------------------------------------------------------------
+    def dataset_create(self, ls, max_neighbors: int = 64) -> "Dataset":
+        """Copy a labelled set (inputs.LabelledSet layout) to the device."""
+        n_atoms = np.ascontiguousarray(ls.n_atoms, np.int32)
+        arrays = [n_atoms, np.ascontiguousarray(ls.boxes, np.float64),
+                  np.ascontiguousarray(ls.pos, np.float64),
+                  np.ascontiguousarray(ls.energy, np.float64),
+                  np.ascontiguousarray(ls.forces, np.float64),
+                  np.ascontiguousarray(ls.virial, np.float64),
+                  np.ascontiguousarray(ls.has_virial, np.uint8)]
+        h = C.c_void_p()
+        self._check(self._lib.nep_dataset_create(
+            self._h, len(n_atoms), *[a.ctypes.data for a in arrays], max_neighbors, C.byref(h)))
+        return Dataset(self, h, len(n_atoms), int(n_atoms.sum()))
+
+    def eval_population(self, ds: "Dataset", Z: torch.Tensor,
+                        lam=(1.0, 1.0, 1.0, 0.05, 0.05), out: torch.Tensor | None = None):
+        _require(Z, torch.float32, None, "Z")
+        n_pop = Z.shape[0]
+        if out is None:
+            out = torch.empty((n_pop, 6), dtype=torch.float64, device=Z.device)
+        lam = np.ascontiguousarray(lam, np.float64)
+        self._check(self._lib.snes_eval_population(self._h, ds._h, n_pop, _ptr(Z),
+                                                   lam.ctypes.data, _ptr(out)))
+        return out
+
+    def snes_sample(self, m: torch.Tensor, s: torch.Tensor, seed: int, generation: int,
+                    n_pop: int, r: torch.Tensor | None = None, Z: torch.Tensor | None = None):
+        n_par = m.shape[0]
+        _require(m, torch.float32, (n_par,), "m")
+        _require(s, torch.float32, (n_par,), "s")
+        if r is None:
+            r = torch.empty((n_pop, n_par), dtype=torch.float32, device=m.device)
+        if Z is None:
+            Z = torch.empty((n_pop, n_par), dtype=torch.float32, device=m.device)
+        self._check(self._lib.snes_sample(self._h, n_par, n_pop, _ptr(m), _ptr(s), seed,
+                                          generation, _ptr(r), _ptr(Z)))
+        return r, Z
+
+    def snes_update(self, m: torch.Tensor, s: torch.Tensor, r: torch.Tensor,
+                    loss: torch.Tensor, eta_m: float = 0.0, eta_s: float = 0.0) -> None:
+        n_pop, n_par = r.shape
+        _require(loss, torch.float64, (n_pop, 6), "loss")
+        self._check(self._lib.snes_update(self._h, n_par, n_pop, _ptr(m), _ptr(s), _ptr(r),
+                                          _ptr(loss), eta_m, eta_s))
+
     def md_step(self, n_steps: int, dt: float, rebuild_every: int, mass: float,
                 pos: torch.Tensor, vel: torch.Tensor, thermo: torch.Tensor | None = None,
                 W: torch.Tensor | None = None, J: torch.Tensor | None = None) -> torch.Tensor:
@@ -208,6 +261,24 @@ class Context:
         self._check(self._lib.nep_md_step(self._h, n_steps, dt, rebuild_every, mass, _ptr(pos),
                                           _ptr(vel), _ptr(thermo), _ptr(W), _ptr(J)))
         return thermo
+
+
+class Dataset:
+    """A training set resident on the device (nep_dataset)."""
+
+    def __init__(self, ctx: Context, handle, n_struct: int, n_atoms: int):
+        self.ctx, self._h, self.n_struct, self.n_atoms = ctx, handle, n_struct, n_atoms
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.ctx._lib.nep_dataset_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 KERNEL_CLASSES = ("partials", "gather", "neighbors", "integrator")

@@ -1,0 +1,131 @@
+"""GPU parity of the SNES population loss, sampling and update against the
+FP64 oracle, through the C ABI.
+
+Loss components of every individual must agree with the oracle to 1e-5
+relative (each component separately); noise and updated search
+distributions to float32 rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2107_08119_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+OH = O.hyper()
+LAM = (1.0, 1.0, 1.0, 0.05, 0.05)
+
+
+def nep_mod():
+    from paper_2107_08119_amd import nep
+    return nep
+
+
+def small_set():
+    ls = I.labelled_set(14, 8, 64, seed=21)
+    # add a one-atom cell (the atom sees only its own images) and a thin triclinic cell
+    one_pos = np.array([[0.3, 0.2, 0.1]])
+    one_box = np.array([[3.9, 0.0, 0.0], [0.4, 4.1, 0.0], [0.2, -0.3, 4.0]])
+    e1, f1, w1 = I.stillinger_weber(one_pos, one_box)
+    tri = I.training_structures(1, 8, 8, seed=5)[0]
+    e2, f2, w2 = I.stillinger_weber(tri.pos, tri.box)
+    comps = I.VIRIAL_COMPONENTS
+    return I.LabelledSet(
+        np.concatenate([ls.n_atoms, [1, len(tri.pos)]]).astype(np.int32),
+        np.vstack([ls.boxes, one_box.reshape(1, 9), tri.box.reshape(1, 9)]),
+        np.vstack([ls.pos, one_pos, tri.pos]),
+        np.concatenate([ls.energy, [e1, e2]]),
+        np.vstack([ls.forces, f1, f2]),
+        np.vstack([ls.virial, [[w1[a, b] for a, b in comps]], [[w2[a, b] for a, b in comps]]]),
+        np.concatenate([ls.has_virial, [1, 0]]).astype(np.uint8))
+
+
+def population(n_pop, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((n_pop, 931)) * 0.1).astype(np.float32)
+
+
+def gpu_losses(ls, Z, cap=200):
+    import torch
+    nep = nep_mod()
+    ctx = nep.Context(0)
+    ctx.load_params(nep.hyper(), Z[0])
+    ds = ctx.dataset_create(ls, max_neighbors=cap)
+    loss = ctx.eval_population(ds, torch.from_numpy(Z).cuda(), LAM)
+    ctx.synchronize()
+    return loss.cpu().numpy(), ctx, ds
+
+
+def test_population_loss_matches_oracle():
+    ls = small_set()
+    Z = population(6, 3)
+    got, _, _ = gpu_losses(ls, Z)
+    for k in range(len(Z)):
+        ref = O.loss(OH, Z[k], ls, LAM, cap=200)
+        np.testing.assert_allclose(got[k], ref, rtol=1e-5, err_msg="individual %d" % k)
+
+
+def test_population_loss_deterministic():
+    ls = small_set()
+    Z = population(4, 4)
+    a, ctx, ds = gpu_losses(ls, Z)
+    import torch
+    b = ctx.eval_population(ds, torch.from_numpy(Z).cuda(), LAM).cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+    # a population of one gives the same numbers as inside a larger population
+    c = ctx.eval_population(ds, torch.from_numpy(Z[2:3].copy()).cuda(), LAM).cpu().numpy()
+    np.testing.assert_array_equal(c[0], a[2])
+
+
+def test_dataset_overflow_is_reported():
+    nep = nep_mod()
+    ctx = nep.Context(0)
+    ctx.load_params(nep.hyper(), population(1, 0)[0])
+    with pytest.raises(nep.NepError) as e:
+        ctx.dataset_create(small_set(), max_neighbors=8)
+    assert e.value.status == nep.NEP_EOVERFLOW
+
+
+def test_snes_sample_matches_oracle():
+    import torch
+    nep = nep_mod()
+    ctx = nep.Context(0)
+    rng = np.random.default_rng(1)
+    m = rng.uniform(-0.5, 0.5, 931).astype(np.float32)
+    s = np.full(931, 0.1, np.float32)
+    r, Z = ctx.snes_sample(torch.from_numpy(m).cuda(), torch.from_numpy(s).cuda(),
+                           seed=0x1234567890AB, generation=7, n_pop=50)
+    r_ref, z_ref = O.snes_sample(m, s, seed=0x1234567890AB, gen=7, n_pop=50)
+    np.testing.assert_allclose(r.cpu().numpy(), r_ref, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(Z.cpu().numpy(), z_ref, rtol=1e-6, atol=1e-7)
+
+
+def test_snes_update_matches_oracle():
+    import torch
+    nep = nep_mod()
+    ctx = nep.Context(0)
+    rng = np.random.default_rng(2)
+    n_pop = 50
+    m = rng.uniform(-0.5, 0.5, 931).astype(np.float32)
+    s = np.full(931, 0.1, np.float32)
+    r = rng.standard_normal((n_pop, 931)).astype(np.float32)
+    loss = np.zeros((n_pop, 6))
+    loss[:, 0] = rng.random(n_pop)
+    loss[7, 0] = loss[3, 0]  # a tie, broken by index
+    md, sd = torch.from_numpy(m).cuda(), torch.from_numpy(s).cuda()
+    ctx.snes_update(md, sd, torch.from_numpy(r).cuda(), torch.from_numpy(loss).cuda())
+    m_ref, s_ref = O.snes_update(m, s, r, loss[:, 0])
+    np.testing.assert_allclose(md.cpu().numpy(), m_ref, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(sd.cpu().numpy(), s_ref, rtol=1e-6)
+
+
+def test_full_size_training_set_sampled():
+    """1000 structures of 8-256 atoms, 50 individuals: two individuals vs the oracle."""
+    ls = I.labelled_set(1000, 8, 256, seed=4)
+    Z = population(50, 5)
+    got, _, _ = gpu_losses(ls, Z, cap=96)
+    for k in (0, 37):
+        ref = O.loss(OH, Z[k], ls, LAM, cap=96)
+        np.testing.assert_allclose(got[k], ref, rtol=1e-5, err_msg="individual %d" % k)
+    assert np.all(np.isfinite(got))
