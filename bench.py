@@ -59,9 +59,41 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-snes", action="store_true", help="skip the SNES generation rate")
+    ap.add_argument("--no-disordered", action="store_true",
+                    help="skip the 512,000-atom disordered heat-current run")
+    ap.add_argument("--disordered-steps", type=int, default=500)
     ap.add_argument("--snes-structures", type=int, default=1000)
     ap.add_argument("--snes-generations", type=int, default=20)
     return ap.parse_args()
+
+
+def disordered_rate(args, nep, I, torch, z):
+    """512,000-atom random Si cube at 2.33 g/cm^3: NVE steps that write the
+    per-atom virial and heat current every step."""
+    pos, box = I.disordered_cell(512000, seed=3)
+    vel = I.maxwell_boltzmann(len(pos), 300.0, seed=2)
+    ctx = nep.Context(0)
+    ctx.load_params(nep.hyper(), z)
+    p, v = nep.soa(pos), nep.soa(vel)
+    ctx.build_neighbors(p, box, skin=0.5, max_neighbors=96)
+    n = len(pos)
+    W = torch.empty((9, n), dtype=torch.float32, device="cuda")
+    J = torch.empty((3, n), dtype=torch.float32, device="cuda")
+    K = args.disordered_steps
+    thermo = torch.empty((K, 5), dtype=torch.float64, device="cuda")
+    ctx.md_step(20, 1.0, 10, I.MASS_SI, p, v, thermo, W, J)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.md_step(K, 1.0, 10, I.MASS_SI, p, v, thermo, W, J)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ctx.synchronize()
+    ms = nep.time_partials(ctx, p, reps=50)
+    return {"workload": "NVE MD of a 512,000-atom random Si cube (2.33 g/cm^3, 2.0 A minimum "
+                        "distance), per-atom W and J written every step, dt 1 fs, rebuild every "
+                        "10 steps", "atom_steps_per_s": n * K / t, "ms_per_step": t / K * 1e3,
+            "steps": K, "k_partials_us": ms * 1e3}
 
 
 def snes_rate(args, ctx, nep, I, torch):
@@ -256,6 +288,8 @@ def main():
             k: (val[0] * 1e3 / val[1] if val[1] else None) for k, val in kt.items()},
         "energy_drift_meV_per_atom": float((e_tot.max() - e_tot.min()) / n * 1e3),
     }
+    if not args.no_disordered:
+        line["disordered_512k"] = disordered_rate(args, nep, I, torch, z)
     if not args.no_snes:
         line["snes"] = snes_rate(args, ctx, nep, I, torch)
     if not args.no_cpu_baseline:

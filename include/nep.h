@@ -146,8 +146,8 @@ nep_status nep_compute(nep_ctx ctx, const double* pos_dev, const double* vel_dev
  * pos_dev, vel_dev: [3][N] float64, updated in place.  thermo_dev
  * [n_steps][5] float64 receives per step (E_pot, E_kin, sum J_x, J_y, J_z)
  * evaluated with the end-of-step velocities.  W_dev [9][N] / J_dev [3][N]
- * (float32, may be NULL) receive the per-atom virial and heat current of the
- * last step.  Requires a prior nep_build_neighbors for this system (its skin
+ * (float32, may be NULL) receive the per-atom virial and heat current at
+ * every step (so they hold the last step's on return).  Requires a prior nep_build_neighbors for this system (its skin
  * and max_neighbors are reused).  Forces of the starting positions are
  * computed first unless the previous call was nep_md_step on the same
  * buffers. */
@@ -212,6 +212,40 @@ nep_status snes_sample(nep_ctx ctx, int n_par, int n_pop, const float* m_dev, co
  * selects (3 + ln n_par) / (5 sqrt(n_par)).  1 <= n_pop <= 1024. */
 nep_status snes_update(nep_ctx ctx, int n_par, int n_pop, float* m_dev, float* s_dev,
                        const float* r_dev, const double* loss_dev, double eta_m, double eta_s);
+
+/* -------------------------------------------------------- differentiation */
+
+/* Replace the positions of a dataset's atoms (pos_dev [3][sum N] float64 on
+ * the device, same order and structures as at creation), wrap them into their
+ * cells and rebuild the lists.  NEP_EOVERFLOW if a list outgrows its capacity. */
+nep_status nep_dataset_set_positions(nep_ctx ctx, nep_dataset ds, const double* pos_dev);
+
+/* Copy the dataset's current (wrapped) positions to pos_dev [3][sum N]. */
+nep_status nep_dataset_get_positions(nep_ctx ctx, nep_dataset ds, double* pos_dev);
+
+/* Forward evaluation of one parameter vector z_dev [N_par] (float32, device)
+ * over a dataset: energy_dev [S] (E_s = sum_i U_i, float64), forces_dev
+ * [3][sum N] (float32, Sec. II A), and, unless NULL, virial_dev [S][9]
+ * (float64, sum_i W_i of each structure, row-major). */
+nep_status nep_dataset_compute(nep_ctx ctx, nep_dataset ds, const float* z_dev,
+                               double* energy_dev, float* forces_dev, double* virial_dev);
+
+/* Backward of the dataset evaluation.  With gE_dev [S] (float64, may be NULL
+ * for zero) and gF_dev [3][sum N] (float32, may be NULL for zero):
+ *   grad_z_dev [N_par] (float64) = d/dz [ sum_s gE_s E_s + sum_i gF_i . F_i ],
+ * the parameter gradient of an energy + force objective.  The force part is
+ * the mixed second derivative sum_a sum_nu d(dU_a/dq_nu)/dz delta q_a,nu with
+ * delta q_a = sum_j (dq_a/dr_aj) (gF_a - gF_j) (partial-force expressions of
+ * Sec. II D applied to gF).  Unless NULL, grad_z32_dev [N_par] receives the
+ * same values in float32 and grad_pos_dev [3][sum N] (float64) the position
+ * gradient of the energy part, -gE_s F_i, which needs forces_dev from
+ * nep_dataset_compute of the same z (the force part's position gradient,
+ * which would need second derivatives, is not computed).  Sums are float64 in
+ * a fixed order. */
+nep_status nep_dataset_backward(nep_ctx ctx, nep_dataset ds, const float* z_dev,
+                                const double* gE_dev, const float* gF_dev,
+                                const float* forces_dev, double* grad_pos_dev,
+                                double* grad_z_dev, float* grad_z32_dev);
 
 /* ----------------------------------------------------------- measurement */
 

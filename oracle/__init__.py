@@ -73,6 +73,7 @@ def lib():
         L.or_md_nve.argtypes = [H, dp, C.c_int, dp, dp, dp, C.c_double, C.c_double, C.c_int,
                                 C.c_int, dp]
         L.or_loss.argtypes = [H, dp, C.c_int, ip, dp, dp, dp, dp, dp, bp, dp, C.c_int, dp]
+        L.or_grad_params.argtypes = [H, dp, C.c_int, ip, dp, dp, dp, dp, C.c_int, dp]
         L.or_philox4x32_10.argtypes = [up, up, up]
         L.or_snes_sample.argtypes = [C.c_int, C.c_int, fp, fp, C.c_uint64, C.c_int, fp, fp]
         L.or_snes_utilities.argtypes = [C.c_int, dp]
@@ -157,11 +158,19 @@ def neighbors(pos, box, rc: float, cap: int = 256):
 
 
 # --------------------------------------------------------------------- NEP
-def nep_eval(h: Hyper, z, pos, box, vel=None, sel=None, cap: int = 256, want_q: bool = False):
+def _params(z, exact: bool):
+    """z as float64: the float32 values promoted, or (exact) as given."""
+    if exact:
+        return _d(z)
+    return _d(np.asarray(z, dtype=np.float32).astype(np.float64))
+
+
+def nep_eval(h: Hyper, z, pos, box, vel=None, sel=None, cap: int = 256, want_q: bool = False,
+             exact: bool = False):
     """Per-atom U, F, W (3x3), J and optionally q for atoms sel (default: all)."""
     pos = _d(pos)
     N = len(pos)
-    z = _d(np.asarray(z, dtype=np.float32).astype(np.float64))
+    z = _params(z, exact)
     if sel is None:
         n_sel, sel_arr = N, None
     else:
@@ -192,6 +201,15 @@ def md_nve(h: Hyper, z, pos, box, vel, mass: float, dt: float, n_steps: int, cap
     _check(lib().or_md_nve(C.byref(h), z, len(pos), pos, _d(box), vel, mass, dt, n_steps, cap,
                            thermo))
     return thermo[:n_steps], pos, vel
+
+
+def grad_params(h: Hyper, z, ds, gE, gF, cap: int = 256, exact: bool = False):
+    """d/dz of sum_s gE_s E_s + sum_i gF_i . F_i over a structure set."""
+    grad = np.zeros(n_par(h))
+    _check(lib().or_grad_params(
+        C.byref(h), _params(z, exact), len(ds.n_atoms), np.ascontiguousarray(ds.n_atoms, np.int32),
+        _d(ds.boxes), _d(ds.pos), _d(gE), _d(gF), cap, grad))
+    return grad
 
 
 def loss(h: Hyper, z, ds, lam=(1.0, 1.0, 1.0, 0.05, 0.05), cap: int = 256):

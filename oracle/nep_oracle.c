@@ -309,51 +309,83 @@ int or_neighbors(int N, const double* pos, const double* H, double rc, int cap, 
 
 /* -------------------------------------------------- NEP, per atom */
 
-/* Descriptor q (Eqs. qin, qinl), network (Eqs. nn1, nn2), dU/dq, and the
- * partial forces p_ij = dU_i/dr_ij of Sec. II D for every listed pair of
- * atom i.  p is [cnt][3].  Scratch arrays are sized by the caller. */
-static void atom_terms(const or_hyper* hp, const double* z, const double* pos, const double* H,
-                       int i, int cnt, const int* jl, const int* img, double* q, double* U,
-                       double* dUdq, double* p) {
-  const int nR = hp->n_max_radial, nA = hp->n_max_angular, lmax = hp->l_max;
-  const int ndes = or_n_des(hp), nneu = hp->n_neuron;
-  const double rcR = hp->rc_radial, rcA = hp->rc_angular;
-  double* d = (double*)malloc(sizeof(double) * 3 * (size_t)(cnt > 0 ? cnt : 1));
-  double* r = (double*)malloc(sizeof(double) * (size_t)(cnt > 0 ? cnt : 1));
-  double* gA = (double*)malloc(sizeof(double) * (nA + 1) * (size_t)(cnt > 0 ? cnt : 1));
-  double* dgA = (double*)malloc(sizeof(double) * (nA + 1) * (size_t)(cnt > 0 ? cnt : 1));
-  double g[64], dg[64], P[16], dP[16];
+/* Geometry of atom i's listed pairs: displacements d [cnt][3], distances r,
+ * and the angular radial functions g_n, g_n' with r_c^A (zero beyond it). */
+typedef struct {
+  int cnt;
+  double* d;
+  double* r;
+  double* gA;
+  double* dgA;
+} or_geom;
 
+static void geom_free(or_geom* G) {
+  free(G->d);
+  free(G->r);
+  free(G->gA);
+  free(G->dgA);
+}
+
+static int geom_build(const or_hyper* hp, const double* pos, const double* H, int i, int cnt,
+                      const int* jl, const int* img, or_geom* G) {
+  const int nA = hp->n_max_angular;
+  const size_t m = (size_t)(cnt > 0 ? cnt : 1);
+  G->cnt = cnt;
+  G->d = (double*)malloc(sizeof(double) * 3 * m);
+  G->r = (double*)malloc(sizeof(double) * m);
+  G->gA = (double*)malloc(sizeof(double) * (nA + 1) * m);
+  G->dgA = (double*)malloc(sizeof(double) * (nA + 1) * m);
+  if (!G->d || !G->r || !G->gA || !G->dgA) {
+    geom_free(G);
+    return -3;
+  }
   for (int s = 0; s < cnt; ++s) {
-    pair_displacement(pos, H, i, jl[s], img[3 * s], img[3 * s + 1], img[3 * s + 2], d + 3 * s);
-    r[s] = sqrt(norm2(d + 3 * s));
-    if (r[s] < rcA) {
-      or_radial_basis(r[s], rcA, nA, gA + (nA + 1) * s, dgA + (nA + 1) * s);
+    pair_displacement(pos, H, i, jl[s], img[3 * s], img[3 * s + 1], img[3 * s + 2], G->d + 3 * s);
+    G->r[s] = sqrt(norm2(G->d + 3 * s));
+    if (G->r[s] < hp->rc_angular) {
+      or_radial_basis(G->r[s], hp->rc_angular, nA, G->gA + (nA + 1) * s, G->dgA + (nA + 1) * s);
     } else {
-      for (int n = 0; n <= nA; ++n) gA[(nA + 1) * s + n] = dgA[(nA + 1) * s + n] = 0.0;
+      for (int n = 0; n <= nA; ++n) G->gA[(nA + 1) * s + n] = G->dgA[(nA + 1) * s + n] = 0.0;
     }
   }
+  return 0;
+}
+
+/* Descriptor q (Eqs. qin, qinl; the angular double sum includes k = j). */
+static void descriptor(const or_hyper* hp, const or_geom* G, double* q) {
+  const int nR = hp->n_max_radial, nA = hp->n_max_angular, lmax = hp->l_max;
+  const int ndes = or_n_des(hp);
+  const double rcR = hp->rc_radial, rcA = hp->rc_angular;
+  const double* d = G->d;
+  const double* r = G->r;
+  double g[64], dg[64], P[16], dP[16];
   for (int v = 0; v < ndes; ++v) q[v] = 0.0;
-  /* radial components q_n = sum_j g_n(r_ij) */
-  for (int s = 0; s < cnt; ++s) {
+  for (int s = 0; s < G->cnt; ++s) {
     if (r[s] >= rcR) continue;
     or_radial_basis(r[s], rcR, nR, g, dg);
     for (int n = 0; n <= nR; ++n) q[n] += g[n];
   }
-  /* angular components: sum over j and k (k = j included) */
-  for (int s = 0; s < cnt; ++s) {
+  for (int s = 0; s < G->cnt; ++s) {
     if (r[s] >= rcA) continue;
-    for (int t = 0; t < cnt; ++t) {
+    for (int t = 0; t < G->cnt; ++t) {
       if (r[t] >= rcA) continue;
       double c = (d[3 * s] * d[3 * t] + d[3 * s + 1] * d[3 * t + 1] + d[3 * s + 2] * d[3 * t + 2]) /
                  (r[s] * r[t]);
       or_legendre(c, lmax, P, dP);
       for (int n = 0; n <= nA; ++n)
         for (int l = 1; l <= lmax; ++l)
-          q[(nR + 1) + n * lmax + (l - 1)] += gA[(nA + 1) * s + n] * gA[(nA + 1) * t + n] * P[l];
+          q[(nR + 1) + n * lmax + (l - 1)] +=
+              G->gA[(nA + 1) * s + n] * G->gA[(nA + 1) * t + n] * P[l];
     }
   }
-  /* network */
+}
+
+/* Network (Eqs. nn1, nn2): U = sum_mu w2 tanh(a_mu) - b2 with
+ * a_mu = sum_nu w1[mu][nu] q_nu - b1[mu]; dU/dq_nu = sum_mu w2 (1 - x^2) w1[mu][nu].
+ * x (the hidden state, [N_neu]) may be NULL. */
+static void network(const or_hyper* hp, const double* z, const double* q, double* U, double* dUdq,
+                    double* x_out) {
+  const int ndes = or_n_des(hp), nneu = hp->n_neuron;
   const double* w1 = z;
   const double* b1 = z + nneu * ndes;
   const double* w2 = b1 + nneu;
@@ -364,11 +396,22 @@ static void atom_terms(const or_hyper* hp, const double* z, const double* pos, c
     double a = -b1[m];
     for (int v = 0; v < ndes; ++v) a += w1[m * ndes + v] * q[v];
     double x = tanh(a);
+    if (x_out) x_out[m] = x;
     u += w2[m] * x;
     for (int v = 0; v < ndes; ++v) dUdq[v] += w2[m] * (1.0 - x * x) * w1[m * ndes + v];
   }
   *U = u - b2;
-  /* partial forces */
+}
+
+/* Partial forces p_s = sum_nu dUdq_nu dq_nu/dr_ij for every listed pair s,
+ * from the radial and angular derivative expressions of Sec. II D. */
+static void partials(const or_hyper* hp, const or_geom* G, const double* dUdq, double* p) {
+  const int nR = hp->n_max_radial, nA = hp->n_max_angular, lmax = hp->l_max;
+  const double rcR = hp->rc_radial, rcA = hp->rc_angular;
+  const double* d = G->d;
+  const double* r = G->r;
+  const int cnt = G->cnt;
+  double g[64], dg[64], P[16], dP[16];
   for (int s = 0; s < cnt; ++s) {
     double* ps = p + 3 * s;
     ps[0] = ps[1] = ps[2] = 0.0;
@@ -386,11 +429,11 @@ static void atom_terms(const or_hyper* hp, const double* z, const double* pos, c
         double ut[3] = {d[3 * t] / r[t], d[3 * t + 1] / r[t], d[3 * t + 2] / r[t]};
         /* same cosine expression as the descriptor sum */
         double c = (d[3 * s] * d[3 * t] + d[3 * s + 1] * d[3 * t + 1] + d[3 * s + 2] * d[3 * t + 2]) /
-            (r[s] * r[t]);
+                   (r[s] * r[t]);
         or_legendre(c, lmax, P, dP);
         for (int n = 0; n <= nA; ++n) {
-          double gs = gA[(nA + 1) * s + n], dgs = dgA[(nA + 1) * s + n];
-          double gt = gA[(nA + 1) * t + n];
+          double gs = G->gA[(nA + 1) * s + n], dgs = G->dgA[(nA + 1) * s + n];
+          double gt = G->gA[(nA + 1) * t + n];
           for (int l = 1; l <= lmax; ++l) {
             double w = dUdq[(nR + 1) + n * lmax + (l - 1)];
             double a1 = 2.0 * dgs * gt * P[l];
@@ -401,10 +444,18 @@ static void atom_terms(const or_hyper* hp, const double* z, const double* pos, c
       }
     }
   }
-  free(d);
-  free(r);
-  free(gA);
-  free(dgA);
+}
+
+/* Descriptor, network and partial forces of atom i (p is [cnt][3]). */
+static void atom_terms(const or_hyper* hp, const double* z, const double* pos, const double* H,
+                       int i, int cnt, const int* jl, const int* img, double* q, double* U,
+                       double* dUdq, double* p) {
+  or_geom G;
+  if (geom_build(hp, pos, H, i, cnt, jl, img, &G)) return;
+  descriptor(hp, &G, q);
+  network(hp, z, q, U, dUdq, NULL);
+  partials(hp, &G, dUdq, p);
+  geom_free(&G);
 }
 
 /* Index of the reverse pair (j -> i, image -n) in atom j's list, or -1. */
@@ -511,6 +562,110 @@ int or_nep_eval(const or_hyper* hp, const double* z, int N, const double* pos, c
   free(need);
   list_free(&L);
   return missing ? -2 : 0;
+}
+
+/* ------------------------------------------------- parameter gradient */
+
+/* Gradient with respect to z of
+ *   G(z) = sum_s gE[s] E_s(z) + sum_i gF_i . F_i(z)
+ * over a set of structures laid out as in or_loss (gF is [sum N][3]).
+ * Energy part: dU_a/dz from Eqs. nn1, nn2.  Force part: by Sec. II A,
+ * sum_i gF_i . F_i = sum over listed pairs (a, j) of p_aj . (gF_a - gF_j), and
+ * p_aj = sum_nu dU_a/dq_nu dq_nu/dr_aj, where dq_nu/dr_aj is evaluated with
+ * the partial-force expressions of Sec. II D for a unit vector dU/dq = e_nu;
+ * only dU_a/dq_nu depends on z, through the network.
+ * Returns 0 or a negative error code. */
+int or_grad_params(const or_hyper* hp, const double* z, int n_struct, const int* n_atoms,
+                   const double* boxes, const double* pos, const double* gE, const double* gF,
+                   int cap, double* grad) {
+  const int ndes = or_n_des(hp), nneu = hp->n_neuron, npar = or_n_par(hp);
+  const double* w1 = z;
+  const double* w2 = z + nneu * ndes + nneu;
+  const double rc = hp->rc_radial > hp->rc_angular ? hp->rc_radial : hp->rc_angular;
+  for (int k = 0; k < npar; ++k) grad[k] = 0.0;
+  size_t off = 0;
+  int status = 0;
+  for (int st = 0; st < n_struct && status == 0; ++st) {
+    const int n = n_atoms[st];
+    const double* P = pos + 3 * off;
+    const double* H = boxes + 9 * st;
+    const double* gFs = gF + 3 * off;
+    unsigned char* need = (unsigned char*)malloc((size_t)n);
+    if (!need) return -3;
+    memset(need, 1, (size_t)n);
+    or_list L;
+    int rcode = build_list(n, P, H, rc, need, cap, &L);
+    free(need);
+    if (rcode) {
+      if (rcode != -3) list_free(&L);
+      return rcode;
+    }
+#pragma omp parallel
+    {
+      double q[256], dUdq[256], x[4096], v[256], e[256];
+      double* mine = (double*)calloc((size_t)npar, sizeof(double));
+      double* gw1 = mine;
+      double* gb1 = mine + nneu * ndes;
+      double* gw2 = gb1 + nneu;
+      double* gb2 = gw2 + nneu;
+#pragma omp for schedule(static)
+      for (int a = 0; a < n; ++a) {
+        or_geom G;
+        const int cnt = L.cnt[a];
+        const int* jl = L.j + (size_t)a * cap;
+        double* D = (double*)malloc(sizeof(double) * 3 * (size_t)(cnt > 0 ? cnt : 1));
+        if (!mine || !D || geom_build(hp, P, H, a, cnt, jl, L.img + (size_t)a * cap * 3, &G)) {
+          free(D);
+#pragma omp atomic write
+          status = -3;
+          continue;
+        }
+        double U;
+        descriptor(hp, &G, q);
+        network(hp, z, q, &U, dUdq, x);
+        /* energy part */
+        for (int m = 0; m < nneu; ++m) {
+          const double sm = 1.0 - x[m] * x[m];
+          for (int nu = 0; nu < ndes; ++nu) gw1[m * ndes + nu] += gE[st] * w2[m] * sm * q[nu];
+          gb1[m] += gE[st] * (-w2[m] * sm);
+          gw2[m] += gE[st] * x[m];
+        }
+        gb2[0] += -gE[st];
+        /* force part: v_nu = sum over pairs of dq_nu/dr_aj . (gF_a - gF_j) */
+        for (int nu = 0; nu < ndes; ++nu) {
+          for (int k = 0; k < ndes; ++k) e[k] = k == nu ? 1.0 : 0.0;
+          partials(hp, &G, e, D);
+          double acc = 0.0;
+          for (int sl = 0; sl < cnt; ++sl) {
+            const int j = jl[sl];
+            for (int c = 0; c < 3; ++c) acc += D[3 * sl + c] * (gFs[3 * a + c] - gFs[3 * j + c]);
+          }
+          v[nu] = acc;
+        }
+        free(D);
+        /* d(dU_a/dq_nu)/dz contracted with v */
+        for (int m = 0; m < nneu; ++m) {
+          const double sm = 1.0 - x[m] * x[m];
+          double wv = 0.0;
+          for (int nu = 0; nu < ndes; ++nu) wv += w1[m * ndes + nu] * v[nu];
+          gw2[m] += sm * wv;
+          gb1[m] += 2.0 * w2[m] * x[m] * sm * wv;
+          for (int kap = 0; kap < ndes; ++kap)
+            gw1[m * ndes + kap] += w2[m] * (-2.0 * x[m] * sm * q[kap] * wv + sm * v[kap]);
+        }
+        geom_free(&G);
+      }
+#pragma omp critical
+      {
+        if (mine)
+          for (int k = 0; k < npar; ++k) grad[k] += mine[k];
+      }
+      free(mine);
+    }
+    list_free(&L);
+    off += (size_t)n;
+  }
+  return status;
 }
 
 /* --------------------------------------------------- molecular dynamics */

@@ -290,12 +290,10 @@ nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every
       ctx->steps_since_rebuild = 0;
     }
     e = timed(ctx, 0, [&] { return launch_partials(ctx, pos_dev); });
-    const bool last = step == n_steps - 1;
     if (e == hipSuccess)
       e = timed(ctx, 1, [&] {
-        return launch_gather(ctx, pos_dev, vel_dev, nullptr, ctx->F.ptr, last ? W_dev : nullptr,
-                             last ? J_dev : nullptr, thermo_dev + (size_t)5 * step, 1, kick,
-                             mass_amu);
+        return launch_gather(ctx, pos_dev, vel_dev, nullptr, ctx->F.ptr, W_dev, J_dev,
+                             thermo_dev + (size_t)5 * step, 1, kick, mass_amu);
       });
     if (e != hipSuccess) return check_hip(ctx, e, "launching force kernels");
   }

@@ -183,8 +183,11 @@ struct nep_dataset_s {
   nep::DevBuf<float4> pin;          // [pop][cap][N]
   nep::DevBuf<float> fown;          // [pop][3][N]
   nep::DevBuf<float> U;             // [pop][N]
-  nep::DevBuf<double> atom_terms;   // [pop][8][N]
+  nep::DevBuf<double> atom_terms;   // [pop][8][N] (loss) or [10][N] (forward)
   nep::DevBuf<double> struct_sq;    // [pop][S][3]
+  // backward workspace
+  nep::DevBuf<float> grad_rec;      // [fields][N]
+  nep::DevBuf<double> grad_part;    // [blocks][N_par]
 };
 
 namespace nep {
@@ -212,6 +215,11 @@ size_t gather_blocks(int n);
 hipError_t launch_kick_drift(nep_ctx ctx, double* pos, double* vel, double kick, double dt);
 // pass 1 over a dataset for n_pop parameter vectors Z [n_pop][n_par].
 hipError_t launch_partials_population(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z);
+
+// backward.hip: parameter (and energy-part position) gradient over a dataset.
+hipError_t launch_backward(nep_ctx ctx, nep_dataset ds, const float* z, const double* gE,
+                           const float* gF, const float* F, double* gpos, double* grad,
+                           float* grad32);
 
 // Launch a kernel on the context's stream.  When a timed kernel class is
 // being launched, its first kernel carries the start event and its last

@@ -118,12 +118,15 @@ __global__ __launch_bounds__(256) void k_ds_build(
 // W_i = sum_j r_ij (x) p_ji from the individual's partials, then the per-atom
 // loss terms (U_i, |F_i - F_i^tar|^2, W_i xx yy zz xy yz zx) in float64 at
 // terms[(8k + q) N + i].
-template <int L>
+// MODE 1 instead writes the forces to F_out [3][N] and the terms
+// (U_i, W_i row-major 9) at terms[q N + i] (one individual).
+template <int L, int MODE>
 __global__ __launch_bounds__(kBlock) void k_ds_gather(
     int N, int cap, const double* __restrict__ pos, const double* __restrict__ boxes,
     const int* __restrict__ struct_of, const uint32_t* __restrict__ nl,
     const int* __restrict__ cnt_r, const float4* __restrict__ pin, const float* __restrict__ fown,
-    const float* __restrict__ U, const double* __restrict__ f_tar, double* __restrict__ terms) {
+    const float* __restrict__ U, const double* __restrict__ f_tar, double* __restrict__ terms,
+    float* __restrict__ F_out) {
   const size_t pk = blockIdx.y;
   pin += pk * (size_t)cap * N;
   fown += pk * 3 * (size_t)N;
@@ -165,7 +168,15 @@ __global__ __launch_bounds__(kBlock) void k_ds_gather(
   f2 = group_sum<L>(f2);
 #pragma unroll
   for (int q = 0; q < 9; ++q) w[q] = group_sum<L>(w[q]);
-  if (active && lane == 0) {
+  if (MODE == 1 && active && lane == 0) {
+    F_out[i] = f0 + fown[i];
+    F_out[N + i] = f1 + fown[N + i];
+    F_out[2 * N + i] = f2 + fown[2 * N + i];
+    terms[i] = (double)U[i];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) terms[(size_t)(1 + q) * N + i] = (double)w[q];
+  }
+  if (MODE == 0 && active && lane == 0) {
     const double F0 = (double)(f0 + fown[i]) - f_tar[i];
     const double F1 = (double)(f1 + fown[N + i]) - f_tar[N + i];
     const double F2 = (double)(f2 + fown[2 * N + i]) - f_tar[2 * N + i];
@@ -216,6 +227,25 @@ __global__ __launch_bounds__(kBlock) void k_ds_struct(
     o[1] = tot[1];
     o[2] = dv;
   }
+}
+
+// Per structure s = blockIdx.x: energy[s] = sum U_i and, unless NULL,
+// virial[s][9] = sum W_i over the structure's atoms (forward terms layout).
+__global__ __launch_bounds__(kBlock) void k_ds_totals(int N, const int* __restrict__ off,
+                                                      const double* __restrict__ terms,
+                                                      double* __restrict__ energy,
+                                                      double* __restrict__ virial) {
+  __shared__ double sw[kBlock / 64][10];
+  const int s = blockIdx.x;
+  double acc[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) acc[q] = 0.0;
+  for (int a = off[s] + threadIdx.x; a < off[s + 1]; a += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < 10; ++q) acc[q] += terms[(size_t)q * N + a];
+  const double v = block_sum<10>(acc, sw);
+  if (threadIdx.x == 0) energy[s] = v;
+  if (virial && threadIdx.x >= 1 && threadIdx.x < 10) virial[9 * (size_t)s + threadIdx.x - 1] = v;
 }
 
 // Per individual k = blockIdx.x: loss[k][6] = (L, L_e, L_f, L_v, L_1, L_2).
@@ -367,6 +397,29 @@ void invert_box(const double* H, double* Hi) {
   Hi[8] = (a * e - b * d) / det;
 }
 
+// Wrap the dataset's positions and build its lists and reverse slots.
+hipError_t build_dataset_lists(nep_ctx ctx, nep_dataset ds) {
+  const int N = ds->N;
+  hipStream_t st = ctx->stream;
+  k_ds_wrap<<<blocks_for(N, kBlock), kBlock, 0, st>>>(N, ds->pos.ptr, ds->boxes.ptr,
+                                                      ds->boxinv.ptr, ds->struct_of.ptr,
+                                                      ds->wrap.ptr);
+  k_ds_build<<<blocks_for((size_t)N * 64, 256), 256, 0, st>>>(
+      N, ds->cap, ds->pos.ptr, ds->boxes.ptr, ds->struct_of.ptr, ds->off.ptr, ds->kimg.ptr,
+      ds->wrap.ptr, ds->rc_r * ds->rc_r, ds->rc_a * ds->rc_a, ds->nl.ptr, ds->cnt_r.ptr,
+      ds->cnt_a.ptr, ctx->flags.ptr);
+  launch_reverse(ctx, N, ds->cap, ds->nl.ptr, ds->cnt_r.ptr, ds->cnt_a.ptr, ds->rev.ptr);
+  return hipGetLastError();
+}
+
+nep_status check_dataset(nep_ctx ctx, nep_dataset ds) {
+  if (!ds || ds->ctx != ctx) return fail(ctx, NEP_EINVAL, "dataset belongs to another context");
+  if (!ctx->have_params) return fail(ctx, NEP_ESTATE, "nep_load_params must come first");
+  if (ds->rc_r != ctx->hyper.rc_radial || ds->rc_a != ctx->hyper.rc_angular)
+    return fail(ctx, NEP_ESTATE, "dataset lists were built for other cutoffs");
+  return NEP_OK;
+}
+
 }  // namespace
 }  // namespace nep
 
@@ -465,18 +518,7 @@ nep_status nep_dataset_create(nep_ctx ctx, int n_struct, const int* n_atoms_host
   up(ds->f_tar.ptr, ftT.data(), sizeof(double) * 3 * N);
   up(ds->w_tar.ptr, virial_host, sizeof(double) * 6 * S);
   up(ds->has_v.ptr, hv.data(), sizeof(int) * S);
-  if (e == hipSuccess) {
-    k_ds_wrap<<<blocks_for(N, kBlock), kBlock, 0, st>>>(N, ds->pos.ptr, ds->boxes.ptr,
-                                                        ds->boxinv.ptr, ds->struct_of.ptr,
-                                                        ds->wrap.ptr);
-    const double rl = rc_r, ra = rc_a;
-    k_ds_build<<<blocks_for((size_t)N * 64, 256), 256, 0, st>>>(
-        N, max_neighbors, ds->pos.ptr, ds->boxes.ptr, ds->struct_of.ptr, ds->off.ptr,
-        ds->kimg.ptr, ds->wrap.ptr, rl * rl, ra * ra, ds->nl.ptr, ds->cnt_r.ptr, ds->cnt_a.ptr,
-        ctx->flags.ptr);
-    launch_reverse(ctx, N, max_neighbors, ds->nl.ptr, ds->cnt_r.ptr, ds->cnt_a.ptr, ds->rev.ptr);
-    e = hipGetLastError();
-  }
+  if (e == hipSuccess) e = build_dataset_lists(ctx, ds);
   if (e != hipSuccess) {
     nep_dataset_destroy(ds);
     return check_hip(ctx, e, "creating the dataset");
@@ -515,16 +557,88 @@ void nep_dataset_destroy(nep_dataset ds) {
   ds->U.release();
   ds->atom_terms.release();
   ds->struct_sq.release();
+  ds->grad_rec.release();
+  ds->grad_part.release();
   delete ds;
+}
+
+nep_status nep_dataset_set_positions(nep_ctx ctx, nep_dataset ds, const double* pos_dev) {
+  if (!ctx) return NEP_EINVAL;
+  if (!ds || ds->ctx != ctx) return fail(ctx, NEP_EINVAL, "dataset belongs to another context");
+  if (!pos_dev) return fail(ctx, NEP_EINVAL, "pos_dev is NULL");
+  DeviceGuard guard(ctx->device);
+  hipError_t e = hipMemcpyAsync(ds->pos.ptr, pos_dev, sizeof(double) * 3 * ds->N,
+                                hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = build_dataset_lists(ctx, ds);
+  if (e != hipSuccess) return check_hip(ctx, e, "rebuilding dataset lists");
+  return nep_synchronize(ctx);
+}
+
+nep_status nep_dataset_get_positions(nep_ctx ctx, nep_dataset ds, double* pos_dev) {
+  if (!ctx) return NEP_EINVAL;
+  if (!ds || ds->ctx != ctx) return fail(ctx, NEP_EINVAL, "dataset belongs to another context");
+  if (!pos_dev) return fail(ctx, NEP_EINVAL, "pos_dev is NULL");
+  DeviceGuard guard(ctx->device);
+  return check_hip(ctx,
+                   hipMemcpyAsync(pos_dev, ds->pos.ptr, sizeof(double) * 3 * ds->N,
+                                  hipMemcpyDeviceToDevice, ctx->stream),
+                   "copying dataset positions");
+}
+
+nep_status nep_dataset_compute(nep_ctx ctx, nep_dataset ds, const float* z_dev,
+                               double* energy_dev, float* forces_dev, double* virial_dev) {
+  if (!ctx) return NEP_EINVAL;
+  nep_status chk = check_dataset(ctx, ds);
+  if (chk != NEP_OK) return chk;
+  if (!z_dev || !energy_dev || !forces_dev) return fail(ctx, NEP_EINVAL, "NULL argument");
+  const int N = ds->N, S = ds->S;
+  DeviceGuard guard(ctx->device);
+  hipError_t e = ds->pin.ensure((size_t)ds->cap * N);
+  if (e == hipSuccess) e = ds->fown.ensure((size_t)3 * N);
+  if (e == hipSuccess) e = ds->U.ensure((size_t)N);
+  if (e == hipSuccess) e = ds->atom_terms.ensure((size_t)10 * N);
+  if (e != hipSuccess) return check_hip(ctx, e, "allocating dataset workspace");
+  e = timed(ctx, 0, [&] { return launch_partials_population(ctx, ds, 1, z_dev); });
+  if (e == hipSuccess)
+    e = timed(ctx, 1, [&] {
+      launch_kernel(ctx, true, false, k_ds_gather<kLanes, 1>,
+                    dim3(blocks_for((size_t)N * kLanes, kBlock), 1), dim3(kBlock), N, ds->cap,
+                    (const double*)ds->pos.ptr, (const double*)ds->boxes.ptr,
+                    (const int*)ds->struct_of.ptr, (const uint32_t*)ds->nl.ptr,
+                    (const int*)ds->cnt_r.ptr, (const float4*)ds->pin.ptr,
+                    (const float*)ds->fown.ptr, (const float*)ds->U.ptr, (const double*)nullptr,
+                    ds->atom_terms.ptr, forces_dev);
+      launch_kernel(ctx, false, true, k_ds_totals, dim3(S), dim3(kBlock), N,
+                    (const int*)ds->off.ptr, (const double*)ds->atom_terms.ptr, energy_dev,
+                    virial_dev);
+      return hipGetLastError();
+    });
+  return check_hip(ctx, e, "launching dataset forward");
+}
+
+nep_status nep_dataset_backward(nep_ctx ctx, nep_dataset ds, const float* z_dev,
+                                const double* gE_dev, const float* gF_dev,
+                                const float* forces_dev, double* grad_pos_dev,
+                                double* grad_z_dev, float* grad_z32_dev) {
+  if (!ctx) return NEP_EINVAL;
+  nep_status chk = check_dataset(ctx, ds);
+  if (chk != NEP_OK) return chk;
+  if (!z_dev || !grad_z_dev) return fail(ctx, NEP_EINVAL, "z_dev and grad_z_dev are required");
+  if (grad_pos_dev && !forces_dev)
+    return fail(ctx, NEP_EINVAL, "grad_pos_dev needs forces_dev from nep_dataset_compute");
+  DeviceGuard guard(ctx->device);
+  hipError_t e = timed(ctx, 0, [&] {
+    return launch_backward(ctx, ds, z_dev, gE_dev, gF_dev, forces_dev, grad_pos_dev, grad_z_dev,
+                           grad_z32_dev);
+  });
+  return check_hip(ctx, e, "launching the backward pass");
 }
 
 nep_status snes_eval_population(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z_dev,
                                 const double* lambda_host, double* loss_dev) {
   if (!ctx) return NEP_EINVAL;
-  if (!ds || ds->ctx != ctx) return fail(ctx, NEP_EINVAL, "dataset belongs to another context");
-  if (!ctx->have_params) return fail(ctx, NEP_ESTATE, "nep_load_params must come first");
-  if (ds->rc_r != ctx->hyper.rc_radial || ds->rc_a != ctx->hyper.rc_angular)
-    return fail(ctx, NEP_ESTATE, "dataset lists were built for other cutoffs");
+  nep_status chk = check_dataset(ctx, ds);
+  if (chk != NEP_OK) return chk;
   if (n_pop < 1 || n_pop > 65535) return fail(ctx, NEP_EINVAL, "n_pop must be in [1, 65535]");
   if (!Z_dev || !lambda_host || !loss_dev) return fail(ctx, NEP_EINVAL, "NULL argument");
   const int N = ds->N, S = ds->S;
@@ -538,13 +652,13 @@ nep_status snes_eval_population(nep_ctx ctx, nep_dataset ds, int n_pop, const fl
   e = timed(ctx, 0, [&] { return launch_partials_population(ctx, ds, n_pop, Z_dev); });
   if (e == hipSuccess)
     e = timed(ctx, 1, [&] {
-      launch_kernel(ctx, true, false, k_ds_gather<kLanes>,
+      launch_kernel(ctx, true, false, k_ds_gather<kLanes, 0>,
                     dim3(blocks_for((size_t)N * kLanes, kBlock), n_pop), dim3(kBlock), N, ds->cap,
                     (const double*)ds->pos.ptr, (const double*)ds->boxes.ptr,
                     (const int*)ds->struct_of.ptr, (const uint32_t*)ds->nl.ptr,
                     (const int*)ds->cnt_r.ptr, (const float4*)ds->pin.ptr,
                     (const float*)ds->fown.ptr, (const float*)ds->U.ptr,
-                    (const double*)ds->f_tar.ptr, ds->atom_terms.ptr);
+                    (const double*)ds->f_tar.ptr, ds->atom_terms.ptr, (float*)nullptr);
       launch_kernel(ctx, false, false, k_ds_struct, dim3(S, n_pop), dim3(kBlock), N, S,
                     (const int*)ds->off.ptr, (const double*)ds->atom_terms.ptr,
                     (const double*)ds->e_tar.ptr, (const double*)ds->w_tar.ptr,

@@ -116,77 +116,71 @@ def random_packing(n_atoms: int, box_length: float, d_min: float, seed: int,
                    batch: int = 65536) -> np.ndarray:
     """Uniform random points in a periodic cube, no two closer than d_min.
 
-    Candidates are drawn in batches and accepted in draw order: a candidate is
-    kept iff it is at least d_min away (minimum image) from every atom kept
-    before it.  The result depends only on the seed.
+    Candidates are drawn uniformly in batches.  A candidate is kept iff it is
+    at least d_min away (minimum image) from every atom kept before its batch
+    and from every earlier candidate of its batch that passed that first test.
+    Kept candidates are appended in draw order until n_atoms are placed.  The
+    result depends only on the seed.
     """
     rng = np.random.default_rng(seed)
     L = float(box_length)
     ncell = max(3, int(L // d_min))
     cw = L / ncell
-    cap = 8
+    cap = 5  # cells are about d_min wide; more than 5 members raises
     grid = -np.ones((ncell, ncell, ncell, cap), dtype=np.int64)
     fill = np.zeros((ncell, ncell, ncell), dtype=np.int64)
     pos = np.empty((n_atoms, 3), dtype=np.float64)
     n = 0
     d2min = d_min * d_min
     offs = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
+
+    def clashes(points, cells, g, pts, earlier_only):
+        """True where a point has a grid member closer than d_min."""
+        hit = np.zeros(len(points), dtype=bool)
+        me = np.arange(len(points))
+        for o in offs:
+            c = (cells + o) % ncell
+            ids = g[c[:, 0], c[:, 1], c[:, 2]]
+            valid = ids >= 0
+            if earlier_only:
+                valid &= ids < me[:, None]
+            p = pts[np.where(valid, ids, 0)]
+            d = p - points[:, None, :]
+            d -= L * np.round(d / L)
+            hit |= np.any(valid & (np.sum(d * d, axis=-1) < d2min), axis=1)
+        return hit
+
+    def ranks_in_cells(cells):
+        """Order of points by cell (then by index) and each point's rank in its cell."""
+        order = np.lexsort((np.arange(len(cells)), cells[:, 2], cells[:, 1], cells[:, 0]))
+        key = (cells[order, 0] * ncell + cells[order, 1]) * ncell + cells[order, 2]
+        rank = np.arange(len(key)) - np.searchsorted(key, key, side="left")
+        return order, rank
+
+    sgrid = -np.ones((ncell, ncell, ncell, cap), dtype=np.int64)
     while n < n_atoms:
         cand = rng.random((batch, 3)) * L
         cc = np.minimum((cand // cw).astype(np.int64), ncell - 1)
-        ok = np.ones(batch, dtype=bool)
-        # test against atoms already placed
-        for o in offs:
-            c = (cc + o) % ncell
-            ids = grid[c[:, 0], c[:, 1], c[:, 2]]  # [batch, cap]
-            valid = ids >= 0
-            p = pos[np.where(valid, ids, 0)]
-            d = p - cand[:, None, :]
-            d -= L * np.round(d / L)
-            r2 = np.sum(d * d, axis=-1)
-            ok &= ~np.any(valid & (r2 < d2min), axis=1)
-        idx = np.nonzero(ok)[0]
-        # resolve conflicts among this batch's survivors in draw order
-        cand_ok = cand[idx]
-        keep = []
-        kept_pos = []
-        if len(idx):
-            # bucket survivors to find close pairs quickly
-            cidx = cc[idx]
-            buckets: dict = {}
-            for t, c in enumerate(map(tuple, cidx)):
-                buckets.setdefault(c, []).append(t)
-            accepted = np.zeros(len(idx), dtype=bool)
-            for t in range(len(idx)):
-                c = cidx[t]
-                clash = False
-                for o in offs:
-                    key = tuple((c + o) % ncell)
-                    for u in buckets.get(key, ()):
-                        if u >= t or not accepted[u]:
-                            continue
-                        d = cand_ok[u] - cand_ok[t]
-                        d -= L * np.round(d / L)
-                        if float(d @ d) < d2min:
-                            clash = True
-                            break
-                    if clash:
-                        break
-                if not clash:
-                    accepted[t] = True
-            keep = idx[accepted]
-            kept_pos = cand[keep]
-        take = min(len(keep), n_atoms - n)
-        for t in range(take):
-            p = kept_pos[t]
-            c = cc[keep[t]]
-            f = fill[c[0], c[1], c[2]]
-            if f >= cap:
-                raise RuntimeError("packing grid cell overflow")
-            grid[c[0], c[1], c[2], f] = n
-            fill[c[0], c[1], c[2]] = f + 1
-            pos[n] = p
-            n += 1
+        ok = ~clashes(cand, cc, grid, pos, False)
+        surv = cand[ok]
+        sc = cc[ok]
+        # survivors of this batch binned by cell; earlier survivors win
+        order, rank = ranks_in_cells(sc)
+        if len(rank) and rank.max() >= cap:
+            raise RuntimeError("packing grid cell overflow")
+        sgrid[sc[order, 0], sc[order, 1], sc[order, 2], rank] = order
+        keep = ~clashes(surv, sc, sgrid, surv, True)
+        sgrid[sc[:, 0], sc[:, 1], sc[:, 2], :] = -1
+        kept = surv[keep][: n_atoms - n]
+        kc = sc[keep][: n_atoms - n]
+        order, rank = ranks_in_cells(kc)
+        slot = fill[kc[order, 0], kc[order, 1], kc[order, 2]] + rank
+        if len(slot) and slot.max() >= cap:
+            raise RuntimeError("packing grid cell overflow")
+        grid[kc[order, 0], kc[order, 1], kc[order, 2], slot] = n + order
+        np.add.at(fill, (kc[:, 0], kc[:, 1], kc[:, 2]), 1)
+        pos[n:n + len(kept)] = kept
+        n += len(kept)
     return pos
 
 

@@ -26,7 +26,8 @@ EXPORTED = [
     "nep_num_descriptors", "nep_num_params", "nep_load_params", "nep_build_neighbors",
     "nep_get_neighbors", "nep_compute", "nep_md_step", "nep_set_timing", "nep_get_timing",
     "nep_time_partials", "nep_dataset_create", "nep_dataset_destroy", "snes_eval_population",
-    "snes_sample", "snes_update",
+    "snes_sample", "snes_update", "nep_dataset_set_positions", "nep_dataset_get_positions",
+    "nep_dataset_compute", "nep_dataset_backward",
 ]
 
 
@@ -83,6 +84,10 @@ def lib() -> C.CDLL:
         L.snes_eval_population.argtypes = [vp, vp, ip, vp, vp, vp]
         L.snes_sample.argtypes = [vp, ip, ip, vp, vp, C.c_ulonglong, ip, vp, vp]
         L.snes_update.argtypes = [vp, ip, ip, vp, vp, vp, vp, dp, dp]
+        L.nep_dataset_set_positions.argtypes = [vp, vp, vp]
+        L.nep_dataset_get_positions.argtypes = [vp, vp, vp]
+        L.nep_dataset_compute.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.nep_dataset_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         for name in EXPORTED:
             if name not in ("nep_destroy", "nep_last_error", "nep_num_descriptors",
                             "nep_num_params", "nep_dataset_destroy"):
@@ -250,6 +255,43 @@ class Context:
         self._check(self._lib.snes_update(self._h, n_par, n_pop, _ptr(m), _ptr(s), _ptr(r),
                                           _ptr(loss), eta_m, eta_s))
 
+    def dataset_positions(self, ds: "Dataset") -> torch.Tensor:
+        out = torch.empty((3, ds.n_atoms), dtype=torch.float64,
+                          device=torch.device("cuda", self.device))
+        self._check(self._lib.nep_dataset_get_positions(self._h, ds._h, _ptr(out)))
+        return out
+
+    def dataset_set_positions(self, ds: "Dataset", pos: torch.Tensor) -> None:
+        _require(pos, torch.float64, (3, ds.n_atoms), "pos")
+        self._check(self._lib.nep_dataset_set_positions(self._h, ds._h, _ptr(pos)))
+
+    def dataset_compute(self, ds: "Dataset", z: torch.Tensor, virial: bool = False) -> dict:
+        _require(z, torch.float32, None, "z")
+        dev = z.device
+        out = {"E": torch.empty(ds.n_struct, dtype=torch.float64, device=dev),
+               "F": torch.empty((3, ds.n_atoms), dtype=torch.float32, device=dev)}
+        if virial:
+            out["W"] = torch.empty((ds.n_struct, 9), dtype=torch.float64, device=dev)
+        self._check(self._lib.nep_dataset_compute(self._h, ds._h, _ptr(z), _ptr(out["E"]),
+                                                  _ptr(out["F"]), _ptr(out.get("W"))))
+        return out
+
+    def dataset_backward(self, ds: "Dataset", z: torch.Tensor, gE=None, gF=None, F=None,
+                         want_pos: bool = False) -> dict:
+        dev = z.device
+        if gE is not None:
+            _require(gE, torch.float64, (ds.n_struct,), "gE")
+        if gF is not None:
+            _require(gF, torch.float32, (3, ds.n_atoms), "gF")
+        out = {"z": torch.empty(z.shape[0], dtype=torch.float64, device=dev),
+               "z32": torch.empty(z.shape[0], dtype=torch.float32, device=dev)}
+        if want_pos:
+            out["pos"] = torch.empty((3, ds.n_atoms), dtype=torch.float64, device=dev)
+        self._check(self._lib.nep_dataset_backward(
+            self._h, ds._h, _ptr(z), _ptr(gE), _ptr(gF), _ptr(F), _ptr(out.get("pos")),
+            _ptr(out["z"]), _ptr(out["z32"])))
+        return out
+
     def md_step(self, n_steps: int, dt: float, rebuild_every: int, mass: float,
                 pos: torch.Tensor, vel: torch.Tensor, thermo: torch.Tensor | None = None,
                 W: torch.Tensor | None = None, J: torch.Tensor | None = None) -> torch.Tensor:
@@ -268,6 +310,7 @@ class Dataset:
 
     def __init__(self, ctx: Context, handle, n_struct: int, n_atoms: int):
         self.ctx, self._h, self.n_struct, self.n_atoms = ctx, handle, n_struct, n_atoms
+        self._pos_key = None  # (data pointer, version) of the positions last uploaded
 
     def close(self):
         if getattr(self, "_h", None):
@@ -279,6 +322,40 @@ class Dataset:
             self.close()
         except Exception:
             pass
+
+
+class NEPEnergy(torch.autograd.Function):
+    """Energies and forces of a dataset's structures as a differentiable function.
+
+    ``E, F = NEPEnergy.apply(pos, z, ctx, ds)`` with pos [3][N] float64 (the
+    dataset's atoms) and z [N_par] float32.  E is [S] float64 (structure
+    energies), F is [3][N] float32.  The backward pass runs the library's
+    hand-written gradient: dG/dz for G = sum gE.E + sum gF.F, and the position
+    gradient of the energy part, -gE F.  The position gradient of the force
+    part would need second derivatives of U and raises NotImplementedError.
+    """
+
+    @staticmethod
+    def forward(actx, pos, z, ctx, ds):
+        if ds._pos_key != (pos.data_ptr(), pos._version):
+            ctx.dataset_set_positions(ds, pos.detach())
+            ds._pos_key = (pos.data_ptr(), pos._version)
+        out = ctx.dataset_compute(ds, z.detach())
+        actx.save_for_backward(z, out["F"])
+        actx.nep = (ctx, ds)
+        actx.pos_needs_grad = pos.requires_grad
+        return out["E"], out["F"]
+
+    @staticmethod
+    def backward(actx, gE, gF):
+        z, F = actx.saved_tensors
+        ctx, ds = actx.nep
+        gE = None if gE is None else gE.detach().contiguous()
+        gF = None if gF is None else gF.detach().contiguous()
+        if gF is not None and actx.pos_needs_grad and bool(gF.abs().max() > 0):
+            raise NotImplementedError("position gradient of the force part needs the Hessian")
+        g = ctx.dataset_backward(ds, z.detach(), gE, gF, F, want_pos=actx.pos_needs_grad)
+        return g.get("pos"), g["z32"], None, None
 
 
 KERNEL_CLASSES = ("partials", "gather", "neighbors", "integrator")

@@ -1,0 +1,138 @@
+"""The differentiable dataset evaluation (torch.autograd.Function over the C
+ABI): energies and forces against the oracle, the hand-written parameter
+gradient of an energy + force objective against the oracle's float64
+gradient (itself pinned by finite differences), and the position gradient
+of the energy part (-gE F)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2107_08119_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+OH = O.hyper()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def oracle_forward(z, ls):
+    E, F = [], []
+    off = 0
+    for s, n in enumerate(ls.n_atoms):
+        out = O.nep_eval(OH, z, ls.pos[off:off + n], ls.boxes[s].reshape(3, 3))
+        E.append(out["U"].sum())
+        F.append(out["F"])
+        off += n
+    return np.array(E), np.concatenate(F)
+
+
+def setup(ls, z, cap=200):
+    import torch
+    from paper_2107_08119_amd import nep
+    ctx = nep.Context(0)
+    ctx.load_params(nep.hyper(), z)
+    ds = ctx.dataset_create(ls, max_neighbors=cap)
+    return ctx, ds, torch.from_numpy(z).cuda()
+
+
+def test_dataset_forward_matches_oracle():
+    ls = I.labelled_set(6, 64, 160, seed=41)
+    z = I.random_parameters(931, 7)
+    ctx, ds, zt = setup(ls, z)
+    out = ctx.dataset_compute(ds, zt, virial=True)
+    ctx.synchronize()
+    E_ref, F_ref = oracle_forward(z, ls)
+    assert rel(out["E"].cpu().numpy(), E_ref) < 1e-5
+    F = out["F"].cpu().numpy().T  # dataset order: positions were wrapped, forces are not affected
+    assert rel(F, F_ref) < 1e-5
+
+
+def test_parameter_gradient_matches_oracle():
+    import torch
+    ls = I.labelled_set(6, 64, 160, seed=42)
+    z = I.random_parameters(931, 8)
+    ctx, ds, zt = setup(ls, z)
+    rng = np.random.default_rng(3)
+    gE = rng.standard_normal(len(ls.n_atoms))
+    gF = rng.standard_normal((int(ls.n_atoms.sum()), 3)).astype(np.float32)
+    out = ctx.dataset_compute(ds, zt)
+    g = ctx.dataset_backward(ds, zt, torch.from_numpy(gE).cuda(),
+                             torch.from_numpy(np.ascontiguousarray(gF.T)).cuda(), out["F"],
+                             want_pos=True)
+    ctx.synchronize()
+    ref = O.grad_params(OH, z, ls, gE, gF.astype(np.float64))
+    got = g["z"].cpu().numpy()
+    print("grad rel err %.2e" % rel(got, ref))
+    assert rel(got, ref) < 1e-5
+    np.testing.assert_allclose(g["z32"].cpu().numpy(), got.astype(np.float32), rtol=1e-7)
+    # energy-part position gradient: -gE_s F_i
+    E_ref, F_ref = oracle_forward(z, ls)
+    struct = np.repeat(np.arange(len(ls.n_atoms)), ls.n_atoms)
+    assert rel(g["pos"].cpu().numpy().T, -gE[struct][:, None] * F_ref) < 1e-5
+    # energy-only and force-only parts separately
+    g_e = ctx.dataset_backward(ds, zt, torch.from_numpy(gE).cuda(), None)["z"].cpu().numpy()
+    ref_e = O.grad_params(OH, z, ls, gE, np.zeros_like(gF, dtype=np.float64))
+    assert rel(g_e, ref_e) < 1e-5
+    g_f = ctx.dataset_backward(ds, zt, None, torch.from_numpy(np.ascontiguousarray(gF.T)).cuda())
+    ref_f = O.grad_params(OH, z, ls, np.zeros_like(gE), gF.astype(np.float64))
+    assert rel(g_f["z"].cpu().numpy(), ref_f) < 1e-5
+
+
+def test_autograd_function_energy_force_loss():
+    """loss = sum_s ((E_s - E_tar)/N_s)^2 + mean |F - F_tar|^2 through torch.autograd."""
+    import torch
+    from paper_2107_08119_amd import nep
+    ls = I.labelled_set(8, 64, 128, seed=43)
+    z = I.random_parameters(931, 9)
+    ctx, ds, zt = setup(ls, z)
+    pos = ctx.dataset_positions(ds).requires_grad_(False)
+    zt = zt.clone().requires_grad_(True)
+    E, F = nep.NEPEnergy.apply(pos, zt, ctx, ds)
+    n_s = torch.from_numpy(ls.n_atoms.astype(np.float64)).cuda()
+    e_tar = torch.from_numpy(ls.energy).cuda()
+    f_tar = torch.from_numpy(np.ascontiguousarray(ls.forces.T)).float().cuda()
+    loss = (((E - e_tar) / n_s) ** 2).sum() + ((F - f_tar) ** 2).mean()
+    loss.backward()
+    # the same objective's gradient from the oracle, with the oracle's own E and F
+    E_ref, F_ref = oracle_forward(z, ls)
+    gE = 2.0 * (E_ref - ls.energy) / ls.n_atoms ** 2
+    gF = 2.0 * (F_ref - ls.forces) / F_ref.size
+    ref = O.grad_params(OH, z, ls, gE, gF)
+    assert rel(zt.grad.double().cpu().numpy(), ref) < 1e-4
+
+
+def test_energy_position_gradient_is_minus_force():
+    import torch
+    from paper_2107_08119_amd import nep
+    ls = I.labelled_set(4, 64, 96, seed=44)
+    z = I.random_parameters(931, 10)
+    ctx, ds, zt = setup(ls, z)
+    pos = ctx.dataset_positions(ds).clone().requires_grad_(True)
+    E, F = nep.NEPEnergy.apply(pos, zt, ctx, ds)
+    E.sum().backward()
+    np.testing.assert_allclose(pos.grad.cpu().numpy(), -F.double().detach().cpu().numpy(),
+                               rtol=1e-12)
+    with pytest.raises(NotImplementedError):
+        pos.grad = None
+        E2, F2 = nep.NEPEnergy.apply(pos, zt, ctx, ds)
+        (F2 ** 2).sum().backward()
+
+
+def test_full_size_differentiation_set():
+    """256 structures of 64-512 atoms: parameter gradient of an energy + force
+    objective against the oracle."""
+    import torch
+    ls = I.labelled_set(256, 64, 512, seed=6)
+    z = I.random_parameters(931, 1)
+    ctx, ds, zt = setup(ls, z, cap=96)
+    rng = np.random.default_rng(12)
+    gE = rng.standard_normal(len(ls.n_atoms))
+    gF = rng.standard_normal((int(ls.n_atoms.sum()), 3)).astype(np.float32)
+    g = ctx.dataset_backward(ds, zt, torch.from_numpy(gE).cuda(),
+                             torch.from_numpy(np.ascontiguousarray(gF.T)).cuda())
+    ctx.synchronize()
+    ref = O.grad_params(OH, z, ls, gE, gF.astype(np.float64), cap=96)
+    assert rel(g["z"].cpu().numpy(), ref) < 1e-5
