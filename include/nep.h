@@ -113,7 +113,10 @@ nep_status nep_load_params(nep_ctx ctx, const nep_hyper* hyper, const float* z_h
  * each atom's list.  Every lattice image is a separate entry, so boxes
  * thinner than twice the cutoff are handled; images beyond +-3 cells latch
  * NEP_EIMAGE.  max_neighbors bounds the list length (more latches
- * NEP_EOVERFLOW).  n_atoms must be below 2^23.  Requires loaded parameters. */
+ * NEP_EOVERFLOW).  n_atoms must be below 2^23 and max_neighbors * n_atoms
+ * below 2^31.  Requires loaded parameters.  The library keeps its own copy of
+ * the positions, re-sorted into cell order at every list build; results are
+ * always returned in the caller's atom order. */
 nep_status nep_build_neighbors(nep_ctx ctx, int n_atoms, const double* pos_dev,
                                const double* box_host, double skin, int max_neighbors);
 

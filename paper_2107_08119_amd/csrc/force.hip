@@ -27,6 +27,8 @@
 namespace nep {
 namespace {
 
+constexpr int kStage = 40;  // neighbour slots per atom staged in LDS by pass 1
+
 // ------------------------------------------------------------------ pass 1
 // Outputs: U[i]; fown[c*n + i] = sum_j dU_i/dr_ij (component c); and every
 // partial force dU_i/dr_ij written to the reverse slot, pin[t*n + j] with
@@ -53,11 +55,35 @@ __global__ __launch_bounds__(kBlock) void k_partials(
     U += pk * (size_t)n;
   }
   for (int t = threadIdx.x; t < NPAR; t += blockDim.x) sz[t] = zpar[t];
+
+  // Stage the first kStage slots of the block's atoms in LDS: the pair
+  // displacement (float32, formed in float64) and, in .w, the index of the
+  // reverse slot where dU_i/dr_ij is written.  (slot, atom) pairs are spread
+  // over the block with atoms fastest, so the list reads coalesce and every
+  // thread has several independent loads in flight.
+  constexpr int APB = kBlock / L;  // atoms per block
+  __shared__ float4 sd[kStage][APB];
+  const int atom0 = blockIdx.x * APB;
+#pragma unroll
+  for (int t = 0; t < kStage * APB / kBlock; ++t) {
+    const int q = threadIdx.x + t * kBlock;
+    const int sl = q / APB, a = q % APB;
+    const int ia = atom0 + a;
+    if (ia < n && sl < cnt_r[ia]) {
+      const size_t idx = (size_t)sl * n + ia;
+      const double* Ha = MULTI ? boxes + 9 * (size_t)struct_of[ia] : box.h;
+      int j;
+      float dx, dy, dz;
+      displacement(nl[idx], pos, n, pos[ia], pos[n + ia], pos[2 * n + ia], Ha, j, dx, dy, dz);
+      sd[sl][a] = make_float4(dx, dy, dz, __int_as_float(rev[idx] * n + j));
+    }
+  }
   __syncthreads();
 
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gid / L;
   const int lane = gid % L;
+  const int la = threadIdx.x / L;
   const bool active = i < n;
   const int ii = active ? i : 0;
   const int cr = active ? cnt_r[i] : 0;
@@ -65,6 +91,21 @@ __global__ __launch_bounds__(kBlock) void k_partials(
   const double xi = pos[ii], yi = pos[n + ii], zi = pos[2 * n + ii];
   const double* H = MULTI ? boxes + 9 * (size_t)struct_of[ii] : box.h;
   const float rcr_inv = 1.f / rc_r, rca_inv = 1.f / rc_a;
+  // displacement of slot s and where its partial force goes
+  auto pair = [&](int s, float& dx, float& dy, float& dz, int& dst) {
+    if (s < kStage) {
+      const float4 v = sd[s][la];
+      dx = v.x;
+      dy = v.y;
+      dz = v.z;
+      dst = __float_as_int(v.w);
+    } else {
+      const size_t idx = (size_t)s * n + i;
+      int j;
+      displacement(nl[idx], pos, n, xi, yi, zi, H, j, dx, dy, dz);
+      dst = rev[idx] * n + j;
+    }
+  };
 
   float q[NDES];
   float c[NA][NLM];
@@ -77,9 +118,9 @@ __global__ __launch_bounds__(kBlock) void k_partials(
 
   // descriptor sums over this lane's share of the neighbour slots
   for (int s = lane; s < cr; s += L) {
-    int j;
+    int dst;
     float dx, dy, dz;
-    displacement(nl[(size_t)s * n + i], pos, n, xi, yi, zi, H, j, dx, dy, dz);
+    pair(s, dx, dy, dz, dst);
     const float r2 = dx * dx + dy * dy + dz * dz;
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * rinv;
@@ -163,10 +204,9 @@ __global__ __launch_bounds__(kBlock) void k_partials(
   // partial forces p_ij = dU_i/dr_ij for this lane's slots
   float fx = 0.f, fy = 0.f, fz = 0.f;
   for (int s = lane; s < cr; s += L) {
-    int j;
+    int dst;
     float dx, dy, dz;
-    const size_t idx = (size_t)s * n + i;
-    displacement(nl[idx], pos, n, xi, yi, zi, H, j, dx, dy, dz);
+    pair(s, dx, dy, dz, dst);
     const float r2 = dx * dx + dy * dy + dz * dz;
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * rinv;
@@ -211,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_partials(
     fx += px;
     fy += py;
     fz += pz;
-    pin[(size_t)rev[idx] * n + j] = make_float4(px, py, pz, 0.f);
+    pin[(size_t)(unsigned)dst] = make_float4(px, py, pz, 0.f);
   }
   fx = group_sum<L>(fx);
   fy = group_sum<L>(fy);

@@ -115,24 +115,66 @@ __global__ void k_sort_cells(int ncell, const int* __restrict__ start, int* __re
   }
 }
 
-// Copy every atom into its cell-ordered slot: position, index and packed
-// cell offsets, so that the candidates of a cell are contiguous in memory.
-__global__ void k_records(int n, const double* __restrict__ pos, const int* __restrict__ wrap,
-                          const int* __restrict__ members, CellRec* __restrict__ rec,
+// Re-sort atoms into cell order: internal index k takes the atom at old index
+// o = members[k] (cells in order, members by old index).  Positions,
+// velocities (when given), offsets, caller indices and cells move with it, and
+// a 32-byte record (position, index, packed offsets) is written per atom.
+__global__ void k_permute(int n, const int* __restrict__ members, const double* __restrict__ pos,
+                          double* __restrict__ pos_out, const double* __restrict__ vel,
+                          double* __restrict__ vel_out, const int* __restrict__ wrap,
+                          int* __restrict__ wrap_out, const int* __restrict__ perm,
+                          int* __restrict__ perm_out, const int* __restrict__ cell_of,
+                          int* __restrict__ cell_out, CellRec* __restrict__ rec,
                           int* __restrict__ flags) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int j = members[t];
-  const int w0 = wrap[j], w1 = wrap[n + j], w2 = wrap[2 * n + j];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int o = members[k];
+  CellRec r;
+  r.x = pos[o];
+  r.y = pos[n + o];
+  r.z = pos[2 * n + o];
+  pos_out[k] = r.x;
+  pos_out[n + k] = r.y;
+  pos_out[2 * n + k] = r.z;
+  if (vel) {
+    vel_out[k] = vel[o];
+    vel_out[n + k] = vel[n + o];
+    vel_out[2 * n + k] = vel[2 * n + o];
+  }
+  const int w0 = wrap[o], w1 = wrap[n + o], w2 = wrap[2 * n + o];
+  wrap_out[k] = w0;
+  wrap_out[n + k] = w1;
+  wrap_out[2 * n + k] = w2;
+  perm_out[k] = perm[o];
+  cell_out[k] = cell_of[o];
   if (w0 < -127 || w0 > 127 || w1 < -127 || w1 > 127 || w2 < -127 || w2 > 127)
     flags[kFlagImage] = 1;
-  CellRec r;
-  r.x = pos[j];
-  r.y = pos[n + j];
-  r.z = pos[2 * n + j];
-  r.j = j;
+  r.j = k;
   r.w = (w0 & 0xFF) | ((w1 & 0xFF) << 8) | ((w2 & 0xFF) << 16);
-  rec[t] = r;
+  rec[k] = r;
+}
+
+template <class T>
+__global__ void k_take_rows(int n, int rows, const T* __restrict__ src, const int* __restrict__ perm,
+                            T* __restrict__ dst) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int o = perm[k];
+  for (int r = 0; r < rows; ++r) dst[(size_t)r * n + k] = src[(size_t)r * n + o];
+}
+
+template <class T>
+__global__ void k_put_rows(int n, int rows, const T* __restrict__ src, const int* __restrict__ perm,
+                           T* __restrict__ dst) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int o = perm[k];
+  for (int r = 0; r < rows; ++r) dst[(size_t)r * n + o] = src[(size_t)r * n + k];
+}
+
+__global__ void k_iota(int n, int* __restrict__ a) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) a[k] = k;
 }
 
 // G lanes per atom (G = 32) scan the 27 surrounding cells twice, first
@@ -318,19 +360,33 @@ __global__ void k_reverse(int n, int cap, const uint32_t* __restrict__ nl,
   rev[idx] = found;
 }
 
-__global__ void k_unpack(int n, int cap, const uint32_t* __restrict__ nl, int* __restrict__ nbr,
-                         int* __restrict__ img) {
+// Expand the list into the caller's atom numbering: slot s of caller atom
+// perm[k] holds caller atom perm[j].
+__global__ void k_unpack(int n, int cap, const uint32_t* __restrict__ nl,
+                         const int* __restrict__ perm, const int* __restrict__ cnt_r,
+                         const int* __restrict__ cnt_a, const int* __restrict__ rev,
+                         int* __restrict__ nbr, int* __restrict__ img, int* __restrict__ cnt_r_out,
+                         int* __restrict__ cnt_a_out, int* __restrict__ rev_out) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)n * cap) return;
+  const int k = (int)(idx % (size_t)n);
+  const int s = (int)(idx / (size_t)n);
+  const size_t out = (size_t)s * n + perm[k];
+  if (s == 0) {
+    if (cnt_r_out) cnt_r_out[perm[k]] = cnt_r[k];
+    if (cnt_a_out) cnt_a_out[perm[k]] = cnt_a[k];
+  }
+  if (s >= cnt_r[k]) return;
   const uint32_t e = nl[idx];
   int n0, n1, n2;
   unpack_image(e, n0, n1, n2);
-  if (nbr) nbr[idx] = (int)(e & kAtomMask);
+  if (nbr) nbr[out] = perm[(int)(e & kAtomMask)];
   if (img) {
-    img[3 * idx] = n0;
-    img[3 * idx + 1] = n1;
-    img[3 * idx + 2] = n2;
+    img[3 * out] = n0;
+    img[3 * out + 1] = n1;
+    img[3 * out + 2] = n2;
   }
+  if (rev_out) rev_out[out] = rev[idx];
 }
 
 inline unsigned blocks_for(size_t work, int block) { return (unsigned)((work + block - 1) / block); }
@@ -345,12 +401,37 @@ void launch_reverse(nep_ctx ctx, int n, int cap, const uint32_t* nl, const int* 
                 nl, cnt_r, cnt_a, rev, ctx->flags.ptr);
 }
 
-hipError_t unpack_neighbors(nep_ctx ctx, int* nbr, int* img) {
+hipError_t unpack_neighbors(nep_ctx ctx, int* nbr, int* img, int* cnt_r, int* cnt_a, int* rev) {
   const System& s = ctx->sys;
   const size_t ncap = (size_t)s.n * s.cap;
   if (ncap == 0) return hipSuccess;
-  k_unpack<<<blocks_for(ncap, kBlock), kBlock, 0, ctx->stream>>>(s.n, s.cap, s.nl.ptr, nbr, img);
+  k_unpack<<<blocks_for(ncap, kBlock), kBlock, 0, ctx->stream>>>(
+      s.n, s.cap, s.nl.ptr, s.perm.ptr, s.cnt_r.ptr, s.cnt_a.ptr, s.rev.ptr, nbr, img, cnt_r,
+      cnt_a, rev);
   return hipGetLastError();
+}
+
+void launch_take_rows(nep_ctx ctx, int n, int rows, const double* src, double* dst) {
+  if (n == 0) return;
+  launch_kernel(ctx, false, false, k_take_rows<double>, dim3(blocks_for(n, kBlock)), dim3(kBlock),
+                n, rows, src, (const int*)ctx->sys.perm.ptr, dst);
+}
+
+void launch_put_rows(nep_ctx ctx, int n, int rows, const double* src, double* dst) {
+  if (n == 0) return;
+  launch_kernel(ctx, false, false, k_put_rows<double>, dim3(blocks_for(n, kBlock)), dim3(kBlock),
+                n, rows, src, (const int*)ctx->sys.perm.ptr, dst);
+}
+
+void launch_put_rows(nep_ctx ctx, int n, int rows, const float* src, float* dst) {
+  if (n == 0) return;
+  launch_kernel(ctx, false, false, k_put_rows<float>, dim3(blocks_for(n, kBlock)), dim3(kBlock), n,
+                rows, src, (const int*)ctx->sys.perm.ptr, dst);
+}
+
+void launch_iota(nep_ctx ctx, int n, int* dst) {
+  if (n == 0) return;
+  launch_kernel(ctx, false, false, k_iota, dim3(blocks_for(n, kBlock)), dim3(kBlock), n, dst);
 }
 
 void prepare_system_geometry(System& s, const double* H, double rc_r, double rc_a, double skin) {
@@ -391,10 +472,9 @@ void prepare_system_geometry(System& s, const double* H, double rc_r, double rc_
   if (!s.use_cells) s.nc[0] = s.nc[1] = s.nc[2] = 1;
 }
 
-nep_status build_neighbors(nep_ctx ctx, const double* pos_c, bool wrap_in_place) {
+nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
   System& s = ctx->sys;
   const int n = s.n;
-  double* pos = const_cast<double*>(pos_c);  // written only when wrap_in_place
   hipError_t e = hipSuccess;
   const size_t ncap = (size_t)n * s.cap;
   if ((e = s.nl.ensure(ncap)) != hipSuccess || (e = s.rev.ensure(ncap)) != hipSuccess ||
@@ -409,15 +489,19 @@ nep_status build_neighbors(nep_ctx ctx, const double* pos_c, bool wrap_in_place)
     if ((e = s.cell_of.ensure(n)) != hipSuccess || (e = s.cell_cnt.ensure(ncell)) != hipSuccess ||
         (e = s.cell_start.ensure((size_t)ncell + 1)) != hipSuccess ||
         (e = s.cell_fill.ensure(ncell)) != hipSuccess ||
-        (e = s.cell_atoms.ensure(n)) != hipSuccess || (e = s.cell_rec.ensure(n)) != hipSuccess)
+        (e = s.cell_atoms.ensure(n)) != hipSuccess || (e = s.cell_rec.ensure(n)) != hipSuccess ||
+        (e = s.pos_t.ensure((size_t)3 * n)) != hipSuccess ||
+        (e = s.vel_t.ensure((size_t)3 * n)) != hipSuccess ||
+        (e = s.perm_t.ensure(n)) != hipSuccess || (e = s.wrap_t.ensure((size_t)3 * n)) != hipSuccess ||
+        (e = s.cell_t.ensure(n)) != hipSuccess)
       return check_hip(ctx, e, "allocating cell lists");
     launch_kernel(ctx, true, false, k_zero, dim3(blocks_for(ncell, kBlock)), blk, s.cell_cnt.ptr,
                   ncell);
     launch_kernel(ctx, false, false, k_zero, dim3(blocks_for(ncell, kBlock)), blk,
                   s.cell_fill.ptr, ncell);
-    launch_kernel(ctx, false, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, pos, s.box,
-                  s.nc[0], s.nc[1], s.nc[2], 1, wrap_in_place ? 1 : 0, s.wrap.ptr, s.cell_of.ptr,
-                  s.cell_cnt.ptr);
+    launch_kernel(ctx, false, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, s.pos_s.ptr,
+                  s.box, s.nc[0], s.nc[1], s.nc[2], 1, wrap_in_place ? 1 : 0, s.wrap.ptr,
+                  s.cell_of.ptr, s.cell_cnt.ptr);
     launch_kernel(ctx, false, false, k_scan, dim3(1), dim3(1024), ncell,
                   (const int*)s.cell_cnt.ptr, s.cell_start.ptr);
     launch_kernel(ctx, false, false, k_fill, dim3(blocks_for(n, kBlock)), blk, n,
@@ -425,20 +509,28 @@ nep_status build_neighbors(nep_ctx ctx, const double* pos_c, bool wrap_in_place)
                   s.cell_atoms.ptr);
     launch_kernel(ctx, false, false, k_sort_cells, dim3(blocks_for(ncell, kBlock)), blk, ncell,
                   (const int*)s.cell_start.ptr, s.cell_atoms.ptr);
-    launch_kernel(ctx, false, false, k_records, dim3(blocks_for(n, kBlock)), blk, n,
-                  (const double*)pos, (const int*)s.wrap.ptr, (const int*)s.cell_atoms.ptr,
+    launch_kernel(ctx, false, false, k_permute, dim3(blocks_for(n, kBlock)), blk, n,
+                  (const int*)s.cell_atoms.ptr, (const double*)s.pos_s.ptr, s.pos_t.ptr,
+                  have_vel ? (const double*)s.vel_s.ptr : (const double*)nullptr,
+                  have_vel ? s.vel_t.ptr : (double*)nullptr, (const int*)s.wrap.ptr, s.wrap_t.ptr,
+                  (const int*)s.perm.ptr, s.perm_t.ptr, (const int*)s.cell_of.ptr, s.cell_t.ptr,
                   s.cell_rec.ptr, ctx->flags.ptr);
+    s.pos_s.swap(s.pos_t);
+    if (have_vel) s.vel_s.swap(s.vel_t);
+    s.wrap.swap(s.wrap_t);
+    s.perm.swap(s.perm_t);
+    s.cell_of.swap(s.cell_t);
     constexpr int G = 32;
     launch_kernel(ctx, false, false, k_build_cells<G>, dim3(blocks_for((size_t)n * G, kBlock)),
-                  blk, n, s.cap, (const double*)pos, s.box, s.nc[0], s.nc[1], s.nc[2],
+                  blk, n, s.cap, (const double*)s.pos_s.ptr, s.box, s.nc[0], s.nc[1], s.nc[2],
                   (const int*)s.wrap.ptr, (const int*)s.cell_of.ptr,
                   (const int*)s.cell_start.ptr, (const CellRec*)s.cell_rec.ptr, rc2_r, rc2_a,
                   s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr, ctx->flags.ptr);
   } else {
-    launch_kernel(ctx, true, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, pos, s.box, 1, 1,
-                  1, 0, wrap_in_place ? 1 : 0, s.wrap.ptr, (int*)nullptr, (int*)nullptr);
+    launch_kernel(ctx, true, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, s.pos_s.ptr, s.box,
+                  1, 1, 1, 0, wrap_in_place ? 1 : 0, s.wrap.ptr, (int*)nullptr, (int*)nullptr);
     launch_kernel(ctx, false, false, k_build_all_pairs, dim3(blocks_for(n, 64)), dim3(64), n,
-                  s.cap, (const double*)pos, s.box, s.kimg[0], s.kimg[1], s.kimg[2],
+                  s.cap, (const double*)s.pos_s.ptr, s.box, s.kimg[0], s.kimg[1], s.kimg[2],
                   (const int*)s.wrap.ptr, rc2_r, rc2_a, s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr,
                   ctx->flags.ptr);
   }

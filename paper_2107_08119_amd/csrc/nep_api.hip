@@ -38,13 +38,33 @@ bool hyper_valid(const nep_hyper* h) {
 nep_status size_system_buffers(nep_ctx ctx) {
   const System& s = ctx->sys;
   hipError_t e;
+  System& sm = ctx->sys;
   if ((e = ctx->p.ensure((size_t)s.cap * s.n)) != hipSuccess ||
       (e = ctx->U.ensure((size_t)s.n)) != hipSuccess ||
       (e = ctx->fown.ensure((size_t)3 * s.n)) != hipSuccess ||
       (e = ctx->F.ensure((size_t)3 * s.n)) != hipSuccess ||
+      (e = ctx->W.ensure((size_t)9 * s.n)) != hipSuccess ||
+      (e = ctx->J.ensure((size_t)3 * s.n)) != hipSuccess ||
+      (e = sm.pos_s.ensure((size_t)3 * s.n)) != hipSuccess ||
+      (e = sm.vel_s.ensure((size_t)3 * s.n)) != hipSuccess ||
+      (e = sm.perm.ensure((size_t)s.n)) != hipSuccess ||
       (e = ctx->partials.ensure(gather_blocks(s.n) * 16 + 16)) != hipSuccess)
     return check_hip(ctx, e, "allocating system buffers");
   return NEP_OK;
+}
+
+// One force evaluation of the internal state (positions sys.pos_s, velocities
+// sys.vel_s when vel is true): pass 1 and pass 2 into the internal U, F, W, J.
+hipError_t evaluate_internal(nep_ctx ctx, bool vel, double* out, int mode, double kick,
+                             double mass, bool want_w = false, bool want_j = false) {
+  System& s = ctx->sys;
+  hipError_t e = timed(ctx, 0, [&] { return launch_partials(ctx, s.pos_s.ptr); });
+  if (e != hipSuccess) return e;
+  return timed(ctx, 1, [&] {
+    return launch_gather(ctx, s.pos_s.ptr, vel ? s.vel_s.ptr : nullptr, nullptr, ctx->F.ptr,
+                         want_w ? ctx->W.ptr : nullptr, want_j ? ctx->J.ptr : nullptr, out, mode,
+                         kick, mass);
+  });
 }
 
 }  // namespace
@@ -84,6 +104,8 @@ void nep_destroy(nep_ctx ctx) {
   ctx->fown.release();
   ctx->U.release();
   ctx->F.release();
+  ctx->W.release();
+  ctx->J.release();
   ctx->partials.release();
   ctx->totals.release();
   ctx->flags.release();
@@ -167,8 +189,8 @@ nep_status nep_build_neighbors(nep_ctx ctx, int n_atoms, const double* pos_dev,
   if (n_atoms > 0 && !pos_dev) return fail(ctx, NEP_EINVAL, "pos_dev is NULL");
   if (!box_host) return fail(ctx, NEP_EINVAL, "box_host is NULL");
   if (!(skin >= 0.0) || !std::isfinite(skin)) return fail(ctx, NEP_EINVAL, "skin must be >= 0");
-  if (max_neighbors < 1 || (size_t)max_neighbors * (size_t)(n_atoms > 0 ? n_atoms : 1) > (1ull << 40))
-    return fail(ctx, NEP_EINVAL, "max_neighbors must be >= 1");
+  if (max_neighbors < 1 || (size_t)max_neighbors * (size_t)(n_atoms > 0 ? n_atoms : 1) >= (1ull << 31))
+    return fail(ctx, NEP_EINVAL, "need 1 <= max_neighbors and max_neighbors * n_atoms < 2^31");
   for (int k = 0; k < 9; ++k)
     if (!std::isfinite(box_host[k])) return fail(ctx, NEP_EINVAL, "box has non-finite entries");
   System& s = ctx->sys;
@@ -198,7 +220,13 @@ nep_status nep_build_neighbors(nep_ctx ctx, int n_atoms, const double* pos_dev,
   nep_status st = size_system_buffers(ctx);
   if (st != NEP_OK) return st;
   if (n_atoms > 0) {
-    st = build_neighbors(ctx, pos_dev, false);
+    launch_iota(ctx, n_atoms, s.perm.ptr);
+    st = check_hip(ctx,
+                   hipMemcpyAsync(s.pos_s.ptr, pos_dev, sizeof(double) * 3 * n_atoms,
+                                  hipMemcpyDeviceToDevice, ctx->stream),
+                   "copying positions");
+    if (st != NEP_OK) return st;
+    st = build_neighbors(ctx, false, false);
     if (st != NEP_OK) return st;
   }
   ctx->have_list = true;
@@ -210,23 +238,11 @@ nep_status nep_get_neighbors(nep_ctx ctx, int* cnt_radial_dev, int* cnt_angular_
                              int* img_dev, int* rev_dev) {
   if (!ctx) return NEP_EINVAL;
   if (!ctx->have_list) return fail(ctx, NEP_ESTATE, "no neighbour list");
-  const System& s = ctx->sys;
-  if (s.n == 0) return NEP_OK;
+  if (ctx->sys.n == 0) return NEP_OK;
   DeviceGuard guard(ctx->device);
-  const size_t ncap = (size_t)s.n * s.cap;
-  hipError_t e = hipSuccess;
-  if (cnt_radial_dev && e == hipSuccess)
-    e = hipMemcpyAsync(cnt_radial_dev, s.cnt_r.ptr, sizeof(int) * s.n, hipMemcpyDeviceToDevice, ctx->stream);
-  if (cnt_angular_dev && e == hipSuccess)
-    e = hipMemcpyAsync(cnt_angular_dev, s.cnt_a.ptr, sizeof(int) * s.n, hipMemcpyDeviceToDevice, ctx->stream);
-  if (rev_dev && e == hipSuccess)
-    e = hipMemcpyAsync(rev_dev, s.rev.ptr, sizeof(int) * ncap, hipMemcpyDeviceToDevice, ctx->stream);
-  if (e != hipSuccess) return check_hip(ctx, e, "copying neighbour list");
-  if (nbr_dev || img_dev) {
-    e = unpack_neighbors(ctx, nbr_dev, img_dev);
-    if (e != hipSuccess) return check_hip(ctx, e, "unpacking neighbour list");
-  }
-  return NEP_OK;
+  return check_hip(ctx,
+                   unpack_neighbors(ctx, nbr_dev, img_dev, cnt_radial_dev, cnt_angular_dev, rev_dev),
+                   "unpacking neighbour list");
 }
 
 nep_status nep_compute(nep_ctx ctx, const double* pos_dev, const double* vel_dev, float* U_dev,
@@ -234,17 +250,24 @@ nep_status nep_compute(nep_ctx ctx, const double* pos_dev, const double* vel_dev
   if (!ctx) return NEP_EINVAL;
   if (!ctx->have_params || !ctx->have_list)
     return fail(ctx, NEP_ESTATE, "nep_load_params and nep_build_neighbors must come first");
-  if (ctx->sys.n > 0 && (!pos_dev || !F_dev))
-    return fail(ctx, NEP_EINVAL, "pos_dev and F_dev are required");
+  System& s = ctx->sys;
+  const int n = s.n;
+  if (n > 0 && (!pos_dev || !F_dev)) return fail(ctx, NEP_EINVAL, "pos_dev and F_dev are required");
   if (J_dev && !vel_dev) return fail(ctx, NEP_EINVAL, "J_dev needs vel_dev");
   DeviceGuard guard(ctx->device);
   ctx->md_forces_valid = false;
-  hipError_t e = timed(ctx, 0, [&] { return launch_partials(ctx, pos_dev); });
-  if (e == hipSuccess)
-    e = timed(ctx, 1, [&] {
-      return launch_gather(ctx, pos_dev, const_cast<double*>(vel_dev), U_dev, F_dev, W_dev,
-                           J_dev, totals_dev ? totals_dev : ctx->totals.ptr, 0, 0.0, 1.0);
-    });
+  launch_take_rows(ctx, n, 3, pos_dev, s.pos_s.ptr);
+  if (vel_dev) launch_take_rows(ctx, n, 3, vel_dev, s.vel_s.ptr);
+  hipError_t e = evaluate_internal(ctx, vel_dev != nullptr,
+                                   totals_dev ? totals_dev : ctx->totals.ptr, 0, 0.0, 1.0,
+                                   W_dev != nullptr, J_dev != nullptr);
+  if (e == hipSuccess) {
+    launch_put_rows(ctx, n, 3, ctx->F.ptr, F_dev);
+    if (U_dev) launch_put_rows(ctx, n, 1, ctx->U.ptr, U_dev);
+    if (W_dev) launch_put_rows(ctx, n, 9, ctx->W.ptr, W_dev);
+    if (J_dev) launch_put_rows(ctx, n, 3, ctx->J.ptr, J_dev);
+    e = hipGetLastError();
+  }
   return check_hip(ctx, e, "launching force kernels");
 }
 
@@ -259,29 +282,29 @@ nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every
   if (rebuild_every < 1) return fail(ctx, NEP_EINVAL, "rebuild_every must be >= 1");
   if (!(mass_amu > 0.0) || !std::isfinite(mass_amu)) return fail(ctx, NEP_EINVAL, "mass must be > 0");
   if (n_steps == 0) return NEP_OK;
-  if (ctx->sys.n > 0 && (!pos_dev || !vel_dev)) return fail(ctx, NEP_EINVAL, "pos/vel are required");
+  System& s = ctx->sys;
+  const int n = s.n;
+  if (n > 0 && (!pos_dev || !vel_dev)) return fail(ctx, NEP_EINVAL, "pos/vel are required");
   if (!thermo_dev) return fail(ctx, NEP_EINVAL, "thermo_dev is required");
   DeviceGuard guard(ctx->device);
   const double kick = 0.5 * dt_fs * kAccel / mass_amu;
+  // the caller's arrays in the internal (cell) order
+  launch_take_rows(ctx, n, 3, pos_dev, s.pos_s.ptr);
+  launch_take_rows(ctx, n, 3, vel_dev, s.vel_s.ptr);
   hipError_t e = hipSuccess;
   if (!(ctx->md_forces_valid && ctx->md_pos == pos_dev && ctx->md_vel == vel_dev)) {
-    e = timed(ctx, 0, [&] { return launch_partials(ctx, pos_dev); });
-    if (e == hipSuccess)
-      e = timed(ctx, 1, [&] {
-        return launch_gather(ctx, pos_dev, nullptr, nullptr, ctx->F.ptr, nullptr, nullptr,
-                             ctx->totals.ptr, 0, 0.0, mass_amu);
-      });
+    e = evaluate_internal(ctx, false, ctx->totals.ptr, 0, 0.0, mass_amu);
     if (e != hipSuccess) return check_hip(ctx, e, "launching force kernels");
   }
   ctx->md_forces_valid = false;
   for (int step = 0; step < n_steps; ++step) {
-    e = timed(ctx, 3, [&] { return launch_kick_drift(ctx, pos_dev, vel_dev, kick, dt_fs); });
+    e = timed(ctx, 3, [&] { return launch_kick_drift(ctx, s.pos_s.ptr, s.vel_s.ptr, kick, dt_fs); });
     if (e != hipSuccess) return check_hip(ctx, e, "launching integrator");
     if (++ctx->steps_since_rebuild >= rebuild_every) {
-      if (ctx->sys.n > 0) {
+      if (n > 0) {
         nep_status st = NEP_OK;
         e = timed(ctx, 2, [&] {
-          st = build_neighbors(ctx, pos_dev, true);
+          st = build_neighbors(ctx, true, true);
           return st == NEP_OK ? hipSuccess : hipErrorUnknown;
         });
         if (st != NEP_OK) return st;
@@ -289,14 +312,16 @@ nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every
       }
       ctx->steps_since_rebuild = 0;
     }
-    e = timed(ctx, 0, [&] { return launch_partials(ctx, pos_dev); });
-    if (e == hipSuccess)
-      e = timed(ctx, 1, [&] {
-        return launch_gather(ctx, pos_dev, vel_dev, nullptr, ctx->F.ptr, W_dev, J_dev,
-                             thermo_dev + (size_t)5 * step, 1, kick, mass_amu);
-      });
+    e = evaluate_internal(ctx, true, thermo_dev + (size_t)5 * step, 1, kick, mass_amu,
+                          W_dev != nullptr, J_dev != nullptr);
     if (e != hipSuccess) return check_hip(ctx, e, "launching force kernels");
+    if (W_dev) launch_put_rows(ctx, n, 9, ctx->W.ptr, W_dev);
+    if (J_dev) launch_put_rows(ctx, n, 3, ctx->J.ptr, J_dev);
   }
+  launch_put_rows(ctx, n, 3, s.pos_s.ptr, pos_dev);
+  launch_put_rows(ctx, n, 3, s.vel_s.ptr, vel_dev);
+  e = hipGetLastError();
+  if (e != hipSuccess) return check_hip(ctx, e, "copying the state back");
   ctx->md_forces_valid = true;
   ctx->md_pos = pos_dev;
   ctx->md_vel = vel_dev;
@@ -338,11 +363,12 @@ nep_status nep_time_partials(nep_ctx ctx, const double* pos_dev, int reps, doubl
   if (reps < 1 || reps > 100000) return fail(ctx, NEP_EINVAL, "reps must be in [1, 100000]");
   if (ctx->sys.n > 0 && !pos_dev) return fail(ctx, NEP_EINVAL, "pos_dev is NULL");
   DeviceGuard guard(ctx->device);
+  launch_take_rows(ctx, ctx->sys.n, 3, pos_dev, ctx->sys.pos_s.ptr);
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
   if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
-  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_partials(ctx, pos_dev);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_partials(ctx, ctx->sys.pos_s.ptr);
   if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
   if (e == hipSuccess) e = hipEventSynchronize(b);
   float ms = 0.f;

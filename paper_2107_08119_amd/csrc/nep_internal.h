@@ -63,6 +63,14 @@ struct DevBuf {
     ptr = nullptr;
     size = 0;
   }
+  void swap(DevBuf& o) {
+    T* p = ptr;
+    ptr = o.ptr;
+    o.ptr = p;
+    size_t z = size;
+    size = o.size;
+    o.size = z;
+  }
 };
 
 // Device error flags latched by kernels.
@@ -101,6 +109,13 @@ struct System {
   DevBuf<int> cell_fill;   // [ncell]
   DevBuf<int> cell_atoms;  // [n]
   DevBuf<CellRec> cell_rec;  // [n] positions and offsets in cell order
+  // The library works on its own copies of positions and velocities in cell
+  // order (re-sorted at every rebuild); perm[k] is the caller's index of the
+  // atom at internal index k.
+  DevBuf<double> pos_s, pos_t;  // [3][n]
+  DevBuf<double> vel_s, vel_t;  // [3][n]
+  DevBuf<int> perm, perm_t;     // [n]
+  DevBuf<int> wrap_t, cell_t;   // [3][n], [n]
   void release() {
     nl.release();
     cnt_r.release();
@@ -113,6 +128,14 @@ struct System {
     cell_fill.release();
     cell_atoms.release();
     cell_rec.release();
+    pos_s.release();
+    pos_t.release();
+    vel_s.release();
+    vel_t.release();
+    perm.release();
+    perm_t.release();
+    wrap_t.release();
+    cell_t.release();
   }
 };
 
@@ -148,6 +171,8 @@ struct nep_ctx_s {
   nep::DevBuf<float> fown;        // sum_j dU_i/dr_ij, [3][n]
   nep::DevBuf<float> U;           // [n]
   nep::DevBuf<float> F;           // [3][n]
+  nep::DevBuf<float> W;           // [9][n] internal per-atom virials
+  nep::DevBuf<float> J;           // [3][n] internal heat currents
   nep::DevBuf<double> partials;   // [blocks][16] block sums
   nep::DevBuf<double> totals;     // [16]
   nep::DevBuf<int> flags;         // [kNumFlags]
@@ -193,11 +218,20 @@ struct nep_dataset_s {
 namespace nep {
 
 // neighbours.hip
-nep_status build_neighbors(nep_ctx ctx, const double* pos, bool wrap_in_place);
+// Build the list of the internal positions sys.pos_s; on the cell path the
+// atoms (positions, velocities when have_vel, perm) are first re-sorted into
+// cell order.  wrap_in_place maps the internal positions into the box.
+nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel);
+// dst[r*n + k] = src[r*n + perm[k]] (caller order -> internal order).
+void launch_take_rows(nep_ctx ctx, int n, int rows, const double* src, double* dst);
+// dst[r*n + perm[k]] = src[r*n + k] (internal order -> caller order).
+void launch_put_rows(nep_ctx ctx, int n, int rows, const double* src, double* dst);
+void launch_put_rows(nep_ctx ctx, int n, int rows, const float* src, float* dst);
+void launch_iota(nep_ctx ctx, int n, int* dst);
 void prepare_system_geometry(System& s, const double* box_host, double rc_r, double rc_a,
                              double skin);
-// Expand packed entries to atom indices [cap][n] and images [cap][n][3].
-hipError_t unpack_neighbors(nep_ctx ctx, int* nbr, int* img);
+// Expand the list into the caller's numbering (see nep_get_neighbors).
+hipError_t unpack_neighbors(nep_ctx ctx, int* nbr, int* img, int* cnt_r, int* cnt_a, int* rev);
 // Reverse slots of a list (any system, global atom indices).
 void launch_reverse(nep_ctx ctx, int n, int cap, const uint32_t* nl, const int* cnt_r,
                     const int* cnt_a, int* rev);

@@ -446,6 +446,8 @@ nep_status nep_dataset_create(nep_ctx ctx, int n_struct, const int* n_atoms_host
     total += n_atoms_host[s];
   }
   if (total > kMaxAtoms) return fail(ctx, NEP_EINVAL, "more than 2^23 - 1 atoms in total");
+  if ((unsigned long long)total * (unsigned long long)max_neighbors >= (1ull << 31))
+    return fail(ctx, NEP_EINVAL, "max_neighbors * total atoms must be below 2^31");
   const int N = (int)total, S = n_struct;
   const double rc_r = ctx->hyper.rc_radial, rc_a = ctx->hyper.rc_angular;
   std::vector<double> hinv((size_t)9 * S);
