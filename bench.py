@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--disordered-steps", type=int, default=500)
     ap.add_argument("--snes-structures", type=int, default=1000)
     ap.add_argument("--snes-generations", type=int, default=20)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="finish with 5 plain device copies of this many MiB (a known-size "
+                         "kernel that scales the HBM byte counters of a profiler run)")
     return ap.parse_args()
 
 
@@ -181,7 +184,7 @@ def cpu_baseline(h_np, z, pos, box, vel, mass, dt, target_s):
     t0 = time.perf_counter()
     O.nep_eval(h, z, pos, box)
     t_eval = time.perf_counter() - t0
-    steps = int(max(1, min(20, target_s / max(t_eval, 1e-9) - 1)))
+    steps = int(max(1, min(500, target_s / max(t_eval, 1e-9) - 1)))
     t0 = time.perf_counter()
     O.md_nve(h, z, pos, box, vel, mass, dt, steps)
     t = time.perf_counter() - t0
@@ -294,6 +297,13 @@ def main():
         line["snes"] = snes_rate(args, ctx, nep, I, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(h, z, pos, box, vel, mass, dt, args.cpu_seconds)
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = src.numel() * 4
     print(json.dumps(line), flush=True)
 
 

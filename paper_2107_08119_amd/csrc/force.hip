@@ -45,8 +45,9 @@ __global__ __launch_bounds__(kBlock) void k_partials(
     float4* __restrict__ pin, size_t pstride, float* __restrict__ fown, float* __restrict__ U) {
   constexpr int NLM = (LMAX + 1) * (LMAX + 1) - 1;
   constexpr int NDES = NR + NA * LMAX;
-  constexpr int NPAR = (NDES + 2) * NNEU + 1;
-  __shared__ float sz[NPAR];
+  constexpr int RS = nn_row_stride(NDES);  // LDS row of neuron mu: w1[mu][:], b1, w2, padding
+  __shared__ float4 sw4[NNEU * RS / 4];
+  __shared__ float sb2;
   {
     const size_t pk = blockIdx.y;
     zpar += pk * zstride;
@@ -54,28 +55,106 @@ __global__ __launch_bounds__(kBlock) void k_partials(
     fown += pk * 3 * (size_t)n;
     U += pk * (size_t)n;
   }
-  for (int t = threadIdx.x; t < NPAR; t += blockDim.x) sz[t] = zpar[t];
+  {
+    float* sw = reinterpret_cast<float*>(sw4);
+    for (int t = threadIdx.x; t < NNEU * RS; t += blockDim.x) {
+      const int mu = t / RS, v = t % RS;
+      float w = 0.f;
+      if (v < NDES)
+        w = zpar[mu * NDES + v];
+      else if (v == NDES)
+        w = zpar[NNEU * NDES + mu];
+      else if (v == NDES + 1)
+        w = zpar[NNEU * (NDES + 1) + mu];
+      sw[t] = w;
+    }
+    if (threadIdx.x == 0) sb2 = zpar[NNEU * (NDES + 2)];
+  }
 
-  // Stage the first kStage slots of the block's atoms in LDS: the pair
-  // displacement (float32, formed in float64) and, in .w, the index of the
-  // reverse slot where dU_i/dr_ij is written.  (slot, atom) pairs are spread
-  // over the block with atoms fastest, so the list reads coalesce and every
-  // thread has several independent loads in flight.
+  // Stage the first kStage slots of the block's atoms in LDS, keeping only
+  // the pairs inside a cutoff, compacted per atom: first the pairs inside
+  // r_c^A (angular partition of the list), then those inside r_c^R only.
+  // Each entry holds the pair displacement (float32, formed in float64) and,
+  // in .w, the index of the reverse slot where dU_i/dr_ij is written; a slot
+  // whose pair lies beyond r_c^R gets its zero partial force written here.
+  // Thread tid handles atom a = tid % APB at slots w, w + W, ... (w = tid / APB),
+  // so list reads coalesce and every thread has several loads in flight.
   constexpr int APB = kBlock / L;  // atoms per block
+  constexpr int W = kBlock / APB;  // slots staged side by side
+  constexpr int T = kStage / W;    // slots per thread
+  static_assert(kStage % W == 0 && kStage <= 64, "staging shape");
   __shared__ float4 sd[kStage][APB];
-  const int atom0 = blockIdx.x * APB;
+  __shared__ unsigned long long smask[2][W][APB];  // [angular, radial-only][w][atom]
+  __shared__ int scount[2][APB];
+  const float rcr2 = rc_r * rc_r, rca2 = rc_a * rc_a;
+  {
+    const int a = threadIdx.x % APB, w = threadIdx.x / APB;
+    const int ia = blockIdx.x * APB + a;
+    const int cra = ia < n ? cnt_r[ia] : 0;
+    const int caa = ia < n ? cnt_a[ia] : 0;
+    const double* Ha = MULTI && ia < n ? boxes + 9 * (size_t)struct_of[ia] : box.h;
+    const double xa = ia < n ? pos[ia] : 0.0, ya = ia < n ? pos[n + ia] : 0.0,
+                 za = ia < n ? pos[2 * n + ia] : 0.0;
+    // all loads first (clamped to valid addresses), so that the T slots'
+    // list and position reads are in flight together
+    uint32_t e[T];
+    int rv[T];
 #pragma unroll
-  for (int t = 0; t < kStage * APB / kBlock; ++t) {
-    const int q = threadIdx.x + t * kBlock;
-    const int sl = q / APB, a = q % APB;
-    const int ia = atom0 + a;
-    if (ia < n && sl < cnt_r[ia]) {
-      const size_t idx = (size_t)sl * n + ia;
-      const double* Ha = MULTI ? boxes + 9 * (size_t)struct_of[ia] : box.h;
-      int j;
+    for (int t = 0; t < T; ++t) {
+      const int sl = w + t * W;
+      const size_t idx = sl < cra ? (size_t)sl * n + ia : 0;
+      e[t] = nl[idx];
+      rv[t] = rev[idx];
+    }
+    double pj[T][3];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int j = w + t * W < cra ? (int)(e[t] & kAtomMask) : 0;
+      pj[t][0] = pos[j];
+      pj[t][1] = pos[n + j];
+      pj[t][2] = pos[2 * n + j];
+    }
+    float4 v[T];
+    unsigned long long ma = 0, mr = 0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int sl = w + t * W;
       float dx, dy, dz;
-      displacement(nl[idx], pos, n, pos[ia], pos[n + ia], pos[2 * n + ia], Ha, j, dx, dy, dz);
-      sd[sl][a] = make_float4(dx, dy, dz, __int_as_float(rev[idx] * n + j));
+      image_displacement(e[t], pj[t][0], pj[t][1], pj[t][2], xa, ya, za, Ha, dx, dy, dz);
+      const int dst = rv[t] * n + (int)(e[t] & kAtomMask);
+      v[t] = make_float4(dx, dy, dz, __int_as_float(dst));
+      const float r2 = pair_r2(dx, dy, dz);
+      if (sl < cra) {
+        if (sl < caa && r2 < rca2)
+          ma |= 1ull << sl;
+        else if (r2 < rcr2)
+          mr |= 1ull << sl;
+        else
+          pin[(size_t)(unsigned)dst] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    smask[0][w][a] = ma;
+    smask[1][w][a] = mr;
+    __syncthreads();
+    unsigned long long fa = 0, fr = 0;
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      fa |= smask[0][u][a];
+      fr |= smask[1][u][a];
+    }
+    const int na = __popcll(fa);
+    if (w == 0) {
+      scount[0][a] = na;
+      scount[1][a] = __popcll(fr);
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int sl = w + t * W;
+      const unsigned long long bit = 1ull << sl, below = bit - 1;
+      if (fa & bit)
+        sd[__popcll(fa & below)][a] = v[t];
+      else if (fr & bit)
+        sd[na + __popcll(fr & below)][a] = v[t];
     }
   }
   __syncthreads();
@@ -88,22 +167,33 @@ __global__ __launch_bounds__(kBlock) void k_partials(
   const int ii = active ? i : 0;
   const int cr = active ? cnt_r[i] : 0;
   const int ca = active ? cnt_a[i] : 0;
+  const int n_ang = scount[0][la];              // staged pairs inside r_c^A
+  const int n_in = n_ang + scount[1][la];       // staged pairs inside r_c^R
   const double xi = pos[ii], yi = pos[n + ii], zi = pos[2 * n + ii];
   const double* H = MULTI ? boxes + 9 * (size_t)struct_of[ii] : box.h;
   const float rcr_inv = 1.f / rc_r, rca_inv = 1.f / rc_a;
-  // displacement of slot s and where its partial force goes
-  auto pair = [&](int s, float& dx, float& dy, float& dz, int& dst) {
-    if (s < kStage) {
-      const float4 v = sd[s][la];
+  // Work item k of this atom: k < n_in is staged pair k (angular when
+  // k < n_ang); k >= n_in is list slot kStage + (k - n_in), read from the
+  // list and classified here.
+  const int n_work = n_in + (cr > kStage ? cr - kStage : 0);
+  auto pair = [&](int k, float& dx, float& dy, float& dz, int& dst, bool& ang, bool& rad) {
+    if (k < n_in) {
+      const float4 v = sd[k][la];
       dx = v.x;
       dy = v.y;
       dz = v.z;
       dst = __float_as_int(v.w);
+      ang = k < n_ang;
+      rad = true;
     } else {
+      const int s = kStage + (k - n_in);
       const size_t idx = (size_t)s * n + i;
       int j;
       displacement(nl[idx], pos, n, xi, yi, zi, H, j, dx, dy, dz);
       dst = rev[idx] * n + j;
+      const float r2 = pair_r2(dx, dy, dz);
+      ang = s < ca && r2 < rca2;
+      rad = r2 < rcr2;
     }
   };
 
@@ -116,21 +206,22 @@ __global__ __launch_bounds__(kBlock) void k_partials(
 #pragma unroll
     for (int m = 0; m < NLM; ++m) c[a][m] = 0.f;
 
-  // descriptor sums over this lane's share of the neighbour slots
-  for (int s = lane; s < cr; s += L) {
+  // descriptor sums over this lane's share of the pairs
+  for (int k = lane; k < n_work; k += L) {
     int dst;
+    bool ang, rad;
     float dx, dy, dz;
-    pair(s, dx, dy, dz, dst);
-    const float r2 = dx * dx + dy * dy + dz * dz;
+    pair(k, dx, dy, dz, dst, ang, rad);
+    const float r2 = pair_r2(dx, dy, dz);
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * rinv;
-    if (r < rc_r) {
+    if (rad) {
       float g[NR];
       radial_basis<NR, false>(r, rcr_inv, g, nullptr);
 #pragma unroll
       for (int a = 0; a < NR; ++a) q[a] += g[a];
     }
-    if (s < ca && r < rc_a) {
+    if (ang) {
       float g[NA];
       radial_basis<NA, false>(r, rca_inv, g, nullptr);
       const float x = dx * rinv, y = dy * rinv, z = dz * rinv;
@@ -164,29 +255,34 @@ __global__ __launch_bounds__(kBlock) void k_partials(
     }
 
   // network (Eqs. nn1, nn2) and dU/dq; the neurons are split over the lanes
-  const float* w1 = sz;
-  const float* b1 = sz + NNEU * NDES;
-  const float* w2 = b1 + NNEU;
-  const float b2 = w2[NNEU];
   float dq[NDES];
 #pragma unroll
   for (int v = 0; v < NDES; ++v) dq[v] = 0.f;
   float u = 0.f;
   for (int mu = lane; mu < NNEU; mu += L) {
-    float act = -b1[mu];
+    float w[RS];
 #pragma unroll
-    for (int v = 0; v < NDES; ++v) act += w1[mu * NDES + v] * q[v];
+    for (int t = 0; t < RS / 4; ++t) {
+      const float4 r4 = sw4[mu * (RS / 4) + t];
+      w[4 * t] = r4.x;
+      w[4 * t + 1] = r4.y;
+      w[4 * t + 2] = r4.z;
+      w[4 * t + 3] = r4.w;
+    }
+    float act = -w[NDES];
+#pragma unroll
+    for (int v = 0; v < NDES; ++v) act += w[v] * q[v];
     // tanh and its derivative 1 - tanh^2 from e = exp(-2|a|) (no cancellation)
     const float ea = __expf(-2.f * fabsf(act));
     const float inv = __builtin_amdgcn_rcpf(1.f + ea);
     const float th = copysignf((1.f - ea) * inv, act);
     const float sech2 = 4.f * ea * inv * inv;
-    u += w2[mu] * th;
-    const float gmu = w2[mu] * sech2;
+    u += w[NDES + 1] * th;
+    const float gmu = w[NDES + 1] * sech2;
 #pragma unroll
-    for (int v = 0; v < NDES; ++v) dq[v] += gmu * w1[mu * NDES + v];
+    for (int v = 0; v < NDES; ++v) dq[v] += gmu * w[v];
   }
-  u = group_sum<L>(u) - b2;
+  u = group_sum<L>(u) - sb2;
 #pragma unroll
   for (int v = 0; v < NDES; ++v) dq[v] = group_sum<L>(dq[v]);
   if (active && lane == 0) U[i] = u;
@@ -201,18 +297,19 @@ __global__ __launch_bounds__(kBlock) void k_partials(
       for (int m = 0; m < 2 * l + 1; ++m) c[a][l * l - 1 + m] *= f;
     }
 
-  // partial forces p_ij = dU_i/dr_ij for this lane's slots
+  // partial forces p_ij = dU_i/dr_ij for this lane's pairs
   float fx = 0.f, fy = 0.f, fz = 0.f;
-  for (int s = lane; s < cr; s += L) {
+  for (int k = lane; k < n_work; k += L) {
     int dst;
+    bool ang, rad;
     float dx, dy, dz;
-    pair(s, dx, dy, dz, dst);
-    const float r2 = dx * dx + dy * dy + dz * dz;
+    pair(k, dx, dy, dz, dst, ang, rad);
+    const float r2 = pair_r2(dx, dy, dz);
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * rinv;
     const float x = dx * rinv, y = dy * rinv, z = dz * rinv;
     float px = 0.f, py = 0.f, pz = 0.f;
-    if (r < rc_r) {
+    if (rad) {
       float g[NR], dg[NR];
       radial_basis<NR, true>(r, rcr_inv, g, dg);
       float f = 0.f;
@@ -222,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_partials(
       py += f * y;
       pz += f * z;
     }
-    if (s < ca && r < rc_a) {
+    if (ang) {
       float g[NA], dg[NA];
       radial_basis<NA, true>(r, rca_inv, g, dg);
       const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;

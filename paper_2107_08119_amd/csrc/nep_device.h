@@ -132,20 +132,42 @@ __device__ __forceinline__ void radial_basis(float r, float rc_inv, float* g, fl
   X(23, 0.125f * NEP_S35 * (xx * xx - 6.f * xx * yy + yy * yy),                                 \
     0.5f * NEP_S35 * x * (xx - 3.f * yy), 0.5f * NEP_S35 * y * (yy - 3.f * xx), 0.f)
 
-// r_ij = r_j + n.H - r_i formed in float64, rounded to float32; h holds the
-// cell vectors as rows.
+// r_ij = r_j + n.H - r_i formed in float64 from r_j = (xj, yj, zj) and the
+// image code of list entry e, rounded to float32; h holds the cell vectors as
+// rows.
+__device__ __forceinline__ void image_displacement(uint32_t e, double xj, double yj, double zj,
+                                                   double xi, double yi, double zi,
+                                                   const double* h, float& dx, float& dy,
+                                                   float& dz) {
+  int n0, n1, n2;
+  unpack_image(e, n0, n1, n2);
+  const double a0 = (double)n0, a1 = (double)n1, a2 = (double)n2;
+  dx = (float)((xj - xi) + (a0 * h[0] + a1 * h[3] + a2 * h[6]));
+  dy = (float)((yj - yi) + (a0 * h[1] + a1 * h[4] + a2 * h[7]));
+  dz = (float)((zj - zi) + (a0 * h[2] + a1 * h[5] + a2 * h[8]));
+}
+
+// The same for list entry e of atom (xi, yi, zi), reading r_j from pos [3][n].
 __device__ __forceinline__ void displacement(uint32_t e, const double* __restrict__ pos, int n,
                                              double xi, double yi, double zi, const double* h,
                                              int& j, float& dx, float& dy, float& dz) {
   j = (int)(e & kAtomMask);
-  int n0, n1, n2;
-  unpack_image(e, n0, n1, n2);
-  const double a0 = (double)n0, a1 = (double)n1, a2 = (double)n2;
-  dx = (float)((pos[j] - xi) + (a0 * h[0] + a1 * h[3] + a2 * h[6]));
-  dy = (float)((pos[n + j] - yi) + (a0 * h[1] + a1 * h[4] + a2 * h[7]));
-  dz = (float)((pos[2 * n + j] - zi) + (a0 * h[2] + a1 * h[5] + a2 * h[8]));
+  image_displacement(e, pos[j], pos[n + j], pos[2 * n + j], xi, yi, zi, h, dx, dy, dz);
 }
 
+// |r_ij|^2 of a float32 displacement with a fixed rounding sequence, so that
+// the pair (i, j) and its reverse (j, i), whose displacements are exact
+// negatives of each other, are classified alike by every kernel.
+__device__ __forceinline__ float pair_r2(float dx, float dy, float dz) {
+  return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+
+// LDS row of one hidden neuron: its N_des input weights, bias, output weight,
+// padded to a multiple of 4 floats and off a multiple of 32 (no bank aliasing
+// between the rows that the lanes of a group read together).
+constexpr int nn_row_stride(int ndes) {
+  return ((ndes + 2 + 3) / 4) * 4 + ((((ndes + 2 + 3) / 4) * 4) % 32 == 0 ? 4 : 0);
+}
 
 // |r_j + n.H - r_i|^2 evaluated in float64 in the order nep.h documents for
 // the neighbour predicate (no fused multiply-add), h = cell vectors as rows.
