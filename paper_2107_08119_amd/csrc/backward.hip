@@ -165,7 +165,6 @@ __global__ __launch_bounds__(kBlock) void k_grad_atoms(
   // network quantities per neuron (neurons split over the lanes)
   const float* w1 = sz;
   const float* b1 = sz + NNEU * NDES;
-  const float* w2 = b1 + NNEU;
   const float ga = (active && gE) ? (float)gE[struct_of[i]] : 0.f;
   if (active) {
     for (int mu = lane; mu < NNEU; mu += L) {

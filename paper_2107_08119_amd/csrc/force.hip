@@ -370,12 +370,15 @@ __device__ __forceinline__ void block_partials(double (&v)[NQ], double* __restri
   if (threadIdx.x < NQ) partials[(size_t)blockIdx.x * NQ + threadIdx.x] = s;
 }
 
-// One block: out[q] = sum over blocks b (in order of b) of partials[b][q].
+// Block x reduces set x: out[x][q] = sum over blocks b (in order of b) of
+// partials[x][b][q].
 template <int NQ>
 __global__ __launch_bounds__(kBlock) void k_finalize(int nblocks, const double* __restrict__ partials,
                                                       double* __restrict__ out,
                                                       int* __restrict__ flags) {
   __shared__ double sw[kBlock / 64][NQ];
+  partials += (size_t)blockIdx.x * nblocks * NQ;
+  out += (size_t)blockIdx.x * NQ;
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
@@ -389,9 +392,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int nblocks, const double* 
   }
 }
 
-// MODE 0: evaluation -> out[13] = (sum U, sum W_ab (9), sum J (3)).
-// MODE 1: velocity-Verlet second half-kick v += kick F, then
-//         out[5] = (E_pot, E_kin, sum J) with the kicked velocities.
+// MODE 0: evaluation -> block sums of (U, W_ab (9), J (3)).
+// MODE 1: velocity-Verlet second half-kick v += kick F, then block sums of
+//         (E_pot, E_kin, J (3)) with the kicked velocities.
+// MODE 2: MODE 1, then the next step's first half-kick v += kick F and drift
+//         pos_next = pos + dt v (a separate array: pos is still being read).
 template <int L, int MODE>
 __global__ __launch_bounds__(kBlock) void k_gather(
     int n, const double* __restrict__ pos, double* __restrict__ vel,
@@ -399,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     const float4* __restrict__ pin, const float* __restrict__ fown, const float* __restrict__ U,
     Box box, float* __restrict__ U_out,
     float* __restrict__ F, float* __restrict__ W, float* __restrict__ J, double kick,
-    double ekin_factor, double* __restrict__ partials) {
+    double ekin_factor, double dt, double* __restrict__ pos_next, double* __restrict__ partials) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gid / L;
   const int lane = gid % L;
@@ -412,24 +417,45 @@ __global__ __launch_bounds__(kBlock) void k_gather(
   float w[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) w[k] = 0.f;
-  for (int s = lane; s < cr; s += L) {
-    const size_t idx = (size_t)s * n + i;
-    int j;
-    float dx, dy, dz;
-    displacement(nl[idx], pos, n, xi, yi, zi, H, j, dx, dy, dz);
-    const float4 pji = pin[idx];
-    f0 -= pji.x;
-    f1 -= pji.y;
-    f2 -= pji.z;
-    w[0] += dx * pji.x;
-    w[1] += dx * pji.y;
-    w[2] += dx * pji.z;
-    w[3] += dy * pji.x;
-    w[4] += dy * pji.y;
-    w[5] += dy * pji.z;
-    w[6] += dz * pji.x;
-    w[7] += dz * pji.y;
-    w[8] += dz * pji.z;
+  // B slots per lane at a time, all their loads issued before any use
+  constexpr int B = 3;
+  for (int s0 = lane; s0 < cr; s0 += B * L) {
+    uint32_t e[B];
+    float4 p[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int s = s0 + u * L;
+      const size_t idx = s < cr ? (size_t)s * n + i : (size_t)i;  // slot 0 when past the end
+      e[u] = nl[idx];
+      p[u] = pin[idx];
+    }
+    double pj[B][3];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int j = (int)(e[u] & kAtomMask);
+      pj[u][0] = pos[j];
+      pj[u][1] = pos[n + j];
+      pj[u][2] = pos[2 * n + j];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (s0 + u * L >= cr) break;
+      float dx, dy, dz;
+      image_displacement(e[u], pj[u][0], pj[u][1], pj[u][2], xi, yi, zi, H, dx, dy, dz);
+      const float4 pji = p[u];
+      f0 -= pji.x;
+      f1 -= pji.y;
+      f2 -= pji.z;
+      w[0] += dx * pji.x;
+      w[1] += dx * pji.y;
+      w[2] += dx * pji.z;
+      w[3] += dy * pji.x;
+      w[4] += dy * pji.y;
+      w[5] += dy * pji.z;
+      w[6] += dz * pji.x;
+      w[7] += dz * pji.y;
+      w[8] += dz * pji.z;
+    }
   }
   f0 = group_sum<L>(f0) + (active ? fown[i] : 0.f);
   f1 = group_sum<L>(f1) + (active ? fown[n + i] : 0.f);
@@ -455,13 +481,24 @@ __global__ __launch_bounds__(kBlock) void k_gather(
       vx = vel[i];
       vy = vel[n + i];
       vz = vel[2 * n + i];
-      if constexpr (MODE == 1) {
+      if constexpr (MODE >= 1) {
         vx += kick * (double)f0;
         vy += kick * (double)f1;
         vz += kick * (double)f2;
-        vel[i] = vx;
-        vel[n + i] = vy;
-        vel[2 * n + i] = vz;
+        if constexpr (MODE == 1) {
+          vel[i] = vx;
+          vel[n + i] = vy;
+          vel[2 * n + i] = vz;
+        } else {
+          const double ux = vx + kick * (double)f0, uy = vy + kick * (double)f1,
+                       uz = vz + kick * (double)f2;
+          vel[i] = ux;
+          vel[n + i] = uy;
+          vel[2 * n + i] = uz;
+          pos_next[i] = xi + dt * ux;
+          pos_next[n + i] = yi + dt * uy;
+          pos_next[2 * n + i] = zi + dt * uz;
+        }
       }
     }
     const double j0 = (double)w[0] * vx + (double)w[1] * vy + (double)w[2] * vz;
@@ -543,13 +580,10 @@ hipError_t launch_partials_population(nep_ctx ctx, nep_dataset ds, int n_pop, co
 }
 
 hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_out, float* F_out,
-                         float* W_out, float* J_out, double* out, int mode, double kick,
-                         double mass) {
+                         float* W_out, float* J_out, double* block_out, int mode, double kick,
+                         double mass, double dt, double* pos_next, bool last) {
   const System& s = ctx->sys;
-  if (s.n == 0) {
-    if (out) launch_kernel(ctx, true, true, k_zero_d, dim3(1), dim3(64), out, mode == 0 ? 13 : 5);
-    return hipGetLastError();
-  }
+  if (s.n == 0) return hipSuccess;
   const unsigned nb = blocks_for((size_t)s.n * kLanes, kBlock);
   const double ekin_factor = 0.5 * mass / kAccel;
   const uint32_t* nl = s.nl.ptr;
@@ -557,19 +591,29 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
   const float4* p = ctx->p.ptr;
   const float* fown = ctx->fown.ptr;
   const float* U = ctx->U.ptr;
-  if (mode == 0) {
-    launch_kernel(ctx, true, false, k_gather<kLanes, 0>, dim3(nb), dim3(kBlock), s.n, pos, vel, nl,
-                  cnt, p, fown, U, s.box, U_out, F_out, W_out, J_out, kick, ekin_factor,
-                  ctx->partials.ptr);
-    launch_kernel(ctx, false, true, k_finalize<13>, dim3(1), dim3(kBlock), (int)nb,
-                  (const double*)ctx->partials.ptr, out, ctx->flags.ptr);
-  } else {
-    launch_kernel(ctx, true, false, k_gather<kLanes, 1>, dim3(nb), dim3(kBlock), s.n, pos, vel, nl,
-                  cnt, p, fown, U, s.box, U_out, F_out, W_out, J_out, kick, ekin_factor,
-                  ctx->partials.ptr);
-    launch_kernel(ctx, false, true, k_finalize<5>, dim3(1), dim3(kBlock), (int)nb,
-                  (const double*)ctx->partials.ptr, out, ctx->flags.ptr);
-  }
+  auto go = [&](auto kernel) {
+    launch_kernel(ctx, true, last, kernel, dim3(nb), dim3(kBlock), s.n, pos, vel, nl, cnt, p, fown,
+                  U, s.box, U_out, F_out, W_out, J_out, kick, ekin_factor, dt, pos_next, block_out);
+  };
+  if (mode == 0)
+    go(k_gather<kLanes, 0>);
+  else if (mode == 1)
+    go(k_gather<kLanes, 1>);
+  else
+    go(k_gather<kLanes, 2>);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(nep_ctx ctx, int nq, int nsets, const double* block_sums, double* out,
+                           bool first) {
+  if (nsets == 0) return hipSuccess;
+  const int nb = (int)gather_blocks(ctx->sys.n);
+  if (nq == 13)
+    launch_kernel(ctx, first, true, k_finalize<13>, dim3(nsets), dim3(kBlock), nb, block_sums, out,
+                  ctx->flags.ptr);
+  else
+    launch_kernel(ctx, first, true, k_finalize<5>, dim3(nsets), dim3(kBlock), nb, block_sums, out,
+                  ctx->flags.ptr);
   return hipGetLastError();
 }
 

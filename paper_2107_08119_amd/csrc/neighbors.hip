@@ -99,20 +99,17 @@ __global__ void k_fill(int n, const int* __restrict__ cell_of, const int* __rest
   members[start[c] + slot] = i;
 }
 
-// Sort every cell's members by atom index (insertion sort; cells are small).
-__global__ void k_sort_cells(int ncell, const int* __restrict__ start, int* __restrict__ members) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  int b = start[c], e = start[c + 1];
-  for (int k = b + 1; k < e; ++k) {
-    int v = members[k];
-    int t = k - 1;
-    while (t >= b && members[t] > v) {
-      members[t + 1] = members[t];
-      --t;
-    }
-    members[t + 1] = v;
-  }
+// Order every cell's members by atom index: each atom counts the members of
+// its cell with a smaller index and takes that place (cells are small).
+__global__ void k_rank_cells(int n, const int* __restrict__ cell_of, const int* __restrict__ start,
+                             const int* __restrict__ members, int* __restrict__ sorted) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cell_of[i];
+  const int b = start[c], e = start[c + 1];
+  int rank = 0;
+  for (int k = b; k < e; ++k) rank += members[k] < i ? 1 : 0;
+  sorted[b + rank] = i;
 }
 
 // Re-sort atoms into cell order: internal index k takes the atom at old index
@@ -177,13 +174,15 @@ __global__ void k_iota(int n, int* __restrict__ a) {
   if (k < n) a[k] = k;
 }
 
-// G lanes per atom (G = 32) scan the 27 surrounding cells twice, first
-// keeping the angular-range entries, then the remaining radial-range entries.
-// The candidates of the 27 cells are numbered consecutively (cell order, then
+// G lanes per atom (G = 32) scan the 27 surrounding cells once.  The
+// candidates of the 27 cells are numbered consecutively (cell order, then
 // member order) and the G lanes test G consecutive candidates at a time; a
 // ballot and a population count give each kept entry the slot a serial scan
-// would give it, so the order does not depend on G.
-template <int G>
+// would give it, so the order does not depend on G.  Angular-range entries
+// go to the list at once; the remaining radial-range entries wait in LDS (up
+// to RO per atom) and follow them when the scan is done.  An atom with more
+// than RO of them scans its cells a second time for that part.
+template <int G, int RO>
 __global__ __launch_bounds__(256) void k_build_cells(
     int n, int cap, const double* __restrict__ pos, Box box, int nc0, int nc1, int nc2,
     const int* __restrict__ wrap, const int* __restrict__ cell_of, const int* __restrict__ start,
@@ -192,6 +191,7 @@ __global__ __launch_bounds__(256) void k_build_cells(
   static_assert(G >= 27 && G <= 64 && 256 % G == 0, "a group covers the 27 cells");
   __shared__ int s_off[256 / G][28];   // first candidate number of each cell
   __shared__ int s_first[256 / G][27]; // first member slot of each cell
+  __shared__ uint32_t s_ro[256 / G][RO];  // radial-only entries in scan order
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int grp = threadIdx.x / G;
   const int k = gid % G;
@@ -228,43 +228,88 @@ __global__ __launch_bounds__(256) void k_build_cells(
   const int total = s_off[grp][27];
   const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
   const int wi0 = wrap[i], wi1 = wrap[n + i], wi2 = wrap[2 * n + i];
-  int count = 0;
   bool overflow = false, bad_image = false;
-  for (int pass = 0; pass < 2; ++pass) {
+  // candidate c: its list entry and squared distance (r2 < 0 for the atom itself)
+  auto candidate = [&](int c, uint32_t& entry, double& r2) {
+    int lo = 0, hi = 27;  // the cell q that holds candidate c: off[q] <= c < off[q+1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_off[grp][mid] <= c)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int q = lo;
+    const int o0 = q % 3 - 1, o1 = (q / 3) % 3 - 1, o2 = q / 9 - 1;
+    const int e0 = c0 + o0, e1 = c1 + o1, e2 = c2 + o2;
+    const int m0 = e0 < 0 ? -1 : (e0 >= nc0 ? 1 : 0);
+    const int m1 = e1 < 0 ? -1 : (e1 >= nc1 ? 1 : 0);
+    const int m2 = e2 < 0 ? -1 : (e2 >= nc2 ? 1 : 0);
+    const CellRec rc = rec[s_first[grp][q] + (c - s_off[grp][q])];
+    const int j = rc.j;
+    const int n0 = m0 + wi0 - (int)(signed char)(rc.w & 0xFF);
+    const int n1 = m1 + wi1 - (int)(signed char)((rc.w >> 8) & 0xFF);
+    const int n2 = m2 + wi2 - (int)(signed char)((rc.w >> 16) & 0xFF);
+    r2 = -1.0;
+    entry = 0;
+    if (!(j == i && n0 == 0 && n1 == 0 && n2 == 0)) {
+      r2 = list_r2(rc.x, rc.y, rc.z, xi, yi, zi, n0, n1, n2, box.h);
+      if (r2 < rc2_r && (n0 < -3 || n0 > 3 || n1 < -3 || n1 > 3 || n2 < -3 || n2 > 3)) {
+        bad_image = true;
+        r2 = -1.0;
+      }
+      entry = pack_entry(j, n0, n1, n2);
+    }
+  };
+  int na = 0, nro = 0;
+  for (int base = 0; base < total; base += G) {
+    const int c = base + k;
+    bool keep_a = false, keep_r = false;
+    uint32_t entry = 0;
+    if (c < total) {
+      double r2;
+      candidate(c, entry, r2);
+      keep_a = r2 >= 0.0 && r2 < rc2_a;
+      keep_r = r2 >= rc2_a && r2 < rc2_r;
+    }
+    const unsigned long long ba = (__ballot(keep_a) >> shift) & gmask;
+    const unsigned long long br = (__ballot(keep_r) >> shift) & gmask;
+    if (keep_a) {
+      const int slot = na + __popcll(ba & below);
+      if (slot < cap)
+        nl[(size_t)slot * n + i] = entry;
+      else
+        overflow = true;
+    }
+    if (keep_r) {
+      const int t = nro + __popcll(br & below);
+      if (t < RO) s_ro[grp][t] = entry;
+    }
+    na += __popcll(ba);
+    nro += __popcll(br);
+  }
+  if (nro <= RO) {
+    // the group's LDS writes above are read back by other lanes of the group
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (int t = k; t < nro; t += G) {
+      const int slot = na + t;
+      if (slot < cap)
+        nl[(size_t)slot * n + i] = s_ro[grp][t];
+      else
+        overflow = true;
+    }
+  } else {
+    int count = na;
     for (int base = 0; base < total; base += G) {
       const int c = base + k;
       bool keep = false;
       uint32_t entry = 0;
       if (c < total) {
-        int lo = 0, hi = 27;  // the cell q that holds candidate c: off[q] <= c < off[q+1]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (s_off[grp][mid] <= c)
-            lo = mid;
-          else
-            hi = mid;
-        }
-        const int q = lo;
-        const int o0 = q % 3 - 1, o1 = (q / 3) % 3 - 1, o2 = q / 9 - 1;
-        const int e0 = c0 + o0, e1 = c1 + o1, e2 = c2 + o2;
-        const int m0 = e0 < 0 ? -1 : (e0 >= nc0 ? 1 : 0);
-        const int m1 = e1 < 0 ? -1 : (e1 >= nc1 ? 1 : 0);
-        const int m2 = e2 < 0 ? -1 : (e2 >= nc2 ? 1 : 0);
-        const CellRec rc = rec[s_first[grp][q] + (c - s_off[grp][q])];
-        const int j = rc.j;
-        const int n0 = m0 + wi0 - (int)(signed char)(rc.w & 0xFF);
-        const int n1 = m1 + wi1 - (int)(signed char)((rc.w >> 8) & 0xFF);
-        const int n2 = m2 + wi2 - (int)(signed char)((rc.w >> 16) & 0xFF);
-        if (!(j == i && n0 == 0 && n1 == 0 && n2 == 0)) {
-          const double r2 = list_r2(rc.x, rc.y, rc.z, xi, yi, zi, n0, n1, n2, box.h);
-          const bool in_a = r2 < rc2_a;
-          keep = pass == 0 ? in_a : (!in_a && r2 < rc2_r);
-          if (keep && (n0 < -3 || n0 > 3 || n1 < -3 || n1 > 3 || n2 < -3 || n2 > 3)) {
-            bad_image = true;
-            keep = false;
-          }
-          entry = pack_entry(j, n0, n1, n2);
-        }
+        double r2;
+        candidate(c, entry, r2);
+        keep = r2 >= rc2_a && r2 < rc2_r;
       }
       const unsigned long long ball = (__ballot(keep) >> shift) & gmask;
       if (keep) {
@@ -276,9 +321,11 @@ __global__ __launch_bounds__(256) void k_build_cells(
       }
       count += __popcll(ball);
     }
-    if (pass == 0 && k == 0) cnt_a[i] = min(count, cap);
   }
-  if (k == 0) cnt_r[i] = min(count, cap);
+  if (k == 0) {
+    cnt_a[i] = min(na, cap);
+    cnt_r[i] = min(na + nro, cap);
+  }
   if (overflow) flags[kFlagOverflow] = 1;
   if (bad_image) flags[kFlagImage] = 1;
 }
@@ -329,7 +376,11 @@ __global__ void k_build_all_pairs(int n, int cap, const double* __restrict__ pos
 // Slot of the reverse entry (i, -n) in atom j's list, for every entry (j, n)
 // of atom i.  One thread per (slot, atom).  |r_ji| = |r_ij| exactly, so the
 // reverse entry lies in the same part (angular prefix or radial rest) of j's
-// list and only that part is searched.
+// list and only that part is searched.  The lists are symmetric unless a list
+// was cut at its capacity (the overflow flag), so the thread of an entry with
+// j > i also writes the reverse slot of the entry it finds, and entries with
+// j < i are left to that thread; after an overflow every entry searches for
+// itself, so that every reverse slot still names a slot inside j's list.
 __global__ void k_reverse(int n, int cap, const uint32_t* __restrict__ nl,
                           const int* __restrict__ cnt_r, const int* __restrict__ cnt_a,
                           int* __restrict__ rev, int* __restrict__ flags) {
@@ -340,6 +391,8 @@ __global__ void k_reverse(int n, int cap, const uint32_t* __restrict__ nl,
   if (s >= cnt_r[i]) return;
   const uint32_t e = nl[idx];
   const int j = (int)(e & kAtomMask);
+  const bool symmetric = flags[kFlagOverflow] == 0;
+  if (symmetric && j < i) return;
   int n0, n1, n2;
   unpack_image(e, n0, n1, n2);
   const uint32_t target = pack_entry(i, -n0, -n1, -n2);
@@ -356,6 +409,8 @@ __global__ void k_reverse(int n, int cap, const uint32_t* __restrict__ nl,
   if (found < 0) {
     flags[kFlagReverse] = 1;
     found = 0;
+  } else if (symmetric && j != i) {
+    rev[(size_t)found * n + j] = s;
   }
   rev[idx] = found;
 }
@@ -489,7 +544,8 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
     if ((e = s.cell_of.ensure(n)) != hipSuccess || (e = s.cell_cnt.ensure(ncell)) != hipSuccess ||
         (e = s.cell_start.ensure((size_t)ncell + 1)) != hipSuccess ||
         (e = s.cell_fill.ensure(ncell)) != hipSuccess ||
-        (e = s.cell_atoms.ensure(n)) != hipSuccess || (e = s.cell_rec.ensure(n)) != hipSuccess ||
+        (e = s.cell_atoms.ensure(n)) != hipSuccess || (e = s.cell_sorted.ensure(n)) != hipSuccess ||
+        (e = s.cell_rec.ensure(n)) != hipSuccess ||
         (e = s.pos_t.ensure((size_t)3 * n)) != hipSuccess ||
         (e = s.vel_t.ensure((size_t)3 * n)) != hipSuccess ||
         (e = s.perm_t.ensure(n)) != hipSuccess || (e = s.wrap_t.ensure((size_t)3 * n)) != hipSuccess ||
@@ -507,10 +563,11 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
     launch_kernel(ctx, false, false, k_fill, dim3(blocks_for(n, kBlock)), blk, n,
                   (const int*)s.cell_of.ptr, (const int*)s.cell_start.ptr, s.cell_fill.ptr,
                   s.cell_atoms.ptr);
-    launch_kernel(ctx, false, false, k_sort_cells, dim3(blocks_for(ncell, kBlock)), blk, ncell,
-                  (const int*)s.cell_start.ptr, s.cell_atoms.ptr);
+    launch_kernel(ctx, false, false, k_rank_cells, dim3(blocks_for(n, kBlock)), blk, n,
+                  (const int*)s.cell_of.ptr, (const int*)s.cell_start.ptr,
+                  (const int*)s.cell_atoms.ptr, s.cell_sorted.ptr);
     launch_kernel(ctx, false, false, k_permute, dim3(blocks_for(n, kBlock)), blk, n,
-                  (const int*)s.cell_atoms.ptr, (const double*)s.pos_s.ptr, s.pos_t.ptr,
+                  (const int*)s.cell_sorted.ptr, (const double*)s.pos_s.ptr, s.pos_t.ptr,
                   have_vel ? (const double*)s.vel_s.ptr : (const double*)nullptr,
                   have_vel ? s.vel_t.ptr : (double*)nullptr, (const int*)s.wrap.ptr, s.wrap_t.ptr,
                   (const int*)s.perm.ptr, s.perm_t.ptr, (const int*)s.cell_of.ptr, s.cell_t.ptr,
@@ -521,7 +578,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
     s.perm.swap(s.perm_t);
     s.cell_of.swap(s.cell_t);
     constexpr int G = 32;
-    launch_kernel(ctx, false, false, k_build_cells<G>, dim3(blocks_for((size_t)n * G, kBlock)),
+    launch_kernel(ctx, false, false, k_build_cells<G, 64>, dim3(blocks_for((size_t)n * G, kBlock)),
                   blk, n, s.cap, (const double*)s.pos_s.ptr, s.box, s.nc[0], s.nc[1], s.nc[2],
                   (const int*)s.wrap.ptr, (const int*)s.cell_of.ptr,
                   (const int*)s.cell_start.ptr, (const CellRec*)s.cell_rec.ptr, rc2_r, rc2_a,

@@ -46,6 +46,7 @@ nep_status size_system_buffers(nep_ctx ctx) {
       (e = ctx->W.ensure((size_t)9 * s.n)) != hipSuccess ||
       (e = ctx->J.ensure((size_t)3 * s.n)) != hipSuccess ||
       (e = sm.pos_s.ensure((size_t)3 * s.n)) != hipSuccess ||
+      (e = sm.pos_t.ensure((size_t)3 * s.n)) != hipSuccess ||
       (e = sm.vel_s.ensure((size_t)3 * s.n)) != hipSuccess ||
       (e = sm.perm.ensure((size_t)s.n)) != hipSuccess ||
       (e = ctx->partials.ensure(gather_blocks(s.n) * 16 + 16)) != hipSuccess)
@@ -54,16 +55,24 @@ nep_status size_system_buffers(nep_ctx ctx) {
 }
 
 // One force evaluation of the internal state (positions sys.pos_s, velocities
-// sys.vel_s when vel is true): pass 1 and pass 2 into the internal U, F, W, J.
+// sys.vel_s when vel is true): pass 1 and pass 2 into the internal U, F, W, J,
+// with the totals (13 values, or 5 thermo values in the MD modes) in out.
+// MD modes: block sums go to block_out and are reduced later (out unused).
 hipError_t evaluate_internal(nep_ctx ctx, bool vel, double* out, int mode, double kick,
-                             double mass, bool want_w = false, bool want_j = false) {
+                             double mass, bool want_w = false, bool want_j = false,
+                             double* block_out = nullptr, double dt = 0.0,
+                             double* pos_next = nullptr) {
   System& s = ctx->sys;
   hipError_t e = timed(ctx, 0, [&] { return launch_partials(ctx, s.pos_s.ptr); });
   if (e != hipSuccess) return e;
+  double* sums = block_out ? block_out : ctx->partials.ptr;
   return timed(ctx, 1, [&] {
-    return launch_gather(ctx, s.pos_s.ptr, vel ? s.vel_s.ptr : nullptr, nullptr, ctx->F.ptr,
-                         want_w ? ctx->W.ptr : nullptr, want_j ? ctx->J.ptr : nullptr, out, mode,
-                         kick, mass);
+    hipError_t r = launch_gather(ctx, s.pos_s.ptr, vel ? s.vel_s.ptr : nullptr, nullptr,
+                                 ctx->F.ptr, want_w ? ctx->W.ptr : nullptr,
+                                 want_j ? ctx->J.ptr : nullptr, sums, mode, kick, mass, dt,
+                                 pos_next, block_out != nullptr);
+    if (r != hipSuccess || block_out) return r;
+    return launch_finalize(ctx, mode == 0 ? 13 : 5, 1, sums, out, s.n == 0);
   });
 }
 
@@ -297,9 +306,17 @@ nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every
     if (e != hipSuccess) return check_hip(ctx, e, "launching force kernels");
   }
   ctx->md_forces_valid = false;
+  // Thermo block sums of up to `chunk` steps are kept and reduced together.
+  const size_t nb = gather_blocks(n);
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)4 << 20) / (nb * 5 + 1)));
+  if ((e = ctx->partials.ensure((size_t)chunk * nb * 5 + 16)) != hipSuccess)
+    return check_hip(ctx, e, "allocating thermo sums");
+  int pending = 0;
+  // first half-kick and drift of step 0; later steps get theirs from the
+  // previous step's pass 2
+  e = timed(ctx, 3, [&] { return launch_kick_drift(ctx, s.pos_s.ptr, s.vel_s.ptr, kick, dt_fs); });
+  if (e != hipSuccess) return check_hip(ctx, e, "launching integrator");
   for (int step = 0; step < n_steps; ++step) {
-    e = timed(ctx, 3, [&] { return launch_kick_drift(ctx, s.pos_s.ptr, s.vel_s.ptr, kick, dt_fs); });
-    if (e != hipSuccess) return check_hip(ctx, e, "launching integrator");
     if (++ctx->steps_since_rebuild >= rebuild_every) {
       if (n > 0) {
         nep_status st = NEP_OK;
@@ -312,11 +329,22 @@ nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every
       }
       ctx->steps_since_rebuild = 0;
     }
-    e = evaluate_internal(ctx, true, thermo_dev + (size_t)5 * step, 1, kick, mass_amu,
-                          W_dev != nullptr, J_dev != nullptr);
+    const bool last = step == n_steps - 1;
+    e = evaluate_internal(ctx, true, nullptr, last ? 1 : 2, kick, mass_amu, W_dev != nullptr,
+                          J_dev != nullptr, ctx->partials.ptr + (size_t)pending * nb * 5, dt_fs,
+                          last ? nullptr : s.pos_t.ptr);
     if (e != hipSuccess) return check_hip(ctx, e, "launching force kernels");
+    if (!last && n > 0) s.pos_s.swap(s.pos_t);
     if (W_dev) launch_put_rows(ctx, n, 9, ctx->W.ptr, W_dev);
     if (J_dev) launch_put_rows(ctx, n, 3, ctx->J.ptr, J_dev);
+    if (++pending == chunk || last) {
+      e = timed(ctx, 3, [&] {
+        return launch_finalize(ctx, 5, pending, ctx->partials.ptr,
+                               thermo_dev + (size_t)5 * (step + 1 - pending), true);
+      });
+      if (e != hipSuccess) return check_hip(ctx, e, "launching thermo sums");
+      pending = 0;
+    }
   }
   launch_put_rows(ctx, n, 3, s.pos_s.ptr, pos_dev);
   launch_put_rows(ctx, n, 3, s.vel_s.ptr, vel_dev);

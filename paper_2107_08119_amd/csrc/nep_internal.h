@@ -107,7 +107,8 @@ struct System {
   DevBuf<int> cell_cnt;    // [ncell]
   DevBuf<int> cell_start;  // [ncell+1]
   DevBuf<int> cell_fill;   // [ncell]
-  DevBuf<int> cell_atoms;  // [n]
+  DevBuf<int> cell_atoms;  // [n] members of each cell, in arrival order
+  DevBuf<int> cell_sorted;  // [n] members of each cell, by atom index
   DevBuf<CellRec> cell_rec;  // [n] positions and offsets in cell order
   // The library works on its own copies of positions and velocities in cell
   // order (re-sorted at every rebuild); perm[k] is the caller's index of the
@@ -127,6 +128,7 @@ struct System {
     cell_start.release();
     cell_fill.release();
     cell_atoms.release();
+    cell_sorted.release();
     cell_rec.release();
     pos_s.release();
     pos_t.release();
@@ -242,9 +244,14 @@ bool have_force_variant(const nep_hyper& h);
 hipError_t launch_partials(nep_ctx ctx, const double* pos);
 // mode 0: plain evaluation (totals = E, W(9), J(3)); mode 1: velocity-Verlet
 // second half-kick fused (vel updated, thermo row written).
+// Pass 2 (k_gather, modes as documented there) writing per-block sums to
+// block_out [gather_blocks(n)][13 or 5]; launch_finalize adds nsets such
+// arrays (consecutive in block_sums) into out [nsets][nq].
 hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_out, float* F_out,
-                         float* W_out, float* J_out, double* out, int mode, double kick,
-                         double mass);
+                         float* W_out, float* J_out, double* block_out, int mode, double kick,
+                         double mass, double dt, double* pos_next, bool last);
+hipError_t launch_finalize(nep_ctx ctx, int nq, int nsets, const double* block_sums, double* out,
+                           bool first);
 size_t gather_blocks(int n);
 hipError_t launch_kick_drift(nep_ctx ctx, double* pos, double* vel, double kick, double dt);
 // pass 1 over a dataset for n_pop parameter vectors Z [n_pop][n_par].

@@ -235,3 +235,30 @@ def test_md_energy_error_scales_as_dt_squared():
         spans.append(e.max() - e.min())
     ratio = spans[0] / spans[1]
     assert 3.0 < ratio < 5.5, (spans, ratio)
+
+
+def test_md_in_pieces_matches_one_call():
+    """A trajectory split over several md_step calls (rebuilds straddling the
+    calls, thermo sums reduced in chunks of up to 64 steps) equals one call bit
+    for bit, on a box large enough for the cell-list path; its first steps
+    match the oracle."""
+    nep = nep_mod()
+    pos, box = I.diamond_supercell(4, 4, 4)  # 512 atoms, 21.7 A: 3 cells per edge
+    rng = np.random.default_rng(11)
+    pos = I.wrap_positions(pos + rng.normal(0.0, 0.05, pos.shape), box)
+    z = I.random_parameters(931, 1)
+    vel = I.maxwell_boltzmann(len(pos), 300.0, 2)
+    runs = []
+    for pieces in ((74,), (3, 70, 1)):
+        ctx = nep.Context(0)
+        ctx.load_params(nep.hyper(), z)
+        p, v = nep.soa(pos), nep.soa(vel)
+        ctx.build_neighbors(p, box, skin=0.5, max_neighbors=64)
+        th = [ctx.md_step(k, 1.0, 10, I.MASS_SI, p, v).cpu().numpy() for k in pieces]
+        ctx.synchronize()
+        runs.append((np.concatenate(th), nep.aos(p), nep.aos(v)))
+    for a, b in zip(runs[0], runs[1]):
+        np.testing.assert_array_equal(a, b)
+    th_ref, _, _ = O.md_nve(OH, z, pos, box, vel, I.MASS_SI, 1.0, 12)
+    assert rel(runs[0][0][:12, 0], th_ref[:, 0]) < TOL
+    assert rel(runs[0][0][:12, 1], th_ref[:, 1]) < TOL
