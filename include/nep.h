@@ -191,10 +191,30 @@ void nep_dataset_destroy(nep_dataset ds);
  *   L_v = sqrt(sum_{s with virial} sum_6 ((W_s - W_s^tar)/N_s)^2 / (6 N_v)),
  *   L_1 = mean |z|,  L_2 = sqrt(mean z^2),
  * where U_s and W_s = sum_i W_i are the NEP energy and virial of structure s.
- * All individuals are evaluated by the same launches; sums are float64 in a
- * fixed order.  The dataset must belong to ctx and match its hyperparameters. */
+ * All individuals are evaluated by the same launches (pass 1 of every
+ * individual on every atom, then one block per structure and individual),
+ * reusing pair records and descriptors cached when the dataset's positions
+ * were set; sums are float64 in a fixed order.  The kernels use the tile
+ * shape chosen by snes_autotune (4 lanes per atom until then).  The dataset
+ * must belong to ctx and match its hyperparameters.  NEP_EINVAL if the
+ * dataset exceeds one launch (more than 65535 structures or about 2 million
+ * atoms). */
 nep_status snes_eval_population(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z_dev,
                                 const double* lambda_host, double* loss_dev);
+
+/* Tile-shape autotuner for snes_eval_population on this dataset: times each
+ * compiled shape of the population kernels (2, 4 and 8 lanes per atom; 128,
+ * 64 and 32 atoms per block) over `reps` evaluations (1..1000) of Z_dev
+ * [n_pop][N_par] with HIP events on the context's stream, and keeps the
+ * fastest for later calls on the dataset.  Host outputs (either may be NULL):
+ * *lanes_out = chosen lanes per atom; ms_out[3] = mean ms per evaluation of
+ * the shapes in the order above.  Waits for the stream. */
+nep_status snes_autotune(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z_dev, int reps,
+                         int* lanes_out, double* ms_out);
+
+/* Use `lanes` (2, 4 or 8) lanes per atom in the population kernels of this
+ * dataset, e.g. to reproduce a tuned choice.  NEP_EINVAL for other values. */
+nep_status snes_set_tile(nep_ctx ctx, nep_dataset ds, int lanes);
 
 /* Draw the population of generation `generation` (Sec. II E 2, step 2a):
  * r_dev [n_pop][n_par] standard normal (float32) and Z_dev = m + s . r
@@ -215,6 +235,24 @@ nep_status snes_sample(nep_ctx ctx, int n_par, int n_pop, const float* m_dev, co
  * selects (3 + ln n_par) / (5 sqrt(n_par)).  1 <= n_pop <= 1024. */
 nep_status snes_update(nep_ctx ctx, int n_par, int n_pop, float* m_dev, float* s_dev,
                        const float* r_dev, const double* loss_dev, double eta_m, double eta_s);
+
+/* n_gen generations of SNES on the device (Sec. II E 2): generation g =
+ * generation .. generation + n_gen - 1 runs snes_sample (seed, g),
+ * snes_eval_population and snes_update exactly as the separate calls do,
+ * with m_dev, s_dev [n_par] updated in place and r_dev, Z_dev
+ * [n_pop][n_par], loss_dev [n_pop][6] as their workspaces (they hold the last
+ * generation's values afterwards).  best_dev [n_gen][6] (float64, may be
+ * NULL) receives the loss terms of each generation's best individual (NaN
+ * ranks last, ties by index).  The generation's launches are captured once
+ * into a HIP graph and replayed n_gen times on the context's stream; the
+ * generation counter lives in device memory, so nothing returns to the host
+ * between generations.  The graph is kept for the next call with the same
+ * arguments.  n_par must equal N_par of the loaded hyperparameters;
+ * 1 <= n_pop <= 1024. */
+nep_status snes_run(nep_ctx ctx, nep_dataset ds, int n_par, int n_pop, float* m_dev,
+                    float* s_dev, unsigned long long seed, int generation, int n_gen,
+                    const double* lambda_host, double eta_m, double eta_s, float* r_dev,
+                    float* Z_dev, double* loss_dev, double* best_dev);
 
 /* -------------------------------------------------------- differentiation */
 

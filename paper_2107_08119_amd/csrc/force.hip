@@ -2,18 +2,10 @@
 // and the scatter-free gather of forces, virials and heat currents (pass 2).
 //
 // Pass 1 works on L consecutive lanes per atom.  The lanes split the atom's
-// neighbour slots, accumulate partial descriptor sums, and combine them with
-// DPP lane permutations, so every lane ends with the full descriptor.  The
-// angular descriptor (Eq. qinl) is evaluated in the factorised form that the
-// addition theorem gives (paper, text after Eq. N_des): with real harmonics
-// Yhat_lm normalised so that sum_m Yhat_lm(u) Yhat_lm(v) = P_l(u.v),
-//   q_nl = sum_j sum_k g_n(r_ij) g_n(r_ik) P_l(cos theta_ijk) = sum_m c_nlm^2,
-//   c_nlm = sum_j g_n(r_ij) Yhat_lm(r_ij / r_ij),
-// which costs O(M) per atom instead of O(M^2) and equals the double sum
-// (j = k terms included) up to rounding.  The partial force (Sec. II D) is
-//   dU_i/dr_ij = sum_n dU/dq_n g_n'(r) u
-//              + sum_lm [ B_lm Yhat_lm(u) u + A_lm (grad Yhat_lm - u (u.grad Yhat_lm)) / r ],
-// with a_nlm = 2 dU/dq_nl c_nlm, A_lm = sum_n a_nlm g_n(r), B_lm = sum_n a_nlm g_n'(r).
+// pairs, accumulate partial descriptor sums, and combine them with DPP lane
+// permutations, so every lane ends with the full descriptor.  The model's
+// terms (factorised angular descriptor, network, partial force) are in
+// nep_terms.h.
 //
 // Pass 1 also sums the atom's own partials, sum_j p_ij, and stores every p_ij
 // in the reverse slot of atom j's list (each slot is written exactly once).
@@ -22,7 +14,7 @@
 // reads of its own slots; no atomics touch forces and the result is
 // reproducible bit for bit.  Totals are summed in float64 per block and the
 // block sums are added in block order by a one-block kernel.
-#include "nep_device.h"
+#include "nep_terms.h"
 
 namespace nep {
 namespace {
@@ -37,16 +29,15 @@ constexpr int kStage = 40;  // neighbour slots per atom staged in LDS by pass 1
 // Population: blockIdx.y selects parameter vector k at zpar + k*zstride and
 // its outputs at pin + k*pstride, fown + 3nk, U + nk.
 template <int NR, int NA, int LMAX, int NNEU, int L, bool MULTI>
-__global__ __launch_bounds__(kBlock) void k_partials(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_partials(
     int n, const double* __restrict__ pos, const uint32_t* __restrict__ nl,
     const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, const int* __restrict__ rev,
     Box box, const double* __restrict__ boxes, const int* __restrict__ struct_of,
     const float* __restrict__ zpar, size_t zstride, float rc_r, float rc_a,
     float4* __restrict__ pin, size_t pstride, float* __restrict__ fown, float* __restrict__ U) {
-  constexpr int NLM = (LMAX + 1) * (LMAX + 1) - 1;
-  constexpr int NDES = NR + NA * LMAX;
-  constexpr int RS = nn_row_stride(NDES);  // LDS row of neuron mu: w1[mu][:], b1, w2, padding
-  __shared__ float4 sw4[NNEU * RS / 4];
+  constexpr int NLM = Model<NR, NA, LMAX>::kNLM;
+  constexpr int NDES = Model<NR, NA, LMAX>::kNDES;
+  __shared__ float4 sw4[NetRows<NDES, NNEU>::kFloat4];
   __shared__ float sb2;
   {
     const size_t pk = blockIdx.y;
@@ -55,21 +46,7 @@ __global__ __launch_bounds__(kBlock) void k_partials(
     fown += pk * 3 * (size_t)n;
     U += pk * (size_t)n;
   }
-  {
-    float* sw = reinterpret_cast<float*>(sw4);
-    for (int t = threadIdx.x; t < NNEU * RS; t += blockDim.x) {
-      const int mu = t / RS, v = t % RS;
-      float w = 0.f;
-      if (v < NDES)
-        w = zpar[mu * NDES + v];
-      else if (v == NDES)
-        w = zpar[NNEU * NDES + mu];
-      else if (v == NDES + 1)
-        w = zpar[NNEU * (NDES + 1) + mu];
-      sw[t] = w;
-    }
-    if (threadIdx.x == 0) sb2 = zpar[NNEU * (NDES + 2)];
-  }
+  load_net_rows<NDES, NNEU>(zpar, sw4, &sb2);
 
   // Stage the first kStage slots of the block's atoms in LDS, keeping only
   // the pairs inside a cutoff, compacted per atom: first the pairs inside
@@ -212,30 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_partials(
     bool ang, rad;
     float dx, dy, dz;
     pair(k, dx, dy, dz, dst, ang, rad);
-    const float r2 = pair_r2(dx, dy, dz);
-    const float rinv = __builtin_amdgcn_rsqf(r2);
-    const float r = r2 * rinv;
-    if (rad) {
-      float g[NR];
-      radial_basis<NR, false>(r, rcr_inv, g, nullptr);
-#pragma unroll
-      for (int a = 0; a < NR; ++a) q[a] += g[a];
-    }
-    if (ang) {
-      float g[NA];
-      radial_basis<NA, false>(r, rca_inv, g, nullptr);
-      const float x = dx * rinv, y = dy * rinv, z = dz * rinv;
-      const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
-      const float xyz = xy * z;
-      (void)xyz;
-#define NEP_ACC(idx, YV, GX, GY, GZ)                    \
-  if constexpr ((idx) < NLM) {                          \
-    const float yv = (YV);                              \
-    _Pragma("unroll") for (int a = 0; a < NA; ++a) c[a][idx] += g[a] * yv; \
-  }
-      NEP_YLM_TABLE(NEP_ACC)
-#undef NEP_ACC
-    }
+    pair_descriptor<NR, NA, LMAX>(dx, dy, dz, rad, ang, rcr_inv, rca_inv, q, c);
   }
 #pragma unroll
   for (int a = 0; a < NR; ++a) q[a] = group_sum<L>(q[a]);
@@ -243,59 +197,13 @@ __global__ __launch_bounds__(kBlock) void k_partials(
   for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int m = 0; m < NLM; ++m) c[a][m] = group_sum<L>(c[a][m]);
-  // angular components q_nl = sum_m c_nlm^2
-#pragma unroll
-  for (int a = 0; a < NA; ++a)
-#pragma unroll
-    for (int l = 1; l <= LMAX; ++l) {
-      float s2 = 0.f;
-#pragma unroll
-      for (int m = 0; m < 2 * l + 1; ++m) s2 += c[a][l * l - 1 + m] * c[a][l * l - 1 + m];
-      q[NR + a * LMAX + (l - 1)] = s2;
-    }
+  angular_invariants<NR, NA, LMAX>(c, q);
 
-  // network (Eqs. nn1, nn2) and dU/dq; the neurons are split over the lanes
   float dq[NDES];
-#pragma unroll
-  for (int v = 0; v < NDES; ++v) dq[v] = 0.f;
-  float u = 0.f;
-  for (int mu = lane; mu < NNEU; mu += L) {
-    float w[RS];
-#pragma unroll
-    for (int t = 0; t < RS / 4; ++t) {
-      const float4 r4 = sw4[mu * (RS / 4) + t];
-      w[4 * t] = r4.x;
-      w[4 * t + 1] = r4.y;
-      w[4 * t + 2] = r4.z;
-      w[4 * t + 3] = r4.w;
-    }
-    float act = -w[NDES];
-#pragma unroll
-    for (int v = 0; v < NDES; ++v) act += w[v] * q[v];
-    // tanh and its derivative 1 - tanh^2 from e = exp(-2|a|) (no cancellation)
-    const float ea = __expf(-2.f * fabsf(act));
-    const float inv = __builtin_amdgcn_rcpf(1.f + ea);
-    const float th = copysignf((1.f - ea) * inv, act);
-    const float sech2 = 4.f * ea * inv * inv;
-    u += w[NDES + 1] * th;
-    const float gmu = w[NDES + 1] * sech2;
-#pragma unroll
-    for (int v = 0; v < NDES; ++v) dq[v] += gmu * w[v];
-  }
-  u = group_sum<L>(u) - sb2;
-#pragma unroll
-  for (int v = 0; v < NDES; ++v) dq[v] = group_sum<L>(dq[v]);
+  float u;
+  network<NDES, NNEU, L>(q, sw4, sb2, lane, dq, u);
   if (active && lane == 0) U[i] = u;
-
-  // a_nlm = 2 dU/dq_nl c_nlm, stored in place of c
-#pragma unroll
-  for (int a = 0; a < NA; ++a)
-#pragma unroll
-    for (int l = 1; l <= LMAX; ++l) {
-      const float f = 2.f * dq[NR + a * LMAX + (l - 1)];
-#pragma unroll
-      for (int m = 0; m < 2 * l + 1; ++m) c[a][l * l - 1 + m] *= f;
-    }
+  angular_coefficients<NR, NA, LMAX>(dq, c);
 
   // partial forces p_ij = dU_i/dr_ij for this lane's pairs
   float fx = 0.f, fy = 0.f, fz = 0.f;
@@ -304,47 +212,8 @@ __global__ __launch_bounds__(kBlock) void k_partials(
     bool ang, rad;
     float dx, dy, dz;
     pair(k, dx, dy, dz, dst, ang, rad);
-    const float r2 = pair_r2(dx, dy, dz);
-    const float rinv = __builtin_amdgcn_rsqf(r2);
-    const float r = r2 * rinv;
-    const float x = dx * rinv, y = dy * rinv, z = dz * rinv;
-    float px = 0.f, py = 0.f, pz = 0.f;
-    if (rad) {
-      float g[NR], dg[NR];
-      radial_basis<NR, true>(r, rcr_inv, g, dg);
-      float f = 0.f;
-#pragma unroll
-      for (int a = 0; a < NR; ++a) f += dq[a] * dg[a];
-      px += f * x;
-      py += f * y;
-      pz += f * z;
-    }
-    if (ang) {
-      float g[NA], dg[NA];
-      radial_basis<NA, true>(r, rca_inv, g, dg);
-      const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
-      const float xyz = xy * z;
-      (void)xyz;
-      float sb = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-#define NEP_PF(idx, YV, GX, GY, GZ)                 \
-  if constexpr ((idx) < NLM) {                      \
-    float A = 0.f, B = 0.f;                         \
-    _Pragma("unroll") for (int a = 0; a < NA; ++a) { \
-      A += c[a][idx] * g[a];                        \
-      B += c[a][idx] * dg[a];                       \
-    }                                               \
-    sb += B * (YV);                                 \
-    gx += A * (GX);                                 \
-    gy += A * (GY);                                 \
-    gz += A * (GZ);                                 \
-  }
-      NEP_YLM_TABLE(NEP_PF)
-#undef NEP_PF
-      const float ug = x * gx + y * gy + z * gz;
-      px += sb * x + (gx - x * ug) * rinv;
-      py += sb * y + (gy - y * ug) * rinv;
-      pz += sb * z + (gz - z * ug) * rinv;
-    }
+    float px, py, pz;
+    pair_force<NR, NA, LMAX>(dx, dy, dz, rad, ang, rcr_inv, rca_inv, dq, c, px, py, pz);
     fx += px;
     fy += py;
     fz += pz;

@@ -118,6 +118,8 @@ void nep_destroy(nep_ctx ctx) {
   ctx->partials.release();
   ctx->totals.release();
   ctx->flags.release();
+  ctx->snes_graph.release();
+  ctx->gen_counter.release();
   delete ctx;
 }
 

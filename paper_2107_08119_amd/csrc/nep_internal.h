@@ -157,6 +157,25 @@ struct KernelTimer {
 
 }  // namespace nep
 
+namespace nep {
+// A generation of snes_run captured as a HIP graph, with everything it was
+// captured for (pointers, sizes, rates, kernel shape).
+struct SnesGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> ptr_key;
+  std::vector<double> val_key;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    ptr_key.clear();
+    val_key.clear();
+  }
+};
+}  // namespace nep
+
 struct nep_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -186,6 +205,10 @@ struct nep_ctx_s {
   nep::KernelTimer timer;
   // events of the kernel class being launched (set by nep::timed)
   hipEvent_t ev_first = nullptr, ev_last = nullptr;
+  // snes_run: generation counter and first generation of the call, and the
+  // captured generation
+  nep::DevBuf<int> gen_counter;  // [2]
+  nep::SnesGraph snes_graph;
 };
 
 // A training set on the device (structures concatenated).
@@ -206,18 +229,44 @@ struct nep_dataset_s {
   nep::DevBuf<int> has_v;      // [S]
   nep::DevBuf<uint32_t> nl;    // [cap][N]
   nep::DevBuf<int> cnt_r, cnt_a, rev, wrap;
+  // geometry cache for population evaluation (positions are fixed)
+  nep::DevBuf<float4> prec;    // [cap][N] compacted in-range pairs: r_ij, reverse record
+  nep::DevBuf<int> pcidx;      // [cap][N] compacted index of each list slot, or -1
+  nep::DevBuf<int> pn_ang;     // [N] pairs inside r_c^A (they come first)
+  nep::DevBuf<int> pn_in;      // [N] pairs inside a cutoff
+  nep::DevBuf<float> desc;     // [N][152] q_i (29) and c_nlm (120), padded
+  int pop_variant = 1;         // population kernel shape: 0, 1, 2 = 2, 4, 8 lanes per atom
+  unsigned long long serial = 0;  // unique per dataset created by the process
+  bool pop_tuned = false;
   // population workspace
   nep::DevBuf<float4> pin;          // [pop][cap][N]
   nep::DevBuf<float> fown;          // [pop][3][N]
   nep::DevBuf<float> U;             // [pop][N]
-  nep::DevBuf<double> atom_terms;   // [pop][8][N] (loss) or [10][N] (forward)
-  nep::DevBuf<double> struct_sq;    // [pop][S][3]
+  nep::DevBuf<double> atom_terms;   // [10][N] per-atom U and W (forward)
+  nep::DevBuf<double> struct_sq;    // [pop][S][3] squared errors per structure
   // backward workspace
   nep::DevBuf<float> grad_rec;      // [fields][N]
   nep::DevBuf<double> grad_part;    // [blocks][N_par]
+  void release_cache() {
+    prec.release();
+    pcidx.release();
+    pn_ang.release();
+    pn_in.release();
+    desc.release();
+  }
 };
 
 namespace nep {
+
+// population.hip
+// Pair records and per-atom descriptors of a dataset's current positions.
+hipError_t prepare_dataset_geometry(nep_ctx ctx, nep_dataset ds);
+// Loss sums sq[k][s][3] of n_pop individuals (Z [n_pop][N_par]) with the
+// given kernel variant (0..population_variants()-1).
+hipError_t launch_population(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z, int variant,
+                             bool first);
+int population_variants();
+int population_lanes(int variant);
 
 // neighbours.hip
 // Build the list of the internal positions sys.pos_s; on the cell path the

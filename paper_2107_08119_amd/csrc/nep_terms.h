@@ -1,0 +1,207 @@
+// Per-pair and per-atom terms of the NEP model shared by the force kernels:
+// descriptor accumulation of one pair, the network with its input gradient,
+// and the partial force of one pair.
+//
+// The angular descriptor (Eq. qinl) is used in the factorised form that the
+// addition theorem gives (paper, text after Eq. N_des): with real harmonics
+// Yhat_lm normalised so that sum_m Yhat_lm(u) Yhat_lm(v) = P_l(u.v),
+//   q_nl = sum_j sum_k g_n(r_ij) g_n(r_ik) P_l(cos theta_ijk) = sum_m c_nlm^2,
+//   c_nlm = sum_j g_n(r_ij) Yhat_lm(r_ij / r_ij),
+// which equals the double sum (j = k terms included) up to rounding.  The
+// partial force (Sec. II D) is
+//   dU_i/dr_ij = sum_n dU/dq_n g_n'(r) u
+//              + sum_lm [ B_lm Yhat_lm(u) u + A_lm (grad Yhat_lm - u (u.grad Yhat_lm)) / r ],
+// with a_nlm = 2 dU/dq_nl c_nlm, A_lm = sum_n a_nlm g_n(r), B_lm = sum_n a_nlm g_n'(r).
+#pragma once
+
+#include "nep_device.h"
+
+namespace nep {
+
+template <int NR, int NA, int LMAX>
+struct Model {
+  static constexpr int kNLM = (LMAX + 1) * (LMAX + 1) - 1;  // harmonics l = 1..LMAX
+  static constexpr int kNDES = NR + NA * LMAX;
+};
+
+// Add pair (dx, dy, dz) to the radial sums q[0..NR) (when rad) and to the
+// angular moments c[NA][NLM] (when ang).
+template <int NR, int NA, int LMAX>
+__device__ __forceinline__ void pair_descriptor(float dx, float dy, float dz, bool rad, bool ang,
+                                                float rcr_inv, float rca_inv, float* q,
+                                                float (&c)[NA][Model<NR, NA, LMAX>::kNLM]) {
+  constexpr int NLM = Model<NR, NA, LMAX>::kNLM;
+  const float r2 = pair_r2(dx, dy, dz);
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float r = r2 * rinv;
+  if (rad) {
+    float g[NR];
+    radial_basis<NR, false>(r, rcr_inv, g, nullptr);
+#pragma unroll
+    for (int a = 0; a < NR; ++a) q[a] += g[a];
+  }
+  if (ang) {
+    float g[NA];
+    radial_basis<NA, false>(r, rca_inv, g, nullptr);
+    const float x = dx * rinv, y = dy * rinv, z = dz * rinv;
+    const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+    const float xyz = xy * z;
+    (void)xyz;
+#define NEP_ACC(idx, YV, GX, GY, GZ)                                        \
+  if constexpr ((idx) < NLM) {                                              \
+    const float yv = (YV);                                                  \
+    _Pragma("unroll") for (int a = 0; a < NA; ++a) c[a][idx] += g[a] * yv; \
+  }
+    NEP_YLM_TABLE(NEP_ACC)
+#undef NEP_ACC
+  }
+}
+
+// Angular components q[NR + n LMAX + l - 1] = sum_m c_nlm^2.
+template <int NR, int NA, int LMAX>
+__device__ __forceinline__ void angular_invariants(const float (&c)[NA][Model<NR, NA, LMAX>::kNLM],
+                                                   float* q) {
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int l = 1; l <= LMAX; ++l) {
+      float s2 = 0.f;
+#pragma unroll
+      for (int m = 0; m < 2 * l + 1; ++m) s2 += c[a][l * l - 1 + m] * c[a][l * l - 1 + m];
+      q[NR + a * LMAX + (l - 1)] = s2;
+    }
+}
+
+// LDS layout of the network: NNEU rows of RS floats (w1 row, b1, w2, padding).
+template <int NDES, int NNEU>
+struct NetRows {
+  static constexpr int RS = nn_row_stride(NDES);
+  static constexpr int kFloat4 = NNEU * RS / 4;
+};
+
+// Fill the LDS rows from z = [w1 (NNEU x NDES), b1, w2, b2]; returns nothing,
+// b2 goes to *b2_out (thread 0).  All threads of the block take part.
+template <int NDES, int NNEU>
+__device__ __forceinline__ void load_net_rows(const float* __restrict__ z, float4* rows,
+                                              float* b2_out) {
+  constexpr int RS = NetRows<NDES, NNEU>::RS;
+  float* sw = reinterpret_cast<float*>(rows);
+  for (int t = threadIdx.x; t < NNEU * RS; t += blockDim.x) {
+    const int mu = t / RS, v = t % RS;
+    float w = 0.f;
+    if (v < NDES)
+      w = z[mu * NDES + v];
+    else if (v == NDES)
+      w = z[NNEU * NDES + mu];
+    else if (v == NDES + 1)
+      w = z[NNEU * (NDES + 1) + mu];
+    sw[t] = w;
+  }
+  if (threadIdx.x == 0) *b2_out = z[NNEU * (NDES + 2)];
+}
+
+// The network (Eqs. nn1, nn2) and dU/dq, neurons split over the L lanes of
+// the atom's group; every lane ends with the full U and dq.
+template <int NDES, int NNEU, int L>
+__device__ __forceinline__ void network(const float* q, const float4* rows, float b2, int lane,
+                                        float* dq, float& u) {
+  constexpr int RS = NetRows<NDES, NNEU>::RS;
+#pragma unroll
+  for (int v = 0; v < NDES; ++v) dq[v] = 0.f;
+  u = 0.f;
+  for (int mu = lane; mu < NNEU; mu += L) {
+    float w[RS];
+#pragma unroll
+    for (int t = 0; t < RS / 4; ++t) {
+      const float4 r4 = rows[mu * (RS / 4) + t];
+      w[4 * t] = r4.x;
+      w[4 * t + 1] = r4.y;
+      w[4 * t + 2] = r4.z;
+      w[4 * t + 3] = r4.w;
+    }
+    float act = -w[NDES];
+#pragma unroll
+    for (int v = 0; v < NDES; ++v) act += w[v] * q[v];
+    // tanh and its derivative 1 - tanh^2 from e = exp(-2|a|) (no cancellation)
+    const float ea = __expf(-2.f * fabsf(act));
+    const float inv = __builtin_amdgcn_rcpf(1.f + ea);
+    const float th = copysignf((1.f - ea) * inv, act);
+    const float sech2 = 4.f * ea * inv * inv;
+    u += w[NDES + 1] * th;
+    const float gmu = w[NDES + 1] * sech2;
+#pragma unroll
+    for (int v = 0; v < NDES; ++v) dq[v] += gmu * w[v];
+  }
+  u = group_sum<L>(u) - b2;
+#pragma unroll
+  for (int v = 0; v < NDES; ++v) dq[v] = group_sum<L>(dq[v]);
+}
+
+// a_nlm = 2 dU/dq_nl c_nlm, in place of c.
+template <int NR, int NA, int LMAX>
+__device__ __forceinline__ void angular_coefficients(const float* dq,
+                                                     float (&c)[NA][Model<NR, NA, LMAX>::kNLM]) {
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int l = 1; l <= LMAX; ++l) {
+      const float f = 2.f * dq[NR + a * LMAX + (l - 1)];
+#pragma unroll
+      for (int m = 0; m < 2 * l + 1; ++m) c[a][l * l - 1 + m] *= f;
+    }
+}
+
+// Partial force dU_i/dr_ij of pair (dx, dy, dz) from dq (radial part, when
+// rad) and the angular coefficients a (when ang).
+template <int NR, int NA, int LMAX>
+__device__ __forceinline__ void pair_force(float dx, float dy, float dz, bool rad, bool ang,
+                                           float rcr_inv, float rca_inv, const float* dq,
+                                           const float (&c)[NA][Model<NR, NA, LMAX>::kNLM],
+                                           float& px, float& py, float& pz) {
+  constexpr int NLM = Model<NR, NA, LMAX>::kNLM;
+  const float r2 = pair_r2(dx, dy, dz);
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float r = r2 * rinv;
+  const float x = dx * rinv, y = dy * rinv, z = dz * rinv;
+  px = 0.f;
+  py = 0.f;
+  pz = 0.f;
+  if (rad) {
+    float g[NR], dg[NR];
+    radial_basis<NR, true>(r, rcr_inv, g, dg);
+    float f = 0.f;
+#pragma unroll
+    for (int a = 0; a < NR; ++a) f += dq[a] * dg[a];
+    px += f * x;
+    py += f * y;
+    pz += f * z;
+  }
+  if (ang) {
+    float g[NA], dg[NA];
+    radial_basis<NA, true>(r, rca_inv, g, dg);
+    const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+    const float xyz = xy * z;
+    (void)xyz;
+    float sb = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+#define NEP_PF(idx, YV, GX, GY, GZ)                   \
+  if constexpr ((idx) < NLM) {                        \
+    float A = 0.f, B = 0.f;                           \
+    _Pragma("unroll") for (int a = 0; a < NA; ++a) {  \
+      A += c[a][idx] * g[a];                          \
+      B += c[a][idx] * dg[a];                         \
+    }                                                 \
+    sb += B * (YV);                                   \
+    gx += A * (GX);                                   \
+    gy += A * (GY);                                   \
+    gz += A * (GZ);                                   \
+  }
+    NEP_YLM_TABLE(NEP_PF)
+#undef NEP_PF
+    const float ug = x * gx + y * gy + z * gz;
+    px += sb * x + (gx - x * ug) * rinv;
+    py += sb * y + (gy - y * ug) * rinv;
+    pz += sb * z + (gz - z * ug) * rinv;
+  }
+}
+
+}  // namespace nep

@@ -15,6 +15,8 @@
 #include <string>
 #include <vector>
 
+#include <atomic>
+
 #include "nep_device.h"
 
 namespace nep {
@@ -114,24 +116,15 @@ __global__ __launch_bounds__(256) void k_ds_build(
 
 // ------------------------------------------------- population loss terms
 
-// Per (atom, individual k = blockIdx.y): F_i = sum_j p_ij - sum_j p_ji and
-// W_i = sum_j r_ij (x) p_ji from the individual's partials, then the per-atom
-// loss terms (U_i, |F_i - F_i^tar|^2, W_i xx yy zz xy yz zx) in float64 at
-// terms[(8k + q) N + i].
-// MODE 1 instead writes the forces to F_out [3][N] and the terms
-// (U_i, W_i row-major 9) at terms[q N + i] (one individual).
-template <int L, int MODE>
+// One individual: per atom F_i = sum_j p_ij - sum_j p_ji into F_out [3][N],
+// and the terms (U_i, W_i row-major 9, W_i = sum_j r_ij (x) p_ji) at
+// terms[q N + i].
+template <int L>
 __global__ __launch_bounds__(kBlock) void k_ds_gather(
-    int N, int cap, const double* __restrict__ pos, const double* __restrict__ boxes,
+    int N, const double* __restrict__ pos, const double* __restrict__ boxes,
     const int* __restrict__ struct_of, const uint32_t* __restrict__ nl,
     const int* __restrict__ cnt_r, const float4* __restrict__ pin, const float* __restrict__ fown,
-    const float* __restrict__ U, const double* __restrict__ f_tar, double* __restrict__ terms,
-    float* __restrict__ F_out) {
-  const size_t pk = blockIdx.y;
-  pin += pk * (size_t)cap * N;
-  fown += pk * 3 * (size_t)N;
-  U += pk * (size_t)N;
-  terms += pk * 8 * (size_t)N;
+    const float* __restrict__ U, double* __restrict__ terms, float* __restrict__ F_out) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gid / L;
   const int lane = gid % L;
@@ -168,64 +161,13 @@ __global__ __launch_bounds__(kBlock) void k_ds_gather(
   f2 = group_sum<L>(f2);
 #pragma unroll
   for (int q = 0; q < 9; ++q) w[q] = group_sum<L>(w[q]);
-  if (MODE == 1 && active && lane == 0) {
+  if (active && lane == 0) {
     F_out[i] = f0 + fown[i];
     F_out[N + i] = f1 + fown[N + i];
     F_out[2 * N + i] = f2 + fown[2 * N + i];
     terms[i] = (double)U[i];
 #pragma unroll
     for (int q = 0; q < 9; ++q) terms[(size_t)(1 + q) * N + i] = (double)w[q];
-  }
-  if (MODE == 0 && active && lane == 0) {
-    const double F0 = (double)(f0 + fown[i]) - f_tar[i];
-    const double F1 = (double)(f1 + fown[N + i]) - f_tar[N + i];
-    const double F2 = (double)(f2 + fown[2 * N + i]) - f_tar[2 * N + i];
-    terms[i] = (double)U[i];
-    terms[(size_t)N + i] = F0 * F0 + F1 * F1 + F2 * F2;
-    terms[2 * (size_t)N + i] = (double)w[0];  // xx
-    terms[3 * (size_t)N + i] = (double)w[4];  // yy
-    terms[4 * (size_t)N + i] = (double)w[8];  // zz
-    terms[5 * (size_t)N + i] = (double)w[1];  // xy
-    terms[6 * (size_t)N + i] = (double)w[5];  // yz
-    terms[7 * (size_t)N + i] = (double)w[6];  // zx
-  }
-}
-
-// Per (structure s = blockIdx.x, individual k = blockIdx.y): sums of the
-// per-atom terms over the structure, then sq[(k S + s) 3 + (0, 1, 2)] =
-// (((U_s - E_s)/N_s)^2, sum_i |dF_i|^2, sum_6 ((W_s - W_s^tar)/N_s)^2 or 0).
-__global__ __launch_bounds__(kBlock) void k_ds_struct(
-    int N, int S, const int* __restrict__ off, const double* __restrict__ terms,
-    const double* __restrict__ e_tar, const double* __restrict__ w_tar,
-    const int* __restrict__ has_v, double* __restrict__ sq) {
-  __shared__ double sw[kBlock / 64][8];
-  __shared__ double tot[8];
-  const int s = blockIdx.x;
-  const size_t pk = blockIdx.y;
-  const double* t = terms + pk * 8 * (size_t)N;
-  const int a0 = off[s], a1 = off[s + 1];
-  double acc[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x)
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] += t[(size_t)q * N + a];
-  const double v = block_sum<8>(acc, sw);
-  if (threadIdx.x < 8) tot[threadIdx.x] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double ns = (double)(a1 - a0);
-    const double de = (tot[0] - e_tar[s]) / ns;
-    double dv = 0.0;
-    if (has_v[s])
-      for (int c = 0; c < 6; ++c) {
-        const double d = (tot[2 + c] - w_tar[6 * s + c]) / ns;
-        dv += d * d;
-      }
-    double* o = sq + (pk * S + s) * 3;
-    o[0] = de * de;
-    o[1] = tot[1];
-    o[2] = dv;
   }
 }
 
@@ -313,13 +255,16 @@ __device__ __forceinline__ void philox(uint32_t (&x)[4], uint32_t k0, uint32_t k
   }
 }
 
+// Generation `gen`, or gen_dev[0] when gen_dev is not NULL.
 __global__ void k_snes_sample(int n_par, const float* __restrict__ m, const float* __restrict__ s,
-                              uint32_t key0, uint32_t key1, uint32_t gen, float* __restrict__ r,
+                              uint32_t key0, uint32_t key1, uint32_t gen,
+                              const int* __restrict__ gen_dev, float* __restrict__ r,
                               float* __restrict__ Z) {
 #pragma clang fp contract(off)
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
   if (4 * b >= n_par) return;
+  if (gen_dev) gen = (uint32_t)gen_dev[0];
   uint32_t x[4] = {(uint32_t)b, (uint32_t)k, gen, 0u};
   philox(x, key0, key1);
   double u[4];
@@ -382,6 +327,35 @@ __global__ __launch_bounds__(kBlock) void k_snes_update(int n_par, int n_pop, fl
   s[v] = (float)(sv * exp(0.5 * eta_s * gs));
 }
 
+// One thread: best[(g - g0) 6 + q] = loss terms of the best individual of
+// generation g = counter[0] (NaN ranks last, ties by index), g0 = counter[1];
+// then counter[0] = g + 1.
+__global__ void k_snes_record(int n_pop, const double* __restrict__ loss, int* __restrict__ counter,
+                              double* __restrict__ best) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int g = counter[0];
+  if (best) {
+    int b = 0;
+    double lb = loss[0] != loss[0] ? INFINITY : loss[0];
+    for (int k = 1; k < n_pop; ++k) {
+      const double lk = loss[6 * k] != loss[6 * k] ? INFINITY : loss[6 * k];
+      if (lk < lb) {
+        lb = lk;
+        b = k;
+      }
+    }
+    for (int q = 0; q < 6; ++q) best[(size_t)(g - counter[1]) * 6 + q] = loss[6 * b + q];
+  }
+  counter[0] = g + 1;
+}
+
+__global__ void k_set_counter(int* __restrict__ counter, int g) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    counter[0] = g;
+    counter[1] = g;
+  }
+}
+
 void invert_box(const double* H, double* Hi) {
   const double a = H[0], b = H[1], c = H[2], d = H[3], e = H[4], f = H[5], g = H[6], h = H[7],
                k = H[8];
@@ -409,7 +383,9 @@ hipError_t build_dataset_lists(nep_ctx ctx, nep_dataset ds) {
       ds->wrap.ptr, ds->rc_r * ds->rc_r, ds->rc_a * ds->rc_a, ds->nl.ptr, ds->cnt_r.ptr,
       ds->cnt_a.ptr, ctx->flags.ptr);
   launch_reverse(ctx, N, ds->cap, ds->nl.ptr, ds->cnt_r.ptr, ds->cnt_a.ptr, ds->rev.ptr);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return prepare_dataset_geometry(ctx, ds);
 }
 
 nep_status check_dataset(nep_ctx ctx, nep_dataset ds) {
@@ -418,6 +394,31 @@ nep_status check_dataset(nep_ctx ctx, nep_dataset ds) {
   if (ds->rc_r != ctx->hyper.rc_radial || ds->rc_a != ctx->hyper.rc_angular)
     return fail(ctx, NEP_ESTATE, "dataset lists were built for other cutoffs");
   return NEP_OK;
+}
+
+// Workspace of snes_eval_population for n_pop individuals.
+hipError_t ensure_population(nep_dataset ds, int n_pop) {
+  const int N = ds->N, S = ds->S;
+  hipError_t e = ds->pin.ensure((size_t)n_pop * ds->cap * N);
+  if (e == hipSuccess) e = ds->fown.ensure((size_t)n_pop * 3 * N);
+  if (e == hipSuccess) e = ds->U.ensure((size_t)n_pop * N);
+  if (e == hipSuccess) e = ds->struct_sq.ensure((size_t)n_pop * 3 * S);
+  return e;
+}
+
+// Enqueue one population evaluation and its loss reduction.
+hipError_t enqueue_population_loss(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z_dev,
+                                   const double* lambda, double* loss_dev, int variant) {
+  hipError_t r = launch_population(ctx, ds, n_pop, Z_dev, variant, true);
+  if (r != hipSuccess) return r;
+  launch_kernel(ctx, false, true, k_ds_loss, dim3(n_pop), dim3(kBlock), ds->S, ds->N,
+                ds->n_virial, ctx->n_par, (const double*)ds->struct_sq.ptr, Z_dev, lambda[0],
+                lambda[1], lambda[2], lambda[3], lambda[4], loss_dev);
+  return hipGetLastError();
+}
+
+bool population_fits(nep_dataset ds) {
+  return ds->S <= 65535 && blocks_for((size_t)ds->N * 8, kBlock) <= 65535;
 }
 
 }  // namespace
@@ -481,6 +482,8 @@ nep_status nep_dataset_create(nep_ctx ctx, int n_struct, const int* n_atoms_host
     }
   nep_dataset ds = new (std::nothrow) nep_dataset_s();
   if (!ds) return fail(ctx, NEP_ENOMEM, "dataset");
+  static std::atomic<unsigned long long> next_serial{0};
+  ds->serial = ++next_serial;
   ds->ctx = ctx;
   ds->S = S;
   ds->N = N;
@@ -561,6 +564,7 @@ void nep_dataset_destroy(nep_dataset ds) {
   ds->struct_sq.release();
   ds->grad_rec.release();
   ds->grad_part.release();
+  ds->release_cache();
   delete ds;
 }
 
@@ -603,13 +607,13 @@ nep_status nep_dataset_compute(nep_ctx ctx, nep_dataset ds, const float* z_dev,
   e = timed(ctx, 0, [&] { return launch_partials_population(ctx, ds, 1, z_dev); });
   if (e == hipSuccess)
     e = timed(ctx, 1, [&] {
-      launch_kernel(ctx, true, false, k_ds_gather<kLanes, 1>,
-                    dim3(blocks_for((size_t)N * kLanes, kBlock), 1), dim3(kBlock), N, ds->cap,
+      launch_kernel(ctx, true, false, k_ds_gather<kLanes>,
+                    dim3(blocks_for((size_t)N * kLanes, kBlock)), dim3(kBlock), N,
                     (const double*)ds->pos.ptr, (const double*)ds->boxes.ptr,
                     (const int*)ds->struct_of.ptr, (const uint32_t*)ds->nl.ptr,
                     (const int*)ds->cnt_r.ptr, (const float4*)ds->pin.ptr,
-                    (const float*)ds->fown.ptr, (const float*)ds->U.ptr, (const double*)nullptr,
-                    ds->atom_terms.ptr, forces_dev);
+                    (const float*)ds->fown.ptr, (const float*)ds->U.ptr, ds->atom_terms.ptr,
+                    forces_dev);
       launch_kernel(ctx, false, true, k_ds_totals, dim3(S), dim3(kBlock), N,
                     (const int*)ds->off.ptr, (const double*)ds->atom_terms.ptr, energy_dev,
                     virial_dev);
@@ -643,33 +647,14 @@ nep_status snes_eval_population(nep_ctx ctx, nep_dataset ds, int n_pop, const fl
   if (chk != NEP_OK) return chk;
   if (n_pop < 1 || n_pop > 65535) return fail(ctx, NEP_EINVAL, "n_pop must be in [1, 65535]");
   if (!Z_dev || !lambda_host || !loss_dev) return fail(ctx, NEP_EINVAL, "NULL argument");
-  const int N = ds->N, S = ds->S;
+  if (!population_fits(ds))
+    return fail(ctx, NEP_EINVAL, "dataset too large for one population launch");
   DeviceGuard guard(ctx->device);
-  hipError_t e = ds->pin.ensure((size_t)n_pop * ds->cap * N);
-  if (e == hipSuccess) e = ds->fown.ensure((size_t)n_pop * 3 * N);
-  if (e == hipSuccess) e = ds->U.ensure((size_t)n_pop * N);
-  if (e == hipSuccess) e = ds->atom_terms.ensure((size_t)n_pop * 8 * N);
-  if (e == hipSuccess) e = ds->struct_sq.ensure((size_t)n_pop * 3 * S);
+  hipError_t e = ensure_population(ds, n_pop);
   if (e != hipSuccess) return check_hip(ctx, e, "allocating population workspace");
-  e = timed(ctx, 0, [&] { return launch_partials_population(ctx, ds, n_pop, Z_dev); });
-  if (e == hipSuccess)
-    e = timed(ctx, 1, [&] {
-      launch_kernel(ctx, true, false, k_ds_gather<kLanes, 0>,
-                    dim3(blocks_for((size_t)N * kLanes, kBlock), n_pop), dim3(kBlock), N, ds->cap,
-                    (const double*)ds->pos.ptr, (const double*)ds->boxes.ptr,
-                    (const int*)ds->struct_of.ptr, (const uint32_t*)ds->nl.ptr,
-                    (const int*)ds->cnt_r.ptr, (const float4*)ds->pin.ptr,
-                    (const float*)ds->fown.ptr, (const float*)ds->U.ptr,
-                    (const double*)ds->f_tar.ptr, ds->atom_terms.ptr, (float*)nullptr);
-      launch_kernel(ctx, false, false, k_ds_struct, dim3(S, n_pop), dim3(kBlock), N, S,
-                    (const int*)ds->off.ptr, (const double*)ds->atom_terms.ptr,
-                    (const double*)ds->e_tar.ptr, (const double*)ds->w_tar.ptr,
-                    (const int*)ds->has_v.ptr, ds->struct_sq.ptr);
-      launch_kernel(ctx, false, true, k_ds_loss, dim3(n_pop), dim3(kBlock), S, N, ds->n_virial,
-                    ctx->n_par, (const double*)ds->struct_sq.ptr, Z_dev, lambda_host[0],
-                    lambda_host[1], lambda_host[2], lambda_host[3], lambda_host[4], loss_dev);
-      return hipGetLastError();
-    });
+  e = timed(ctx, 0, [&] {
+    return enqueue_population_loss(ctx, ds, n_pop, Z_dev, lambda_host, loss_dev, ds->pop_variant);
+  });
   return check_hip(ctx, e, "launching population kernels");
 }
 
@@ -686,7 +671,7 @@ nep_status snes_sample(nep_ctx ctx, int n_par, int n_pop, const float* m_dev, co
     const int nb = (n_par + 3) / 4;
     launch_kernel(ctx, true, true, k_snes_sample, dim3(blocks_for(nb, kBlock), n_pop),
                   dim3(kBlock), n_par, m_dev, s_dev, (uint32_t)(seed & 0xFFFFFFFFull),
-                  (uint32_t)(seed >> 32), (uint32_t)generation, r_dev, Z_dev);
+                  (uint32_t)(seed >> 32), (uint32_t)generation, (const int*)nullptr, r_dev, Z_dev);
     e = hipGetLastError();
   }
   return check_hip(ctx, e, "launching the SNES sampler");
@@ -708,6 +693,149 @@ nep_status snes_update(nep_ctx ctx, int n_par, int n_pop, float* m_dev, float* s
     e = hipGetLastError();
   }
   return check_hip(ctx, e, "launching the SNES update");
+}
+
+nep_status snes_autotune(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z_dev, int reps,
+                         int* lanes_out, double* ms_out) {
+  if (!ctx) return NEP_EINVAL;
+  nep_status chk = check_dataset(ctx, ds);
+  if (chk != NEP_OK) return chk;
+  if (n_pop < 1 || n_pop > 65535) return fail(ctx, NEP_EINVAL, "n_pop must be in [1, 65535]");
+  if (reps < 1 || reps > 1000) return fail(ctx, NEP_EINVAL, "reps must be in [1, 1000]");
+  if (!Z_dev) return fail(ctx, NEP_EINVAL, "Z_dev is NULL");
+  if (!population_fits(ds))
+    return fail(ctx, NEP_EINVAL, "dataset too large for one population launch");
+  DeviceGuard guard(ctx->device);
+  hipError_t e = ensure_population(ds, n_pop);
+  if (e != hipSuccess) return check_hip(ctx, e, "allocating population workspace");
+  const bool timing = ctx->timer.on;
+  ctx->timer.on = false;
+  hipEvent_t a = nullptr, b = nullptr;
+  e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  const int nv = population_variants();
+  int best = ds->pop_variant;
+  double best_ms = 0.0;
+  for (int v = 0; v < nv && e == hipSuccess; ++v) {
+    e = launch_population(ctx, ds, n_pop, Z_dev, v, true);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+      e = launch_population(ctx, ds, n_pop, Z_dev, v, true);
+    if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    const double per = (double)ms / reps;
+    if (ms_out) ms_out[v] = per;
+    if (e == hipSuccess && (v == 0 || per < best_ms)) {
+      best = v;
+      best_ms = per;
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  ctx->timer.on = timing;
+  if (e != hipSuccess) return check_hip(ctx, e, "timing population kernels");
+  ds->pop_variant = best;
+  ds->pop_tuned = true;
+  if (lanes_out) *lanes_out = population_lanes(best);
+  return nep_synchronize(ctx);
+}
+
+nep_status snes_set_tile(nep_ctx ctx, nep_dataset ds, int lanes) {
+  if (!ctx) return NEP_EINVAL;
+  if (!ds || ds->ctx != ctx) return fail(ctx, NEP_EINVAL, "dataset belongs to another context");
+  for (int v = 0; v < population_variants(); ++v)
+    if (population_lanes(v) == lanes) {
+      ds->pop_variant = v;
+      return NEP_OK;
+    }
+  return fail(ctx, NEP_EINVAL, "lanes must be 2, 4 or 8");
+}
+
+nep_status snes_run(nep_ctx ctx, nep_dataset ds, int n_par, int n_pop, float* m_dev,
+                    float* s_dev, unsigned long long seed, int generation, int n_gen,
+                    const double* lambda_host, double eta_m, double eta_s, float* r_dev,
+                    float* Z_dev, double* loss_dev, double* best_dev) {
+  if (!ctx) return NEP_EINVAL;
+  nep_status chk = check_dataset(ctx, ds);
+  if (chk != NEP_OK) return chk;
+  if (n_par != ctx->n_par) return fail(ctx, NEP_EINVAL, "n_par differs from the loaded model");
+  if (n_pop < 1 || n_pop > 1024) return fail(ctx, NEP_EINVAL, "n_pop must be in [1, 1024]");
+  if (generation < 0 || n_gen < 0 || (long long)generation + n_gen > 2147483647LL)
+    return fail(ctx, NEP_EINVAL, "generation range out of bounds");
+  if (!m_dev || !s_dev || !r_dev || !Z_dev || !loss_dev || !lambda_host)
+    return fail(ctx, NEP_EINVAL, "NULL argument");
+  if (!population_fits(ds))
+    return fail(ctx, NEP_EINVAL, "dataset too large for one population launch");
+  if (n_gen == 0) return NEP_OK;
+  if (!(eta_m > 0.0)) eta_m = 1.0;
+  if (!(eta_s > 0.0)) eta_s = (3.0 + std::log((double)n_par)) / (5.0 * std::sqrt((double)n_par));
+  DeviceGuard guard(ctx->device);
+  hipError_t e = ensure_population(ds, n_pop);
+  if (e == hipSuccess) e = ctx->gen_counter.ensure(2);
+  if (e != hipSuccess) return check_hip(ctx, e, "allocating SNES workspace");
+  SnesGraph& G = ctx->snes_graph;
+  const std::vector<const void*> pk = {ds, m_dev, s_dev, r_dev, Z_dev, loss_dev, best_dev,
+                                       ds->pin.ptr, ds->fown.ptr, ds->U.ptr, ds->struct_sq.ptr,
+                                       ds->prec.ptr, ds->desc.ptr, ctx->gen_counter.ptr,
+                                       ctx->stream};
+  const std::vector<double> vk = {(double)ds->serial, (double)n_par, (double)n_pop,
+                                  (double)(seed & 0xFFFFFFFFull), (double)(seed >> 32),
+                                  lambda_host[0], lambda_host[1], lambda_host[2], lambda_host[3],
+                                  lambda_host[4], eta_m, eta_s, (double)ds->pop_variant};
+  if (!G.exec || G.ptr_key != pk || G.val_key != vk) {
+    // the previous graph may still be running on the stream
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return check_hip(ctx, e, "waiting for the stream");
+    G.release();
+    hipStream_t cap = nullptr;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return check_hip(ctx, e, "creating the capture stream");
+    hipStream_t user = ctx->stream;
+    const bool timing = ctx->timer.on;
+    ctx->stream = cap;
+    ctx->timer.on = false;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const int nb = (n_par + 3) / 4;
+      launch_kernel(ctx, false, false, k_snes_sample, dim3(blocks_for(nb, kBlock), n_pop),
+                    dim3(kBlock), n_par, (const float*)m_dev, (const float*)s_dev,
+                    (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32), 0u,
+                    (const int*)ctx->gen_counter.ptr, r_dev, Z_dev);
+      hipError_t le = enqueue_population_loss(ctx, ds, n_pop, Z_dev, lambda_host, loss_dev,
+                                              ds->pop_variant);
+      launch_kernel(ctx, false, false, k_snes_update, dim3(blocks_for(n_par, kBlock)),
+                    dim3(kBlock), n_par, n_pop, m_dev, s_dev, (const float*)r_dev,
+                    (const double*)loss_dev, eta_m, eta_s);
+      launch_kernel(ctx, false, false, k_snes_record, dim3(1), dim3(64), n_pop,
+                    (const double*)loss_dev, ctx->gen_counter.ptr, best_dev);
+      if (le == hipSuccess) le = hipGetLastError();
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(cap, &graph);
+      if (e == hipSuccess && le != hipSuccess) e = le;
+      if (e == hipSuccess) {
+        G.graph = graph;
+        e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+      } else if (graph) {
+        (void)hipGraphDestroy(graph);
+      }
+    }
+    ctx->stream = user;
+    ctx->timer.on = timing;
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+      G.release();
+      return check_hip(ctx, e, "capturing the SNES generation");
+    }
+    G.ptr_key = pk;
+    G.val_key = vk;
+  }
+  launch_kernel(ctx, false, false, k_set_counter, dim3(1), dim3(64), ctx->gen_counter.ptr,
+                generation);
+  e = hipGetLastError();
+  for (int g = 0; g < n_gen && e == hipSuccess; ++g) e = hipGraphLaunch(G.exec, ctx->stream);
+  return check_hip(ctx, e, "launching SNES generations");
 }
 
 }  // extern "C"

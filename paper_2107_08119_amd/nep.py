@@ -27,7 +27,8 @@ EXPORTED = [
     "nep_get_neighbors", "nep_compute", "nep_md_step", "nep_set_timing", "nep_get_timing",
     "nep_time_partials", "nep_dataset_create", "nep_dataset_destroy", "snes_eval_population",
     "snes_sample", "snes_update", "nep_dataset_set_positions", "nep_dataset_get_positions",
-    "nep_dataset_compute", "nep_dataset_backward",
+    "nep_dataset_compute", "nep_dataset_backward", "snes_autotune", "snes_run",
+    "snes_set_tile",
 ]
 
 
@@ -84,6 +85,11 @@ def lib() -> C.CDLL:
         L.snes_eval_population.argtypes = [vp, vp, ip, vp, vp, vp]
         L.snes_sample.argtypes = [vp, ip, ip, vp, vp, C.c_ulonglong, ip, vp, vp]
         L.snes_update.argtypes = [vp, ip, ip, vp, vp, vp, vp, dp, dp]
+        L.snes_autotune.argtypes = [vp, vp, ip, vp, ip, C.POINTER(C.c_int),
+                                    C.POINTER(C.c_double)]
+        L.snes_set_tile.argtypes = [vp, vp, ip]
+        L.snes_run.argtypes = [vp, vp, ip, ip, vp, vp, C.c_ulonglong, ip, ip, vp, dp, dp, vp, vp,
+                               vp, vp]
         L.nep_dataset_set_positions.argtypes = [vp, vp, vp]
         L.nep_dataset_get_positions.argtypes = [vp, vp, vp]
         L.nep_dataset_compute.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -254,6 +260,41 @@ class Context:
         _require(loss, torch.float64, (n_pop, 6), "loss")
         self._check(self._lib.snes_update(self._h, n_par, n_pop, _ptr(m), _ptr(s), _ptr(r),
                                           _ptr(loss), eta_m, eta_s))
+
+    def snes_autotune(self, ds: "Dataset", Z: torch.Tensor, reps: int = 3):
+        """Time the population kernel shapes on this dataset and keep the
+        fastest; returns (lanes per atom chosen, ms per evaluation of the
+        2-, 4- and 8-lane shapes)."""
+        _require(Z, torch.float32, None, "Z")
+        lanes = C.c_int(0)
+        ms = (C.c_double * 3)()
+        self._check(self._lib.snes_autotune(self._h, ds._h, Z.shape[0], _ptr(Z), reps,
+                                            C.byref(lanes), ms))
+        return lanes.value, list(ms)
+
+    def snes_set_tile(self, ds: "Dataset", lanes: int) -> None:
+        self._check(self._lib.snes_set_tile(self._h, ds._h, lanes))
+
+    def snes_run(self, ds: "Dataset", m: torch.Tensor, s: torch.Tensor, seed: int,
+                 generation: int, n_gen: int, r: torch.Tensor, Z: torch.Tensor,
+                 loss: torch.Tensor, lam=(1.0, 1.0, 1.0, 0.05, 0.05), eta_m: float = 0.0,
+                 eta_s: float = 0.0, best: torch.Tensor | None = None):
+        """n_gen SNES generations on the device (sample, evaluate, update per
+        generation, replayed as a HIP graph); returns best [n_gen][6]."""
+        n_pop, n_par = r.shape
+        _require(m, torch.float32, (n_par,), "m")
+        _require(s, torch.float32, (n_par,), "s")
+        _require(r, torch.float32, (n_pop, n_par), "r")
+        _require(Z, torch.float32, (n_pop, n_par), "Z")
+        _require(loss, torch.float64, (n_pop, 6), "loss")
+        if best is None:
+            best = torch.empty((max(n_gen, 1), 6), dtype=torch.float64, device=m.device)
+        _require(best, torch.float64, None, "best")
+        lam = np.ascontiguousarray(lam, np.float64)
+        self._check(self._lib.snes_run(self._h, ds._h, n_par, n_pop, _ptr(m), _ptr(s), seed,
+                                       generation, n_gen, lam.ctypes.data, eta_m, eta_s, _ptr(r),
+                                       _ptr(Z), _ptr(loss), _ptr(best)))
+        return best
 
     def dataset_positions(self, ds: "Dataset") -> torch.Tensor:
         out = torch.empty((3, ds.n_atoms), dtype=torch.float64,

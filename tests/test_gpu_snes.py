@@ -129,3 +129,70 @@ def test_full_size_training_set_sampled():
         ref = O.loss(OH, Z[k], ls, LAM, cap=96)
         np.testing.assert_allclose(got[k], ref, rtol=1e-5, err_msg="individual %d" % k)
     assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("lanes", [2, 4, 8])
+def test_population_tile_shapes_match_oracle(lanes):
+    """Every compiled tile shape of the population kernels gives the oracle's
+    losses; the autotuner picks one of them."""
+    import torch
+    nep = nep_mod()
+    ls = small_set()
+    Z = population(5, 6)
+    ctx = nep.Context(0)
+    ctx.load_params(nep.hyper(), Z[0])
+    ds = ctx.dataset_create(ls, max_neighbors=200)
+    Zt = torch.from_numpy(Z).cuda()
+    chosen, ms = ctx.snes_autotune(ds, Zt, reps=2)
+    assert chosen in (2, 4, 8) and all(t > 0 for t in ms)
+    ctx.snes_set_tile(ds, lanes)
+    got = ctx.eval_population(ds, Zt, LAM).cpu().numpy()
+    for k in range(len(Z)):
+        ref = O.loss(OH, Z[k], ls, LAM, cap=200)
+        np.testing.assert_allclose(got[k], ref, rtol=1e-5, err_msg="individual %d" % k)
+
+
+def test_snes_run_matches_separate_calls():
+    """Generations replayed from the captured graph equal the same generations
+    run as separate calls, bit for bit, across two snes_run calls with eager
+    work and synchronisations in between."""
+    import torch
+    nep = nep_mod()
+    ls = small_set()
+    ctx = nep.Context(0)
+    ctx.load_params(nep.hyper(), population(1, 1)[0])
+    ds = ctx.dataset_create(ls, max_neighbors=200)
+    n_pop, n_par, seed = 8, 931, 77
+    rng = np.random.default_rng(3)
+    m0 = torch.from_numpy(rng.uniform(-0.5, 0.5, n_par).astype(np.float32)).cuda()
+    s0 = torch.full((n_par,), 0.1, dtype=torch.float32, device="cuda")
+
+    def fresh():
+        return (m0.clone(), s0.clone(), torch.empty((n_pop, n_par), device="cuda"),
+                torch.empty((n_pop, n_par), device="cuda"),
+                torch.empty((n_pop, 6), dtype=torch.float64, device="cuda"))
+
+    m, s, r, Z, loss = fresh()
+    eager_best = []
+    for g in range(5):
+        ctx.snes_sample(m, s, seed, g, n_pop, r, Z)
+        ctx.eval_population(ds, Z, LAM, loss)
+        ctx.snes_update(m, s, r, loss)
+        lv = loss.cpu().numpy()
+        key = np.where(np.isnan(lv[:, 0]), np.inf, lv[:, 0])
+        eager_best.append(lv[int(np.argmin(key))])
+    m_e, s_e, loss_e = m.cpu().numpy(), s.cpu().numpy(), loss.cpu().numpy()
+
+    m, s, r, Z, loss = fresh()
+    b1 = ctx.snes_run(ds, m, s, seed, 0, 2, r, Z, loss, LAM).cpu().numpy()
+    ctx.synchronize()
+    # eager work on the same stream between the replays
+    other = ctx.eval_population(ds, torch.from_numpy(population(3, 9)).cuda(), LAM)
+    ctx.synchronize()
+    assert np.isfinite(other.cpu().numpy()).all()
+    b2 = ctx.snes_run(ds, m, s, seed, 2, 3, r, Z, loss, LAM).cpu().numpy()
+    ctx.synchronize()
+    np.testing.assert_array_equal(np.vstack([b1, b2]), np.array(eager_best))
+    np.testing.assert_array_equal(m.cpu().numpy(), m_e)
+    np.testing.assert_array_equal(s.cpu().numpy(), s_e)
+    np.testing.assert_array_equal(loss.cpu().numpy(), loss_e)
