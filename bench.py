@@ -85,6 +85,7 @@ def disordered_rate(args, nep, I, torch, z):
     K = args.disordered_steps
     thermo = torch.empty((K, 5), dtype=torch.float64, device="cuda")
     ctx.md_step(20, 1.0, 10, I.MASS_SI, p, v, thermo, W, J)
+    lanes, _ = ctx.autotune(p, reps=5)
     ctx.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -96,7 +97,7 @@ def disordered_rate(args, nep, I, torch, z):
     return {"workload": "NVE MD of a 512,000-atom random Si cube (2.33 g/cm^3, 2.0 A minimum "
                         "distance), per-atom W and J written every step, dt 1 fs, rebuild every "
                         "10 steps", "atom_steps_per_s": n * K / t, "ms_per_step": t / K * 1e3,
-            "steps": K, "k_partials_us": ms * 1e3}
+            "steps": K, "k_partials_us": ms * 1e3, "tile_lanes_per_atom": lanes}
 
 
 def snes_rate(args, ctx, nep, I, torch):
@@ -233,6 +234,8 @@ def main():
     if args.warmup:
         ctx.md_step(args.warmup, dt, rebuild, mass, p, v, thermo)
     ctx.synchronize()
+    # pass-1 tile shape for this system (the library's autotuner)
+    lanes, tile_ms = ctx.autotune(p, reps=20)
     nb = ctx.get_neighbors()
     mean_slots = float(nb["cnt_radial"].double().mean())
     # timed region: K steps, no instrumentation
@@ -296,6 +299,9 @@ def main():
             "timing": "HIP events around 200 back-to-back launches on the library stream",
             "algorithmic_GBps": (BYTE_ATOM + BYTE_SLOT * mean_slots) * n / avg_s / 1e9,
         },
+        "tile": {"lanes_per_atom": lanes,
+                 "us_per_launch": {"2": tile_ms[0] * 1e3, "4": tile_ms[1] * 1e3,
+                                   "8": tile_ms[2] * 1e3}},
         "kernel_us_per_launch_instrumented": {
             k: (val[0] * 1e3 / val[1] if val[1] else None) for k, val in kt.items()},
         "energy_drift_meV_per_atom": float((e_tot.max() - e_tot.min()) / n * 1e3),

@@ -309,6 +309,21 @@ nep_status nep_get_timing(nep_ctx ctx, double* ms_out, int* launches_out);
  * Needs loaded parameters and a neighbour list; 1 <= reps <= 100000. */
 nep_status nep_time_partials(nep_ctx ctx, const double* pos_dev, int reps, double* ms_per_launch);
 
+/* Tile-shape autotuner for the descriptor/network/partial-force kernel on
+ * the current system at pos_dev (as for nep_compute): times the compiled
+ * shapes (2, 4 and 8 lanes per atom; 128, 64 and 32 atoms per block) over
+ * `reps` launches each (1..10000) with HIP events on the context's stream and
+ * keeps the fastest for later nep_compute / nep_md_step calls.  Host outputs
+ * (either may be NULL): *lanes_out = chosen lanes per atom; ms_out[3] = mean
+ * ms per launch of each shape in the order above.  Needs loaded parameters
+ * and a neighbour list; waits for the stream. */
+nep_status nep_autotune(nep_ctx ctx, const double* pos_dev, int reps, int* lanes_out,
+                        double* ms_out);
+
+/* Use `lanes` (2, 4 or 8) lanes per atom in the descriptor/network/partial-
+ * force kernel of this context.  NEP_EINVAL for other values. */
+nep_status nep_set_tile(nep_ctx ctx, int lanes);
+
 #ifdef __cplusplus
 }
 #endif

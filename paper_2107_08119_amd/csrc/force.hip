@@ -19,7 +19,11 @@
 namespace nep {
 namespace {
 
-constexpr int kStage = 40;  // neighbour slots per atom staged in LDS by pass 1
+// Neighbour slots per atom staged in LDS by pass 1: 40 KB of staged pairs per
+// block (at most 64, the width of the per-atom slot masks).
+constexpr int stage_slots(int atoms_per_block) {
+  return 2560 / atoms_per_block < 64 ? 2560 / atoms_per_block : 64;
+}
 
 // ------------------------------------------------------------------ pass 1
 // Outputs: U[i]; fown[c*n + i] = sum_j dU_i/dr_ij (component c); and every
@@ -48,7 +52,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
   load_net_rows<NDES, NNEU>(zpar, sw4, &sb2);
 
-  // Stage the first kStage slots of the block's atoms in LDS, keeping only
+  // Stage the first KS slots of the block's atoms in LDS, keeping only
   // the pairs inside a cutoff, compacted per atom: first the pairs inside
   // r_c^A (angular partition of the list), then those inside r_c^R only.
   // Each entry holds the pair displacement (float32, formed in float64) and,
@@ -57,10 +61,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   // Thread tid handles atom a = tid % APB at slots w, w + W, ... (w = tid / APB),
   // so list reads coalesce and every thread has several loads in flight.
   constexpr int APB = kBlock / L;  // atoms per block
+  constexpr int KS = stage_slots(APB);
   constexpr int W = kBlock / APB;  // slots staged side by side
-  constexpr int T = kStage / W;    // slots per thread
-  static_assert(kStage % W == 0 && kStage <= 64, "staging shape");
-  __shared__ float4 sd[kStage][APB];
+  constexpr int T = KS / W;        // slots per thread
+  static_assert(KS % W == 0 && KS <= 64, "staging shape");
+  __shared__ float4 sd[KS][APB];
   __shared__ unsigned long long smask[2][W][APB];  // [angular, radial-only][w][atom]
   __shared__ int scount[2][APB];
   const float rcr2 = rc_r * rc_r, rca2 = rc_a * rc_a;
@@ -150,9 +155,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   const double* H = MULTI ? boxes + 9 * (size_t)struct_of[ii] : box.h;
   const float rcr_inv = 1.f / rc_r, rca_inv = 1.f / rc_a;
   // Work item k of this atom: k < n_in is staged pair k (angular when
-  // k < n_ang); k >= n_in is list slot kStage + (k - n_in), read from the
+  // k < n_ang); k >= n_in is list slot KS + (k - n_in), read from the
   // list and classified here.
-  const int n_work = n_in + (cr > kStage ? cr - kStage : 0);
+  const int n_work = n_in + (cr > KS ? cr - KS : 0);
   auto pair = [&](int k, float& dx, float& dy, float& dz, int& dst, bool& ang, bool& rad) {
     if (k < n_in) {
       const float4 v = sd[k][la];
@@ -163,7 +168,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       ang = k < n_ang;
       rad = true;
     } else {
-      const int s = kStage + (k - n_in);
+      const int s = KS + (k - n_in);
       const size_t idx = (size_t)s * n + i;
       int j;
       displacement(nl[idx], pos, n, xi, yi, zi, H, j, dx, dy, dz);
@@ -423,16 +428,31 @@ bool have_force_variant(const nep_hyper& h) { return is_default_variant(h); }
 
 size_t gather_blocks(int n) { return blocks_for((size_t)n * kLanes, kBlock); }
 
-hipError_t launch_partials(nep_ctx ctx, const double* pos) {
+template <int L>
+void launch_partials_shape(nep_ctx ctx, const double* pos, bool first, bool last) {
+  const System& s = ctx->sys;
+  const unsigned nb = blocks_for((size_t)s.n * L, kBlock);
+  launch_kernel(ctx, first, last, k_partials<9, 5, 4, 30, L, false>, dim3(nb), dim3(kBlock), s.n,
+                pos, (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr, (const int*)s.cnt_a.ptr,
+                (const int*)s.rev.ptr, s.box, (const double*)nullptr, (const int*)nullptr,
+                (const float*)ctx->z.ptr, (size_t)0, (float)ctx->hyper.rc_radial,
+                (float)ctx->hyper.rc_angular, ctx->p.ptr, (size_t)0, ctx->fown.ptr, ctx->U.ptr);
+}
+
+hipError_t launch_partials(nep_ctx ctx, const double* pos, int variant) {
   const System& s = ctx->sys;
   if (s.n == 0) return hipSuccess;
-  const unsigned nb = blocks_for((size_t)s.n * kLanes, kBlock);
-  launch_kernel(ctx, true, true, k_partials<9, 5, 4, 30, kLanes, false>, dim3(nb), dim3(kBlock),
-                s.n, pos, (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr,
-                (const int*)s.cnt_a.ptr, (const int*)s.rev.ptr, s.box, (const double*)nullptr,
-                (const int*)nullptr, (const float*)ctx->z.ptr, (size_t)0,
-                (float)ctx->hyper.rc_radial, (float)ctx->hyper.rc_angular, ctx->p.ptr, (size_t)0,
-                ctx->fown.ptr, ctx->U.ptr);
+  if (variant < 0) variant = ctx->md_variant;
+  switch (variant) {
+    case 0:
+      launch_partials_shape<2>(ctx, pos, true, true);
+      break;
+    case 2:
+      launch_partials_shape<8>(ctx, pos, true, true);
+      break;
+    default:
+      launch_partials_shape<4>(ctx, pos, true, true);
+  }
   return hipGetLastError();
 }
 

@@ -64,9 +64,10 @@ __global__ void k_bin(int n, double* __restrict__ pos, Box box, int nc0, int nc1
   }
 }
 
-// Exclusive prefix sum of m counts by one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan(int m, const int* __restrict__ cnt,
-                                               int* __restrict__ start) {
+// Exclusive prefix sum of m counts by one block of 1024 threads; the counts
+// are cleared for the next build and the fill counters for k_fill.
+__global__ __launch_bounds__(1024) void k_scan(int m, int* __restrict__ cnt,
+                                               int* __restrict__ start, int* __restrict__ fill) {
   __shared__ int part[1024];
   const int t = threadIdx.x;
   const int per = (m + 1023) / 1024;
@@ -86,6 +87,8 @@ __global__ __launch_bounds__(1024) void k_scan(int m, const int* __restrict__ cn
   for (int k = b; k < e; ++k) {
     start[k] = run;
     run += cnt[k];
+    cnt[k] = 0;   // ready for the next build
+    fill[k] = 0;  // for k_fill, next
   }
   if (t == 1023) start[m] = part[1023];
 }
@@ -187,10 +190,13 @@ __global__ __launch_bounds__(256) void k_build_cells(
     int n, int cap, const double* __restrict__ pos, Box box, int nc0, int nc1, int nc2,
     const int* __restrict__ wrap, const int* __restrict__ cell_of, const int* __restrict__ start,
     const CellRec* __restrict__ rec, double rc2_r, double rc2_a, uint32_t* __restrict__ nl,
-    int* __restrict__ cnt_r, int* __restrict__ cnt_a, int* __restrict__ flags) {
+    uint32_t* __restrict__ nl_rm, int* __restrict__ cnt_r, int* __restrict__ cnt_a,
+    int* __restrict__ flags) {
   static_assert(G >= 27 && G <= 64 && 256 % G == 0, "a group covers the 27 cells");
+  constexpr int kMap = 512;            // candidates whose cell is looked up in a table
   __shared__ int s_off[256 / G][28];   // first candidate number of each cell
   __shared__ int s_first[256 / G][27]; // first member slot of each cell
+  __shared__ uint8_t s_cell[256 / G][kMap];  // cell of candidate c
   __shared__ uint32_t s_ro[256 / G][RO];  // radial-only entries in scan order
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int grp = threadIdx.x / G;
@@ -224,6 +230,9 @@ __global__ __launch_bounds__(256) void k_build_cells(
     for (int q = 1; q <= 27; ++q) s_off[grp][q] += s_off[grp][q - 1];
   }
   __syncthreads();
+  if (k < 27)
+    for (int c = s_off[grp][k]; c < s_off[grp][k + 1] && c < kMap; ++c) s_cell[grp][c] = (uint8_t)k;
+  __syncthreads();
   if (!active) return;  // whole groups leave together
   const int total = s_off[grp][27];
   const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
@@ -231,15 +240,20 @@ __global__ __launch_bounds__(256) void k_build_cells(
   bool overflow = false, bad_image = false;
   // candidate c: its list entry and squared distance (r2 < 0 for the atom itself)
   auto candidate = [&](int c, uint32_t& entry, double& r2) {
-    int lo = 0, hi = 27;  // the cell q that holds candidate c: off[q] <= c < off[q+1]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_off[grp][mid] <= c)
-        lo = mid;
-      else
-        hi = mid;
+    int q;  // the cell that holds candidate c: off[q] <= c < off[q+1]
+    if (c < kMap) {
+      q = s_cell[grp][c];
+    } else {
+      int lo = 0, hi = 27;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_off[grp][mid] <= c)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      q = lo;
     }
-    const int q = lo;
     const int o0 = q % 3 - 1, o1 = (q / 3) % 3 - 1, o2 = q / 9 - 1;
     const int e0 = c0 + o0, e1 = c1 + o1, e2 = c2 + o2;
     const int m0 = e0 < 0 ? -1 : (e0 >= nc0 ? 1 : 0);
@@ -276,10 +290,12 @@ __global__ __launch_bounds__(256) void k_build_cells(
     const unsigned long long br = (__ballot(keep_r) >> shift) & gmask;
     if (keep_a) {
       const int slot = na + __popcll(ba & below);
-      if (slot < cap)
+      if (slot < cap) {
         nl[(size_t)slot * n + i] = entry;
-      else
+        nl_rm[(size_t)i * cap + slot] = entry;
+      } else {
         overflow = true;
+      }
     }
     if (keep_r) {
       const int t = nro + __popcll(br & below);
@@ -295,10 +311,12 @@ __global__ __launch_bounds__(256) void k_build_cells(
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     for (int t = k; t < nro; t += G) {
       const int slot = na + t;
-      if (slot < cap)
+      if (slot < cap) {
         nl[(size_t)slot * n + i] = s_ro[grp][t];
-      else
+        nl_rm[(size_t)i * cap + slot] = s_ro[grp][t];
+      } else {
         overflow = true;
+      }
     }
   } else {
     int count = na;
@@ -314,10 +332,12 @@ __global__ __launch_bounds__(256) void k_build_cells(
       const unsigned long long ball = (__ballot(keep) >> shift) & gmask;
       if (keep) {
         const int slot = count + __popcll(ball & below);
-        if (slot < cap)
+        if (slot < cap) {
           nl[(size_t)slot * n + i] = entry;
-        else
+          nl_rm[(size_t)i * cap + slot] = entry;
+        } else {
           overflow = true;
+        }
       }
       count += __popcll(ball);
     }
@@ -382,8 +402,9 @@ __global__ void k_build_all_pairs(int n, int cap, const double* __restrict__ pos
 // j < i are left to that thread; after an overflow every entry searches for
 // itself, so that every reverse slot still names a slot inside j's list.
 __global__ void k_reverse(int n, int cap, const uint32_t* __restrict__ nl,
-                          const int* __restrict__ cnt_r, const int* __restrict__ cnt_a,
-                          int* __restrict__ rev, int* __restrict__ flags) {
+                          const uint32_t* __restrict__ nl_rm, const int* __restrict__ cnt_r,
+                          const int* __restrict__ cnt_a, int* __restrict__ rev,
+                          int* __restrict__ flags) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)n * cap) return;
   const int i = (int)(idx % (size_t)n);
@@ -400,10 +421,20 @@ __global__ void k_reverse(int n, int cap, const uint32_t* __restrict__ nl,
   const int t0 = angular ? 0 : cnt_a[j];
   const int t1 = angular ? cnt_a[j] : cnt_r[j];
   int found = -1;
-  for (int t = t0; t < t1; ++t) {
-    if (nl[(size_t)t * n + j] == target) {
-      found = t;
-      break;
+  if (nl_rm) {  // j's entries are contiguous
+    const uint32_t* row = nl_rm + (size_t)j * cap;
+    for (int t = t0; t < t1; ++t) {
+      if (row[t] == target) {
+        found = t;
+        break;
+      }
+    }
+  } else {
+    for (int t = t0; t < t1; ++t) {
+      if (nl[(size_t)t * n + j] == target) {
+        found = t;
+        break;
+      }
     }
   }
   if (found < 0) {
@@ -453,7 +484,7 @@ void launch_reverse(nep_ctx ctx, int n, int cap, const uint32_t* nl, const int* 
   const size_t ncap = (size_t)n * cap;
   if (ncap == 0) return;
   launch_kernel(ctx, false, false, k_reverse, dim3(blocks_for(ncap, kBlock)), dim3(kBlock), n, cap,
-                nl, cnt_r, cnt_a, rev, ctx->flags.ptr);
+                nl, (const uint32_t*)nullptr, cnt_r, cnt_a, rev, ctx->flags.ptr);
 }
 
 hipError_t unpack_neighbors(nep_ctx ctx, int* nbr, int* img, int* cnt_r, int* cnt_a, int* rev) {
@@ -541,7 +572,9 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
   const dim3 blk(kBlock);
   if (s.use_cells) {
     const int ncell = s.nc[0] * s.nc[1] * s.nc[2];
-    if ((e = s.cell_of.ensure(n)) != hipSuccess || (e = s.cell_cnt.ensure(ncell)) != hipSuccess ||
+    const int* cnt_before = s.cell_cnt.ptr;
+    if ((e = s.nl_rm.ensure(ncap)) != hipSuccess || (e = s.cell_of.ensure(n)) != hipSuccess ||
+        (e = s.cell_cnt.ensure(ncell)) != hipSuccess ||
         (e = s.cell_start.ensure((size_t)ncell + 1)) != hipSuccess ||
         (e = s.cell_fill.ensure(ncell)) != hipSuccess ||
         (e = s.cell_atoms.ensure(n)) != hipSuccess || (e = s.cell_sorted.ensure(n)) != hipSuccess ||
@@ -551,15 +584,16 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
         (e = s.perm_t.ensure(n)) != hipSuccess || (e = s.wrap_t.ensure((size_t)3 * n)) != hipSuccess ||
         (e = s.cell_t.ensure(n)) != hipSuccess)
       return check_hip(ctx, e, "allocating cell lists");
-    launch_kernel(ctx, true, false, k_zero, dim3(blocks_for(ncell, kBlock)), blk, s.cell_cnt.ptr,
-                  ncell);
-    launch_kernel(ctx, false, false, k_zero, dim3(blocks_for(ncell, kBlock)), blk,
-                  s.cell_fill.ptr, ncell);
-    launch_kernel(ctx, false, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, s.pos_s.ptr,
+    const bool zero = s.cell_cnt.ptr != cnt_before || s.cells_zeroed_for != ncell;
+    if (zero)
+      launch_kernel(ctx, true, false, k_zero, dim3(blocks_for(ncell, kBlock)), blk,
+                    s.cell_cnt.ptr, ncell);
+    launch_kernel(ctx, !zero, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, s.pos_s.ptr,
                   s.box, s.nc[0], s.nc[1], s.nc[2], 1, wrap_in_place ? 1 : 0, s.wrap.ptr,
                   s.cell_of.ptr, s.cell_cnt.ptr);
-    launch_kernel(ctx, false, false, k_scan, dim3(1), dim3(1024), ncell,
-                  (const int*)s.cell_cnt.ptr, s.cell_start.ptr);
+    launch_kernel(ctx, false, false, k_scan, dim3(1), dim3(1024), ncell, s.cell_cnt.ptr,
+                  s.cell_start.ptr, s.cell_fill.ptr);
+    s.cells_zeroed_for = ncell;
     launch_kernel(ctx, false, false, k_fill, dim3(blocks_for(n, kBlock)), blk, n,
                   (const int*)s.cell_of.ptr, (const int*)s.cell_start.ptr, s.cell_fill.ptr,
                   s.cell_atoms.ptr);
@@ -582,7 +616,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
                   blk, n, s.cap, (const double*)s.pos_s.ptr, s.box, s.nc[0], s.nc[1], s.nc[2],
                   (const int*)s.wrap.ptr, (const int*)s.cell_of.ptr,
                   (const int*)s.cell_start.ptr, (const CellRec*)s.cell_rec.ptr, rc2_r, rc2_a,
-                  s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr, ctx->flags.ptr);
+                  s.nl.ptr, s.nl_rm.ptr, s.cnt_r.ptr, s.cnt_a.ptr, ctx->flags.ptr);
   } else {
     launch_kernel(ctx, true, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, s.pos_s.ptr, s.box,
                   1, 1, 1, 0, wrap_in_place ? 1 : 0, s.wrap.ptr, (int*)nullptr, (int*)nullptr);
@@ -592,8 +626,9 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
                   ctx->flags.ptr);
   }
   launch_kernel(ctx, false, true, k_reverse, dim3(blocks_for(ncap, kBlock)), blk, n, s.cap,
-                (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr, (const int*)s.cnt_a.ptr,
-                s.rev.ptr, ctx->flags.ptr);
+                (const uint32_t*)s.nl.ptr,
+                s.use_cells ? (const uint32_t*)s.nl_rm.ptr : (const uint32_t*)nullptr,
+                (const int*)s.cnt_r.ptr, (const int*)s.cnt_a.ptr, s.rev.ptr, ctx->flags.ptr);
   return check_hip(ctx, hipGetLastError(), "launching neighbour kernels");
 }
 

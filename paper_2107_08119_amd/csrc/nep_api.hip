@@ -411,4 +411,53 @@ nep_status nep_time_partials(nep_ctx ctx, const double* pos_dev, int reps, doubl
   return NEP_OK;
 }
 
+nep_status nep_autotune(nep_ctx ctx, const double* pos_dev, int reps, int* lanes_out,
+                        double* ms_out) {
+  if (!ctx) return NEP_EINVAL;
+  if (!ctx->have_params || !ctx->have_list)
+    return fail(ctx, NEP_ESTATE, "nep_load_params and nep_build_neighbors must come first");
+  if (reps < 1 || reps > 10000) return fail(ctx, NEP_EINVAL, "reps must be in [1, 10000]");
+  if (ctx->sys.n > 0 && !pos_dev) return fail(ctx, NEP_EINVAL, "pos_dev is NULL");
+  DeviceGuard guard(ctx->device);
+  launch_take_rows(ctx, ctx->sys.n, 3, pos_dev, ctx->sys.pos_s.ptr);
+  const bool timing = ctx->timer.on;
+  ctx->timer.on = false;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  int best = ctx->md_variant;
+  double best_ms = 0.0;
+  for (int v = 0; v < 3 && e == hipSuccess; ++v) {
+    e = launch_partials(ctx, ctx->sys.pos_s.ptr, v);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_partials(ctx, ctx->sys.pos_s.ptr, v);
+    if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    const double per = (double)ms / reps;
+    if (ms_out) ms_out[v] = per;
+    if (e == hipSuccess && (v == 0 || per < best_ms)) {
+      best = v;
+      best_ms = per;
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  ctx->timer.on = timing;
+  ctx->md_forces_valid = false;  // the partial forces were recomputed
+  if (e != hipSuccess) return check_hip(ctx, e, "timing the partial-force kernel");
+  ctx->md_variant = best;
+  if (lanes_out) *lanes_out = 2 << best;
+  return NEP_OK;
+}
+
+nep_status nep_set_tile(nep_ctx ctx, int lanes) {
+  if (!ctx) return NEP_EINVAL;
+  if (lanes != 2 && lanes != 4 && lanes != 8) return fail(ctx, NEP_EINVAL, "lanes must be 2, 4 or 8");
+  ctx->md_variant = lanes == 2 ? 0 : (lanes == 4 ? 1 : 2);
+  ctx->md_forces_valid = false;
+  return NEP_OK;
+}
+
 }  // extern "C"

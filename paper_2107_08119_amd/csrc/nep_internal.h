@@ -95,10 +95,12 @@ struct System {
   double skin = 0.0;
   double rc_list_r = 0, rc_list_a = 0;  // rc + skin
   bool use_cells = false;
+  int cells_zeroed_for = -1;  // cell_cnt is known zero for this cell count (-1: unknown)
   int nc[3] = {1, 1, 1};
   int kimg[3] = {0, 0, 0};  // image range for the all-pairs builder
   // device arrays (owned by the context)
   DevBuf<uint32_t> nl;     // [cap][n]
+  DevBuf<uint32_t> nl_rm;  // [n][cap] the same entries per atom (reverse-slot search)
   DevBuf<int> cnt_r;       // [n]
   DevBuf<int> cnt_a;       // [n]
   DevBuf<int> rev;         // [cap][n]
@@ -119,6 +121,7 @@ struct System {
   DevBuf<int> wrap_t, cell_t;   // [3][n], [n]
   void release() {
     nl.release();
+    nl_rm.release();
     cnt_r.release();
     cnt_a.release();
     rev.release();
@@ -195,6 +198,7 @@ struct nep_ctx_s {
   nep::DevBuf<float> W;           // [9][n] internal per-atom virials
   nep::DevBuf<float> J;           // [3][n] internal heat currents
   nep::DevBuf<double> partials;   // [blocks][16] block sums
+  int md_variant = 1;             // pass-1 tile shape: 0, 1, 2 = 2, 4, 8 lanes per atom
   nep::DevBuf<double> totals;     // [16]
   nep::DevBuf<int> flags;         // [kNumFlags]
   // molecular dynamics state
@@ -290,7 +294,9 @@ void launch_reverse(nep_ctx ctx, int n, int cap, const uint32_t* nl, const int* 
 // force.hip
 bool have_force_variant(const nep_hyper& h);
 // pass 1: descriptor, network, partial forces; pass 2: scatter-free gather.
-hipError_t launch_partials(nep_ctx ctx, const double* pos);
+// Pass 1 on the internal system with tile shape `variant` (0, 1, 2 = 2, 4, 8
+// lanes per atom; -1 = the context's choice).
+hipError_t launch_partials(nep_ctx ctx, const double* pos, int variant = -1);
 // mode 0: plain evaluation (totals = E, W(9), J(3)); mode 1: velocity-Verlet
 // second half-kick fused (vel updated, thermo row written).
 // Pass 2 (k_gather, modes as documented there) writing per-block sums to

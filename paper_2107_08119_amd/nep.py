@@ -28,7 +28,7 @@ EXPORTED = [
     "nep_time_partials", "nep_dataset_create", "nep_dataset_destroy", "snes_eval_population",
     "snes_sample", "snes_update", "nep_dataset_set_positions", "nep_dataset_get_positions",
     "nep_dataset_compute", "nep_dataset_backward", "snes_autotune", "snes_run",
-    "snes_set_tile",
+    "snes_set_tile", "nep_autotune", "nep_set_tile",
 ]
 
 
@@ -88,6 +88,8 @@ def lib() -> C.CDLL:
         L.snes_autotune.argtypes = [vp, vp, ip, vp, ip, C.POINTER(C.c_int),
                                     C.POINTER(C.c_double)]
         L.snes_set_tile.argtypes = [vp, vp, ip]
+        L.nep_autotune.argtypes = [vp, vp, ip, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.nep_set_tile.argtypes = [vp, ip]
         L.snes_run.argtypes = [vp, vp, ip, ip, vp, vp, C.c_ulonglong, ip, ip, vp, dp, dp, vp, vp,
                                vp, vp]
         L.nep_dataset_set_positions.argtypes = [vp, vp, vp]
@@ -214,6 +216,19 @@ class Context:
             self._h, _ptr(pos), _ptr(vel), _ptr(out.get("U")), _ptr(out["F"]),
             _ptr(out.get("W")), _ptr(out.get("J")), _ptr(out.get("totals"))))
         return out
+
+    def autotune(self, pos: torch.Tensor, reps: int = 20):
+        """Time the pass-1 tile shapes on the current system and keep the
+        fastest; returns (lanes per atom chosen, ms per launch of the 2-, 4-
+        and 8-lane shapes)."""
+        _require(pos, torch.float64, (3, self.n), "pos")
+        lanes = C.c_int(0)
+        ms = (C.c_double * 3)()
+        self._check(self._lib.nep_autotune(self._h, _ptr(pos), reps, C.byref(lanes), ms))
+        return lanes.value, list(ms)
+
+    def set_tile(self, lanes: int) -> None:
+        self._check(self._lib.nep_set_tile(self._h, lanes))
 
     # -- training ------------------------------------------------------------
     def dataset_create(self, ls, max_neighbors: int = 64) -> "Dataset":

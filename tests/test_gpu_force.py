@@ -262,3 +262,32 @@ def test_md_in_pieces_matches_one_call():
     th_ref, _, _ = O.md_nve(OH, z, pos, box, vel, I.MASS_SI, 1.0, 12)
     assert rel(runs[0][0][:12, 0], th_ref[:, 0]) < TOL
     assert rel(runs[0][0][:12, 1], th_ref[:, 1]) < TOL
+
+
+@pytest.mark.parametrize("lanes", [2, 4, 8])
+def test_tile_shapes_match_oracle(parity_case, lanes):
+    """Every compiled pass-1 tile shape gives the oracle's U, F, W, J, on the
+    small-box path and on the cell-list path (slots beyond the LDS stage
+    included); the autotuner picks one of them."""
+    nep = nep_mod()
+    pos, box, z, vel, ref = parity_case
+    ctx = nep.Context(0)
+    ctx.load_params(nep.hyper(), z)
+    p = nep.soa(pos)
+    ctx.build_neighbors(p, box, skin=0.5, max_neighbors=64)
+    chosen, ms = ctx.autotune(p, reps=3)
+    assert chosen in (2, 4, 8) and all(t > 0 for t in ms)
+    ctx.set_tile(lanes)
+    out, _ = gpu_eval(pos, box, z, vel, ctx=ctx)
+    for k in ("U", "F", "W", "J"):
+        assert rel(out[k], ref[k]) < TOL, k
+    # a denser cell-list case: a compressed, jittered 4x4x4 diamond (more slots per atom)
+    pos2, box2 = I.diamond_supercell(4, 4, 4, a=4.9)
+    rng = np.random.default_rng(12)
+    pos2 = I.wrap_positions(pos2 + rng.normal(0.0, 0.08, pos2.shape), box2)
+    vel2 = I.maxwell_boltzmann(len(pos2), 300.0, 3)
+    out2, _ = gpu_eval(pos2, box2, z, vel2, ctx=ctx, cap=96)
+    sel = np.arange(0, len(pos2), 7)
+    ref2 = O.nep_eval(OH, z, pos2, box2, vel=vel2, sel=sel)
+    for k in ("U", "F", "W", "J"):
+        assert rel(out2[k][sel], ref2[k]) < TOL, k
