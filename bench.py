@@ -47,6 +47,32 @@ FLOP_SLOT, FLOP_RADIAL, FLOP_ANGULAR, FLOP_ATOM = 29, 227, 1257, 4246
 # Algorithmic HBM bytes of the same kernel per atom: own position 24, counts 8,
 # list 4 per slot, partial force written 16 per slot, site energy 4.
 BYTE_ATOM, BYTE_SLOT = 36, 20
+# Measured HBM traffic of one k_partials launch of this workload: rocprofv3
+# --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this bench (KiB per dispatch;
+# profiles/k_partials_nve64k_counters.md), each scaled by what the counter
+# reads for a plain device copy of known size (--copy-probe-mib: FETCH_SIZE
+# reports half the bytes read, WRITE_SIZE all bytes written).  They hold only
+# for the kernel sources they were taken with (hash below); otherwise the
+# bench reports traffic null.
+COUNTERS = {"sources_sha256": None, "fetch_kib": None, "write_kib": None}
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+KERNEL_SOURCES = ["force.hip", "nep_terms.h", "nep_device.h", "nep_internal.h"]
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2107_08119_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_partials launch from the recorded counters, or None."""
+    if COUNTERS["sources_sha256"] is None or COUNTERS["sources_sha256"] != kernel_sources_hash():
+        return None
+    return 1024.0 * (FETCH_SCALE * COUNTERS["fetch_kib"] + WRITE_SCALE * COUNTERS["write_kib"])
 
 
 def parse():
@@ -293,7 +319,7 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "flop_per_atom": flop_atom,
             "avg_launch_us": avg_s * 1e6,
             "timing": "HIP events around 200 back-to-back launches on the library stream",

@@ -177,161 +177,123 @@ __global__ void k_iota(int n, int* __restrict__ a) {
   if (k < n) a[k] = k;
 }
 
-// G lanes per atom (G = 32) scan the 27 surrounding cells once.  The
-// candidates of the 27 cells are numbered consecutively (cell order, then
-// member order) and the G lanes test G consecutive candidates at a time; a
-// ballot and a population count give each kept entry the slot a serial scan
-// would give it, so the order does not depend on G.  Angular-range entries
-// go to the list at once; the remaining radial-range entries wait in LDS (up
-// to RO per atom) and follow them when the scan is done.  An atom with more
-// than RO of them scans its cells a second time for that part.
-template <int G, int RO>
-__global__ __launch_bounds__(256) void k_build_cells(
+// One block per cell: the records of the 27 surrounding cells are staged in
+// LDS once (up to MAXC of them; the rest are read from global memory) and
+// every atom of the cell is scanned by a group of G lanes.  The candidates are
+// numbered consecutively (cell order, then member order) and the G lanes test
+// G consecutive candidates at a time; a ballot and a population count give
+// each kept entry the slot a serial scan would give it, so the order does not
+// depend on G.  Angular-range entries go to the list at once; the remaining
+// radial-range entries wait in LDS (up to RO per atom) and follow them when
+// the scan is done.  An atom with more than RO of them scans its cells a
+// second time for that part.  Atoms are in cell order, so a cell's atoms are
+// start[c] .. start[c+1]-1.
+template <int G, int RO, int MAXC, int NT>
+__global__ __launch_bounds__(NT) void k_build_cells(
     int n, int cap, const double* __restrict__ pos, Box box, int nc0, int nc1, int nc2,
-    const int* __restrict__ wrap, const int* __restrict__ cell_of, const int* __restrict__ start,
+    const int* __restrict__ wrap, const int* __restrict__ start,
     const CellRec* __restrict__ rec, double rc2_r, double rc2_a, uint32_t* __restrict__ nl,
     uint32_t* __restrict__ nl_rm, int* __restrict__ cnt_r, int* __restrict__ cnt_a,
     int* __restrict__ flags) {
-  static_assert(G >= 27 && G <= 64 && 256 % G == 0, "a group covers the 27 cells");
-  constexpr int kMap = 512;            // candidates whose cell is looked up in a table
-  __shared__ int s_off[256 / G][28];   // first candidate number of each cell
-  __shared__ int s_first[256 / G][27]; // first member slot of each cell
-  __shared__ uint8_t s_cell[256 / G][kMap];  // cell of candidate c
-  __shared__ uint32_t s_ro[256 / G][RO];  // radial-only entries in scan order
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int grp = threadIdx.x / G;
-  const int k = gid % G;
-  const int i = gid / G;
-  const bool active = i < n;
-  const int shift = (threadIdx.x & 63) - k;  // first lane of the group within its wave
-  const unsigned long long below = (1ull << k) - 1ull;
-  const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
-  const int ii = active ? i : 0;
-  const int cell = cell_of[ii];
+  static_assert(G == 32 || G == 64, "lane groups inside one wave");
+  constexpr int NG = NT / G;  // atoms scanned side by side
+  __shared__ int s_off[28];    // first candidate number of each neighbour cell
+  __shared__ int s_first[27];  // first member slot of each neighbour cell
+  __shared__ int s_img[27];    // packed periodic image offset of each neighbour cell
+  __shared__ CellRec s_rec[MAXC];
+  __shared__ uint8_t s_cell[MAXC];
+  __shared__ uint32_t s_ro[NG][RO];  // radial-only entries in scan order
+  const int cell = blockIdx.x;
   const int c0 = cell % nc0, c1 = (cell / nc0) % nc1, c2 = cell / (nc0 * nc1);
-  // lane k < 27 looks up neighbour cell k (offsets o2, o1, o0 in -1..1, o0 fastest)
-  int my_cnt = 0;
-  if (k < 27) {
-    int d0 = c0 + k % 3 - 1, d1 = c1 + (k / 3) % 3 - 1, d2 = c2 + k / 9 - 1;
-    d0 -= (d0 < 0 ? -1 : (d0 >= nc0 ? 1 : 0)) * nc0;
-    d1 -= (d1 < 0 ? -1 : (d1 >= nc1 ? 1 : 0)) * nc1;
-    d2 -= (d2 < 0 ? -1 : (d2 >= nc2 ? 1 : 0)) * nc2;
-    const int cc = (d2 * nc1 + d1) * nc0 + d0;
-    const int b = start[cc];
-    my_cnt = start[cc + 1] - b;
-    s_first[grp][k] = b;
-  }
-  // exclusive prefix of the 27 counts (serial over the group's first lane)
-  __syncthreads();
-  if (k < 27) s_off[grp][k + 1] = my_cnt;
-  __syncthreads();
-  if (k == 0) {
-    s_off[grp][0] = 0;
-    for (int q = 1; q <= 27; ++q) s_off[grp][q] += s_off[grp][q - 1];
-  }
-  __syncthreads();
-  if (k < 27)
-    for (int c = s_off[grp][k]; c < s_off[grp][k + 1] && c < kMap; ++c) s_cell[grp][c] = (uint8_t)k;
-  __syncthreads();
-  if (!active) return;  // whole groups leave together
-  const int total = s_off[grp][27];
-  const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
-  const int wi0 = wrap[i], wi1 = wrap[n + i], wi2 = wrap[2 * n + i];
-  bool overflow = false, bad_image = false;
-  // candidate c: its list entry and squared distance (r2 < 0 for the atom itself)
-  auto candidate = [&](int c, uint32_t& entry, double& r2) {
-    int q;  // the cell that holds candidate c: off[q] <= c < off[q+1]
-    if (c < kMap) {
-      q = s_cell[grp][c];
-    } else {
-      int lo = 0, hi = 27;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_off[grp][mid] <= c)
-          lo = mid;
-        else
-          hi = mid;
-      }
-      q = lo;
-    }
-    const int o0 = q % 3 - 1, o1 = (q / 3) % 3 - 1, o2 = q / 9 - 1;
-    const int e0 = c0 + o0, e1 = c1 + o1, e2 = c2 + o2;
+  const int tid = threadIdx.x;
+  // thread q < 27 looks up neighbour cell q (offsets o2, o1, o0 in -1..1, o0 fastest)
+  if (tid < 27) {
+    const int e0 = c0 + tid % 3 - 1, e1 = c1 + (tid / 3) % 3 - 1, e2 = c2 + tid / 9 - 1;
     const int m0 = e0 < 0 ? -1 : (e0 >= nc0 ? 1 : 0);
     const int m1 = e1 < 0 ? -1 : (e1 >= nc1 ? 1 : 0);
     const int m2 = e2 < 0 ? -1 : (e2 >= nc2 ? 1 : 0);
-    const CellRec rc = rec[s_first[grp][q] + (c - s_off[grp][q])];
-    const int j = rc.j;
-    const int n0 = m0 + wi0 - (int)(signed char)(rc.w & 0xFF);
-    const int n1 = m1 + wi1 - (int)(signed char)((rc.w >> 8) & 0xFF);
-    const int n2 = m2 + wi2 - (int)(signed char)((rc.w >> 16) & 0xFF);
-    r2 = -1.0;
-    entry = 0;
-    if (!(j == i && n0 == 0 && n1 == 0 && n2 == 0)) {
-      r2 = list_r2(rc.x, rc.y, rc.z, xi, yi, zi, n0, n1, n2, box.h);
-      if (r2 < rc2_r && (n0 < -3 || n0 > 3 || n1 < -3 || n1 > 3 || n2 < -3 || n2 > 3)) {
-        bad_image = true;
-        r2 = -1.0;
-      }
-      entry = pack_entry(j, n0, n1, n2);
-    }
-  };
-  int na = 0, nro = 0;
-  for (int base = 0; base < total; base += G) {
-    const int c = base + k;
-    bool keep_a = false, keep_r = false;
-    uint32_t entry = 0;
-    if (c < total) {
-      double r2;
-      candidate(c, entry, r2);
-      keep_a = r2 >= 0.0 && r2 < rc2_a;
-      keep_r = r2 >= rc2_a && r2 < rc2_r;
-    }
-    const unsigned long long ba = (__ballot(keep_a) >> shift) & gmask;
-    const unsigned long long br = (__ballot(keep_r) >> shift) & gmask;
-    if (keep_a) {
-      const int slot = na + __popcll(ba & below);
-      if (slot < cap) {
-        nl[(size_t)slot * n + i] = entry;
-        nl_rm[(size_t)i * cap + slot] = entry;
-      } else {
-        overflow = true;
-      }
-    }
-    if (keep_r) {
-      const int t = nro + __popcll(br & below);
-      if (t < RO) s_ro[grp][t] = entry;
-    }
-    na += __popcll(ba);
-    nro += __popcll(br);
+    const int cc = ((e2 - m2 * nc2) * nc1 + (e1 - m1 * nc1)) * nc0 + (e0 - m0 * nc0);
+    const int b = start[cc];
+    s_first[tid] = b;
+    s_off[tid + 1] = start[cc + 1] - b;
+    s_img[tid] = (m0 + 1) | ((m1 + 1) << 2) | ((m2 + 1) << 4);
   }
-  if (nro <= RO) {
-    // the group's LDS writes above are read back by other lanes of the group
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    for (int t = k; t < nro; t += G) {
-      const int slot = na + t;
-      if (slot < cap) {
-        nl[(size_t)slot * n + i] = s_ro[grp][t];
-        nl_rm[(size_t)i * cap + slot] = s_ro[grp][t];
+  __syncthreads();
+  if (tid == 0) {
+    s_off[0] = 0;
+    for (int q = 1; q <= 27; ++q) s_off[q] += s_off[q - 1];
+  }
+  __syncthreads();
+  const int total = s_off[27];
+  if (tid < 27)
+    for (int c = s_off[tid]; c < s_off[tid + 1] && c < MAXC; ++c) s_cell[c] = (uint8_t)tid;
+  __syncthreads();
+  for (int c = tid; c < total && c < MAXC; c += NT) {
+    const int q = s_cell[c];
+    s_rec[c] = rec[s_first[q] + (c - s_off[q])];
+  }
+  __syncthreads();
+
+  const int grp = tid / G;
+  const int k = tid % G;
+  const int shift = (tid & 63) - k;  // first lane of the group within its wave
+  const unsigned long long below = (1ull << k) - 1ull;
+  const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+  const int a1 = start[cell + 1];
+  for (int i = start[cell] + grp; i < a1; i += NG) {
+    const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+    const int wi0 = wrap[i], wi1 = wrap[n + i], wi2 = wrap[2 * n + i];
+    bool overflow = false, bad_image = false;
+    // candidate c: its list entry and squared distance (r2 < 0 for the atom itself)
+    auto candidate = [&](int c, uint32_t& entry, double& r2) {
+      int q;  // the cell that holds candidate c: off[q] <= c < off[q+1]
+      CellRec rc;
+      if (c < MAXC) {
+        q = s_cell[c];
+        rc = s_rec[c];
       } else {
-        overflow = true;
+        int lo = 0, hi = 27;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_off[mid] <= c)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        q = lo;
+        rc = rec[s_first[q] + (c - s_off[q])];
       }
-    }
-  } else {
-    int count = na;
+      const int im = s_img[q];
+      const int j = rc.j;
+      const int n0 = (im & 3) - 1 + wi0 - (int)(signed char)(rc.w & 0xFF);
+      const int n1 = ((im >> 2) & 3) - 1 + wi1 - (int)(signed char)((rc.w >> 8) & 0xFF);
+      const int n2 = ((im >> 4) & 3) - 1 + wi2 - (int)(signed char)((rc.w >> 16) & 0xFF);
+      r2 = -1.0;
+      entry = 0;
+      if (!(j == i && n0 == 0 && n1 == 0 && n2 == 0)) {
+        r2 = list_r2(rc.x, rc.y, rc.z, xi, yi, zi, n0, n1, n2, box.h);
+        if (r2 < rc2_r && (n0 < -3 || n0 > 3 || n1 < -3 || n1 > 3 || n2 < -3 || n2 > 3)) {
+          bad_image = true;
+          r2 = -1.0;
+        }
+        entry = pack_entry(j, n0, n1, n2);
+      }
+    };
+    int na = 0, nro = 0;
     for (int base = 0; base < total; base += G) {
       const int c = base + k;
-      bool keep = false;
+      bool keep_a = false, keep_r = false;
       uint32_t entry = 0;
       if (c < total) {
         double r2;
         candidate(c, entry, r2);
-        keep = r2 >= rc2_a && r2 < rc2_r;
+        keep_a = r2 >= 0.0 && r2 < rc2_a;
+        keep_r = r2 >= rc2_a && r2 < rc2_r;
       }
-      const unsigned long long ball = (__ballot(keep) >> shift) & gmask;
-      if (keep) {
-        const int slot = count + __popcll(ball & below);
+      const unsigned long long ba = (__ballot(keep_a) >> shift) & gmask;
+      const unsigned long long br = (__ballot(keep_r) >> shift) & gmask;
+      if (keep_a) {
+        const int slot = na + __popcll(ba & below);
         if (slot < cap) {
           nl[(size_t)slot * n + i] = entry;
           nl_rm[(size_t)i * cap + slot] = entry;
@@ -339,15 +301,62 @@ __global__ __launch_bounds__(256) void k_build_cells(
           overflow = true;
         }
       }
-      count += __popcll(ball);
+      if (keep_r) {
+        const int t = nro + __popcll(br & below);
+        if (t < RO) s_ro[grp][t] = entry;
+      }
+      na += __popcll(ba);
+      nro += __popcll(br);
     }
+    if (nro <= RO) {
+      // the group's LDS writes above are read back by other lanes of the group
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      for (int t = k; t < nro; t += G) {
+        const int slot = na + t;
+        if (slot < cap) {
+          nl[(size_t)slot * n + i] = s_ro[grp][t];
+          nl_rm[(size_t)i * cap + slot] = s_ro[grp][t];
+        } else {
+          overflow = true;
+        }
+      }
+    } else {
+      int count = na;
+      for (int base = 0; base < total; base += G) {
+        const int c = base + k;
+        bool keep = false;
+        uint32_t entry = 0;
+        if (c < total) {
+          double r2;
+          candidate(c, entry, r2);
+          keep = r2 >= rc2_a && r2 < rc2_r;
+        }
+        const unsigned long long ball = (__ballot(keep) >> shift) & gmask;
+        if (keep) {
+          const int slot = count + __popcll(ball & below);
+          if (slot < cap) {
+            nl[(size_t)slot * n + i] = entry;
+            nl_rm[(size_t)i * cap + slot] = entry;
+          } else {
+            overflow = true;
+          }
+        }
+        count += __popcll(ball);
+      }
+    }
+    if (k == 0) {
+      cnt_a[i] = min(na, cap);
+      cnt_r[i] = min(na + nro, cap);
+    }
+    if (overflow) flags[kFlagOverflow] = 1;
+    if (bad_image) flags[kFlagImage] = 1;
+    // the group reuses s_ro for its next atom
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
-  if (k == 0) {
-    cnt_a[i] = min(na, cap);
-    cnt_r[i] = min(na + nro, cap);
-  }
-  if (overflow) flags[kFlagOverflow] = 1;
-  if (bad_image) flags[kFlagImage] = 1;
 }
 
 // One thread per atom: every atom j and every image m in [-k, k]^3 of the
@@ -401,49 +410,52 @@ __global__ void k_build_all_pairs(int n, int cap, const double* __restrict__ pos
 // j > i also writes the reverse slot of the entry it finds, and entries with
 // j < i are left to that thread; after an overflow every entry searches for
 // itself, so that every reverse slot still names a slot inside j's list.
-__global__ void k_reverse(int n, int cap, const uint32_t* __restrict__ nl,
+__global__ void k_reverse(int n, int cap, int width, const uint32_t* __restrict__ nl,
                           const uint32_t* __restrict__ nl_rm, const int* __restrict__ cnt_r,
                           const int* __restrict__ cnt_a, int* __restrict__ rev,
                           int* __restrict__ flags) {
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)n * cap) return;
-  const int i = (int)(idx % (size_t)n);
-  const int s = (int)(idx / (size_t)n);
-  if (s >= cnt_r[i]) return;
-  const uint32_t e = nl[idx];
-  const int j = (int)(e & kAtomMask);
+  // thread (s0, i) handles slots s0, s0 + width, ... of atom i
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)n * width) return;
+  const int i = (int)(t % (size_t)n);
+  const int cr = cnt_r[i], ca = cnt_a[i];
   const bool symmetric = flags[kFlagOverflow] == 0;
-  if (symmetric && j < i) return;
-  int n0, n1, n2;
-  unpack_image(e, n0, n1, n2);
-  const uint32_t target = pack_entry(i, -n0, -n1, -n2);
-  const bool angular = s < cnt_a[i];
-  const int t0 = angular ? 0 : cnt_a[j];
-  const int t1 = angular ? cnt_a[j] : cnt_r[j];
-  int found = -1;
-  if (nl_rm) {  // j's entries are contiguous
-    const uint32_t* row = nl_rm + (size_t)j * cap;
-    for (int t = t0; t < t1; ++t) {
-      if (row[t] == target) {
-        found = t;
-        break;
+  for (int s = (int)(t / (size_t)n); s < cr; s += width) {
+    const size_t idx = (size_t)s * n + i;
+    const uint32_t e = nl[idx];
+    const int j = (int)(e & kAtomMask);
+    if (symmetric && j < i) continue;
+    int n0, n1, n2;
+    unpack_image(e, n0, n1, n2);
+    const uint32_t target = pack_entry(i, -n0, -n1, -n2);
+    const bool angular = s < ca;
+    const int t0 = angular ? 0 : cnt_a[j];
+    const int t1 = angular ? cnt_a[j] : cnt_r[j];
+    int found = -1;
+    if (nl_rm) {  // j's entries are contiguous
+      const uint32_t* row = nl_rm + (size_t)j * cap;
+      for (int u = t0; u < t1; ++u) {
+        if (row[u] == target) {
+          found = u;
+          break;
+        }
+      }
+    } else {
+      for (int u = t0; u < t1; ++u) {
+        if (nl[(size_t)u * n + j] == target) {
+          found = u;
+          break;
+        }
       }
     }
-  } else {
-    for (int t = t0; t < t1; ++t) {
-      if (nl[(size_t)t * n + j] == target) {
-        found = t;
-        break;
-      }
+    if (found < 0) {
+      flags[kFlagReverse] = 1;
+      found = 0;
+    } else if (symmetric && j != i) {
+      rev[(size_t)found * n + j] = s;
     }
+    rev[idx] = found;
   }
-  if (found < 0) {
-    flags[kFlagReverse] = 1;
-    found = 0;
-  } else if (symmetric && j != i) {
-    rev[(size_t)found * n + j] = s;
-  }
-  rev[idx] = found;
 }
 
 // Expand the list into the caller's atom numbering: slot s of caller atom
@@ -483,8 +495,10 @@ void launch_reverse(nep_ctx ctx, int n, int cap, const uint32_t* nl, const int* 
                     const int* cnt_a, int* rev) {
   const size_t ncap = (size_t)n * cap;
   if (ncap == 0) return;
-  launch_kernel(ctx, false, false, k_reverse, dim3(blocks_for(ncap, kBlock)), dim3(kBlock), n, cap,
-                nl, (const uint32_t*)nullptr, cnt_r, cnt_a, rev, ctx->flags.ptr);
+  const int width = cap < 40 ? cap : 40;
+  launch_kernel(ctx, false, false, k_reverse, dim3(blocks_for((size_t)n * width, kBlock)),
+                dim3(kBlock), n, cap, width, nl, (const uint32_t*)nullptr, cnt_r, cnt_a, rev,
+                ctx->flags.ptr);
 }
 
 hipError_t unpack_neighbors(nep_ctx ctx, int* nbr, int* img, int* cnt_r, int* cnt_a, int* rev) {
@@ -611,12 +625,11 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
     s.wrap.swap(s.wrap_t);
     s.perm.swap(s.perm_t);
     s.cell_of.swap(s.cell_t);
-    constexpr int G = 32;
-    launch_kernel(ctx, false, false, k_build_cells<G, 64>, dim3(blocks_for((size_t)n * G, kBlock)),
-                  blk, n, s.cap, (const double*)s.pos_s.ptr, s.box, s.nc[0], s.nc[1], s.nc[2],
-                  (const int*)s.wrap.ptr, (const int*)s.cell_of.ptr,
-                  (const int*)s.cell_start.ptr, (const CellRec*)s.cell_rec.ptr, rc2_r, rc2_a,
-                  s.nl.ptr, s.nl_rm.ptr, s.cnt_r.ptr, s.cnt_a.ptr, ctx->flags.ptr);
+    launch_kernel(ctx, false, false, k_build_cells<32, 64, 640, 384>, dim3(ncell), dim3(384), n,
+                  s.cap, (const double*)s.pos_s.ptr, s.box, s.nc[0], s.nc[1], s.nc[2],
+                  (const int*)s.wrap.ptr, (const int*)s.cell_start.ptr,
+                  (const CellRec*)s.cell_rec.ptr, rc2_r, rc2_a, s.nl.ptr, s.nl_rm.ptr, s.cnt_r.ptr,
+                  s.cnt_a.ptr, ctx->flags.ptr);
   } else {
     launch_kernel(ctx, true, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, s.pos_s.ptr, s.box,
                   1, 1, 1, 0, wrap_in_place ? 1 : 0, s.wrap.ptr, (int*)nullptr, (int*)nullptr);
@@ -625,8 +638,9 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
                   (const int*)s.wrap.ptr, rc2_r, rc2_a, s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr,
                   ctx->flags.ptr);
   }
-  launch_kernel(ctx, false, true, k_reverse, dim3(blocks_for(ncap, kBlock)), blk, n, s.cap,
-                (const uint32_t*)s.nl.ptr,
+  const int width = s.cap < 40 ? s.cap : 40;
+  launch_kernel(ctx, false, true, k_reverse, dim3(blocks_for((size_t)n * width, kBlock)), blk, n,
+                s.cap, width, (const uint32_t*)s.nl.ptr,
                 s.use_cells ? (const uint32_t*)s.nl_rm.ptr : (const uint32_t*)nullptr,
                 (const int*)s.cnt_r.ptr, (const int*)s.cnt_a.ptr, s.rev.ptr, ctx->flags.ptr);
   return check_hip(ctx, hipGetLastError(), "launching neighbour kernels");
