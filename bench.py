@@ -54,7 +54,8 @@ BYTE_ATOM, BYTE_SLOT = 36, 20
 # reports half the bytes read, WRITE_SIZE all bytes written).  They hold only
 # for the kernel sources they were taken with (hash below); otherwise the
 # bench reports traffic null.
-COUNTERS = {"sources_sha256": None, "fetch_kib": None, "write_kib": None}
+COUNTERS = {"sources_sha256": "b90bddca187702f5a778fdd3f4d19cef80a917a9fc9468bcb1ce6654756b5102",
+            "fetch_kib": 10809.17, "write_kib": 58874.96}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ["force.hip", "nep_terms.h", "nep_device.h", "nep_internal.h"]
 

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   const float rcr2 = rc_r * rc_r, rca2 = rc_a * rc_a;
   {
     const int a = threadIdx.x % APB, w = threadIdx.x / APB;
-    const int ia = blockIdx.x * APB + a;
+    const int ia = (int)xcd_block(blockIdx.x, gridDim.x) * APB + a;
     const int cra = ia < n ? cnt_r[ia] : 0;
     const int caa = ia < n ? cnt_a[ia] : 0;
     const double* Ha = MULTI && ia < n ? boxes + 9 * (size_t)struct_of[ia] : box.h;
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
   __syncthreads();
 
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gid = (int)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int i = gid / L;
   const int lane = gid % L;
   const int la = threadIdx.x / L;
@@ -238,10 +238,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 // Per-block sums of NQ doubles, written to partials[block][NQ]; a second
 // kernel adds the blocks in order (no device-scope fence in the hot kernel).
 template <int NQ>
-__device__ __forceinline__ void block_partials(double (&v)[NQ], double* __restrict__ partials) {
+__device__ __forceinline__ void block_partials(double (&v)[NQ], double* __restrict__ partials,
+                                               unsigned block) {
   __shared__ double sw[kBlock / 64][NQ];
   const double s = block_sum<NQ>(v, sw);
-  if (threadIdx.x < NQ) partials[(size_t)blockIdx.x * NQ + threadIdx.x] = s;
+  if (threadIdx.x < NQ) partials[(size_t)block * NQ + threadIdx.x] = s;
 }
 
 // Block x reduces set x: out[x][q] = sum over blocks b (in order of b) of
@@ -279,7 +280,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     Box box, float* __restrict__ U_out,
     float* __restrict__ F, float* __restrict__ W, float* __restrict__ J, double kick,
     double ekin_factor, double dt, double* __restrict__ pos_next, double* __restrict__ partials) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned bx = xcd_block(blockIdx.x, gridDim.x);
+  const int gid = (int)bx * blockDim.x + threadIdx.x;
   const int i = gid / L;
   const int lane = gid % L;
   const bool active = i < n;
@@ -397,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(
       v[4] = j2;
     }
   }
-  block_partials<NQ>(v, partials);
+  block_partials<NQ>(v, partials, bx);
 }
 
 __global__ void k_kick_drift(int n, double* __restrict__ pos, double* __restrict__ vel,

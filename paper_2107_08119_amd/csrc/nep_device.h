@@ -8,6 +8,19 @@ namespace nep {
 constexpr int kBlock = 256;
 constexpr float kPi = 3.14159265358979323846f;
 
+// ------------------------------------------------------ XCD-aware blocks
+// Workgroups are dispatched to the 8 XCDs of the chip in turn (block b to XCD
+// b mod 8), and every XCD has its own L2.  xcd_block maps the dispatch index
+// b of nb blocks to a logical block so that each XCD gets one contiguous
+// range of logical blocks (a bijection for any nb): neighbouring atoms, whose
+// positions and partial-force slots the blocks share, then meet in one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned q = nb / kXcds, rem = nb % kXcds;
+  const unsigned x = b % kXcds, r = b / kXcds;
+  return x < rem ? x * (q + 1) + r : rem * (q + 1) + (x - rem) * q + r;
+}
+
 // ----------------------------------------------------------- lane groups
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
@@ -178,6 +191,28 @@ __device__ __forceinline__ double list_r2(double xj, double yj, double zj, doubl
   const double dx = (xj - xi) + ((a0 * h[0] + a1 * h[3]) + a2 * h[6]);
   const double dy = (yj - yi) + ((a0 * h[1] + a1 * h[4]) + a2 * h[7]);
   const double dz = (zj - zi) + ((a0 * h[2] + a1 * h[5]) + a2 * h[8]);
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// The lattice shift n.H of list_r2 alone (same operation order), and the
+// squared distance from a precomputed shift: list_r2_shifted(.., image_shift(n))
+// equals list_r2(.., n) bit for bit.
+__device__ __forceinline__ void image_shift(int n0, int n1, int n2, const double* h, double& sx,
+                                            double& sy, double& sz) {
+#pragma clang fp contract(off)
+  const double a0 = (double)n0, a1 = (double)n1, a2 = (double)n2;
+  sx = (a0 * h[0] + a1 * h[3]) + a2 * h[6];
+  sy = (a0 * h[1] + a1 * h[4]) + a2 * h[7];
+  sz = (a0 * h[2] + a1 * h[5]) + a2 * h[8];
+}
+
+__device__ __forceinline__ double list_r2_shifted(double xj, double yj, double zj, double xi,
+                                                  double yi, double zi, double sx, double sy,
+                                                  double sz) {
+#pragma clang fp contract(off)
+  const double dx = (xj - xi) + sx;
+  const double dy = (yj - yi) + sy;
+  const double dz = (zj - zi) + sz;
   return (dx * dx + dy * dy) + dz * dz;
 }
 

@@ -146,13 +146,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     float* __restrict__ fown, float* __restrict__ U) {
   __shared__ float4 rows[NetRows<NDES, NNEU>::kFloat4];
   __shared__ float b2;
-  const size_t k = blockIdx.x;
+  // logical (individual, atom block), contiguous atom blocks per XCD
+  const unsigned lb = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+  const size_t k = lb % gridDim.x;
+  const unsigned by = lb / gridDim.x;
   load_net_rows<NDES, NNEU>(Z + k * (size_t)n_par, rows, &b2);
   pin += k * pstride;
   fown += k * 3 * (size_t)N;
   U += k * (size_t)N;
   __syncthreads();
-  const int gid = blockIdx.y * blockDim.x + threadIdx.x;
+  const int gid = (int)by * blockDim.x + threadIdx.x;
   const int i = gid / L;
   const int lane = gid % L;
   const bool active = i < N;
@@ -218,8 +221,10 @@ __global__ __launch_bounds__(kBlock) void k_pop_struct(
     const int* __restrict__ has_v, double* __restrict__ sq) {
   __shared__ double sw[kBlock / 64][8];
   __shared__ double tot[8];
-  const size_t k = blockIdx.x;
-  const int s = blockIdx.y;
+  // logical (individual, structure), contiguous structures per XCD
+  const unsigned lb = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+  const size_t k = lb % gridDim.x;
+  const int s = (int)(lb / gridDim.x);
   pin += k * pstride;
   fown += k * 3 * (size_t)N;
   U += k * (size_t)N;
