@@ -15,6 +15,7 @@
 // nep.h (no fused multiply-add), so the list is reproducible bit for bit.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "nep_device.h"
 
@@ -200,10 +201,11 @@ __global__ __launch_bounds__(NT) void k_build_cells(
   __shared__ int s_off[28];    // first candidate number of each neighbour cell
   __shared__ int s_first[27];  // first member slot of each neighbour cell
   __shared__ int s_img[27];    // packed periodic image offset of each neighbour cell
+  __shared__ double s_shift[27][3];  // its lattice shift (for atoms with equal offsets)
   __shared__ CellRec s_rec[MAXC];
   __shared__ uint8_t s_cell[MAXC];
   __shared__ uint32_t s_ro[NG][RO];  // radial-only entries in scan order
-  const int cell = blockIdx.x;
+  const int cell = (int)xcd_block(blockIdx.x, gridDim.x);
   const int c0 = cell % nc0, c1 = (cell / nc0) % nc1, c2 = cell / (nc0 * nc1);
   const int tid = threadIdx.x;
   // thread q < 27 looks up neighbour cell q (offsets o2, o1, o0 in -1..1, o0 fastest)
@@ -217,6 +219,7 @@ __global__ __launch_bounds__(NT) void k_build_cells(
     s_first[tid] = b;
     s_off[tid + 1] = start[cc + 1] - b;
     s_img[tid] = (m0 + 1) | ((m1 + 1) << 2) | ((m2 + 1) << 4);
+    image_shift(m0, m1, m2, box.h, s_shift[tid][0], s_shift[tid][1], s_shift[tid][2]);
   }
   __syncthreads();
   if (tid == 0) {
@@ -228,10 +231,11 @@ __global__ __launch_bounds__(NT) void k_build_cells(
   if (tid < 27)
     for (int c = s_off[tid]; c < s_off[tid + 1] && c < MAXC; ++c) s_cell[c] = (uint8_t)tid;
   __syncthreads();
-  for (int c = tid; c < total && c < MAXC; c += NT) {
-    const int q = s_cell[c];
-    s_rec[c] = rec[s_first[q] + (c - s_off[q])];
-  }
+  if (total <= MAXC)
+    for (int c = tid; c < total; c += NT) {
+      const int q = s_cell[c];
+      s_rec[c] = rec[s_first[q] + (c - s_off[q])];
+    }
   __syncthreads();
 
   const int grp = tid / G;
@@ -240,6 +244,9 @@ __global__ __launch_bounds__(NT) void k_build_cells(
   const unsigned long long below = (1ull << k) - 1ull;
   const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
   const int a1 = start[cell + 1];
+  // records from LDS when all candidates were staged, else all from global
+  // memory (two instantiations, so that neither path uses generic addresses)
+  auto scan = [&](auto staged) {
   for (int i = start[cell] + grp; i < a1; i += NG) {
     const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
     const int wi0 = wrap[i], wi1 = wrap[n + i], wi2 = wrap[2 * n + i];
@@ -248,7 +255,7 @@ __global__ __launch_bounds__(NT) void k_build_cells(
     auto candidate = [&](int c, uint32_t& entry, double& r2) {
       int q;  // the cell that holds candidate c: off[q] <= c < off[q+1]
       CellRec rc;
-      if (c < MAXC) {
+      if constexpr (decltype(staged)::value) {
         q = s_cell[c];
         rc = s_rec[c];
       } else {
@@ -265,13 +272,20 @@ __global__ __launch_bounds__(NT) void k_build_cells(
       }
       const int im = s_img[q];
       const int j = rc.j;
-      const int n0 = (im & 3) - 1 + wi0 - (int)(signed char)(rc.w & 0xFF);
-      const int n1 = ((im >> 2) & 3) - 1 + wi1 - (int)(signed char)((rc.w >> 8) & 0xFF);
-      const int n2 = ((im >> 4) & 3) - 1 + wi2 - (int)(signed char)((rc.w >> 16) & 0xFF);
+      const int d0 = wi0 - (int)(signed char)(rc.w & 0xFF);
+      const int d1 = wi1 - (int)(signed char)((rc.w >> 8) & 0xFF);
+      const int d2 = wi2 - (int)(signed char)((rc.w >> 16) & 0xFF);
+      const int n0 = (im & 3) - 1 + d0;
+      const int n1 = ((im >> 2) & 3) - 1 + d1;
+      const int n2 = ((im >> 4) & 3) - 1 + d2;
       r2 = -1.0;
       entry = 0;
       if (!(j == i && n0 == 0 && n1 == 0 && n2 == 0)) {
-        r2 = list_r2(rc.x, rc.y, rc.z, xi, yi, zi, n0, n1, n2, box.h);
+        if ((d0 | d1 | d2) == 0)  // the neighbour cell's own shift (atoms in the cell)
+          r2 = list_r2_shifted(rc.x, rc.y, rc.z, xi, yi, zi, s_shift[q][0], s_shift[q][1],
+                               s_shift[q][2]);
+        else
+          r2 = list_r2(rc.x, rc.y, rc.z, xi, yi, zi, n0, n1, n2, box.h);
         if (r2 < rc2_r && (n0 < -3 || n0 > 3 || n1 < -3 || n1 > 3 || n2 < -3 || n2 > 3)) {
           bad_image = true;
           r2 = -1.0;
@@ -310,9 +324,9 @@ __global__ __launch_bounds__(NT) void k_build_cells(
     }
     if (nro <= RO) {
       // the group's LDS writes above are read back by other lanes of the group
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (int t = k; t < nro; t += G) {
         const int slot = na + t;
         if (slot < cap) {
@@ -353,10 +367,15 @@ __global__ __launch_bounds__(NT) void k_build_cells(
     if (overflow) flags[kFlagOverflow] = 1;
     if (bad_image) flags[kFlagImage] = 1;
     // the group reuses s_ro for its next atom
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  };
+  if (total <= MAXC)
+    scan(std::true_type{});
+  else
+    scan(std::false_type{});
 }
 
 // One thread per atom: every atom j and every image m in [-k, k]^3 of the
@@ -432,7 +451,16 @@ __global__ void k_reverse(int n, int cap, int width, const uint32_t* __restrict_
     const int t0 = angular ? 0 : cnt_a[j];
     const int t1 = angular ? cnt_a[j] : cnt_r[j];
     int found = -1;
-    if (nl_rm) {  // j's entries are contiguous
+    if (nl_rm && (cap & 3) == 0) {  // j's entries are contiguous: 4 per load
+      const uint4* row4 = reinterpret_cast<const uint4*>(nl_rm + (size_t)j * cap);
+      for (int u4 = t0 & ~3; u4 < t1 && found < 0; u4 += 4) {
+        const uint4 v = row4[u4 >> 2];
+        if (v.x == target && u4 >= t0) found = u4;
+        else if (v.y == target && u4 + 1 >= t0 && u4 + 1 < t1) found = u4 + 1;
+        else if (v.z == target && u4 + 2 >= t0 && u4 + 2 < t1) found = u4 + 2;
+        else if (v.w == target && u4 + 3 >= t0 && u4 + 3 < t1) found = u4 + 3;
+      }
+    } else if (nl_rm) {
       const uint32_t* row = nl_rm + (size_t)j * cap;
       for (int u = t0; u < t1; ++u) {
         if (row[u] == target) {
