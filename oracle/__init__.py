@@ -72,6 +72,8 @@ def lib():
                                   dp, dp, dp, dp, C.c_void_p]
         L.or_md_nve.argtypes = [H, dp, C.c_int, dp, dp, dp, C.c_double, C.c_double, C.c_int,
                                 C.c_int, dp]
+        L.or_md_driven.argtypes = [H, dp, C.c_int, dp, dp, dp, C.c_double, C.c_double, C.c_int,
+                                   C.c_int, C.c_void_p, dp]
         L.or_loss.argtypes = [H, dp, C.c_int, ip, dp, dp, dp, dp, dp, bp, dp, C.c_int, dp]
         L.or_grad_params.argtypes = [H, dp, C.c_int, ip, dp, dp, dp, dp, C.c_int, dp]
         L.or_philox4x32_10.argtypes = [up, up, up]
@@ -192,14 +194,17 @@ def nep_eval(h: Hyper, z, pos, box, vel=None, sel=None, cap: int = 256, want_q: 
     return out
 
 
-def md_nve(h: Hyper, z, pos, box, vel, mass: float, dt: float, n_steps: int, cap: int = 256):
-    """Velocity-Verlet NVE; returns (thermo [n_steps, 5], pos, vel)."""
+def md_nve(h: Hyper, z, pos, box, vel, mass: float, dt: float, n_steps: int, cap: int = 256,
+           fe=None):
+    """Velocity-Verlet NVE (with the HNEMD driving force F_e . W_i when fe is
+    given, Sec. II B); returns (thermo [n_steps, 5], pos, vel)."""
     pos = _d(pos).copy()
     vel = _d(vel).copy()
     thermo = np.zeros((max(n_steps, 1), 5))
     z = _d(np.asarray(z, dtype=np.float32).astype(np.float64))
-    _check(lib().or_md_nve(C.byref(h), z, len(pos), pos, _d(box), vel, mass, dt, n_steps, cap,
-                           thermo))
+    fe_arr = None if fe is None else _d(np.asarray(fe, dtype=np.float64).reshape(3))
+    _check(lib().or_md_driven(C.byref(h), z, len(pos), pos, _d(box), vel, mass, dt, n_steps, cap,
+                              None if fe_arr is None else fe_arr.ctypes.data, thermo))
     return thermo[:n_steps], pos, vel
 
 

@@ -670,12 +670,24 @@ int or_grad_params(const or_hyper* hp, const double* z, int n_struct, const int*
 
 /* --------------------------------------------------- molecular dynamics */
 
-/* Velocity-Verlet NVE trajectory with exact cutoffs at every step.
+/* F_i += F_e . W_i for every atom (W_i row-major, (W_i)_ab at 3a + b). */
+static void add_driving_force(int N, const double* fe, const double* W, double* F) {
+  for (int i = 0; i < N; ++i) {
+    const double* w = W + 9 * (size_t)i;
+    for (int b = 0; b < 3; ++b) F[3 * (size_t)i + b] += fe[0] * w[b] + fe[1] * w[3 + b] + fe[2] * w[6 + b];
+  }
+}
+
+/* Velocity-Verlet trajectory with exact cutoffs at every step.
  * pos/vel [N][3] are updated in place; thermo [n_steps][5] receives
  * E_pot, E_kin (eV), and the total heat current sum_i J_i (3 components)
- * after each step.  mass in amu, dt in fs. */
-int or_md_nve(const or_hyper* hp, const double* z, int N, double* pos, const double* H,
-              double* vel, double mass, double dt, int n_steps, int cap, double* thermo) {
+ * after each step.  mass in amu, dt in fs.  With fe != NULL every atom also
+ * feels the homogeneous driving force of the HNEMD method (Sec. II B):
+ * F_i^ext = F_e . W_i, i.e. (F_i^ext)_b = sum_a (F_e)_a (W_i)_ab, with F_e in
+ * 1/Angstrom; fe == NULL is plain NVE. */
+int or_md_driven(const or_hyper* hp, const double* z, int N, double* pos, const double* H,
+                 double* vel, double mass, double dt, int n_steps, int cap, const double* fe,
+                 double* thermo) {
   double* U = (double*)malloc(sizeof(double) * (size_t)N);
   double* F = (double*)malloc(sizeof(double) * 3 * (size_t)N);
   double* W = (double*)malloc(sizeof(double) * 9 * (size_t)N);
@@ -686,6 +698,7 @@ int or_md_nve(const or_hyper* hp, const double* z, int N, double* pos, const dou
     return -3;
   }
   int rcode = or_nep_eval(hp, z, N, pos, H, NULL, N, NULL, cap, U, F, W, NULL, NULL);
+  if (rcode == 0 && fe) add_driving_force(N, fe, W, F);
   const double k = OR_ACCEL / mass;
   for (int step = 0; step < n_steps && rcode == 0; ++step) {
     for (int i = 0; i < 3 * N; ++i) {
@@ -694,6 +707,7 @@ int or_md_nve(const or_hyper* hp, const double* z, int N, double* pos, const dou
     }
     rcode = or_nep_eval(hp, z, N, pos, H, NULL, N, NULL, cap, U, F, W, NULL, NULL);
     if (rcode) break;
+    if (fe) add_driving_force(N, fe, W, F);
     for (int i = 0; i < 3 * N; ++i) vel[i] += 0.5 * dt * k * F[i];
     /* heat current J_i = W_i . v_i with the end-of-step velocities */
     double ep = 0.0, ek = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
@@ -716,6 +730,12 @@ int or_md_nve(const or_hyper* hp, const double* z, int N, double* pos, const dou
   free(F);
   free(W);
   return rcode;
+}
+
+/* Velocity-Verlet NVE: or_md_driven without a driving force. */
+int or_md_nve(const or_hyper* hp, const double* z, int N, double* pos, const double* H,
+              double* vel, double mass, double dt, int n_steps, int cap, double* thermo) {
+  return or_md_driven(hp, z, N, pos, H, vel, mass, dt, n_steps, cap, NULL, thermo);
 }
 
 /* ------------------------------------------------------------ loss */

@@ -343,6 +343,34 @@ def test_velocity_verlet_free_particles():
     np.testing.assert_allclose(v, vel, atol=1e-15)
 
 
+def test_driving_force_power_is_fe_dot_heat_current():
+    """HNEMD (Sec. II B): the driving force F_i = F_e . W_i does work at the
+    rate sum_i F_i . v_i = F_e . sum_i W_i v_i = F_e . J, so the total energy
+    changes by the time integral of F_e . J (to O(dt^2) in velocity Verlet).
+    The transposed contraction W_i . F_e would give F_e . sum_i W_i^T v_i."""
+    pos, box = I.diamond_supercell(2, 2, 2)
+    rng = np.random.default_rng(8)
+    pos = pos + rng.standard_normal(pos.shape) * 0.03
+    vel = I.maxwell_boltzmann(len(pos), 300.0, 9)
+    z = I.random_parameters(O.n_par(H), 1)
+    fe = np.array([0.4, -0.25, 0.3])
+    dt, n = 0.05, 80
+    th, _, _ = O.md_nve(H, z, pos, box, vel, I.MASS_SI, dt, n, fe=fe)
+    first = O.nep_eval(H, z, pos, box, vel=vel)
+    e0 = first["U"].sum() + 0.5 * I.MASS_SI * (vel ** 2).sum() / I.ACCEL_UNIT
+    j = np.vstack([first["J"].sum(0), th[:, 2:]])
+    power = j @ fe
+    injected = dt * np.cumsum(0.5 * (power[:-1] + power[1:]))
+    de = th[:, 0] + th[:, 1] - e0
+    assert abs(injected[-1]) > 20 * np.abs(de - injected).max(), (injected[-1], de[-1])
+    # the same run without the field conserves energy to the integrator's error
+    th0, _, _ = O.md_nve(H, z, pos, box, vel, I.MASS_SI, dt, n)
+    assert np.abs(th0[:, 0] + th0[:, 1] - e0).max() < 0.05 * abs(injected[-1])
+    # no field and a zero field are the same trajectory
+    thz, _, _ = O.md_nve(H, z, pos, box, vel, I.MASS_SI, dt, 5, fe=np.zeros(3))
+    np.testing.assert_array_equal(thz, th0[:5])
+
+
 # -------------------------------------------------------------------- loss
 @pytest.fixture(scope="module")
 def tiny_set():
