@@ -54,8 +54,8 @@ BYTE_ATOM, BYTE_SLOT = 36, 20
 # reports half the bytes read, WRITE_SIZE all bytes written).  They hold only
 # for the kernel sources they were taken with (hash below); otherwise the
 # bench reports traffic null.
-COUNTERS = {"sources_sha256": "b90bddca187702f5a778fdd3f4d19cef80a917a9fc9468bcb1ce6654756b5102",
-            "fetch_kib": 10809.17, "write_kib": 58874.96}
+COUNTERS = {"sources_sha256": "7904ee82ca856fb38e7f5c5caeffa255cf74832cf6166adb36184ffb8ce88617",
+            "fetch_kib": 10792.25, "write_kib": 59168.99}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ["force.hip", "nep_terms.h", "nep_device.h", "nep_internal.h"]
 
@@ -125,6 +125,37 @@ def disordered_rate(args, nep, I, torch, z):
                         "distance), per-atom W and J written every step, dt 1 fs, rebuild every "
                         "10 steps", "atom_steps_per_s": n * K / t, "ms_per_step": t / K * 1e3,
             "steps": K, "k_partials_us": ms * 1e3, "tile_lanes_per_atom": lanes}
+
+
+def paper_model_rate(nep, I, torch, steps=100):
+    """The paper's speed test (Sec. III D) in kind: 8000-atom bulk Si, 100 MD
+    steps, with the general-Si model sizes of Sec. III B (r_c 5/5 A, n_max
+    15/15, l_max 4, 50 neurons: an 80-50-1 network, 4101 parameters), random
+    parameters (the work does not depend on their values); NVE, no thermostat."""
+    h = nep.hyper(5.0, 5.0, 15, 15, 4, 50)
+    z = I.random_parameters(nep.num_params(h), seed=1, std=0.02)
+    pos, box = I.diamond_supercell(10, 10, 10)
+    vel = I.maxwell_boltzmann(len(pos), 300.0, seed=2)
+    ctx = nep.Context(0)
+    ctx.load_params(h, z)
+    p, v = nep.soa(pos), nep.soa(vel)
+    ctx.build_neighbors(p, box, skin=0.5, max_neighbors=96)
+    ctx.md_step(10, 1.0, 10, I.MASS_SI, p, v)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.md_step(steps, 1.0, 10, I.MASS_SI, p, v)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ctx.synchronize()
+    ms = nep.time_partials(ctx, p, reps=50)
+    rate = len(pos) * steps / t
+    return {"workload": "8000-atom Si diamond (10x10x10 cells), NEP 80-50-1 (r_c 5/5 A, "
+                        "n_max 15/15, l_max 4, 50 neurons), %d NVE steps, dt 1 fs, rebuild every "
+                        "10 steps, one-wave-per-atom kernel" % steps,
+            "atom_steps_per_s": rate, "ms_per_step": t / steps * 1e3, "k_partials_us": ms * 1e3,
+            "paper_v100_atom_steps_per_s": ">1e7 (context: another GPU)",
+            "ratio_to_1e7": rate / 1e7}
 
 
 def snes_rate(args, ctx, nep, I, torch):
@@ -333,6 +364,21 @@ def main():
             k: (val[0] * 1e3 / val[1] if val[1] else None) for k, val in kt.items()},
         "energy_drift_meV_per_atom": float((e_tot.max() - e_tot.min()) / n * 1e3),
     }
+    # HNEMD (Sec. II B): the same system driven by F_e . W_i, F_e = 1 um^-1 along x
+    fe = (1.0e-4, 0.0, 0.0)
+    k_h = min(args.steps, 200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th_h = ctx.md_step(k_h, dt, rebuild, mass, p, v, thermo, fe=fe)
+    torch.cuda.synchronize()
+    t_h = time.perf_counter() - t0
+    ctx.synchronize()
+    line["hnemd_64k"] = {
+        "workload": "the same 64,000-atom system with the HNEMD driving force F_e . W_i, "
+                    "F_e = (1e-4, 0, 0) 1/A (1 um^-1)",
+        "atom_steps_per_s": n * k_h / t_h, "steps": k_h,
+        "mean_Jx_eV_A_per_fs": float(th_h[:k_h, 2].mean().item())}
+    line["paper_model_8k"] = paper_model_rate(nep, I, torch)
     if not args.no_disordered:
         line["disordered_512k"] = disordered_rate(args, nep, I, torch, z)
     if not args.no_snes:

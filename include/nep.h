@@ -57,8 +57,11 @@ typedef enum {
  * order l_max (l = 1..l_max) and hidden neurons N_neu.  The descriptor has
  * N_des = (n_max^R+1) + (n_max^A+1) l_max components (Eq. N_des) and the
  * network N_par = (N_des+2) N_neu + 1 parameters (Eq. N_par).  Requires
- * 0 < rc_angular <= rc_radial.  Compiled variants: (n_max^R, n_max^A, l_max,
- * N_neu) = (8, 4, 4, 30); other values return NEP_ENOTIMPL. */
+ * 0 < rc_angular <= rc_radial.  Force evaluation and MD: (n_max^R, n_max^A,
+ * l_max, N_neu) = (8, 4, 4, 30) has tuned kernels (2, 4 or 8 lanes per atom);
+ * any n_max^R, n_max^A <= 15, 1 <= l_max <= 4, N_neu <= 64 (e.g. the paper's
+ * 80-50-1 silicon model) runs on a one-wave-per-atom kernel; other sizes
+ * return NEP_ENOTIMPL.  Datasets, SNES and the backward need (8, 4, 4, 30). */
 typedef struct {
   double rc_radial, rc_angular;
   int n_max_radial, n_max_angular, l_max, n_neuron;
@@ -157,6 +160,16 @@ nep_status nep_compute(nep_ctx ctx, const double* pos_dev, const double* vel_dev
 nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every,
                        double mass_amu, double* pos_dev, double* vel_dev, double* thermo_dev,
                        float* W_dev, float* J_dev);
+
+/* nep_md_step with the homogeneous driving force of the HNEMD method (Sec.
+ * II B): every atom also feels F_i^ext = F_e . W_i, i.e.
+ * (F_i^ext)_b = sum_a fe_host[a] (W_i)_ab, with W_i the per-atom virial of the
+ * same step (fe_host [3] in 1/Angstrom, host memory).  The energy then grows
+ * at the rate F_e . J.  fe = (0, 0, 0) is nep_md_step.  The forces kept for
+ * the next call include the driving force of this call's F_e. */
+nep_status nep_md_step_driven(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every,
+                              double mass_amu, const double* fe_host, double* pos_dev,
+                              double* vel_dev, double* thermo_dev, float* W_dev, float* J_dev);
 
 /* ---------------------------------------------------- training (SNES) */
 
@@ -321,7 +334,8 @@ nep_status nep_autotune(nep_ctx ctx, const double* pos_dev, int reps, int* lanes
                         double* ms_out);
 
 /* Use `lanes` (2, 4 or 8) lanes per atom in the descriptor/network/partial-
- * force kernel of this context.  NEP_EINVAL for other values. */
+ * force kernel of this context, or 64 for the one-wave-per-atom kernel that
+ * every model size uses.  NEP_EINVAL for other values. */
 nep_status nep_set_tile(nep_ctx ctx, int lanes);
 
 #ifdef __cplusplus

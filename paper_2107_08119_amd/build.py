@@ -9,8 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnep.so")
-SOURCES = ["nep_api.hip", "neighbors.hip", "force.hip", "snes.hip", "population.hip",
-           "backward.hip"]
+SOURCES = ["nep_api.hip", "neighbors.hip", "force.hip", "generic.hip", "snes.hip",
+           "population.hip", "backward.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -279,7 +279,9 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     const float4* __restrict__ pin, const float* __restrict__ fown, const float* __restrict__ U,
     Box box, float* __restrict__ U_out,
     float* __restrict__ F, float* __restrict__ W, float* __restrict__ J, double kick,
-    double ekin_factor, double dt, double* __restrict__ pos_next, double* __restrict__ partials) {
+    double ekin_factor, double dt,
+    double* __restrict__ pos_next, float fe0, float fe1, float fe2,
+    double* __restrict__ partials) {
   const unsigned bx = xcd_block(blockIdx.x, gridDim.x);
   const int gid = (int)bx * blockDim.x + threadIdx.x;
   const int i = gid / L;
@@ -338,6 +340,11 @@ __global__ __launch_bounds__(kBlock) void k_gather(
   f2 = group_sum<L>(f2) + (active ? fown[2 * n + i] : 0.f);
 #pragma unroll
   for (int k = 0; k < 9; ++k) w[k] = group_sum<L>(w[k]);
+  if constexpr (MODE >= 1) {  // HNEMD driving force F_e . W_i (zero without a field)
+    f0 += fe0 * w[0] + fe1 * w[3] + fe2 * w[6];
+    f1 += fe0 * w[1] + fe1 * w[4] + fe2 * w[7];
+    f2 += fe0 * w[2] + fe1 * w[5] + fe2 * w[8];
+  }
 
   constexpr int NQ = MODE == 0 ? 13 : 5;
   double v[NQ];
@@ -426,7 +433,9 @@ inline unsigned blocks_for(size_t work, int block) { return (unsigned)((work + b
 
 }  // namespace
 
-bool have_force_variant(const nep_hyper& h) { return is_default_variant(h); }
+bool have_force_variant(const nep_hyper& h) { return is_default_variant(h) || generic_supports(h); }
+
+bool have_training_variant(const nep_hyper& h) { return is_default_variant(h); }
 
 size_t gather_blocks(int n) { return blocks_for((size_t)n * kLanes, kBlock); }
 
@@ -445,6 +454,7 @@ hipError_t launch_partials(nep_ctx ctx, const double* pos, int variant) {
   const System& s = ctx->sys;
   if (s.n == 0) return hipSuccess;
   if (variant < 0) variant = ctx->md_variant;
+  if (!is_default_variant(ctx->hyper) || variant == 3) return launch_partials_generic(ctx, pos);
   switch (variant) {
     case 0:
       launch_partials_shape<2>(ctx, pos, true, true);
@@ -472,7 +482,7 @@ hipError_t launch_partials_population(nep_ctx ctx, nep_dataset ds, int n_pop, co
 
 hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_out, float* F_out,
                          float* W_out, float* J_out, double* block_out, int mode, double kick,
-                         double mass, double dt, double* pos_next, bool last) {
+                         double mass, double dt, double* pos_next, const double* fe, bool last) {
   const System& s = ctx->sys;
   if (s.n == 0) return hipSuccess;
   const unsigned nb = blocks_for((size_t)s.n * kLanes, kBlock);
@@ -484,7 +494,8 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
   const float* U = ctx->U.ptr;
   auto go = [&](auto kernel) {
     launch_kernel(ctx, true, last, kernel, dim3(nb), dim3(kBlock), s.n, pos, vel, nl, cnt, p, fown,
-                  U, s.box, U_out, F_out, W_out, J_out, kick, ekin_factor, dt, pos_next, block_out);
+                  U, s.box, U_out, F_out, W_out, J_out, kick, ekin_factor, dt, pos_next,
+                  (float)fe[0], (float)fe[1], (float)fe[2], block_out);
   };
   if (mode == 0)
     go(k_gather<kLanes, 0>);

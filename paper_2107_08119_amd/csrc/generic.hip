@@ -1,0 +1,282 @@
+// Pass 1 for any model size within n_max^R, n_max^A <= 15, l_max <= 4 and
+// at most 64 hidden neurons (the paper's models of Sec. III, e.g. 80-50-1):
+// one 64-lane wave per atom, lanes over the atom's neighbour pairs.
+//
+// The terms are those of nep_terms.h (factorised angular descriptor, network,
+// partial force of Sec. II D), with the per-atom sums done by the wave:
+//   * radial q_n: each lane adds its pairs, then a fixed-order wave sum;
+//   * angular moments c_nlm = sum_j g_n(r_ij) Yhat_lm(u_ij): the lanes write
+//     their pairs' g_n and Yhat_lm to LDS and lane k accumulates outputs
+//     (n, lm) = k, k + 64, ... over the pairs in index order;
+//   * network: lane mu evaluates neuron mu; dU/dq_v is formed by lane v from
+//     the neurons' w2 sech^2 in LDS;
+//   * partial forces: lane p evaluates pair p from dU/dq and a_nlm in LDS.
+// Every sum has a fixed order, so results are reproducible bit for bit.
+#include "nep_terms.h"
+
+namespace nep {
+namespace {
+
+constexpr int kMaxR = 16, kMaxA = 16, kMaxLM = 24, kMaxNeu = 64;
+constexpr int kMaxDes = kMaxR + kMaxA * 4;
+constexpr int kWaves = 4;  // atoms per block
+
+// Sum over the 64 lanes of a wave in a fixed order; every lane gets the
+// same bits (each step adds two partial sums, which commutes exactly).
+__device__ __forceinline__ float wave_sum(float v) {
+  v = group_sum<16>(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Radial basis g_n, n < nb (<= 16), and optionally g_n' (runtime size).
+__device__ __forceinline__ void radial_basis_n(float r, float rc_inv, int nb, float* g, float* dg) {
+  float gg[kMaxR], dd[kMaxR];
+  radial_basis<kMaxR, true>(r, rc_inv, gg, dd);
+#pragma unroll
+  for (int n = 0; n < kMaxR; ++n) {
+    g[n] = n < nb ? gg[n] : 0.f;
+    if (dg) dg[n] = n < nb ? dd[n] : 0.f;
+  }
+}
+
+__global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
+    int n, const double* __restrict__ pos, const uint32_t* __restrict__ nl,
+    const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, const int* __restrict__ rev,
+    Box box, const float* __restrict__ z, int NR, int NA, int LMAX, int NNEU, float rc_r,
+    float rc_a, float4* __restrict__ pin, float* __restrict__ fown, float* __restrict__ U) {
+  const int NLM = (LMAX + 1) * (LMAX + 1) - 1;
+  const int NDES = NR + NA * LMAX;
+  const int RS = NDES + 1;  // LDS row of neuron mu: w1[mu][:] (padded)
+  __shared__ float s_w1[kMaxNeu * (kMaxDes + 1)];
+  __shared__ float s_b1[kMaxNeu], s_w2[kMaxNeu];
+  __shared__ float s_g[kWaves][64][kMaxA + 1];   // angular g_n of each lane's pair
+  __shared__ float s_y[kWaves][64][kMaxLM + 1];  // Yhat_lm of each lane's pair
+  __shared__ float s_q[kWaves][kMaxDes];
+  __shared__ float s_dq[kWaves][kMaxDes];
+  __shared__ float s_c[kWaves][kMaxA * kMaxLM];  // c_nlm, then a_nlm
+  __shared__ float s_gmu[kWaves][kMaxNeu];
+  for (int t = threadIdx.x; t < NNEU * NDES; t += blockDim.x)
+    s_w1[(t / NDES) * RS + t % NDES] = z[t];
+  for (int t = threadIdx.x; t < NNEU; t += blockDim.x) {
+    s_b1[t] = z[NNEU * NDES + t];
+    s_w2[t] = z[NNEU * (NDES + 1) + t];
+  }
+  const float b2 = z[NNEU * (NDES + 2)];
+  __syncthreads();
+
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int i = (int)xcd_block(blockIdx.x, gridDim.x) * kWaves + wave;
+  if (i >= n) return;  // whole waves leave together; no block barrier below
+  const int cr = cnt_r[i], ca = cnt_a[i];
+  const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+  const float rcr_inv = 1.f / rc_r, rca_inv = 1.f / rc_a;
+  const float rcr2 = rc_r * rc_r, rca2 = rc_a * rc_a;
+  const int nout = NA * NLM;  // angular moments, lane k owns k, k + 64, ...
+  float qr[kMaxR];
+  float cacc[(kMaxA * kMaxLM + 63) / 64];
+#pragma unroll
+  for (int a = 0; a < kMaxR; ++a) qr[a] = 0.f;
+#pragma unroll
+  for (int r = 0; r < (kMaxA * kMaxLM + 63) / 64; ++r) cacc[r] = 0.f;
+  auto wave_lds_sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+
+  // ---- descriptor
+  for (int base = 0; base < cr; base += 64) {
+    const int s = base + lane;
+    float g[kMaxA], yh[kMaxLM];
+#pragma unroll
+    for (int a = 0; a < kMaxA; ++a) g[a] = 0.f;
+#pragma unroll
+    for (int m = 0; m < kMaxLM; ++m) yh[m] = 0.f;
+    if (s < cr) {
+      int j;
+      float dx, dy, dz;
+      displacement(nl[(size_t)s * n + i], pos, n, xi, yi, zi, box.h, j, dx, dy, dz);
+      const float r2 = pair_r2(dx, dy, dz);
+      const float rinv = __builtin_amdgcn_rsqf(r2);
+      const float r = r2 * rinv;
+      if (r2 < rcr2) {
+        float gr[kMaxR];
+        radial_basis_n(r, rcr_inv, NR, gr, nullptr);
+#pragma unroll
+        for (int a = 0; a < kMaxR; ++a) qr[a] += gr[a];
+      }
+      if (s < ca && r2 < rca2) {
+        radial_basis_n(r, rca_inv, NA, g, nullptr);
+        harmonics(dx * rinv, dy * rinv, dz * rinv, yh);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < kMaxA; ++a) s_g[wave][lane][a] = g[a];
+#pragma unroll
+    for (int m = 0; m < kMaxLM; ++m) s_y[wave][lane][m] = yh[m];
+    wave_lds_sync();
+    const int np = min(64, cr - base);
+#pragma unroll
+    for (int r = 0; r < (kMaxA * kMaxLM + 63) / 64; ++r) {
+      const int k = lane + 64 * r;
+      if (k < nout) {
+        const int a = k / NLM, m = k % NLM;
+        float acc = cacc[r];
+        for (int p = 0; p < np; ++p) acc += s_g[wave][p][a] * s_y[wave][p][m];
+        cacc[r] = acc;
+      }
+    }
+    wave_lds_sync();
+  }
+  // radial components and angular moments to LDS
+#pragma unroll
+  for (int a = 0; a < kMaxR; ++a) {
+    const float v = wave_sum(qr[a]);
+    if (lane == 0 && a < NR) s_q[wave][a] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < (kMaxA * kMaxLM + 63) / 64; ++r) {
+    const int k = lane + 64 * r;
+    if (k < nout) s_c[wave][k] = cacc[r];
+  }
+  wave_lds_sync();
+  // angular components q_nl = sum_m c_nlm^2
+  if (lane < NA * LMAX) {
+    const int a = lane / LMAX, l = lane % LMAX + 1;
+    float s2 = 0.f;
+    for (int m = 0; m < 2 * l + 1; ++m) {
+      const float v = s_c[wave][a * NLM + l * l - 1 + m];
+      s2 += v * v;
+    }
+    s_q[wave][NR + a * LMAX + (l - 1)] = s2;
+  }
+  wave_lds_sync();
+
+  // ---- network (Eqs. nn1, nn2): lane mu is neuron mu
+  float u = 0.f;
+  if (lane < NNEU) {
+    float act = -s_b1[lane];
+    for (int v = 0; v < NDES; ++v) act += s_w1[lane * RS + v] * s_q[wave][v];
+    const float ea = __expf(-2.f * fabsf(act));
+    const float inv = __builtin_amdgcn_rcpf(1.f + ea);
+    const float th = copysignf((1.f - ea) * inv, act);
+    u = s_w2[lane] * th;
+    s_gmu[wave][lane] = s_w2[lane] * (4.f * ea * inv * inv);
+  }
+  u = wave_sum(u) - b2;
+  if (lane == 0) U[i] = u;
+  wave_lds_sync();
+  // dU/dq_v: lane v (two rounds for up to 128 descriptor components)
+  for (int v = lane; v < NDES; v += 64) {
+    float d = 0.f;
+    for (int mu = 0; mu < NNEU; ++mu) d += s_gmu[wave][mu] * s_w1[mu * RS + v];
+    s_dq[wave][v] = d;
+  }
+  wave_lds_sync();
+  // a_nlm = 2 dU/dq_nl c_nlm
+#pragma unroll
+  for (int r = 0; r < (kMaxA * kMaxLM + 63) / 64; ++r) {
+    const int k = lane + 64 * r;
+    if (k < nout) {
+      const int a = k / NLM, m = k % NLM;
+      int l = 1;
+      while ((l + 1) * (l + 1) - 1 <= m) ++l;
+      s_c[wave][k] = 2.f * s_dq[wave][NR + a * LMAX + (l - 1)] * s_c[wave][k];
+    }
+  }
+  wave_lds_sync();
+
+  // ---- partial forces: lane p is pair p
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  for (int base = 0; base < cr; base += 64) {
+    const int s = base + lane;
+    if (s < cr) {
+      const size_t idx = (size_t)s * n + i;
+      int j;
+      float dx, dy, dz;
+      displacement(nl[idx], pos, n, xi, yi, zi, box.h, j, dx, dy, dz);
+      const int dst = rev[idx] * n + j;
+      const float r2 = pair_r2(dx, dy, dz);
+      const float rinv = __builtin_amdgcn_rsqf(r2);
+      const float r = r2 * rinv;
+      const float x = dx * rinv, y = dy * rinv, z = dz * rinv;
+      float px = 0.f, py = 0.f, pz = 0.f;
+      if (r2 < rcr2) {
+        float g[kMaxR], dg[kMaxR];
+        radial_basis_n(r, rcr_inv, NR, g, dg);
+        float f = 0.f;
+#pragma unroll
+        for (int a = 0; a < kMaxR; ++a)
+          if (a < NR) f += s_dq[wave][a] * dg[a];
+        px += f * x;
+        py += f * y;
+        pz += f * z;
+      }
+      if (s < ca && r2 < rca2) {
+        float g[kMaxA], dg[kMaxA];
+        radial_basis_n(r, rca_inv, NA, g, dg);
+        const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+        const float xyz = xy * z;
+        (void)xyz;
+        float sb = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        const float* aw = s_c[wave];
+#define NEP_PF(idx, YV, GX, GY, GZ)                     \
+  if ((idx) < NLM) {                                    \
+    float A = 0.f, B = 0.f;                             \
+    for (int a = 0; a < NA; ++a) {                      \
+      const float c = aw[a * NLM + (idx)];              \
+      A += c * g[a];                                    \
+      B += c * dg[a];                                   \
+    }                                                   \
+    sb += B * (YV);                                     \
+    gx += A * (GX);                                     \
+    gy += A * (GY);                                     \
+    gz += A * (GZ);                                     \
+  }
+        NEP_YLM_TABLE(NEP_PF)
+#undef NEP_PF
+        const float ug = x * gx + y * gy + z * gz;
+        px += sb * x + (gx - x * ug) * rinv;
+        py += sb * y + (gy - y * ug) * rinv;
+        pz += sb * z + (gz - z * ug) * rinv;
+      }
+      fx += px;
+      fy += py;
+      fz += pz;
+      pin[(size_t)(unsigned)dst] = make_float4(px, py, pz, 0.f);
+    }
+  }
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  fz = wave_sum(fz);
+  if (lane == 0) {
+    fown[i] = fx;
+    fown[n + i] = fy;
+    fown[2 * n + i] = fz;
+  }
+}
+
+inline unsigned blocks_for(size_t work, int block) { return (unsigned)((work + block - 1) / block); }
+
+}  // namespace
+
+bool generic_supports(const nep_hyper& h) {
+  return h.n_max_radial + 1 <= kMaxR && h.n_max_angular + 1 <= kMaxA && h.l_max >= 1 &&
+         h.l_max <= 4 && h.n_neuron <= kMaxNeu;
+}
+
+hipError_t launch_partials_generic(nep_ctx ctx, const double* pos) {
+  const System& s = ctx->sys;
+  if (s.n == 0) return hipSuccess;
+  const nep_hyper& h = ctx->hyper;
+  launch_kernel(ctx, true, true, k_partials_generic, dim3(blocks_for(s.n, kWaves)),
+                dim3(64 * kWaves), s.n, pos, (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr,
+                (const int*)s.cnt_a.ptr, (const int*)s.rev.ptr, s.box, (const float*)ctx->z.ptr,
+                h.n_max_radial + 1, h.n_max_angular + 1, h.l_max, h.n_neuron,
+                (float)h.rc_radial, (float)h.rc_angular, ctx->p.ptr, ctx->fown.ptr, ctx->U.ptr);
+  return hipGetLastError();
+}
+
+}  // namespace nep

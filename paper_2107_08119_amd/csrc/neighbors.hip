@@ -94,6 +94,55 @@ __global__ __launch_bounds__(1024) void k_scan(int m, int* __restrict__ cnt,
   if (t == 1023) start[m] = part[1023];
 }
 
+// The same scan for many cells in three launches: block b scans counts
+// [1024 b, 1024 b + 1024) (k_scan_blocks), one block scans the block totals
+// (k_scan_totals), every block adds its offset and clears the counters
+// (k_scan_add).
+__device__ __forceinline__ int block_exclusive_scan_1024(int v, int* part, int& total) {
+  const int t = threadIdx.x;
+  part[t] = v;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int u = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += u;
+    __syncthreads();
+  }
+  total = part[1023];
+  return part[t] - v;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_blocks(int m, const int* __restrict__ cnt,
+                                                      int* __restrict__ start,
+                                                      int* __restrict__ block_total) {
+  __shared__ int part[1024];
+  const int k = blockIdx.x * 1024 + threadIdx.x;
+  int total;
+  const int ex = block_exclusive_scan_1024(k < m ? cnt[k] : 0, part, total);
+  if (k < m) start[k] = ex;
+  if (threadIdx.x == 0) block_total[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_totals(int nb, int m, int* __restrict__ block_total,
+                                                      int* __restrict__ start) {
+  __shared__ int part[1024];
+  int total;
+  const int v = threadIdx.x < nb ? block_total[threadIdx.x] : 0;
+  const int ex = block_exclusive_scan_1024(v, part, total);
+  __syncthreads();
+  if (threadIdx.x < nb) block_total[threadIdx.x] = ex;
+  if (threadIdx.x == 0) start[m] = total;
+}
+
+__global__ void k_scan_add(int m, const int* __restrict__ block_offset, int* __restrict__ start,
+                           int* __restrict__ cnt, int* __restrict__ fill) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  start[k] += block_offset[k / 1024];
+  cnt[k] = 0;   // ready for the next build
+  fill[k] = 0;  // for k_fill, next
+}
+
 __global__ void k_fill(int n, const int* __restrict__ cell_of, const int* __restrict__ start,
                        int* __restrict__ fill, int* __restrict__ members) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -617,6 +666,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
     const int* cnt_before = s.cell_cnt.ptr;
     if ((e = s.nl_rm.ensure(ncap)) != hipSuccess || (e = s.cell_of.ensure(n)) != hipSuccess ||
         (e = s.cell_cnt.ensure(ncell)) != hipSuccess ||
+        (e = s.scan_part.ensure(1024)) != hipSuccess ||
         (e = s.cell_start.ensure((size_t)ncell + 1)) != hipSuccess ||
         (e = s.cell_fill.ensure(ncell)) != hipSuccess ||
         (e = s.cell_atoms.ensure(n)) != hipSuccess || (e = s.cell_sorted.ensure(n)) != hipSuccess ||
@@ -633,8 +683,19 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
     launch_kernel(ctx, !zero, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, s.pos_s.ptr,
                   s.box, s.nc[0], s.nc[1], s.nc[2], 1, wrap_in_place ? 1 : 0, s.wrap.ptr,
                   s.cell_of.ptr, s.cell_cnt.ptr);
-    launch_kernel(ctx, false, false, k_scan, dim3(1), dim3(1024), ncell, s.cell_cnt.ptr,
-                  s.cell_start.ptr, s.cell_fill.ptr);
+    const int nsb = (ncell + 1023) / 1024;
+    if (ncell > 16384 && nsb <= 1024) {
+      launch_kernel(ctx, false, false, k_scan_blocks, dim3(nsb), dim3(1024), ncell,
+                    (const int*)s.cell_cnt.ptr, s.cell_start.ptr, s.scan_part.ptr);
+      launch_kernel(ctx, false, false, k_scan_totals, dim3(1), dim3(1024), nsb, ncell,
+                    s.scan_part.ptr, s.cell_start.ptr);
+      launch_kernel(ctx, false, false, k_scan_add, dim3(blocks_for(ncell, kBlock)), blk, ncell,
+                    (const int*)s.scan_part.ptr, s.cell_start.ptr, s.cell_cnt.ptr,
+                    s.cell_fill.ptr);
+    } else {
+      launch_kernel(ctx, false, false, k_scan, dim3(1), dim3(1024), ncell, s.cell_cnt.ptr,
+                    s.cell_start.ptr, s.cell_fill.ptr);
+    }
     s.cells_zeroed_for = ncell;
     launch_kernel(ctx, false, false, k_fill, dim3(blocks_for(n, kBlock)), blk, n,
                   (const int*)s.cell_of.ptr, (const int*)s.cell_start.ptr, s.cell_fill.ptr,

@@ -61,7 +61,9 @@ nep_status size_system_buffers(nep_ctx ctx) {
 hipError_t evaluate_internal(nep_ctx ctx, bool vel, double* out, int mode, double kick,
                              double mass, bool want_w = false, bool want_j = false,
                              double* block_out = nullptr, double dt = 0.0,
-                             double* pos_next = nullptr) {
+                             double* pos_next = nullptr, const double* fe = nullptr) {
+  static const double kNoField[3] = {0.0, 0.0, 0.0};
+  if (!fe) fe = kNoField;
   System& s = ctx->sys;
   hipError_t e = timed(ctx, 0, [&] { return launch_partials(ctx, s.pos_s.ptr); });
   if (e != hipSuccess) return e;
@@ -70,7 +72,7 @@ hipError_t evaluate_internal(nep_ctx ctx, bool vel, double* out, int mode, doubl
     hipError_t r = launch_gather(ctx, s.pos_s.ptr, vel ? s.vel_s.ptr : nullptr, nullptr,
                                  ctx->F.ptr, want_w ? ctx->W.ptr : nullptr,
                                  want_j ? ctx->J.ptr : nullptr, sums, mode, kick, mass, dt,
-                                 pos_next, block_out != nullptr);
+                                 pos_next, fe, block_out != nullptr);
     if (r != hipSuccess || block_out) return r;
     return launch_finalize(ctx, mode == 0 ? 13 : 5, 1, sums, out, s.n == 0);
   });
@@ -285,6 +287,14 @@ nep_status nep_compute(nep_ctx ctx, const double* pos_dev, const double* vel_dev
 nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every,
                        double mass_amu, double* pos_dev, double* vel_dev, double* thermo_dev,
                        float* W_dev, float* J_dev) {
+  const double none[3] = {0.0, 0.0, 0.0};
+  return nep_md_step_driven(ctx, n_steps, dt_fs, rebuild_every, mass_amu, none, pos_dev,
+                            vel_dev, thermo_dev, W_dev, J_dev);
+}
+
+nep_status nep_md_step_driven(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every,
+                              double mass_amu, const double* fe_host, double* pos_dev,
+                              double* vel_dev, double* thermo_dev, float* W_dev, float* J_dev) {
   if (!ctx) return NEP_EINVAL;
   if (!ctx->have_params || !ctx->have_list)
     return fail(ctx, NEP_ESTATE, "nep_load_params and nep_build_neighbors must come first");
@@ -292,6 +302,9 @@ nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every
   if (!(dt_fs > 0.0) || !std::isfinite(dt_fs)) return fail(ctx, NEP_EINVAL, "dt must be > 0");
   if (rebuild_every < 1) return fail(ctx, NEP_EINVAL, "rebuild_every must be >= 1");
   if (!(mass_amu > 0.0) || !std::isfinite(mass_amu)) return fail(ctx, NEP_EINVAL, "mass must be > 0");
+  if (!fe_host) return fail(ctx, NEP_EINVAL, "fe_host is NULL");
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(fe_host[c])) return fail(ctx, NEP_EINVAL, "fe has non-finite entries");
   if (n_steps == 0) return NEP_OK;
   System& s = ctx->sys;
   const int n = s.n;
@@ -302,17 +315,21 @@ nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every
   // the caller's arrays in the internal (cell) order
   launch_take_rows(ctx, n, 3, pos_dev, s.pos_s.ptr);
   launch_take_rows(ctx, n, 3, vel_dev, s.vel_s.ptr);
-  hipError_t e = hipSuccess;
-  if (!(ctx->md_forces_valid && ctx->md_pos == pos_dev && ctx->md_vel == vel_dev)) {
-    e = evaluate_internal(ctx, false, ctx->totals.ptr, 0, 0.0, mass_amu);
-    if (e != hipSuccess) return check_hip(ctx, e, "launching force kernels");
-  }
-  ctx->md_forces_valid = false;
   // Thermo block sums of up to `chunk` steps are kept and reduced together.
   const size_t nb = gather_blocks(n);
   const int chunk = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)4 << 20) / (nb * 5 + 1)));
-  if ((e = ctx->partials.ensure((size_t)chunk * nb * 5 + 16)) != hipSuccess)
-    return check_hip(ctx, e, "allocating thermo sums");
+  hipError_t e = ctx->partials.ensure((size_t)chunk * nb * 5 + 16);
+  if (e != hipSuccess) return check_hip(ctx, e, "allocating thermo sums");
+  const bool same_field = ctx->md_fe[0] == fe_host[0] && ctx->md_fe[1] == fe_host[1] &&
+                          ctx->md_fe[2] == fe_host[2];
+  if (!(ctx->md_forces_valid && ctx->md_pos == pos_dev && ctx->md_vel == vel_dev && same_field)) {
+    // forces of the starting positions (with the driving force: mode 1 with a
+    // zero kick computes F + F_e . W and leaves the velocities unchanged)
+    e = evaluate_internal(ctx, true, nullptr, 1, 0.0, mass_amu, false, false, ctx->partials.ptr,
+                          0.0, nullptr, fe_host);
+    if (e != hipSuccess) return check_hip(ctx, e, "launching force kernels");
+  }
+  ctx->md_forces_valid = false;
   int pending = 0;
   // first half-kick and drift of step 0; later steps get theirs from the
   // previous step's pass 2
@@ -333,10 +350,13 @@ nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every
     }
     const bool last = step == n_steps - 1;
     e = evaluate_internal(ctx, true, nullptr, last ? 1 : 2, kick, mass_amu, W_dev != nullptr,
-                          J_dev != nullptr, ctx->partials.ptr + (size_t)pending * nb * 5, dt_fs,
-                          last ? nullptr : s.pos_t.ptr);
+                          J_dev != nullptr,
+                          ctx->partials.ptr + (size_t)pending * nb * 5, dt_fs,
+                          last ? nullptr : s.pos_t.ptr, fe_host);
     if (e != hipSuccess) return check_hip(ctx, e, "launching force kernels");
     if (!last && n > 0) s.pos_s.swap(s.pos_t);
+    // per-atom W and J of this step in the caller's order (the gather writes
+    // them in cell order: coalesced, then one scatter pass each)
     if (W_dev) launch_put_rows(ctx, n, 9, ctx->W.ptr, W_dev);
     if (J_dev) launch_put_rows(ctx, n, 3, ctx->J.ptr, J_dev);
     if (++pending == chunk || last) {
@@ -355,6 +375,7 @@ nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every
   ctx->md_forces_valid = true;
   ctx->md_pos = pos_dev;
   ctx->md_vel = vel_dev;
+  for (int c = 0; c < 3; ++c) ctx->md_fe[c] = fe_host[c];
   return NEP_OK;
 }
 
@@ -427,7 +448,13 @@ nep_status nep_autotune(nep_ctx ctx, const double* pos_dev, int reps, int* lanes
   if (e == hipSuccess) e = hipEventCreate(&b);
   int best = ctx->md_variant;
   double best_ms = 0.0;
+  // other model sizes have the one-wave-per-atom kernel only
+  const int nv = have_training_variant(ctx->hyper) ? 3 : 1;
   for (int v = 0; v < 3 && e == hipSuccess; ++v) {
+    if (v >= nv) {
+      if (ms_out) ms_out[v] = ms_out[0];
+      continue;
+    }
     e = launch_partials(ctx, ctx->sys.pos_s.ptr, v);  // warm-up
     if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
     for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_partials(ctx, ctx->sys.pos_s.ptr, v);
@@ -447,15 +474,16 @@ nep_status nep_autotune(nep_ctx ctx, const double* pos_dev, int reps, int* lanes
   ctx->timer.on = timing;
   ctx->md_forces_valid = false;  // the partial forces were recomputed
   if (e != hipSuccess) return check_hip(ctx, e, "timing the partial-force kernel");
-  ctx->md_variant = best;
-  if (lanes_out) *lanes_out = 2 << best;
+  ctx->md_variant = nv == 3 ? best : 3;
+  if (lanes_out) *lanes_out = nv == 3 ? 2 << best : 64;
   return NEP_OK;
 }
 
 nep_status nep_set_tile(nep_ctx ctx, int lanes) {
   if (!ctx) return NEP_EINVAL;
-  if (lanes != 2 && lanes != 4 && lanes != 8) return fail(ctx, NEP_EINVAL, "lanes must be 2, 4 or 8");
-  ctx->md_variant = lanes == 2 ? 0 : (lanes == 4 ? 1 : 2);
+  if (lanes != 2 && lanes != 4 && lanes != 8 && lanes != 64)
+    return fail(ctx, NEP_EINVAL, "lanes must be 2, 4, 8 or 64");
+  ctx->md_variant = lanes == 2 ? 0 : (lanes == 4 ? 1 : (lanes == 8 ? 2 : 3));
   ctx->md_forces_valid = false;
   return NEP_OK;
 }

@@ -109,6 +109,7 @@ struct System {
   DevBuf<int> cell_cnt;    // [ncell]
   DevBuf<int> cell_start;  // [ncell+1]
   DevBuf<int> cell_fill;   // [ncell]
+  DevBuf<int> scan_part;   // [1024] block totals of the multi-block cell scan
   DevBuf<int> cell_atoms;  // [n] members of each cell, in arrival order
   DevBuf<int> cell_sorted;  // [n] members of each cell, by atom index
   DevBuf<CellRec> cell_rec;  // [n] positions and offsets in cell order
@@ -130,6 +131,7 @@ struct System {
     cell_cnt.release();
     cell_start.release();
     cell_fill.release();
+    scan_part.release();
     cell_atoms.release();
     cell_sorted.release();
     cell_rec.release();
@@ -198,13 +200,14 @@ struct nep_ctx_s {
   nep::DevBuf<float> W;           // [9][n] internal per-atom virials
   nep::DevBuf<float> J;           // [3][n] internal heat currents
   nep::DevBuf<double> partials;   // [blocks][16] block sums
-  int md_variant = 1;             // pass-1 tile shape: 0, 1, 2 = 2, 4, 8 lanes per atom
+  int md_variant = 1;             // pass-1 tile shape: 0, 1, 2, 3 = 2, 4, 8, 64 lanes per atom
   nep::DevBuf<double> totals;     // [16]
   nep::DevBuf<int> flags;         // [kNumFlags]
   // molecular dynamics state
   bool md_forces_valid = false;
   const double* md_pos = nullptr;
   const double* md_vel = nullptr;
+  double md_fe[3] = {0.0, 0.0, 0.0};  // driving force included in the kept forces
   int steps_since_rebuild = 0;
   nep::KernelTimer timer;
   // events of the kernel class being launched (set by nep::timed)
@@ -293,18 +296,26 @@ void launch_reverse(nep_ctx ctx, int n, int cap, const uint32_t* nl, const int* 
 
 // force.hip
 bool have_force_variant(const nep_hyper& h);
+// The dataset (training, differentiation) kernels exist for the default sizes only.
+bool have_training_variant(const nep_hyper& h);
+// generic.hip: pass 1 for any size with n_max <= 15, l_max <= 4, <= 64 neurons
+// (one wave per atom).
+bool generic_supports(const nep_hyper& h);
+hipError_t launch_partials_generic(nep_ctx ctx, const double* pos);
 // pass 1: descriptor, network, partial forces; pass 2: scatter-free gather.
 // Pass 1 on the internal system with tile shape `variant` (0, 1, 2 = 2, 4, 8
-// lanes per atom; -1 = the context's choice).
+// lanes per atom, 3 = one wave per atom; -1 = the context's choice).  Models
+// other than the default sizes always use the one-wave-per-atom kernel.
 hipError_t launch_partials(nep_ctx ctx, const double* pos, int variant = -1);
 // mode 0: plain evaluation (totals = E, W(9), J(3)); mode 1: velocity-Verlet
 // second half-kick fused (vel updated, thermo row written).
 // Pass 2 (k_gather, modes as documented there) writing per-block sums to
 // block_out [gather_blocks(n)][13 or 5]; launch_finalize adds nsets such
-// arrays (consecutive in block_sums) into out [nsets][nq].
+// arrays (consecutive in block_sums) into out [nsets][nq].  fe [3]: the
+// HNEMD driving field added as F_e . W_i in the MD modes.
 hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_out, float* F_out,
                          float* W_out, float* J_out, double* block_out, int mode, double kick,
-                         double mass, double dt, double* pos_next, bool last);
+                         double mass, double dt, double* pos_next, const double* fe, bool last);
 hipError_t launch_finalize(nep_ctx ctx, int nq, int nsets, const double* block_sums, double* out,
                            bool first);
 size_t gather_blocks(int n);

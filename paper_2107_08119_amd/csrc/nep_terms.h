@@ -57,6 +57,16 @@ __device__ __forceinline__ void pair_descriptor(float dx, float dy, float dz, bo
   }
 }
 
+// The 24 harmonics Yhat_lm (l = 1..4) of the unit vector (x, y, z).
+__device__ __forceinline__ void harmonics(float x, float y, float z, float (&out)[24]) {
+  const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+  const float xyz = xy * z;
+  (void)xyz;
+#define NEP_Y(idx, YV, GX, GY, GZ) out[idx] = (YV);
+  NEP_YLM_TABLE(NEP_Y)
+#undef NEP_Y
+}
+
 // Angular components q[NR + n LMAX + l - 1] = sum_m c_nlm^2.
 template <int NR, int NA, int LMAX>
 __device__ __forceinline__ void angular_invariants(const float (&c)[NA][Model<NR, NA, LMAX>::kNLM],

@@ -391,6 +391,8 @@ hipError_t build_dataset_lists(nep_ctx ctx, nep_dataset ds) {
 nep_status check_dataset(nep_ctx ctx, nep_dataset ds) {
   if (!ds || ds->ctx != ctx) return fail(ctx, NEP_EINVAL, "dataset belongs to another context");
   if (!ctx->have_params) return fail(ctx, NEP_ESTATE, "nep_load_params must come first");
+  if (!have_training_variant(ctx->hyper))
+    return fail(ctx, NEP_ENOTIMPL, "dataset kernels are compiled for (8, 4, 4, 30) only");
   if (ds->rc_r != ctx->hyper.rc_radial || ds->rc_a != ctx->hyper.rc_angular)
     return fail(ctx, NEP_ESTATE, "dataset lists were built for other cutoffs");
   return NEP_OK;
@@ -436,6 +438,8 @@ nep_status nep_dataset_create(nep_ctx ctx, int n_struct, const int* n_atoms_host
   if (!ctx || !out) return NEP_EINVAL;
   *out = nullptr;
   if (!ctx->have_params) return fail(ctx, NEP_ESTATE, "nep_load_params must come first");
+  if (!have_training_variant(ctx->hyper))
+    return fail(ctx, NEP_ENOTIMPL, "dataset kernels are compiled for (8, 4, 4, 30) only");
   if (n_struct < 1) return fail(ctx, NEP_EINVAL, "n_struct must be >= 1");
   if (!n_atoms_host || !boxes_host || !pos_host || !energy_host || !forces_host || !virial_host ||
       !has_virial_host)

@@ -28,7 +28,7 @@ EXPORTED = [
     "nep_time_partials", "nep_dataset_create", "nep_dataset_destroy", "snes_eval_population",
     "snes_sample", "snes_update", "nep_dataset_set_positions", "nep_dataset_get_positions",
     "nep_dataset_compute", "nep_dataset_backward", "snes_autotune", "snes_run",
-    "snes_set_tile", "nep_autotune", "nep_set_tile",
+    "snes_set_tile", "nep_autotune", "nep_set_tile", "nep_md_step_driven",
 ]
 
 
@@ -76,6 +76,7 @@ def lib() -> C.CDLL:
         L.nep_get_neighbors.argtypes = [vp, vp, vp, vp, vp, vp]
         L.nep_compute.argtypes = [vp, vp, vp, vp, fp, vp, vp, vp]
         L.nep_md_step.argtypes = [vp, ip, dp, ip, dp, vp, vp, vp, vp, vp]
+        L.nep_md_step_driven.argtypes = [vp, ip, dp, ip, dp, vp, vp, vp, vp, vp, vp]
         L.nep_set_timing.argtypes = [vp, ip]
         L.nep_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.nep_time_partials.argtypes = [vp, vp, ip, C.POINTER(C.c_double)]
@@ -350,14 +351,24 @@ class Context:
 
     def md_step(self, n_steps: int, dt: float, rebuild_every: int, mass: float,
                 pos: torch.Tensor, vel: torch.Tensor, thermo: torch.Tensor | None = None,
-                W: torch.Tensor | None = None, J: torch.Tensor | None = None) -> torch.Tensor:
+                W: torch.Tensor | None = None, J: torch.Tensor | None = None,
+                fe=None) -> torch.Tensor:
+        """Velocity-Verlet steps; with fe = (Fx, Fy, Fz) in 1/Angstrom the HNEMD
+        driving force F_e . W_i acts on every atom (nep_md_step_driven)."""
         n = self.n
         _require(pos, torch.float64, (3, n), "pos")
         _require(vel, torch.float64, (3, n), "vel")
         if thermo is None:
             thermo = torch.empty((max(n_steps, 1), 5), dtype=torch.float64, device=pos.device)
-        self._check(self._lib.nep_md_step(self._h, n_steps, dt, rebuild_every, mass, _ptr(pos),
-                                          _ptr(vel), _ptr(thermo), _ptr(W), _ptr(J)))
+        if fe is None:
+            self._check(self._lib.nep_md_step(self._h, n_steps, dt, rebuild_every, mass,
+                                              _ptr(pos), _ptr(vel), _ptr(thermo), _ptr(W),
+                                              _ptr(J)))
+        else:
+            f = np.ascontiguousarray(fe, np.float64).reshape(3)
+            self._check(self._lib.nep_md_step_driven(
+                self._h, n_steps, dt, rebuild_every, mass, f.ctypes.data, _ptr(pos), _ptr(vel),
+                _ptr(thermo), _ptr(W), _ptr(J)))
         return thermo
 
 

