@@ -226,6 +226,65 @@ def snes_rate(args, ctx, nep, I, torch):
     }
 
 
+def autograd_rate(nep, I, torch, z, reps=20, n_plain=32):
+    """The differentiable form: 256 SW-labelled Si structures of 64-512 atoms,
+    one call = NEPEnergy forward (E, F; dE/dr = -F) and the hand-written
+    backward of an energy + force loss to dL/dz; against the same objective
+    per structure from a host loop (one single-structure dataset each)."""
+    ls = I.labelled_set(256, 64, 512, seed=6)
+    ctx = nep.Context(0)
+    ctx.load_params(nep.hyper(), z)
+    ds = ctx.dataset_create(ls, max_neighbors=96)
+    zt = torch.from_numpy(np.asarray(z, np.float32)).cuda().requires_grad_(True)
+
+    def objective(d, lab):
+        pos = ctx.dataset_positions(d)
+        n_s = torch.from_numpy(lab.n_atoms.astype(np.float64)).cuda()
+        e_tar = torch.from_numpy(lab.energy).cuda()
+        f_tar = torch.from_numpy(np.ascontiguousarray(lab.forces.T)).float().cuda()
+
+        def call():
+            zt.grad = None
+            E, F = nep.NEPEnergy.apply(pos, zt, ctx, d)
+            loss = (((E - e_tar) / n_s) ** 2).sum() + ((F - f_tar) ** 2).mean()
+            loss.backward()
+        return call
+
+    call = objective(ds, ls)
+    call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        call()
+    torch.cuda.synchronize()
+    t_call = (time.perf_counter() - t0) / reps
+    # per-structure path: the first n_plain structures, each its own dataset
+    off = np.concatenate([[0], np.cumsum(ls.n_atoms)])
+    calls = []
+    for k in range(n_plain):
+        sub = I.LabelledSet(n_atoms=ls.n_atoms[k:k + 1], pos=ls.pos[off[k]:off[k + 1]],
+                            boxes=ls.boxes[k:k + 1], energy=ls.energy[k:k + 1],
+                            forces=ls.forces[off[k]:off[k + 1]], virial=ls.virial[k:k + 1],
+                            has_virial=ls.has_virial[k:k + 1])
+        calls.append(objective(ctx.dataset_create(sub, max_neighbors=96), sub))
+    for c in calls:
+        c()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in calls:
+        c()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / n_plain * len(ls.n_atoms)
+    return {"workload": "NEPEnergy autograd over 256 SW-labelled Si structures of 64-512 atoms "
+                        "(%d atoms), NEP 29-30-1: forward E, F and backward dL/dz of an "
+                        "energy + force loss" % int(ls.n_atoms.sum()),
+            "structures_per_s": len(ls.n_atoms) / t_call, "ms_per_call": t_call * 1e3,
+            "plain_per_structure_structures_per_s": len(ls.n_atoms) / t_plain,
+            "plain_path": "the same call per structure on single-structure datasets, timed on "
+                          "%d structures and scaled to 256" % n_plain,
+            "speedup_vs_plain": t_plain / t_call}
+
+
 def pair_counts(pos, box, rc):
     """Mean number of neighbours within rc (periodic orthorhombic box)."""
     from scipy.spatial import cKDTree
@@ -379,6 +438,7 @@ def main():
         "atom_steps_per_s": n * k_h / t_h, "steps": k_h,
         "mean_Jx_eV_A_per_fs": float(th_h[:k_h, 2].mean().item())}
     line["paper_model_8k"] = paper_model_rate(nep, I, torch)
+    line["autograd_256"] = autograd_rate(nep, I, torch, z)
     if not args.no_disordered:
         line["disordered_512k"] = disordered_rate(args, nep, I, torch, z)
     if not args.no_snes:

@@ -714,7 +714,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
     s.wrap.swap(s.wrap_t);
     s.perm.swap(s.perm_t);
     s.cell_of.swap(s.cell_t);
-    launch_kernel(ctx, false, false, k_build_cells<32, 64, 640, 384>, dim3(ncell), dim3(384), n,
+    launch_kernel(ctx, false, false, k_build_cells<32, 64, 640, 256>, dim3(ncell), dim3(256), n,
                   s.cap, (const double*)s.pos_s.ptr, s.box, s.nc[0], s.nc[1], s.nc[2],
                   (const int*)s.wrap.ptr, (const int*)s.cell_start.ptr,
                   (const CellRec*)s.cell_rec.ptr, rc2_r, rc2_a, s.nl.ptr, s.nl_rm.ptr, s.cnt_r.ptr,
