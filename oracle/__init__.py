@@ -70,10 +70,14 @@ def lib():
         L.or_neighbors.argtypes = [C.c_int, dp, dp, C.c_double, C.c_int, ip, ip, ip]
         L.or_nep_eval.argtypes = [H, dp, C.c_int, dp, dp, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
                                   dp, dp, dp, dp, C.c_void_p]
+        L.or_nep_eval_species.argtypes = [H, dp, C.c_int, dp, dp, C.c_void_p, C.c_void_p, C.c_int,
+                                          C.c_void_p, C.c_int, dp, dp, dp, dp, C.c_void_p]
         L.or_md_nve.argtypes = [H, dp, C.c_int, dp, dp, dp, C.c_double, C.c_double, C.c_int,
                                 C.c_int, dp]
         L.or_md_driven.argtypes = [H, dp, C.c_int, dp, dp, dp, C.c_double, C.c_double, C.c_int,
                                    C.c_int, C.c_void_p, dp]
+        L.or_md_species.argtypes = [H, dp, C.c_int, dp, dp, C.c_void_p, C.c_void_p, dp,
+                                    C.c_double, C.c_double, C.c_int, C.c_int, C.c_void_p, dp]
         L.or_loss.argtypes = [H, dp, C.c_int, ip, dp, dp, dp, dp, dp, bp, dp, C.c_int, dp]
         L.or_grad_params.argtypes = [H, dp, C.c_int, ip, dp, dp, dp, dp, C.c_int, dp]
         L.or_philox4x32_10.argtypes = [up, up, up]
@@ -168,8 +172,9 @@ def _params(z, exact: bool):
 
 
 def nep_eval(h: Hyper, z, pos, box, vel=None, sel=None, cap: int = 256, want_q: bool = False,
-             exact: bool = False):
-    """Per-atom U, F, W (3x3), J and optionally q for atoms sel (default: all)."""
+             exact: bool = False, Z=None):
+    """Per-atom U, F, W (3x3), J and optionally q for atoms sel (default: all).
+    Z: atomic numbers [N] of a multicomponent system (pair weight sqrt(Z_i Z_j))."""
     pos = _d(pos)
     N = len(pos)
     z = _params(z, exact)
@@ -184,8 +189,12 @@ def nep_eval(h: Hyper, z, pos, box, vel=None, sel=None, cap: int = 256, want_q: 
     J = np.zeros((max(n_sel, 1), 3))
     q = np.zeros((max(n_sel, 1), n_des(h))) if want_q else None
     v = _d(vel) if vel is not None else None
-    _check(lib().or_nep_eval(
-        C.byref(h), z, N, pos, _d(box), v.ctypes.data if v is not None else None, n_sel,
+    Zi = None if Z is None else np.ascontiguousarray(Z, dtype=np.int32)
+    if Zi is not None and len(Zi) != N:
+        raise ValueError("Z must have one entry per atom")
+    _check(lib().or_nep_eval_species(
+        C.byref(h), z, N, pos, _d(box), None if Zi is None else Zi.ctypes.data,
+        v.ctypes.data if v is not None else None, n_sel,
         sel_arr.ctypes.data if sel_arr is not None else None, cap, U, F, W, J,
         q.ctypes.data if q is not None else None))
     out = {"U": U[:n_sel], "F": F[:n_sel], "W": W[:n_sel].reshape(-1, 3, 3), "J": J[:n_sel]}
@@ -194,17 +203,26 @@ def nep_eval(h: Hyper, z, pos, box, vel=None, sel=None, cap: int = 256, want_q: 
     return out
 
 
-def md_nve(h: Hyper, z, pos, box, vel, mass: float, dt: float, n_steps: int, cap: int = 256,
-           fe=None):
+def md_nve(h: Hyper, z, pos, box, vel, mass, dt: float, n_steps: int, cap: int = 256,
+           fe=None, Z=None):
     """Velocity-Verlet NVE (with the HNEMD driving force F_e . W_i when fe is
-    given, Sec. II B); returns (thermo [n_steps, 5], pos, vel)."""
+    given, Sec. II B); returns (thermo [n_steps, 5], pos, vel).  mass is one
+    value in amu or one per atom; Z: atomic numbers of a multicomponent system."""
     pos = _d(pos).copy()
     vel = _d(vel).copy()
     thermo = np.zeros((max(n_steps, 1), 5))
     z = _d(np.asarray(z, dtype=np.float32).astype(np.float64))
     fe_arr = None if fe is None else _d(np.asarray(fe, dtype=np.float64).reshape(3))
-    _check(lib().or_md_driven(C.byref(h), z, len(pos), pos, _d(box), vel, mass, dt, n_steps, cap,
-                              None if fe_arr is None else fe_arr.ctypes.data, thermo))
+    m = np.asarray(mass, dtype=np.float64)
+    masses = None if m.ndim == 0 else _d(m)
+    if masses is not None and len(masses) != len(pos):
+        raise ValueError("one mass per atom")
+    Zi = None if Z is None else np.ascontiguousarray(Z, dtype=np.int32)
+    _check(lib().or_md_species(C.byref(h), z, len(pos), pos, _d(box),
+                               None if Zi is None else Zi.ctypes.data,
+                               None if masses is None else masses.ctypes.data, vel,
+                               float(m) if masses is None else 0.0, dt, n_steps, cap,
+                               None if fe_arr is None else fe_arr.ctypes.data, thermo))
     return thermo[:n_steps], pos, vel
 
 

@@ -310,11 +310,18 @@ int or_neighbors(int N, const double* pos, const double* H, double rc, int cap, 
 /* -------------------------------------------------- NEP, per atom */
 
 /* Geometry of atom i's listed pairs: displacements d [cnt][3], distances r,
- * and the angular radial functions g_n, g_n' with r_c^A (zero beyond it). */
+ * species weights w, and the angular radial functions g_n, g_n' with r_c^A
+ * (zero beyond it), species weight included.
+ *
+ * Multicomponent systems (Sec. II C, multicomponent paragraph): the cutoff
+ * function of pair (i, j) is multiplied by sqrt(Z_i Z_j), Z = atomic number,
+ * so every radial function g_n(r_ij) and its derivative carries that factor.
+ * Without species (Z == NULL) the factor is 1. */
 typedef struct {
   int cnt;
   double* d;
   double* r;
+  double* w;
   double* gA;
   double* dgA;
 } or_geom;
@@ -322,28 +329,35 @@ typedef struct {
 static void geom_free(or_geom* G) {
   free(G->d);
   free(G->r);
+  free(G->w);
   free(G->gA);
   free(G->dgA);
 }
 
-static int geom_build(const or_hyper* hp, const double* pos, const double* H, int i, int cnt,
-                      const int* jl, const int* img, or_geom* G) {
+static int geom_build(const or_hyper* hp, const double* pos, const double* H, const int* Z,
+                      int i, int cnt, const int* jl, const int* img, or_geom* G) {
   const int nA = hp->n_max_angular;
   const size_t m = (size_t)(cnt > 0 ? cnt : 1);
   G->cnt = cnt;
   G->d = (double*)malloc(sizeof(double) * 3 * m);
   G->r = (double*)malloc(sizeof(double) * m);
+  G->w = (double*)malloc(sizeof(double) * m);
   G->gA = (double*)malloc(sizeof(double) * (nA + 1) * m);
   G->dgA = (double*)malloc(sizeof(double) * (nA + 1) * m);
-  if (!G->d || !G->r || !G->gA || !G->dgA) {
+  if (!G->d || !G->r || !G->w || !G->gA || !G->dgA) {
     geom_free(G);
     return -3;
   }
   for (int s = 0; s < cnt; ++s) {
     pair_displacement(pos, H, i, jl[s], img[3 * s], img[3 * s + 1], img[3 * s + 2], G->d + 3 * s);
     G->r[s] = sqrt(norm2(G->d + 3 * s));
+    G->w[s] = Z ? sqrt((double)Z[i] * (double)Z[jl[s]]) : 1.0;
     if (G->r[s] < hp->rc_angular) {
       or_radial_basis(G->r[s], hp->rc_angular, nA, G->gA + (nA + 1) * s, G->dgA + (nA + 1) * s);
+      for (int n = 0; n <= nA; ++n) {
+        G->gA[(nA + 1) * s + n] *= G->w[s];
+        G->dgA[(nA + 1) * s + n] *= G->w[s];
+      }
     } else {
       for (int n = 0; n <= nA; ++n) G->gA[(nA + 1) * s + n] = G->dgA[(nA + 1) * s + n] = 0.0;
     }
@@ -363,7 +377,7 @@ static void descriptor(const or_hyper* hp, const or_geom* G, double* q) {
   for (int s = 0; s < G->cnt; ++s) {
     if (r[s] >= rcR) continue;
     or_radial_basis(r[s], rcR, nR, g, dg);
-    for (int n = 0; n <= nR; ++n) q[n] += g[n];
+    for (int n = 0; n <= nR; ++n) q[n] += G->w[s] * g[n];
   }
   for (int s = 0; s < G->cnt; ++s) {
     if (r[s] >= rcA) continue;
@@ -420,7 +434,7 @@ static void partials(const or_hyper* hp, const or_geom* G, const double* dUdq, d
     if (rs < rcR) {
       or_radial_basis(rs, rcR, nR, g, dg);
       double f = 0.0;
-      for (int n = 0; n <= nR; ++n) f += dUdq[n] * dg[n];
+      for (int n = 0; n <= nR; ++n) f += dUdq[n] * G->w[s] * dg[n];
       for (int c = 0; c < 3; ++c) ps[c] += f * us[c];
     }
     if (rs < rcA) {
@@ -448,10 +462,10 @@ static void partials(const or_hyper* hp, const or_geom* G, const double* dUdq, d
 
 /* Descriptor, network and partial forces of atom i (p is [cnt][3]). */
 static void atom_terms(const or_hyper* hp, const double* z, const double* pos, const double* H,
-                       int i, int cnt, const int* jl, const int* img, double* q, double* U,
-                       double* dUdq, double* p) {
+                       const int* Z, int i, int cnt, const int* jl, const int* img, double* q,
+                       double* U, double* dUdq, double* p) {
   or_geom G;
-  if (geom_build(hp, pos, H, i, cnt, jl, img, &G)) return;
+  if (geom_build(hp, pos, H, Z, i, cnt, jl, img, &G)) return;
   descriptor(hp, &G, q);
   network(hp, z, q, U, dUdq, NULL);
   partials(hp, &G, dUdq, p);
@@ -473,12 +487,14 @@ static int find_reverse(const or_list* L, int i, int j, const int* n) {
  *   pos [N][3], H [3][3] rows = cell vectors, vel [N][3] or NULL, z [N_par];
  *   outputs indexed by position in sel: U [n_sel], F [n_sel][3],
  *   W [n_sel][9] row-major (W_ab = sum_j (r_ij)_a (dU_j/dr_ji)_b),
- *   J [n_sel][3] (zero when vel is NULL), q [n_sel][N_des] (may be NULL).
+ *   J [n_sel][3] (zero when vel is NULL), q [n_sel][N_des] (may be NULL);
+ *   Z [N] atomic numbers of a multicomponent system, or NULL (one species).
  * Returns 0, -1 on neighbour capacity overflow, -2 on a missing reverse pair,
  * -3 on allocation failure. */
-int or_nep_eval(const or_hyper* hp, const double* z, int N, const double* pos, const double* H,
-                const double* vel, int n_sel, const int* sel, int cap, double* U, double* F,
-                double* W, double* J, double* q_out) {
+int or_nep_eval_species(const or_hyper* hp, const double* z, int N, const double* pos,
+                        const double* H, const int* Z, const double* vel, int n_sel,
+                        const int* sel, int cap, double* U, double* F, double* W, double* J,
+                        double* q_out) {
   const int ndes = or_n_des(hp);
   double rc = hp->rc_radial > hp->rc_angular ? hp->rc_radial : hp->rc_angular;
   unsigned char* need = (unsigned char*)calloc((size_t)(N > 0 ? N : 1), 1);
@@ -519,7 +535,7 @@ int or_nep_eval(const or_hyper* hp, const double* z, int N, const double* pos, c
   for (int i = 0; i < N; ++i) {
     if (!need[i]) continue;
     double dUdq[256];
-    atom_terms(hp, z, pos, H, i, L.cnt[i], L.j + (size_t)i * cap, L.img + (size_t)i * cap * 3,
+    atom_terms(hp, z, pos, H, Z, i, L.cnt[i], L.j + (size_t)i * cap, L.img + (size_t)i * cap * 3,
                qall + (size_t)i * ndes, Uall + i, dUdq, p + (size_t)i * cap * 3);
   }
   int missing = 0;
@@ -562,6 +578,13 @@ int or_nep_eval(const or_hyper* hp, const double* z, int N, const double* pos, c
   free(need);
   list_free(&L);
   return missing ? -2 : 0;
+}
+
+/* or_nep_eval_species of a one-species system. */
+int or_nep_eval(const or_hyper* hp, const double* z, int N, const double* pos, const double* H,
+                const double* vel, int n_sel, const int* sel, int cap, double* U, double* F,
+                double* W, double* J, double* q_out) {
+  return or_nep_eval_species(hp, z, N, pos, H, NULL, vel, n_sel, sel, cap, U, F, W, J, q_out);
 }
 
 /* ------------------------------------------------- parameter gradient */
@@ -614,7 +637,7 @@ int or_grad_params(const or_hyper* hp, const double* z, int n_struct, const int*
         const int cnt = L.cnt[a];
         const int* jl = L.j + (size_t)a * cap;
         double* D = (double*)malloc(sizeof(double) * 3 * (size_t)(cnt > 0 ? cnt : 1));
-        if (!mine || !D || geom_build(hp, P, H, a, cnt, jl, L.img + (size_t)a * cap * 3, &G)) {
+        if (!mine || !D || geom_build(hp, P, H, NULL, a, cnt, jl, L.img + (size_t)a * cap * 3, &G)) {
           free(D);
 #pragma omp atomic write
           status = -3;
@@ -681,13 +704,15 @@ static void add_driving_force(int N, const double* fe, const double* W, double* 
 /* Velocity-Verlet trajectory with exact cutoffs at every step.
  * pos/vel [N][3] are updated in place; thermo [n_steps][5] receives
  * E_pot, E_kin (eV), and the total heat current sum_i J_i (3 components)
- * after each step.  mass in amu, dt in fs.  With fe != NULL every atom also
+ * after each step.  mass in amu (per atom from masses [N] when that is not
+ * NULL), dt in fs; Z [N] atomic numbers of a multicomponent system or NULL.
+ * With fe != NULL every atom also
  * feels the homogeneous driving force of the HNEMD method (Sec. II B):
  * F_i^ext = F_e . W_i, i.e. (F_i^ext)_b = sum_a (F_e)_a (W_i)_ab, with F_e in
  * 1/Angstrom; fe == NULL is plain NVE. */
-int or_md_driven(const or_hyper* hp, const double* z, int N, double* pos, const double* H,
-                 double* vel, double mass, double dt, int n_steps, int cap, const double* fe,
-                 double* thermo) {
+int or_md_species(const or_hyper* hp, const double* z, int N, double* pos, const double* H,
+                  const int* Z, const double* masses, double* vel, double mass, double dt,
+                  int n_steps, int cap, const double* fe, double* thermo) {
   double* U = (double*)malloc(sizeof(double) * (size_t)N);
   double* F = (double*)malloc(sizeof(double) * 3 * (size_t)N);
   double* W = (double*)malloc(sizeof(double) * 9 * (size_t)N);
@@ -697,25 +722,26 @@ int or_md_driven(const or_hyper* hp, const double* z, int N, double* pos, const 
     free(W);
     return -3;
   }
-  int rcode = or_nep_eval(hp, z, N, pos, H, NULL, N, NULL, cap, U, F, W, NULL, NULL);
+  int rcode = or_nep_eval_species(hp, z, N, pos, H, Z, NULL, N, NULL, cap, U, F, W, NULL, NULL);
   if (rcode == 0 && fe) add_driving_force(N, fe, W, F);
-  const double k = OR_ACCEL / mass;
   for (int step = 0; step < n_steps && rcode == 0; ++step) {
     for (int i = 0; i < 3 * N; ++i) {
-      vel[i] += 0.5 * dt * k * F[i];
+      vel[i] += 0.5 * dt * (OR_ACCEL / (masses ? masses[i / 3] : mass)) * F[i];
       pos[i] += dt * vel[i];
     }
-    rcode = or_nep_eval(hp, z, N, pos, H, NULL, N, NULL, cap, U, F, W, NULL, NULL);
+    rcode = or_nep_eval_species(hp, z, N, pos, H, Z, NULL, N, NULL, cap, U, F, W, NULL, NULL);
     if (rcode) break;
     if (fe) add_driving_force(N, fe, W, F);
-    for (int i = 0; i < 3 * N; ++i) vel[i] += 0.5 * dt * k * F[i];
+    for (int i = 0; i < 3 * N; ++i)
+      vel[i] += 0.5 * dt * (OR_ACCEL / (masses ? masses[i / 3] : mass)) * F[i];
     /* heat current J_i = W_i . v_i with the end-of-step velocities */
     double ep = 0.0, ek = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
     for (int i = 0; i < N; ++i) {
       const double* w = W + 9 * (size_t)i;
       const double* v = vel + 3 * (size_t)i;
       ep += U[i];
-      ek += 0.5 * mass * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / OR_ACCEL;
+      ek += 0.5 * (masses ? masses[i] : mass) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) /
+            OR_ACCEL;
       j0 += w[0] * v[0] + w[1] * v[1] + w[2] * v[2];
       j1 += w[3] * v[0] + w[4] * v[1] + w[5] * v[2];
       j2 += w[6] * v[0] + w[7] * v[1] + w[8] * v[2];
@@ -730,6 +756,13 @@ int or_md_driven(const or_hyper* hp, const double* z, int N, double* pos, const 
   free(F);
   free(W);
   return rcode;
+}
+
+/* One species, one mass. */
+int or_md_driven(const or_hyper* hp, const double* z, int N, double* pos, const double* H,
+                 double* vel, double mass, double dt, int n_steps, int cap, const double* fe,
+                 double* thermo) {
+  return or_md_species(hp, z, N, pos, H, NULL, NULL, vel, mass, dt, n_steps, cap, fe, thermo);
 }
 
 /* Velocity-Verlet NVE: or_md_driven without a driving force. */

@@ -61,6 +61,31 @@ def diamond_supercell(n1: int, n2: int, n3: int, a: float = DIAMOND_SI_A):
     return pos, box
 
 
+# Two-species test system: rock-salt PbTe (Pb on the fcc sites, Te on the
+# octahedral sites), the kind of ionic crystal the paper fits with a longer
+# radial than angular cutoff.
+PBTE_A = 6.46  # Angstrom, room-temperature lattice constant of PbTe
+Z_PB, Z_TE = 82, 52  # atomic numbers
+MASS_PB, MASS_TE = 207.2, 127.60  # amu
+_ROCKSALT_A = np.array([[0.0, 0.0, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]])
+_ROCKSALT_B = _ROCKSALT_A + np.array([0.5, 0.0, 0.0])
+
+
+def rocksalt_supercell(n1: int, n2: int, n3: int, a: float = PBTE_A):
+    """Conventional 8-atom rock-salt cells repeated n1 x n2 x n3: (pos, box,
+    Z, masses), four Pb then four Te per cell."""
+    cells = np.array(
+        [[i, j, k] for i in range(n1) for j in range(n2) for k in range(n3)], dtype=np.float64
+    )
+    basis = np.concatenate([_ROCKSALT_A, _ROCKSALT_B % 1.0])
+    frac = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3)
+    n_cells = len(cells)
+    Z = np.tile(np.array([Z_PB] * 4 + [Z_TE] * 4, dtype=np.int32), n_cells)
+    masses = np.where(Z == Z_PB, MASS_PB, MASS_TE).astype(np.float64)
+    box = np.diag([n1 * a, n2 * a, n3 * a]).astype(np.float64)
+    return frac * a, box, Z, masses
+
+
 def wrap_positions(pos: np.ndarray, box: np.ndarray) -> np.ndarray:
     """Map positions into the cell spanned by the box rows (fractional in [0,1))."""
     frac = pos @ np.linalg.inv(box)
@@ -87,26 +112,39 @@ def random_parameters(n_par: int, seed: int, std: float = 0.1) -> np.ndarray:
     return (rng.standard_normal(n_par) * std).astype(np.float32)
 
 
-def maxwell_boltzmann(n_atoms: int, temperature: float, seed: int, mass: float = MASS_SI):
-    """Velocities (Angstrom/fs) drawn from the Maxwell-Boltzmann distribution.
+def maxwell_boltzmann(n_atoms: int, temperature: float, seed: int, mass=MASS_SI):
+    """Velocities (Angstrom/fs) drawn from the Maxwell-Boltzmann distribution;
+    mass is one value in amu or one per atom.
 
     The centre-of-mass velocity is removed and the result is rescaled so that
     the kinetic temperature with 3N-3 degrees of freedom equals `temperature`.
     """
     rng = np.random.default_rng(seed)
-    sigma = math.sqrt(BOLTZMANN_EV * temperature / mass * ACCEL_UNIT)
-    v = rng.standard_normal((n_atoms, 3)) * sigma
-    v -= v.mean(axis=0, keepdims=True)
+    if np.ndim(mass) == 0:
+        sigma = math.sqrt(BOLTZMANN_EV * temperature / mass * ACCEL_UNIT)
+        v = rng.standard_normal((n_atoms, 3)) * sigma
+        v -= v.mean(axis=0, keepdims=True)
+        m = float(mass)
+    else:
+        m = np.asarray(mass, dtype=np.float64).reshape(n_atoms, 1)
+        v = rng.standard_normal((n_atoms, 3)) * np.sqrt(BOLTZMANN_EV * temperature / m * ACCEL_UNIT)
+        v -= (m * v).sum(axis=0, keepdims=True) / m.sum()
     if n_atoms > 1:
-        ekin = 0.5 * mass * float(np.sum(v * v)) / ACCEL_UNIT
+        if np.ndim(m) == 0:
+            ekin = 0.5 * m * float(np.sum(v * v)) / ACCEL_UNIT
+        else:
+            ekin = 0.5 * float(np.sum(m * v * v)) / ACCEL_UNIT
         t_now = 2.0 * ekin / ((3 * n_atoms - 3) * BOLTZMANN_EV)
         v *= math.sqrt(temperature / t_now)
     return v
 
 
-def kinetic_energy(vel: np.ndarray, mass: float = MASS_SI) -> float:
-    """Kinetic energy in eV of velocities in Angstrom/fs."""
-    return 0.5 * mass * float(np.sum(vel * vel)) / ACCEL_UNIT
+def kinetic_energy(vel: np.ndarray, mass=MASS_SI) -> float:
+    """Kinetic energy in eV of velocities in Angstrom/fs (one mass or one per atom)."""
+    if np.ndim(mass) == 0:
+        return 0.5 * mass * float(np.sum(vel * vel)) / ACCEL_UNIT
+    m = np.asarray(mass, dtype=np.float64).reshape(len(vel), 1)
+    return 0.5 * float(np.sum(m * vel * vel)) / ACCEL_UNIT
 
 
 # ---------------------------------------------------------------------------

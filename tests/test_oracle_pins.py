@@ -371,6 +371,122 @@ def test_driving_force_power_is_fe_dot_heat_current():
     np.testing.assert_array_equal(thz, th0[:5])
 
 
+# ------------------------------------------------ multicomponent weighting
+# Sec. II C (multicomponent systems): the cutoff function of pair (i, j) is
+# multiplied by sqrt(Z_i Z_j).  PbTe-like model: r_c 8/4 A, n_max 12/6.
+HP = O.hyper(8.0, 4.0, 12, 6, 4, 40)
+
+
+@pytest.fixture(scope="module")
+def pbte_cell():
+    pos, box, Z, masses = I.rocksalt_supercell(2, 2, 2)
+    rng = np.random.default_rng(21)
+    pos = pos + rng.standard_normal(pos.shape) * 0.08
+    z = I.random_parameters(O.n_par(HP), 3, std=0.05)
+    return pos, box, Z, masses, z
+
+
+def test_species_one_everywhere_is_the_one_species_model(small_cell):
+    pos, box, z = small_cell
+    a = O.nep_eval(H, z, pos, box, want_q=True)
+    b = O.nep_eval(H, z, pos, box, want_q=True, Z=np.ones(len(pos), np.int32))
+    for k in ("q", "U", "F", "W"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_species_uniform_number_scales_radial_once_angular_twice(small_cell):
+    """One species of atomic number Z0: every pair weight is Z0, so the
+    radial components (linear in g_n) scale by Z0 and the angular ones
+    (quadratic) by Z0^2."""
+    pos, box, z = small_cell
+    a = O.nep_eval(H, z, pos, box, want_q=True)["q"]
+    b = O.nep_eval(H, z, pos, box, want_q=True, Z=np.full(len(pos), 14, np.int32))["q"]
+    nr = H.n_max_radial + 1
+    np.testing.assert_allclose(b[:, :nr], 14.0 * a[:, :nr], rtol=1e-13)
+    np.testing.assert_allclose(b[:, nr:], 196.0 * a[:, nr:], rtol=1e-12, atol=1e-14)
+
+
+def test_species_weight_is_sqrt_of_both_numbers(pbte_cell):
+    """Two sublattices with numbers (Za, Zb); for an atom of the first,
+    q_radial = sqrt(Za) (sqrt(Za) S_a + sqrt(Zb) S_b) and
+    q_angular = Za |sqrt(Za) C_a + sqrt(Zb) C_b|^2 (sums over each
+    sublattice).  S, C are fixed from three evaluations and the fourth,
+    (Za, Zb) = (4, 9), is predicted; a weight Z_j, sqrt(Z_j) or Z_i Z_j fails."""
+    pos, box, Z, _, z = pbte_cell
+    first = Z == Z[0]
+
+    def q(za, zb):
+        zz = np.where(first, za, zb).astype(np.int32)
+        return O.nep_eval(HP, z, pos, box, want_q=True, Z=zz)["q"][first]
+    nr = HP.n_max_radial + 1
+    q11, q14, q10 = q(1, 1), q(1, 4), q(1, 0)
+    # radial: q(1, zb) = S_a + sqrt(zb) S_b
+    s_b = q14[:, :nr] - q11[:, :nr]
+    s_a = q11[:, :nr] - s_b
+    np.testing.assert_allclose(q10[:, :nr], s_a, rtol=1e-10, atol=1e-12)
+    q49 = q(4, 9)
+    np.testing.assert_allclose(q49[:, :nr], 2.0 * (2.0 * s_a + 3.0 * s_b), rtol=1e-10, atol=1e-12)
+    # angular: q(1, zb) = a + 2 b t + c t^2 with t = sqrt(zb)
+    qa0, qa1, qa2 = q10[:, nr:], q11[:, nr:], q14[:, nr:]
+    c = 0.5 * (qa2 - 2.0 * qa1 + qa0)
+    b = 0.5 * (qa1 - qa0 - c)
+    a = qa0
+    np.testing.assert_allclose(q49[:, nr:], 4.0 * (4.0 * a + 12.0 * b + 9.0 * c),
+                               rtol=1e-9, atol=1e-10)
+
+
+def test_species_central_atom_is_distinguished(pbte_cell):
+    """Swapping the species of one atom rescales its own descriptor by
+    sqrt(Z'/Z) (radial) and Z'/Z (angular): the same environment around a
+    different central species gives a different descriptor."""
+    pos, box, Z, _, z = pbte_cell
+    nr = HP.n_max_radial + 1
+    a = O.nep_eval(HP, z, pos, box, want_q=True, Z=Z)["q"][0]
+    Z2 = Z.copy()
+    Z2[0] = I.Z_TE
+    b = O.nep_eval(HP, z, pos, box, want_q=True, Z=Z2)["q"][0]
+    ratio = I.Z_TE / I.Z_PB
+    np.testing.assert_allclose(b[:nr], math.sqrt(ratio) * a[:nr], rtol=1e-12)
+    np.testing.assert_allclose(b[nr:], ratio * a[nr:], rtol=1e-11, atol=1e-14)
+
+
+def test_species_forces_finite_difference_and_invariance(pbte_cell):
+    pos, box, Z, _, z = pbte_cell
+    out = O.nep_eval(HP, z, pos, box, Z=Z)
+    h = 1e-5  # the weights (up to 82) make U stiff: the O(h^2) error at 1e-4 is ~1e-5
+    for i in (0, 5, 37):
+        for c in range(3):
+            p = pos.copy()
+            p[i, c] += h
+            ep = O.nep_eval(HP, z, p, box, Z=Z)["U"].sum()
+            p[i, c] -= 2 * h
+            em = O.nep_eval(HP, z, p, box, Z=Z)["U"].sum()
+            assert -(ep - em) / (2 * h) == pytest.approx(out["F"][i, c], rel=1e-6, abs=1e-9)
+    np.testing.assert_allclose(out["F"].sum(0), 0.0, atol=1e-10)
+    # permuting atoms together with their numbers permutes the results
+    perm = np.random.default_rng(4).permutation(len(pos))
+    o2 = O.nep_eval(HP, z, pos[perm], box, Z=Z[perm])
+    np.testing.assert_allclose(o2["U"], out["U"][perm], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(o2["F"], out["F"][perm], atol=1e-11)
+
+
+def test_species_md_conserves_energy_with_per_atom_masses(pbte_cell):
+    """Velocity Verlet with per-atom masses: the energy error scales as dt^2,
+    and equal per-atom masses reproduce the one-mass trajectory exactly."""
+    pos, box, Z, masses, z = pbte_cell
+    vel = I.maxwell_boltzmann(len(pos), 300.0, 9, masses)
+    spans = []
+    for dt, n in ((2.0, 50), (1.0, 100)):
+        th, _, _ = O.md_nve(HP, z, pos, box, vel, masses, dt, n, Z=Z)
+        e = th[:, 0] + th[:, 1]
+        spans.append(e.max() - e.min())
+    assert 3.0 < spans[0] / spans[1] < 5.5, spans
+    th1, p1, v1 = O.md_nve(HP, z, pos, box, vel, 100.0, 1.0, 5, Z=Z)
+    th2, p2, v2 = O.md_nve(HP, z, pos, box, vel, np.full(len(pos), 100.0), 1.0, 5, Z=Z)
+    np.testing.assert_array_equal(th1, th2)
+    np.testing.assert_array_equal(v1, v2)
+
+
 # -------------------------------------------------------------------- loss
 @pytest.fixture(scope="module")
 def tiny_set():
