@@ -132,6 +132,23 @@ nep_status nep_build_neighbors(nep_ctx ctx, int n_atoms, const double* pos_dev,
 nep_status nep_get_neighbors(nep_ctx ctx, int* cnt_radial_dev, int* cnt_angular_dev,
                              int* nbr_dev, int* img_dev, int* rev_dev);
 
+/* Multicomponent system (Sec. II C, multicomponent systems): atomic numbers
+ * atomic_numbers_host [n] (caller order, 1..118) multiply the cutoff function
+ * of every pair (i, j) by sqrt(Z_i Z_j), in the radial and angular terms
+ * alike; one network serves every species.  masses_amu_host [n] (> 0, or
+ * NULL) gives each atom its own mass in nep_md_step / nep_md_step_driven,
+ * whose mass_amu is then only a reference value (still > 0).  n must equal
+ * the atom count of the last nep_build_neighbors (NEP_ESTATE before any);
+ * the arrays are copied (host memory, synchronous) and persist across list
+ * rebuilds until a build with another atom count or a call with
+ * atomic_numbers_host == NULL, which returns to one species with the mass of
+ * each call.  With species set, forces come from the one-wave-per-atom
+ * kernel (nep_autotune reports 64 lanes).  The training entry points
+ * (datasets, SNES, backward) remain one-species.  NEP_EINVAL for n or a value
+ * out of range. */
+nep_status nep_set_species(nep_ctx ctx, int n, const int* atomic_numbers_host,
+                           const double* masses_amu_host);
+
 /* ------------------------------------------------------------ evaluation */
 
 /* One force evaluation of the system last passed to nep_build_neighbors

@@ -281,6 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     float* __restrict__ F, float* __restrict__ W, float* __restrict__ J, double kick,
     double ekin_factor, double dt,
     double* __restrict__ pos_next, float fe0, float fe1, float fe2,
+    const double* __restrict__ mass_c, const int* __restrict__ perm, double mref,
     double* __restrict__ partials) {
   const unsigned bx = xcd_block(blockIdx.x, gridDim.x);
   const int gid = (int)bx * blockDim.x + threadIdx.x;
@@ -361,21 +362,29 @@ __global__ __launch_bounds__(kBlock) void k_gather(
 #pragma unroll
       for (int k = 0; k < 9; ++k) W[(size_t)k * n + i] = w[k];
     double vx = 0.0, vy = 0.0, vz = 0.0;
+    // per-atom mass (caller order): the kick and kinetic factors were formed
+    // for mass mref
+    double ki = kick, ekf = ekin_factor;
+    if (mass_c) {
+      const double m = mass_c[perm[i]];
+      ki = kick * (mref / m);
+      ekf = ekin_factor * (m / mref);
+    }
     if (vel) {
       vx = vel[i];
       vy = vel[n + i];
       vz = vel[2 * n + i];
       if constexpr (MODE >= 1) {
-        vx += kick * (double)f0;
-        vy += kick * (double)f1;
-        vz += kick * (double)f2;
+        vx += ki * (double)f0;
+        vy += ki * (double)f1;
+        vz += ki * (double)f2;
         if constexpr (MODE == 1) {
           vel[i] = vx;
           vel[n + i] = vy;
           vel[2 * n + i] = vz;
         } else {
-          const double ux = vx + kick * (double)f0, uy = vy + kick * (double)f1,
-                       uz = vz + kick * (double)f2;
+          const double ux = vx + ki * (double)f0, uy = vy + ki * (double)f1,
+                       uz = vz + ki * (double)f2;
           vel[i] = ux;
           vel[n + i] = uy;
           vel[2 * n + i] = uz;
@@ -401,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(
       v[11] = j1;
       v[12] = j2;
     } else {
-      v[1] = ekin_factor * (vx * vx + vy * vy + vz * vz);
+      v[1] = ekf * (vx * vx + vy * vy + vz * vz);
       v[2] = j0;
       v[3] = j1;
       v[4] = j2;
@@ -411,10 +420,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(
 }
 
 __global__ void k_kick_drift(int n, double* __restrict__ pos, double* __restrict__ vel,
-                             const float* __restrict__ F, double kick, double dt) {
+                             const float* __restrict__ F, double kick, double dt,
+                             const double* __restrict__ mass_c, const int* __restrict__ perm,
+                             double mref) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 3 * n) return;
-  const double v = vel[t] + kick * (double)F[t];
+  const double k = mass_c ? kick * (mref / mass_c[perm[t % n]]) : kick;
+  const double v = vel[t] + k * (double)F[t];
   vel[t] = v;
   pos[t] += dt * v;
 }
@@ -455,7 +467,8 @@ hipError_t launch_partials(nep_ctx ctx, const double* pos, int variant) {
   const System& s = ctx->sys;
   if (s.n == 0) return hipSuccess;
   if (variant < 0) variant = ctx->md_variant;
-  if (!is_default_variant(ctx->hyper) || variant == 3) return launch_partials_generic(ctx, pos);
+  if (!is_default_variant(ctx->hyper) || variant == 3 || ctx->species_on())
+    return launch_partials_generic(ctx, pos);
   switch (variant) {
     case 0:
       launch_partials_shape<2>(ctx, pos, true, true);
@@ -493,10 +506,13 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
   const float4* p = ctx->p.ptr;
   const float* fown = ctx->fown.ptr;
   const float* U = ctx->U.ptr;
+  const bool per_atom = ctx->species_on() && ctx->have_masses;
+  const double* mass_c = per_atom ? (const double*)ctx->masses.ptr : (const double*)nullptr;
   auto go = [&](auto kernel) {
     launch_kernel(ctx, true, last, kernel, dim3(nb), dim3(kBlock), s.n, pos, vel, nl, cnt, p, fown,
                   U, s.box, U_out, F_out, W_out, J_out, kick, ekin_factor, dt, pos_next,
-                  (float)fe[0], (float)fe[1], (float)fe[2], block_out);
+                  (float)fe[0], (float)fe[1], (float)fe[2], mass_c, (const int*)s.perm.ptr, mass,
+                  block_out);
   };
   if (mode == 0)
     go(k_gather<kLanes, 0>);
@@ -520,11 +536,15 @@ hipError_t launch_finalize(nep_ctx ctx, int nq, int nsets, const double* block_s
   return hipGetLastError();
 }
 
-hipError_t launch_kick_drift(nep_ctx ctx, double* pos, double* vel, double kick, double dt) {
+hipError_t launch_kick_drift(nep_ctx ctx, double* pos, double* vel, double kick, double mass,
+                             double dt) {
   const int n = ctx->sys.n;
   if (n == 0) return hipSuccess;
+  const bool per_atom = ctx->species_on() && ctx->have_masses;
   launch_kernel(ctx, true, true, k_kick_drift, dim3(blocks_for((size_t)3 * n, kBlock)),
-                dim3(kBlock), n, pos, vel, (const float*)ctx->F.ptr, kick, dt);
+                dim3(kBlock), n, pos, vel, (const float*)ctx->F.ptr, kick, dt,
+                per_atom ? (const double*)ctx->masses.ptr : (const double*)nullptr,
+                (const int*)ctx->sys.perm.ptr, mass);
   return hipGetLastError();
 }
 

@@ -45,7 +45,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
     int n, const double* __restrict__ pos, const uint32_t* __restrict__ nl,
     const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, const int* __restrict__ rev,
     Box box, const float* __restrict__ z, int NR, int NA, int LMAX, int NNEU, float rc_r,
-    float rc_a, float4* __restrict__ pin, float* __restrict__ fown, float* __restrict__ U) {
+    float rc_a, const float* __restrict__ wsp, const int* __restrict__ perm,
+    float4* __restrict__ pin, float* __restrict__ fown, float* __restrict__ U) {
   const int NLM = (LMAX + 1) * (LMAX + 1) - 1;
   const int NDES = NR + NA * LMAX;
   const int RS = NDES + 1;  // LDS row of neuron mu: w1[mu][:] (padded)
@@ -71,6 +72,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
   if (i >= n) return;  // whole waves leave together; no block barrier below
   const int cr = cnt_r[i], ca = cnt_a[i];
   const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+  // multicomponent weight of pair (i, j): sqrt(Z_i) sqrt(Z_j), 1 for one species
+  const float wi = wsp ? wsp[perm[i]] : 1.f;
   const float rcr_inv = 1.f / rc_r, rca_inv = 1.f / rc_a;
   const float rcr2 = rc_r * rc_r, rca2 = rc_a * rc_a;
   const int nout = NA * NLM;  // angular moments, lane k owns k, k + 64, ...
@@ -98,6 +101,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
       int j;
       float dx, dy, dz;
       displacement(nl[(size_t)s * n + i], pos, n, xi, yi, zi, box.h, j, dx, dy, dz);
+      const float wij = wsp ? wi * wsp[perm[j]] : 1.f;
       const float r2 = pair_r2(dx, dy, dz);
       const float rinv = __builtin_amdgcn_rsqf(r2);
       const float r = r2 * rinv;
@@ -105,10 +109,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
         float gr[kMaxR];
         radial_basis_n(r, rcr_inv, NR, gr, nullptr);
 #pragma unroll
-        for (int a = 0; a < kMaxR; ++a) qr[a] += gr[a];
+        for (int a = 0; a < kMaxR; ++a) qr[a] += wij * gr[a];
       }
       if (s < ca && r2 < rca2) {
         radial_basis_n(r, rca_inv, NA, g, nullptr);
+#pragma unroll
+        for (int a = 0; a < kMaxA; ++a) g[a] *= wij;
         harmonics(dx * rinv, dy * rinv, dz * rinv, yh);
       }
     }
@@ -242,6 +248,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
         py += sb * y + (gy - y * ug) * rinv;
         pz += sb * z + (gz - z * ug) * rinv;
       }
+      if (wsp) {  // every term of the pair carries its weight once
+        const float wij = wi * wsp[perm[j]];
+        px *= wij;
+        py *= wij;
+        pz *= wij;
+      }
       fx += px;
       fy += py;
       fz += pz;
@@ -275,7 +287,9 @@ hipError_t launch_partials_generic(nep_ctx ctx, const double* pos) {
                 dim3(64 * kWaves), s.n, pos, (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr,
                 (const int*)s.cnt_a.ptr, (const int*)s.rev.ptr, s.box, (const float*)ctx->z.ptr,
                 h.n_max_radial + 1, h.n_max_angular + 1, h.l_max, h.n_neuron,
-                (float)h.rc_radial, (float)h.rc_angular, ctx->p.ptr, ctx->fown.ptr, ctx->U.ptr);
+                (float)h.rc_radial, (float)h.rc_angular,
+                ctx->species_on() ? (const float*)ctx->species_w.ptr : (const float*)nullptr,
+                (const int*)s.perm.ptr, ctx->p.ptr, ctx->fown.ptr, ctx->U.ptr);
   return hipGetLastError();
 }
 

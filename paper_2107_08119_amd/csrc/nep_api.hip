@@ -4,6 +4,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "nep_internal.h"
 
@@ -112,6 +113,8 @@ void nep_destroy(nep_ctx ctx) {
   ctx->sys.release();
   ctx->z.release();
   ctx->p.release();
+  ctx->species_w.release();
+  ctx->masses.release();
   ctx->fown.release();
   ctx->U.release();
   ctx->F.release();
@@ -226,6 +229,10 @@ nep_status nep_build_neighbors(nep_ctx ctx, int n_atoms, const double* pos_dev,
     s.nc[a] = probe.nc[a];
     s.kimg[a] = probe.kimg[a];
   }
+  if (ctx->species_n != n_atoms) {  // species describe another system
+    ctx->species_n = 0;
+    ctx->have_masses = false;
+  }
   s.n = n_atoms;
   s.cap = max_neighbors;
   ctx->have_list = false;
@@ -244,6 +251,46 @@ nep_status nep_build_neighbors(nep_ctx ctx, int n_atoms, const double* pos_dev,
   }
   ctx->have_list = true;
   ctx->steps_since_rebuild = 0;
+  return NEP_OK;
+}
+
+nep_status nep_set_species(nep_ctx ctx, int n, const int* atomic_numbers_host,
+                           const double* masses_amu_host) {
+  if (!ctx) return NEP_EINVAL;
+  if (!atomic_numbers_host) {
+    ctx->species_n = 0;
+    ctx->have_masses = false;
+    ctx->md_forces_valid = false;
+    return NEP_OK;
+  }
+  if (!ctx->have_list) return fail(ctx, NEP_ESTATE, "nep_build_neighbors must come first");
+  if (n != ctx->sys.n || n < 1) return fail(ctx, NEP_EINVAL, "n must equal the system's atom count");
+  std::vector<float> w((size_t)n);
+  for (int k = 0; k < n; ++k) {
+    const int Z = atomic_numbers_host[k];
+    if (Z < 1 || Z > 118) return fail(ctx, NEP_EINVAL, "atomic numbers must be in 1..118");
+    w[k] = (float)std::sqrt((double)Z);
+  }
+  if (masses_amu_host)
+    for (int k = 0; k < n; ++k)
+      if (!(masses_amu_host[k] > 0.0) || !std::isfinite(masses_amu_host[k]))
+        return fail(ctx, NEP_EINVAL, "masses must be > 0");
+  DeviceGuard guard(ctx->device);
+  hipError_t e = ctx->species_w.ensure((size_t)n);
+  if (e == hipSuccess && masses_amu_host) e = ctx->masses.ensure((size_t)n);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpy(ctx->species_w.ptr, w.data(), sizeof(float) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess && masses_amu_host)
+    e = hipMemcpy(ctx->masses.ptr, masses_amu_host, sizeof(double) * n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    ctx->species_n = 0;
+    ctx->have_masses = false;
+    return check_hip(ctx, e, "copying species");
+  }
+  ctx->species_n = n;
+  ctx->have_masses = masses_amu_host != nullptr;
+  ctx->md_forces_valid = false;
   return NEP_OK;
 }
 
@@ -333,7 +380,9 @@ nep_status nep_md_step_driven(nep_ctx ctx, int n_steps, double dt_fs, int rebuil
   int pending = 0;
   // first half-kick and drift of step 0; later steps get theirs from the
   // previous step's pass 2
-  e = timed(ctx, 3, [&] { return launch_kick_drift(ctx, s.pos_s.ptr, s.vel_s.ptr, kick, dt_fs); });
+  e = timed(ctx, 3, [&] {
+    return launch_kick_drift(ctx, s.pos_s.ptr, s.vel_s.ptr, kick, mass_amu, dt_fs);
+  });
   if (e != hipSuccess) return check_hip(ctx, e, "launching integrator");
   for (int step = 0; step < n_steps; ++step) {
     if (++ctx->steps_since_rebuild >= rebuild_every) {
@@ -449,7 +498,7 @@ nep_status nep_autotune(nep_ctx ctx, const double* pos_dev, int reps, int* lanes
   int best = ctx->md_variant;
   double best_ms = 0.0;
   // other model sizes have the one-wave-per-atom kernel only
-  const int nv = have_training_variant(ctx->hyper) ? 3 : 1;
+  const int nv = have_training_variant(ctx->hyper) && !ctx->species_on() ? 3 : 1;
   for (int v = 0; v < 3 && e == hipSuccess; ++v) {
     if (v >= nv) {
       if (ms_out) ms_out[v] = ms_out[0];

@@ -201,6 +201,11 @@ struct nep_ctx_s {
   nep::DevBuf<float> J;           // [3][n] internal heat currents
   nep::DevBuf<double> partials;   // [blocks][16] block sums
   int md_variant = 1;             // pass-1 tile shape: 0, 1, 2, 3 = 2, 4, 8, 64 lanes per atom
+  // multicomponent system (caller order): sqrt(Z) per atom and optional masses
+  int species_n = 0;              // atoms the arrays describe; 0 = one species
+  bool have_masses = false;
+  nep::DevBuf<float> species_w;   // [n] sqrt(atomic number)
+  nep::DevBuf<double> masses;     // [n] amu
   nep::DevBuf<double> totals;     // [16]
   nep::DevBuf<int> flags;         // [kNumFlags]
   // molecular dynamics state
@@ -216,6 +221,8 @@ struct nep_ctx_s {
   // captured generation
   nep::DevBuf<int> gen_counter;  // [2]
   nep::SnesGraph snes_graph;
+  // species weights and masses apply to the current system
+  bool species_on() const { return species_n > 0 && species_n == sys.n; }
 };
 
 // A training set on the device (structures concatenated).
@@ -319,7 +326,8 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
 hipError_t launch_finalize(nep_ctx ctx, int nq, int nsets, const double* block_sums, double* out,
                            bool first);
 size_t gather_blocks(int n);
-hipError_t launch_kick_drift(nep_ctx ctx, double* pos, double* vel, double kick, double dt);
+hipError_t launch_kick_drift(nep_ctx ctx, double* pos, double* vel, double kick, double mass,
+                             double dt);
 // pass 1 over a dataset for n_pop parameter vectors Z [n_pop][n_par].
 hipError_t launch_partials_population(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z);
 

@@ -28,7 +28,7 @@ EXPORTED = [
     "nep_time_partials", "nep_dataset_create", "nep_dataset_destroy", "snes_eval_population",
     "snes_sample", "snes_update", "nep_dataset_set_positions", "nep_dataset_get_positions",
     "nep_dataset_compute", "nep_dataset_backward", "snes_autotune", "snes_run",
-    "snes_set_tile", "nep_autotune", "nep_set_tile", "nep_md_step_driven",
+    "snes_set_tile", "nep_autotune", "nep_set_tile", "nep_md_step_driven", "nep_set_species",
 ]
 
 
@@ -77,6 +77,7 @@ def lib() -> C.CDLL:
         L.nep_compute.argtypes = [vp, vp, vp, vp, fp, vp, vp, vp]
         L.nep_md_step.argtypes = [vp, ip, dp, ip, dp, vp, vp, vp, vp, vp]
         L.nep_md_step_driven.argtypes = [vp, ip, dp, ip, dp, vp, vp, vp, vp, vp, vp]
+        L.nep_set_species.argtypes = [vp, ip, vp, vp]
         L.nep_set_timing.argtypes = [vp, ip]
         L.nep_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.nep_time_partials.argtypes = [vp, vp, ip, C.POINTER(C.c_double)]
@@ -230,6 +231,18 @@ class Context:
 
     def set_tile(self, lanes: int) -> None:
         self._check(self._lib.nep_set_tile(self._h, lanes))
+
+    def set_species(self, atomic_numbers=None, masses=None) -> None:
+        """Atomic numbers [N] (caller order) of a multicomponent system, whose
+        pair weights are sqrt(Z_i Z_j), and optional per-atom masses [N] (amu)
+        for md_step; None returns to one species (nep_set_species)."""
+        if atomic_numbers is None:
+            self._check(self._lib.nep_set_species(self._h, 0, None, None))
+            return
+        Z = np.ascontiguousarray(atomic_numbers, np.int32)
+        m = None if masses is None else np.ascontiguousarray(masses, np.float64)
+        self._check(self._lib.nep_set_species(self._h, len(Z), Z.ctypes.data,
+                                              None if m is None else m.ctypes.data))
 
     # -- training ------------------------------------------------------------
     def dataset_create(self, ls, max_neighbors: int = 64) -> "Dataset":
