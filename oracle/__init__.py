@@ -4,7 +4,8 @@ Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
 this package.  It is a thin ctypes wrapper over ``nep_oracle.c`` (plain C,
 float64, literal double sums), which shares no code with the GPU library.
 See the header of ``nep_oracle.c`` for the passages of the paper each
-function follows.
+function follows.  ``spectral.py`` (plain numpy, float64) holds the spectral
+heat-current analysis of Sec. II B.
 """
 from __future__ import annotations
 

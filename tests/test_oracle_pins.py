@@ -487,6 +487,85 @@ def test_species_md_conserves_energy_with_per_atom_masses(pbte_cell):
     np.testing.assert_array_equal(v1, v2)
 
 
+# ---------------------------------------- spectral heat-current analysis
+# Sec. II B: K(t) = sum_i <W_i(0) . v_i(t)>, (2/TV) int K e^{iwt} dt =
+# kappa(w) F_e, and the quantum correction x^2 e^x / (e^x - 1)^2.
+from oracle import spectral as SP  # noqa: E402
+
+
+def test_correlation_of_constant_signals_and_origin_counts():
+    rng = np.random.default_rng(1)
+    W0 = rng.standard_normal((5, 3, 3))
+    v0 = rng.standard_normal((5, 3))
+    S, M = 7, 4
+    K, counts = SP.virial_velocity_correlation(np.repeat(W0[None], S, 0),
+                                               np.repeat(v0[None], S, 0), M)
+    np.testing.assert_array_equal(counts, [7, 6, 5, 4])
+    np.testing.assert_allclose(K, np.repeat(np.einsum("iab,ib->a", W0, v0)[None], M, 0),
+                               rtol=1e-13)
+
+
+def test_correlation_of_a_cosine_is_a_dirichlet_sum():
+    """v_i(t) = a_i cos(O t), W_i constant: the mean over the n = S - k
+    origins of cos(O (t0 + k)) has the closed form
+    sin(n O / 2) / (n sin(O / 2)) cos(O (k + (n - 1) / 2))."""
+    rng = np.random.default_rng(2)
+    N, S, M, om = 4, 23, 9, 0.37
+    B = rng.standard_normal((N, 3, 3))
+    a = rng.standard_normal((N, 3))
+    t = np.arange(S)
+    v = a[None] * np.cos(om * t)[:, None, None]
+    K, _ = SP.virial_velocity_correlation(np.repeat(B[None], S, 0), v, M)
+    amp = np.einsum("iab,ib->a", B, a)
+    for k in range(M):
+        n = S - k
+        mean_cos = math.sin(n * om / 2) / (n * math.sin(om / 2)) * math.cos(om * (k + (n - 1) / 2))
+        np.testing.assert_allclose(K[k], amp * mean_cos, rtol=1e-10, atol=1e-13)
+
+
+def test_spectrum_of_an_exponential_correlation_is_lorentzian():
+    """K(t) = K0 e^{-t/tau}: 2 int_0^inf K cos(w t) dt = 2 K0 tau / (1 + w^2 tau^2);
+    the Hann window over t_max = 40 tau changes it by < 1%."""
+    tau, dt, M = 50.0, 1.0, 2001  # fs
+    K0 = np.array([2.0, -1.0, 0.5])
+    K = K0[None] * np.exp(-np.arange(M) * dt / tau)[:, None]
+    T, V, fe = 300.0, 1.0e4, 1.0e-4
+    nu = np.array([0.0, 0.5, 1.0, 3.0])  # THz
+    kap = SP.spectral_conductivity(K, dt, T, V, fe, nu)
+    w = 2 * math.pi * nu * 1.0e-3  # 1/fs
+    lor = 2.0 * tau / (1.0 + (w * tau) ** 2)
+    ref = SP.KAPPA_UNIT * 2.0 / (T * V * fe) * K0[:, None] * lor[None]
+    np.testing.assert_allclose(kap, ref, rtol=1e-2)
+
+
+def test_spectrum_integrates_to_the_total_conductivity():
+    """Sum rule: int_0^{nu_Nyquist} kappa(nu) dnu = kappa_total = K(0) / (T V F_e)
+    (in W/m/K), for any sampled K (cosines of integer lags integrate to
+    zero up to the Nyquist frequency)."""
+    rng = np.random.default_rng(3)
+    M, dt = 60, 2.0
+    K = rng.standard_normal((M, 3))
+    T, V, fe = 250.0, 3.0e4, 2.0e-4
+    nu_n = 1.0 / (2.0 * dt * 1.0e-3)
+    nu = np.linspace(0.0, nu_n, 20001)
+    kap = SP.spectral_conductivity(K, dt, T, V, fe, nu)
+    total = np.trapezoid(kap, nu, axis=1)
+    ref = SP.KAPPA_UNIT * 1.0e3 * K[0] / (T * V * fe)
+    np.testing.assert_allclose(total, ref, rtol=2e-5)
+
+
+def test_quantum_factor_is_the_harmonic_oscillator_heat_capacity_ratio():
+    """x^2 e^x / (e^x - 1)^2 = ((x/2) / sinh(x/2))^2; 1 - x^2/12 for small x."""
+    T = 300.0
+    nu = np.array([1e-6, 0.1, 1.0, 6.25, 15.0, 40.0])
+    q = SP.quantum_factor(nu, T)
+    x = SP.HBAR * 2 * math.pi * nu * 1e12 / (SP.KB * T)
+    np.testing.assert_allclose(q, (0.5 * x / np.sinh(0.5 * x)) ** 2, rtol=1e-12)
+    np.testing.assert_allclose(q[:2], 1.0 - x[:2] ** 2 / 12.0, rtol=1e-6)
+    assert np.all(np.diff(q) < 0) and q[-1] < 0.07  # 40 THz at 300 K: x = 6.4
+    assert SP.quantum_factor(np.array([0.0]), T)[0] == 1.0
+
+
 # -------------------------------------------------------------------- loss
 @pytest.fixture(scope="module")
 def tiny_set():
