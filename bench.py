@@ -55,7 +55,7 @@ BYTE_ATOM, BYTE_SLOT = 36, 20
 # for the kernel sources they were taken with (hash below); otherwise the
 # bench reports traffic null.
 COUNTERS = {"sources_sha256": "e567e9b7140472e55c303691f1d19a3f8c4f39768dbc0166af5654970b07e21f",
-            "fetch_kib": 10832.35, "write_kib": 58894.33}
+            "fetch_kib": 10804.64, "write_kib": 58986.13}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ["force.hip", "nep_terms.h", "nep_device.h", "nep_internal.h"]
 
@@ -125,6 +125,52 @@ def disordered_rate(args, nep, I, torch, z):
                         "distance), per-atom W and J written every step, dt 1 fs, rebuild every "
                         "10 steps", "atom_steps_per_s": n * K / t, "ms_per_step": t / K * 1e3,
             "steps": K, "k_partials_us": ms * 1e3, "tile_lanes_per_atom": lanes}
+
+
+def spectral_rate(ctx, nep, torch, p, v, n, box, dt, rebuild, mass, fe, n_lags=250,
+                  every=2, samples=300):
+    """HNEMD with the virial-velocity correlation (Sec. II B): per-atom W_i and
+    v_i sampled every `every` steps into a ring of n_lags samples, then the
+    spectral conductivity and its quantum correction.  Reports the MD rate
+    with sampling, the sampling kernels' time at a full ring and their HBM
+    rate (n_lags x 36 B of virials read per atom and sample)."""
+    W = torch.empty((9, n), dtype=torch.float32, device="cuda")
+    corr = nep.Correlation(ctx, n, n_lags)
+    ctx.md_step(every, dt, rebuild, mass, p, v, W=W, fe=fe)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(samples):
+        ctx.md_step(every, dt, rebuild, mass, p, v, W=W, fe=fe)
+        corr.sample(W, v)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    # the sampling kernels alone, ring full (n_lags lags per sample)
+    reps = 20
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        corr.sample(W, v)
+    torch.cuda.synchronize()
+    t_s = (time.perf_counter() - t1) / reps
+    K, n_s = corr.get()
+    volume = float(abs(np.linalg.det(box)))
+    nu = np.linspace(0.0, 25.0, 251)
+    kap, kq = corr.spectrum(every * dt, 300.0, volume, fe[0], nu)
+    kx = float(np.trapezoid(kap[0], nu))
+    kqx = float(np.trapezoid(kq[0], nu))
+    corr.close()
+    bytes_sample = n_lags * 36.0 * n + 24.0 * n + 72.0 * n  # ring reads, v, W copy in and out
+    return {"workload": "HNEMD of the 64,000-atom diamond (F_e = 1e-4 1/A along x) with W_i and "
+                        "v_i sampled every %d steps into a %d-sample correlation ring, %d samples; "
+                        "spectrum 0-25 THz with the quantum correction" % (every, n_lags, samples),
+            "atom_steps_per_s": n * every * samples / t,
+            "us_per_sample_full_ring": t_s * 1e6,
+            "sample_GBps": bytes_sample / t_s / 1e9,
+            "sample_hbm_frac": bytes_sample / t_s / 8.0e12,
+            "samples": n_s,
+            "kappa_xx_W_per_mK_0_25THz": kx, "kappa_q_xx_W_per_mK_0_25THz": kqx,
+            "note": "kappa from %d fs of correlation: a throughput run, not a converged "
+                    "conductivity" % int(n_lags * every * dt)}
 
 
 def paper_model_rate(nep, I, torch, steps=100):
@@ -470,6 +516,8 @@ def main():
                     "F_e = (1e-4, 0, 0) 1/A (1 um^-1)",
         "atom_steps_per_s": n * k_h / t_h, "steps": k_h,
         "mean_Jx_eV_A_per_fs": float(th_h[:k_h, 2].mean().item())}
+    line["hnemd_spectral_64k"] = spectral_rate(ctx, nep, torch, p, v, n, box, dt, rebuild, mass,
+                                               fe)
     line["paper_model_8k"] = paper_model_rate(nep, I, torch)
     line["autograd_256"] = autograd_rate(nep, I, torch, z)
     line["pbte_64k"] = pbte_rate(nep, I, torch)

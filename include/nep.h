@@ -39,6 +39,7 @@ extern "C" {
 
 typedef struct nep_ctx_s* nep_ctx;
 typedef struct nep_dataset_s* nep_dataset;
+typedef struct nep_vvcf_s* nep_vvcf;
 
 typedef enum {
   NEP_OK = 0,
@@ -187,6 +188,44 @@ nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every
 nep_status nep_md_step_driven(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every,
                               double mass_amu, const double* fe_host, double* pos_dev,
                               double* vel_dev, double* thermo_dev, float* W_dev, float* J_dev);
+
+/* ------------------------------------------ spectral heat transport */
+
+/* Virial-velocity correlation of an HNEMD run (Sec. II B):
+ *   K_mu(t) = sum_i < sum_nu (W_i(0))_mu,nu (v_i(t))_nu >,
+ * averaged over every time origin of the sampled trajectory, for lags
+ * t = 0 .. n_lags-1 sample intervals.  The last n_lags samples' per-atom
+ * virials are kept on the device (n_lags * 9 * n_atoms float32, at most
+ * 64 GB).  *out owns them until nep_vvcf_destroy.  NEP_EINVAL for sizes out
+ * of range. */
+nep_status nep_vvcf_create(nep_ctx ctx, int n_atoms, int n_lags, nep_vvcf* out);
+void nep_vvcf_destroy(nep_vvcf v);
+
+/* Add one sample: W_dev [9][N] float32 per-atom virials ((W_i)_ab at row
+ * 3a+b, as written by nep_md_step) and vel_dev [3][N] float64 velocities of
+ * the same instant, both in the caller's order, on the device.  Every lag
+ * k <= min(samples, n_lags-1) gains the term of origin (this sample - k).
+ * Sums are float64, in a fixed order.  Asynchronous on the context's stream. */
+nep_status nep_vvcf_sample(nep_ctx ctx, nep_vvcf v, const float* W_dev, const double* vel_dev);
+
+/* The averaged correlation K_host [n_lags][3] (eV A/fs; lags with no
+ * origin yet are 0) and the number of samples (either may be NULL).
+ * Synchronous. */
+nep_status nep_vvcf_get(nep_ctx ctx, nep_vvcf v, double* K_host, long long* samples);
+
+/* Spectral conductivity from (2/TV) int K_mu(t) e^{i w t} dt = kappa_mu(w) F_e
+ * for a driving force of magnitude fe (1/A) along one axis, samples dt_fs
+ * apart, temperature (K) and volume (A^3): K is taken even in t, windowed by
+ * (1 + cos(pi k / (n_lags-1)))/2 and summed by the trapezoid rule.  At the
+ * n_nu frequencies nu_thz_host (THz, w = 2 pi nu): kappa_host [3][n_nu] in
+ * W/(m K THz) (so int_0^inf kappa d nu is the conductivity in W/(m K)) and,
+ * if not NULL, the quantum-corrected kappa_q_host [3][n_nu] =
+ * kappa x^2 e^x / (e^x - 1)^2 with x = hbar w / k_B T (the correction of
+ * Sec. IV C for disordered materials).  Host arrays; synchronous.
+ * NEP_ESTATE before the first sample. */
+nep_status nep_vvcf_spectrum(nep_ctx ctx, nep_vvcf v, double dt_fs, double temperature,
+                             double volume, double fe, int n_nu, const double* nu_thz_host,
+                             double* kappa_host, double* kappa_q_host);
 
 /* ---------------------------------------------------- training (SNES) */
 

@@ -2,7 +2,8 @@
 INFRASTRUCTURE ONLY (tests, the smoke check and the benchmark's CPU leg).
 
 Follows Sec. II B of the paper (spectral decomposition of the HNEMD heat
-current) and its quantum-correction formula for disordered materials:
+current) and the quantum-correction formula of Sec. IV C (disordered
+materials):
 
 * virial-velocity correlation K(t) = sum_i < W_i(0) . v_i(t) >_ne, the
   average taken over every time origin of the sampled trajectory, with

@@ -29,6 +29,7 @@ EXPORTED = [
     "snes_sample", "snes_update", "nep_dataset_set_positions", "nep_dataset_get_positions",
     "nep_dataset_compute", "nep_dataset_backward", "snes_autotune", "snes_run",
     "snes_set_tile", "nep_autotune", "nep_set_tile", "nep_md_step_driven", "nep_set_species",
+    "nep_vvcf_create", "nep_vvcf_destroy", "nep_vvcf_sample", "nep_vvcf_get", "nep_vvcf_spectrum",
 ]
 
 
@@ -78,6 +79,12 @@ def lib() -> C.CDLL:
         L.nep_md_step.argtypes = [vp, ip, dp, ip, dp, vp, vp, vp, vp, vp]
         L.nep_md_step_driven.argtypes = [vp, ip, dp, ip, dp, vp, vp, vp, vp, vp, vp]
         L.nep_set_species.argtypes = [vp, ip, vp, vp]
+        L.nep_vvcf_create.argtypes = [vp, ip, ip, C.POINTER(vp)]
+        L.nep_vvcf_destroy.argtypes = [vp]
+        L.nep_vvcf_destroy.restype = None
+        L.nep_vvcf_sample.argtypes = [vp, vp, vp, vp]
+        L.nep_vvcf_get.argtypes = [vp, vp, vp, C.POINTER(C.c_longlong)]
+        L.nep_vvcf_spectrum.argtypes = [vp, vp, dp, dp, dp, dp, ip, vp, vp, vp]
         L.nep_set_timing.argtypes = [vp, ip]
         L.nep_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.nep_time_partials.argtypes = [vp, vp, ip, C.POINTER(C.c_double)]
@@ -100,7 +107,7 @@ def lib() -> C.CDLL:
         L.nep_dataset_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         for name in EXPORTED:
             if name not in ("nep_destroy", "nep_last_error", "nep_num_descriptors",
-                            "nep_num_params", "nep_dataset_destroy"):
+                            "nep_num_params", "nep_dataset_destroy", "nep_vvcf_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -395,6 +402,51 @@ class Dataset:
     def close(self):
         if getattr(self, "_h", None):
             self.ctx._lib.nep_dataset_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Correlation:
+    """Virial-velocity correlation of an HNEMD run and its spectral
+    conductivity (nep_vvcf_*, Sec. II B)."""
+
+    def __init__(self, ctx: Context, n_atoms: int, n_lags: int):
+        h = C.c_void_p()
+        ctx._check(ctx._lib.nep_vvcf_create(ctx._h, n_atoms, n_lags, C.byref(h)))
+        self.ctx, self._h, self.n_atoms, self.n_lags = ctx, h, n_atoms, n_lags
+
+    def sample(self, W: torch.Tensor, vel: torch.Tensor) -> None:
+        """W [9][N] float32 and vel [3][N] float64 device tensors (caller order)."""
+        assert W.dtype == torch.float32 and W.is_contiguous() and W.numel() == 9 * self.n_atoms
+        assert vel.dtype == torch.float64 and vel.is_contiguous() and vel.numel() == 3 * self.n_atoms
+        self.ctx._check(self.ctx._lib.nep_vvcf_sample(self.ctx._h, self._h, _ptr(W), _ptr(vel)))
+
+    def get(self):
+        """(K [n_lags, 3] in eV A/fs as numpy, number of samples)."""
+        K = np.zeros((self.n_lags, 3))
+        n = C.c_longlong()
+        self.ctx._check(self.ctx._lib.nep_vvcf_get(self.ctx._h, self._h, K.ctypes.data,
+                                                   C.byref(n)))
+        return K, n.value
+
+    def spectrum(self, dt_fs: float, temperature: float, volume: float, fe: float, nu_thz):
+        """(kappa, kappa_q) [3, len(nu)] in W/(m K THz) at frequencies nu_thz."""
+        nu = np.ascontiguousarray(nu_thz, np.float64)
+        kap = np.zeros((3, len(nu)))
+        kq = np.zeros((3, len(nu)))
+        self.ctx._check(self.ctx._lib.nep_vvcf_spectrum(
+            self.ctx._h, self._h, dt_fs, temperature, volume, fe, len(nu), nu.ctypes.data,
+            kap.ctypes.data, kq.ctypes.data))
+        return kap, kq
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.ctx._lib.nep_vvcf_destroy(self._h)
             self._h = None
 
     def __del__(self):
