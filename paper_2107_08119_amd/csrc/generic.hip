@@ -123,7 +123,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
 #pragma unroll
     for (int m = 0; m < kMaxLM; ++m) s_y[wave][lane][m] = yh[m];
     wave_lds_sync();
-    const int np = min(64, cr - base);
+    // pairs past the list's angular part have g = 0: skip them
+    const int np = max(0, min(64, min(cr, ca) - base));
 #pragma unroll
     for (int r = 0; r < (kMaxA * kMaxLM + 63) / 64; ++r) {
       const int k = lane + 64 * r;

@@ -95,6 +95,37 @@ __device__ __forceinline__ void radial_basis(float r, float rc_inv, float* g, fl
   }
 }
 
+// The pieces of g_n and g_n' without the products: T_n(x), dT_n/dx = n U_{n-1}(x)
+// for n = 1..NB-1 (entry 0 unused), f_c, f_c' and dx/dr, so that
+//   g_n = f_c (T_n + 1) / 2,  g_n' = f_c' (T_n + 1) / 2 + f_c (dx/dr) T_n' / 2.
+template <int NB>
+__device__ __forceinline__ void chebyshev_terms(float r, float rc_inv, float& fc, float& dfc,
+                                                float& dxdr, float* T, float* dT) {
+  const float t = r * rc_inv;
+  float sy, cy;
+  sincos_quarter_turn(kPi * (t - 0.5f), sy, cy);
+  fc = 0.5f * (1.f - sy);
+  dfc = -0.5f * kPi * rc_inv * cy;
+  const float tm1 = t - 1.f;
+  const float x = 2.f * tm1 * tm1 - 1.f;
+  dxdr = 4.f * tm1 * rc_inv;
+  float U[NB];
+  T[0] = 1.f;
+  U[0] = 1.f;
+  dT[0] = 0.f;
+  if constexpr (NB > 1) {
+    T[1] = x;
+    U[1] = 2.f * x;
+    dT[1] = 1.f;
+  }
+#pragma unroll
+  for (int n = 2; n < NB; ++n) {
+    T[n] = 2.f * x * T[n - 1] - T[n - 2];
+    U[n] = 2.f * x * U[n - 1] - U[n - 2];
+    dT[n] = (float)n * U[n - 1];
+  }
+}
+
 // ------------------------------------------------------- angular harmonics
 // Real harmonics for l = 1..4 scaled by sqrt(4 pi/(2l+1)) so that
 // sum_m Y_lm(u) Y_lm(v) = P_l(u.v) for unit u, v, written as polynomials in

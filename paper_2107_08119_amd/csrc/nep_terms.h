@@ -12,6 +12,10 @@
 //   dU_i/dr_ij = sum_n dU/dq_n g_n'(r) u
 //              + sum_lm [ B_lm Yhat_lm(u) u + A_lm (grad Yhat_lm - u (u.grad Yhat_lm)) / r ],
 // with a_nlm = 2 dU/dq_nl c_nlm, A_lm = sum_n a_nlm g_n(r), B_lm = sum_n a_nlm g_n'(r).
+// Since g_n = f_c (T_n + 1)/2, both come from At_lm = a'_0lm + sum_{n>=1} a_nlm T_n
+// (a'_0lm = 2 a_0lm + sum_{n>=1} a_nlm, folded once per atom) and
+// D_lm = sum_{n>=1} a_nlm T_n':  A_lm = f_c At_lm / 2,
+// B_lm = f_c' At_lm / 2 + f_c (dx/dr) D_lm / 2.
 #pragma once
 
 #include "nep_device.h"
@@ -147,10 +151,12 @@ __device__ __forceinline__ void network(const float* q, const float4* rows, floa
   for (int v = 0; v < NDES; ++v) dq[v] = group_sum<L>(dq[v]);
 }
 
-// a_nlm = 2 dU/dq_nl c_nlm, in place of c.
+// a_nlm = 2 dU/dq_nl c_nlm in place of c, then row 0 replaced by
+// a'_0lm = 2 a_0lm + sum_{n>=1} a_nlm (the constant part of sum_n a_nlm (T_n + 1)).
 template <int NR, int NA, int LMAX>
 __device__ __forceinline__ void angular_coefficients(const float* dq,
                                                      float (&c)[NA][Model<NR, NA, LMAX>::kNLM]) {
+  constexpr int NLM = Model<NR, NA, LMAX>::kNLM;
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -159,10 +165,17 @@ __device__ __forceinline__ void angular_coefficients(const float* dq,
 #pragma unroll
       for (int m = 0; m < 2 * l + 1; ++m) c[a][l * l - 1 + m] *= f;
     }
+#pragma unroll
+  for (int m = 0; m < NLM; ++m) {
+    float s = 2.f * c[0][m];
+#pragma unroll
+    for (int a = 1; a < NA; ++a) s += c[a][m];
+    c[0][m] = s;
+  }
 }
 
 // Partial force dU_i/dr_ij of pair (dx, dy, dz) from dq (radial part, when
-// rad) and the angular coefficients a (when ang).
+// rad) and the angular coefficients a as left by angular_coefficients (when ang).
 template <int NR, int NA, int LMAX>
 __device__ __forceinline__ void pair_force(float dx, float dy, float dz, bool rad, bool ang,
                                            float rcr_inv, float rca_inv, const float* dq,
@@ -187,26 +200,32 @@ __device__ __forceinline__ void pair_force(float dx, float dy, float dz, bool ra
     pz += f * z;
   }
   if (ang) {
-    float g[NA], dg[NA];
-    radial_basis<NA, true>(r, rca_inv, g, dg);
+    float fc, dfc, dxdr, T[NA], dT[NA];
+    chebyshev_terms<NA>(r, rca_inv, fc, dfc, dxdr, T, dT);
     const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
     const float xyz = xy * z;
     (void)xyz;
-    float sb = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+    float sa = 0.f, sd = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
 #define NEP_PF(idx, YV, GX, GY, GZ)                   \
   if constexpr ((idx) < NLM) {                        \
-    float A = 0.f, B = 0.f;                           \
-    _Pragma("unroll") for (int a = 0; a < NA; ++a) {  \
-      A += c[a][idx] * g[a];                          \
-      B += c[a][idx] * dg[a];                         \
+    float At = c[0][idx], D = 0.f;                    \
+    _Pragma("unroll") for (int a = 1; a < NA; ++a) {  \
+      At += c[a][idx] * T[a];                         \
+      D += c[a][idx] * dT[a];                         \
     }                                                 \
-    sb += B * (YV);                                   \
-    gx += A * (GX);                                   \
-    gy += A * (GY);                                   \
-    gz += A * (GZ);                                   \
+    sa += At * (YV);                                  \
+    sd += D * (YV);                                   \
+    gx += At * (GX);                                  \
+    gy += At * (GY);                                  \
+    gz += At * (GZ);                                  \
   }
     NEP_YLM_TABLE(NEP_PF)
 #undef NEP_PF
+    const float sb = 0.5f * (dfc * sa + fc * dxdr * sd);
+    const float hf = 0.5f * fc;
+    gx *= hf;
+    gy *= hf;
+    gz *= hf;
     const float ug = x * gx + y * gy + z * gz;
     px += sb * x + (gx - x * ug) * rinv;
     py += sb * y + (gy - y * ug) * rinv;
