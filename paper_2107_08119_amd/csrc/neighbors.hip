@@ -214,12 +214,18 @@ __global__ void k_take_rows(int n, int rows, const T* __restrict__ src, const in
 }
 
 template <class T>
-__global__ void k_put_rows(int n, int rows, const T* __restrict__ src, const int* __restrict__ perm,
+__global__ void k_put_rows(int n, int rows, const T* __restrict__ src, const int* __restrict__ iperm,
                            T* __restrict__ dst) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int k = iperm[c];
+  for (int r = 0; r < rows; ++r) dst[(size_t)r * n + c] = src[(size_t)r * n + k];
+}
+
+// iperm[perm[k]] = k.
+__global__ void k_invert_perm(int n, const int* __restrict__ perm, int* __restrict__ iperm) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const int o = perm[k];
-  for (int r = 0; r < rows; ++r) dst[(size_t)r * n + o] = src[(size_t)r * n + k];
+  if (k < n) iperm[perm[k]] = k;
 }
 
 __global__ void k_iota(int n, int* __restrict__ a) {
@@ -597,13 +603,13 @@ void launch_take_rows(nep_ctx ctx, int n, int rows, const double* src, double* d
 void launch_put_rows(nep_ctx ctx, int n, int rows, const double* src, double* dst) {
   if (n == 0) return;
   launch_kernel(ctx, false, false, k_put_rows<double>, dim3(blocks_for(n, kBlock)), dim3(kBlock),
-                n, rows, src, (const int*)ctx->sys.perm.ptr, dst);
+                n, rows, src, (const int*)ctx->sys.iperm.ptr, dst);
 }
 
 void launch_put_rows(nep_ctx ctx, int n, int rows, const float* src, float* dst) {
   if (n == 0) return;
   launch_kernel(ctx, false, false, k_put_rows<float>, dim3(blocks_for(n, kBlock)), dim3(kBlock), n,
-                rows, src, (const int*)ctx->sys.perm.ptr, dst);
+                rows, src, (const int*)ctx->sys.iperm.ptr, dst);
 }
 
 void launch_iota(nep_ctx ctx, int n, int* dst) {
@@ -656,6 +662,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
   const size_t ncap = (size_t)n * s.cap;
   if ((e = s.nl.ensure(ncap)) != hipSuccess || (e = s.rev.ensure(ncap)) != hipSuccess ||
       (e = s.cnt_r.ensure(n)) != hipSuccess || (e = s.cnt_a.ensure(n)) != hipSuccess ||
+      (e = s.iperm.ensure(n)) != hipSuccess ||
       (e = s.wrap.ensure((size_t)3 * n)) != hipSuccess)
     return check_hip(ctx, e, "allocating neighbour lists");
   const double rc2_r = s.rc_list_r * s.rc_list_r;
@@ -727,6 +734,10 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
                   (const int*)s.wrap.ptr, rc2_r, rc2_a, s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr,
                   ctx->flags.ptr);
   }
+  // caller index -> internal index, for the coalesced copies back
+  if (n > 0)
+    launch_kernel(ctx, false, false, k_invert_perm, dim3(blocks_for(n, kBlock)), blk, n,
+                  (const int*)s.perm.ptr, s.iperm.ptr);
   const int width = s.cap < 40 ? s.cap : 40;
   launch_kernel(ctx, false, true, k_reverse, dim3(blocks_for((size_t)n * width, kBlock)), blk, n,
                 s.cap, width, (const uint32_t*)s.nl.ptr,

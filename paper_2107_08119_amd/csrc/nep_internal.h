@@ -115,10 +115,11 @@ struct System {
   DevBuf<CellRec> cell_rec;  // [n] positions and offsets in cell order
   // The library works on its own copies of positions and velocities in cell
   // order (re-sorted at every rebuild); perm[k] is the caller's index of the
-  // atom at internal index k.
+  // atom at internal index k, iperm[c] the internal index of caller atom c.
   DevBuf<double> pos_s, pos_t;  // [3][n]
   DevBuf<double> vel_s, vel_t;  // [3][n]
   DevBuf<int> perm, perm_t;     // [n]
+  DevBuf<int> iperm;            // [n]
   DevBuf<int> wrap_t, cell_t;   // [3][n], [n]
   void release() {
     nl.release();
@@ -141,6 +142,7 @@ struct System {
     vel_t.release();
     perm.release();
     perm_t.release();
+    iperm.release();
     wrap_t.release();
     cell_t.release();
   }
@@ -289,7 +291,8 @@ int population_lanes(int variant);
 nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel);
 // dst[r*n + k] = src[r*n + perm[k]] (caller order -> internal order).
 void launch_take_rows(nep_ctx ctx, int n, int rows, const double* src, double* dst);
-// dst[r*n + perm[k]] = src[r*n + k] (internal order -> caller order).
+// dst[r*n + c] = src[r*n + iperm[c]] (internal order -> caller order; the
+// same as dst[r*n + perm[k]] = src[r*n + k], with coalesced stores).
 void launch_put_rows(nep_ctx ctx, int n, int rows, const double* src, double* dst);
 void launch_put_rows(nep_ctx ctx, int n, int rows, const float* src, float* dst);
 void launch_iota(nep_ctx ctx, int n, int* dst);
