@@ -1,0 +1,113 @@
+"""Degenerate inputs on the GPU path: an empty system, an isolated atom (no
+neighbour: the descriptor is zero and the site energy is the network at
+q = 0), a pair inside r_c^R but outside r_c^A (radial terms only), and a
+ragged cluster whose atoms have from zero to many neighbours, each against
+the FP64 oracle or its closed form."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2107_08119_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def nep_mod():
+    from paper_2107_08119_amd import nep
+    return nep
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def context(z):
+    nep = nep_mod()
+    ctx = nep.Context(0)
+    ctx.load_params(nep.hyper(), z)
+    return nep, ctx
+
+
+def test_empty_system():
+    import torch
+    z = I.random_parameters(931, 1)
+    nep, ctx = context(z)
+    p = torch.zeros((3, 0), dtype=torch.float64, device="cuda")
+    v = torch.zeros((3, 0), dtype=torch.float64, device="cuda")
+    ctx.build_neighbors(p, np.diag([20.0, 20.0, 20.0]), skin=0.5, max_neighbors=32)
+    out = ctx.compute(p, v)
+    th = ctx.md_step(3, 1.0, 2, I.MASS_SI, p, v)
+    ctx.synchronize()
+    assert out["F"].shape == (3, 0)
+    assert not out["totals"].cpu().numpy().any()
+    assert not th.cpu().numpy().any()
+
+
+def test_isolated_atom_is_the_network_at_zero_descriptor():
+    """No neighbour within the list cutoff: q = 0, so
+    U = sum_mu w2[mu] tanh(-b1[mu]) - b2 (Eqs. nn1, nn2), and F = W = 0."""
+    z = I.random_parameters(931, 3)
+    nep, ctx = context(z)
+    pos = np.array([[10.0, 10.0, 10.0]])
+    box = np.diag([30.0, 30.0, 30.0])
+    p = nep.soa(pos)
+    ctx.build_neighbors(p, box, skin=0.5, max_neighbors=16)
+    out = ctx.compute(p, nep.soa(np.array([[0.01, -0.02, 0.03]])))
+    ctx.synchronize()
+    z64 = z.astype(np.float64)
+    n_des, n_neu = 29, 30
+    b1 = z64[n_neu * n_des:n_neu * (n_des + 1)]
+    w2 = z64[n_neu * (n_des + 1):n_neu * (n_des + 2)]
+    b2 = z64[n_neu * (n_des + 2)]
+    u_ref = float(np.sum(w2 * np.tanh(-b1)) - b2)
+    assert out["U"].cpu().numpy()[0] == pytest.approx(u_ref, rel=TOL)
+    assert not out["F"].cpu().numpy().any()
+    assert not out["W"].cpu().numpy().any()
+
+
+def test_radial_only_pair_matches_oracle():
+    """Two atoms 4.7 A apart: inside r_c^R = 5, outside r_c^A = 4 and outside
+    the angular part of the list (r_c^A + skin = 4.5)."""
+    z = I.random_parameters(931, 4)
+    nep, ctx = context(z)
+    pos = np.array([[10.0, 10.0, 10.0], [14.7, 10.0, 10.0]])
+    box = np.diag([30.0, 30.0, 30.0])
+    p = nep.soa(pos)
+    ctx.build_neighbors(p, box, skin=0.5, max_neighbors=16)
+    out = ctx.compute(p)
+    ctx.synchronize()
+    ref = O.nep_eval(O.hyper(), z, pos, box)
+    assert rel(out["U"].cpu().numpy(), ref["U"]) < TOL
+    assert rel(nep.aos(out["F"]), ref["F"]) < TOL
+    assert rel(nep.aos(out["W"]).reshape(-1, 3, 3), ref["W"]) < TOL
+    nb = ctx.get_neighbors()
+    assert nb["cnt_radial"].cpu().numpy().tolist() == [1, 1]
+    assert nb["cnt_angular"].cpu().numpy().tolist() == [0, 0]
+
+
+def test_ragged_cluster_matches_oracle():
+    """A loose cluster in a large box: neighbour counts from 0 to ~20."""
+    rng = np.random.default_rng(8)
+    z = I.random_parameters(931, 5)
+    nep, ctx = context(z)
+    pts = np.vstack([rng.uniform(0.0, 7.0, (40, 3)), [[25.0, 25.0, 25.0]]])  # one loner
+    keep = [0]
+    for k in range(1, len(pts)):  # no two atoms closer than 1.8 A
+        if np.min(np.linalg.norm(pts[keep] - pts[k], axis=1)) > 1.8:
+            keep.append(k)
+    pos = pts[keep] + 5.0
+    box = np.diag([40.0, 40.0, 40.0])
+    p = nep.soa(pos)
+    ctx.build_neighbors(p, box, skin=0.5, max_neighbors=64)
+    vel = I.maxwell_boltzmann(len(pos), 300.0, 1)
+    out = ctx.compute(p, nep.soa(vel))
+    ctx.synchronize()
+    counts = ctx.get_neighbors()["cnt_radial"].cpu().numpy()
+    assert counts.min() == 0 and counts.max() >= 10
+    ref = O.nep_eval(O.hyper(), z, pos, box, vel=vel)
+    for k, got in (("U", out["U"].cpu().numpy()), ("F", nep.aos(out["F"])),
+                   ("W", nep.aos(out["W"]).reshape(-1, 3, 3)), ("J", nep.aos(out["J"]))):
+        assert rel(got, ref[k]) < TOL, k
