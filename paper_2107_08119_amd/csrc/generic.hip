@@ -17,9 +17,23 @@
 namespace nep {
 namespace {
 
-constexpr int kMaxR = 16, kMaxA = 16, kMaxLM = 24, kMaxNeu = 64;
-constexpr int kMaxDes = kMaxR + kMaxA * 4;
+// Largest sizes of the runtime-sized instantiation.
+constexpr int kMaxR = 16, kMaxA = 16, kMaxNeu = 64;
 constexpr int kWaves = 4;  // atoms per block
+
+// Sizes of one instantiation: TR > 0 fixes (n_max^R + 1, n_max^A + 1, l_max,
+// N_neu) = (TR, TA, TL, TNEU) at compile time (loops unrolled, LDS sized to
+// the model); TR == 0 takes them at run time up to the maxima above.
+template <int TR, int TA, int TL, int TNEU>
+struct Shape {
+  static constexpr bool kFixed = TR > 0;
+  static constexpr int MR = kFixed ? TR : kMaxR;
+  static constexpr int MA = kFixed ? TA : kMaxA;
+  static constexpr int ML = kFixed ? TL : 4;
+  static constexpr int MLM = (ML + 1) * (ML + 1) - 1;
+  static constexpr int MNEU = kFixed ? TNEU : kMaxNeu;
+  static constexpr int MDES = MR + MA * ML;
+};
 
 // Sum over the 64 lanes of a wave in a fixed order; every lane gets the
 // same bits (each step adds two partial sums, which commutes exactly).
@@ -30,23 +44,32 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// Radial basis g_n, n < nb (<= 16), and optionally g_n' (runtime size).
+// Radial basis g_n, n < nb (<= MB), and optionally g_n'.
+template <int MB>
 __device__ __forceinline__ void radial_basis_n(float r, float rc_inv, int nb, float* g, float* dg) {
-  float gg[kMaxR], dd[kMaxR];
-  radial_basis<kMaxR, true>(r, rc_inv, gg, dd);
+  float gg[MB], dd[MB];
+  radial_basis<MB, true>(r, rc_inv, gg, dd);
 #pragma unroll
-  for (int n = 0; n < kMaxR; ++n) {
+  for (int n = 0; n < MB; ++n) {
     g[n] = n < nb ? gg[n] : 0.f;
     if (dg) dg[n] = n < nb ? dd[n] : 0.f;
   }
 }
 
+template <int TR, int TA, int TL, int TNEU>
 __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
     int n, const double* __restrict__ pos, const uint32_t* __restrict__ nl,
     const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, const int* __restrict__ rev,
-    Box box, const float* __restrict__ z, int NR, int NA, int LMAX, int NNEU, float rc_r,
-    float rc_a, const float* __restrict__ wsp, const int* __restrict__ perm,
+    Box box, const float* __restrict__ z, int nr_rt, int na_rt, int lmax_rt, int nneu_rt,
+    float rc_r, float rc_a, const float* __restrict__ wsp, const int* __restrict__ perm,
     float4* __restrict__ pin, float* __restrict__ fown, float* __restrict__ U) {
+  using S = Shape<TR, TA, TL, TNEU>;
+  constexpr int kMaxR = S::MR, kMaxA = S::MA, kMaxLM = S::MLM, kMaxNeu = S::MNEU;
+  constexpr int kMaxDes = S::MDES;
+  const int NR = S::kFixed ? TR : nr_rt;
+  const int NA = S::kFixed ? TA : na_rt;
+  const int LMAX = S::kFixed ? TL : lmax_rt;
+  const int NNEU = S::kFixed ? TNEU : nneu_rt;
   const int NLM = (LMAX + 1) * (LMAX + 1) - 1;
   const int NDES = NR + NA * LMAX;
   const int RS = NDES + 1;  // LDS row of neuron mu: w1[mu][:] (padded)
@@ -107,12 +130,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
       const float r = r2 * rinv;
       if (r2 < rcr2) {
         float gr[kMaxR];
-        radial_basis_n(r, rcr_inv, NR, gr, nullptr);
+        radial_basis_n<kMaxR>(r, rcr_inv, NR, gr, nullptr);
 #pragma unroll
         for (int a = 0; a < kMaxR; ++a) qr[a] += wij * gr[a];
       }
       if (s < ca && r2 < rca2) {
-        radial_basis_n(r, rca_inv, NA, g, nullptr);
+        radial_basis_n<kMaxA>(r, rca_inv, NA, g, nullptr);
 #pragma unroll
         for (int a = 0; a < kMaxA; ++a) g[a] *= wij;
         harmonics(dx * rinv, dy * rinv, dz * rinv, yh);
@@ -212,7 +235,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
       float px = 0.f, py = 0.f, pz = 0.f;
       if (r2 < rcr2) {
         float g[kMaxR], dg[kMaxR];
-        radial_basis_n(r, rcr_inv, NR, g, dg);
+        radial_basis_n<kMaxR>(r, rcr_inv, NR, g, dg);
         float f = 0.f;
 #pragma unroll
         for (int a = 0; a < kMaxR; ++a)
@@ -223,7 +246,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
       }
       if (s < ca && r2 < rca2) {
         float g[kMaxA], dg[kMaxA];
-        radial_basis_n(r, rca_inv, NA, g, dg);
+        radial_basis_n<kMaxA>(r, rca_inv, NA, g, dg);
         const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
         const float xyz = xy * z;
         (void)xyz;
@@ -280,17 +303,44 @@ bool generic_supports(const nep_hyper& h) {
          h.l_max <= 4 && h.n_neuron <= kMaxNeu;
 }
 
-hipError_t launch_partials_generic(nep_ctx ctx, const double* pos) {
+namespace {
+
+template <int TR, int TA, int TL, int TNEU>
+void launch_shape(nep_ctx ctx, const double* pos) {
   const System& s = ctx->sys;
-  if (s.n == 0) return hipSuccess;
   const nep_hyper& h = ctx->hyper;
-  launch_kernel(ctx, true, true, k_partials_generic, dim3(blocks_for(s.n, kWaves)),
-                dim3(64 * kWaves), s.n, pos, (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr,
-                (const int*)s.cnt_a.ptr, (const int*)s.rev.ptr, s.box, (const float*)ctx->z.ptr,
-                h.n_max_radial + 1, h.n_max_angular + 1, h.l_max, h.n_neuron,
-                (float)h.rc_radial, (float)h.rc_angular,
+  launch_kernel(ctx, true, true, k_partials_generic<TR, TA, TL, TNEU>,
+                dim3(blocks_for(s.n, kWaves)), dim3(64 * kWaves), s.n, pos,
+                (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr, (const int*)s.cnt_a.ptr,
+                (const int*)s.rev.ptr, s.box, (const float*)ctx->z.ptr, h.n_max_radial + 1,
+                h.n_max_angular + 1, h.l_max, h.n_neuron, (float)h.rc_radial,
+                (float)h.rc_angular,
                 ctx->species_on() ? (const float*)ctx->species_w.ptr : (const float*)nullptr,
                 (const int*)s.perm.ptr, ctx->p.ptr, ctx->fown.ptr, ctx->U.ptr);
+}
+
+bool is_shape(const nep_hyper& h, int nr, int na, int lmax, int nneu) {
+  return h.n_max_radial + 1 == nr && h.n_max_angular + 1 == na && h.l_max == lmax &&
+         h.n_neuron == nneu;
+}
+
+}  // namespace
+
+// Compile-time sizes for the models of Table I (general Si, silicene, PbTe)
+// and the default model; every other size takes the runtime-sized kernel.
+hipError_t launch_partials_generic(nep_ctx ctx, const double* pos) {
+  if (ctx->sys.n == 0) return hipSuccess;
+  const nep_hyper& h = ctx->hyper;
+  if (is_shape(h, 16, 16, 4, 50))
+    launch_shape<16, 16, 4, 50>(ctx, pos);
+  else if (is_shape(h, 13, 13, 4, 40))
+    launch_shape<13, 13, 4, 40>(ctx, pos);
+  else if (is_shape(h, 13, 7, 4, 40))
+    launch_shape<13, 7, 4, 40>(ctx, pos);
+  else if (is_shape(h, 9, 5, 4, 30))
+    launch_shape<9, 5, 4, 30>(ctx, pos);
+  else
+    launch_shape<0, 0, 0, 0>(ctx, pos);
   return hipGetLastError();
 }
 

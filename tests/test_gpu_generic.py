@@ -89,6 +89,21 @@ def test_paper_model_md_matches_oracle():
     assert rel(nep.aos(v), v_ref) < TOL
 
 
+def test_runtime_sized_kernel_matches_oracle():
+    """A size without a compile-time instantiation (n_max 6/3, l_max 3,
+    20 neurons, r_c 5/4.5 A) runs the runtime-sized kernel."""
+    nep = nep_mod()
+    h = nep.hyper(5.0, 4.5, 6, 3, 3, 20)
+    oh = O.hyper(5.0, 4.5, 6, 3, 3, 20)
+    pos, box = I.parity_cell(2)
+    z = I.random_parameters(O.n_par(oh), 9, std=0.05)
+    vel = I.maxwell_boltzmann(len(pos), 300.0, 5)
+    out, _ = evaluate(h, z, pos, box, vel)
+    ref = O.nep_eval(oh, z, pos, box, vel=vel)
+    for k in ("U", "F", "W", "J"):
+        assert rel(out[k], ref[k]) < TOL, k
+
+
 def test_unsupported_sizes_are_refused():
     nep = nep_mod()
     ctx = nep.Context(0)
