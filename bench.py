@@ -40,13 +40,13 @@ PEAK_HBM_GBS = 8000.0
 #   every list slot (geometry in both loops)                   29
 #   every pair inside r_c^R (radial basis, sum, derivative)   227
 #   every pair inside r_c^A (basis, harmonics, moments,
-#                            partial force)                   1257
+#                            partial force from T_n, T_n' sums)  1177
 #   every atom (angular invariants, 30-neuron network with
-#               derivative, moment scaling)                   4246
-FLOP_SLOT, FLOP_RADIAL, FLOP_ANGULAR, FLOP_ATOM = 29, 227, 1257, 4246
+#               derivative, moment scaling and n = 0 fold)    4366
+FLOP_SLOT, FLOP_RADIAL, FLOP_ANGULAR, FLOP_ATOM = 29, 227, 1177, 4366
 # Algorithmic HBM bytes of the same kernel per atom: own position 24, counts 8,
-# list 4 per slot, partial force written 16 per slot, site energy 4.
-BYTE_ATOM, BYTE_SLOT = 36, 20
+# list 4 per slot, partial force written 12 per slot, site energy 4.
+BYTE_ATOM, BYTE_SLOT = 36, 16
 # Measured HBM traffic of one k_partials launch of this workload: rocprofv3
 # --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this bench (KiB per dispatch;
 # profiles/k_partials_nve64k_counters.md), each scaled by what the counter

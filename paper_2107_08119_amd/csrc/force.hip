@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, const int* __restrict__ rev,
     Box box, const double* __restrict__ boxes, const int* __restrict__ struct_of,
     const float* __restrict__ zpar, size_t zstride, float rc_r, float rc_a,
-    float4* __restrict__ pin, size_t pstride, float* __restrict__ fown, float* __restrict__ U) {
+    Partial3* __restrict__ pin, size_t pstride, float* __restrict__ fown, float* __restrict__ U) {
   constexpr int NLM = Model<NR, NA, LMAX>::kNLM;
   constexpr int NDES = Model<NR, NA, LMAX>::kNDES;
   __shared__ float4 sw4[NetRows<NDES, NNEU>::kFloat4];
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         else if (r2 < rcr2)
           mr |= 1ull << sl;
         else
-          pin[(size_t)(unsigned)dst] = make_float4(0.f, 0.f, 0.f, 0.f);
+          pin[(size_t)(unsigned)dst] = Partial3{0.f, 0.f, 0.f};
       }
     }
     smask[0][w][a] = ma;
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     fx += px;
     fy += py;
     fz += pz;
-    pin[(size_t)(unsigned)dst] = make_float4(px, py, pz, 0.f);
+    pin[(size_t)(unsigned)dst] = Partial3{px, py, pz};
   }
   fx = group_sum<L>(fx);
   fy = group_sum<L>(fy);
@@ -276,7 +276,7 @@ template <int L, int MODE>
 __global__ __launch_bounds__(kBlock) void k_gather(
     int n, const double* __restrict__ pos, double* __restrict__ vel,
     const uint32_t* __restrict__ nl, const int* __restrict__ cnt_r,
-    const float4* __restrict__ pin, const float* __restrict__ fown, const float* __restrict__ U,
+    const Partial3* __restrict__ pin, const float* __restrict__ fown, const float* __restrict__ U,
     Box box, float* __restrict__ U_out,
     float* __restrict__ F, float* __restrict__ W, float* __restrict__ J, double kick,
     double ekin_factor, double dt,
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(
   constexpr int B = 5;
   for (int s0 = lane; s0 < cr; s0 += B * L) {
     uint32_t e[B];
-    float4 p[B];
+    Partial3 p[B];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int s = s0 + u * L;
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(
       if (s0 + u * L >= cr) break;
       float dx, dy, dz;
       image_displacement(e[u], pj[u][0], pj[u][1], pj[u][2], xi, yi, zi, H, dx, dy, dz);
-      const float4 pji = p[u];
+      const Partial3 pji = p[u];
       f0 -= pji.x;
       f1 -= pji.y;
       f2 -= pji.z;
@@ -490,7 +490,8 @@ hipError_t launch_partials_population(nep_ctx ctx, nep_dataset ds, int n_pop, co
                 (const int*)ds->cnt_r.ptr, (const int*)ds->cnt_a.ptr, (const int*)ds->rev.ptr,
                 Box{}, (const double*)ds->boxes.ptr, (const int*)ds->struct_of.ptr, Z,
                 (size_t)ctx->n_par, (float)ctx->hyper.rc_radial, (float)ctx->hyper.rc_angular,
-                ds->pin.ptr, (size_t)ds->cap * ds->N, ds->fown.ptr, ds->U.ptr);
+                reinterpret_cast<Partial3*>(ds->pin.ptr), (size_t)ds->cap * ds->N, ds->fown.ptr,
+                ds->U.ptr);
   return hipGetLastError();
 }
 
@@ -503,7 +504,7 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
   const double ekin_factor = 0.5 * mass / kAccel;
   const uint32_t* nl = s.nl.ptr;
   const int* cnt = s.cnt_r.ptr;
-  const float4* p = ctx->p.ptr;
+  const Partial3* p = ctx->p.ptr;
   const float* fown = ctx->fown.ptr;
   const float* U = ctx->U.ptr;
   const bool per_atom = ctx->species_on() && ctx->have_masses;

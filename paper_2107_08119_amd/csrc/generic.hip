@@ -62,7 +62,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
     const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, const int* __restrict__ rev,
     Box box, const float* __restrict__ z, int nr_rt, int na_rt, int lmax_rt, int nneu_rt,
     float rc_r, float rc_a, const float* __restrict__ wsp, const int* __restrict__ perm,
-    float4* __restrict__ pin, float* __restrict__ fown, float* __restrict__ U) {
+    Partial3* __restrict__ pin, float* __restrict__ fown, float* __restrict__ U) {
   using S = Shape<TR, TA, TL, TNEU>;
   constexpr int kMaxR = S::MR, kMaxA = S::MA, kMaxLM = S::MLM, kMaxNeu = S::MNEU;
   constexpr int kMaxDes = S::MDES;
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
       fx += px;
       fy += py;
       fz += pz;
-      pin[(size_t)(unsigned)dst] = make_float4(px, py, pz, 0.f);
+      pin[(size_t)(unsigned)dst] = Partial3{px, py, pz};
     }
   }
   fx = wave_sum(fx);

@@ -81,6 +81,11 @@ constexpr double kAccel = 1.602176634e-19 / 1.66053906660e-27 * 1.0e-10;
 
 // An atom as a neighbour candidate, stored in cell order: float64 position,
 // index, and integer cell offsets of the raw position packed as 3 x int8.
+// One stored partial force dU_i/dr_ij: 12 bytes (one dwordx3 access).
+struct Partial3 {
+  float x, y, z;
+};
+
 struct alignas(32) CellRec {
   double x, y, z;
   int j;
@@ -195,7 +200,7 @@ struct nep_ctx_s {
   // system
   bool have_list = false;
   nep::System sys;
-  nep::DevBuf<float4> p;          // incoming partial forces dU_j/dr_ji at i's slots, [cap][n]
+  nep::DevBuf<nep::Partial3> p;   // incoming partial forces dU_j/dr_ji at i's slots, [cap][n]
   nep::DevBuf<float> fown;        // sum_j dU_i/dr_ij, [3][n]
   nep::DevBuf<float> U;           // [n]
   nep::DevBuf<float> F;           // [3][n]
@@ -255,7 +260,7 @@ struct nep_dataset_s {
   unsigned long long serial = 0;  // unique per dataset created by the process
   bool pop_tuned = false;
   // population workspace
-  nep::DevBuf<float4> pin;          // [pop][cap][N]
+  nep::DevBuf<float4> pin;          // [pop][cap][N] (dataset evaluation: Partial3 [cap][N])
   nep::DevBuf<float> fown;          // [pop][3][N]
   nep::DevBuf<float> U;             // [pop][N]
   nep::DevBuf<double> atom_terms;   // [10][N] per-atom U and W (forward)

@@ -123,7 +123,7 @@ template <int L>
 __global__ __launch_bounds__(kBlock) void k_ds_gather(
     int N, const double* __restrict__ pos, const double* __restrict__ boxes,
     const int* __restrict__ struct_of, const uint32_t* __restrict__ nl,
-    const int* __restrict__ cnt_r, const float4* __restrict__ pin, const float* __restrict__ fown,
+    const int* __restrict__ cnt_r, const Partial3* __restrict__ pin, const float* __restrict__ fown,
     const float* __restrict__ U, double* __restrict__ terms, float* __restrict__ F_out) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gid / L;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_ds_gather(
     int j;
     float dx, dy, dz;
     displacement(nl[idx], pos, N, xi, yi, zi, H, j, dx, dy, dz);
-    const float4 pji = pin[idx];
+    const Partial3 pji = pin[idx];
     f0 -= pji.x;
     f1 -= pji.y;
     f2 -= pji.z;
@@ -615,7 +615,7 @@ nep_status nep_dataset_compute(nep_ctx ctx, nep_dataset ds, const float* z_dev,
                     dim3(blocks_for((size_t)N * kLanes, kBlock)), dim3(kBlock), N,
                     (const double*)ds->pos.ptr, (const double*)ds->boxes.ptr,
                     (const int*)ds->struct_of.ptr, (const uint32_t*)ds->nl.ptr,
-                    (const int*)ds->cnt_r.ptr, (const float4*)ds->pin.ptr,
+                    (const int*)ds->cnt_r.ptr, reinterpret_cast<const Partial3*>(ds->pin.ptr),
                     (const float*)ds->fown.ptr, (const float*)ds->U.ptr, ds->atom_terms.ptr,
                     forces_dev);
       launch_kernel(ctx, false, true, k_ds_totals, dim3(S), dim3(kBlock), N,
