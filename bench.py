@@ -51,11 +51,15 @@ BYTE_ATOM, BYTE_SLOT = 36, 16
 # --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this bench (KiB per dispatch;
 # profiles/k_partials_nve64k_counters.md), each scaled by what the counter
 # reads for a plain device copy of known size (--copy-probe-mib: FETCH_SIZE
-# reports half the bytes read, WRITE_SIZE all bytes written).  They hold only
-# for the kernel sources they were taken with (hash below); otherwise the
-# bench reports traffic null.
-COUNTERS = {"sources_sha256": "5c040b4194cd7976eb6cf13bc9db2977a7e9676d986b8906c7214464766ea5b4",
-            "fetch_kib": 10969.35, "write_kib": 62912.61}
+# reports half the bytes read, WRITE_SIZE all bytes written), one entry per
+# tile shape (lanes per atom: FETCH_SIZE, WRITE_SIZE).  They hold only for the
+# kernel sources they were taken with (hash below); otherwise, or for a tile
+# without an entry, the bench reports traffic null.
+COUNTERS = {"sources_sha256": "92ac0d1eb485c0c2456766185be0d272cb157ea8adb5e81d0f1df29559a93fb5",
+            "kib": {
+                    "2": [12428.91, 59386.82],
+                    "4": [10758.63, 55187.87],
+                    "8": [10806.40, 65039.80]}}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ["force.hip", "nep_terms.h", "nep_device.h", "nep_internal.h"]
 
@@ -69,11 +73,15 @@ def kernel_sources_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per k_partials launch from the recorded counters, or None."""
+def measured_traffic(lanes):
+    """HBM bytes per k_partials launch of the chosen tile shape (lanes per atom)
+    from the recorded counters, or None."""
     if COUNTERS["sources_sha256"] is None or COUNTERS["sources_sha256"] != kernel_sources_hash():
         return None
-    return 1024.0 * (FETCH_SCALE * COUNTERS["fetch_kib"] + WRITE_SCALE * COUNTERS["write_kib"])
+    kib = COUNTERS["kib"].get(str(lanes))
+    if kib is None:
+        return None
+    return 1024.0 * (FETCH_SCALE * kib[0] + WRITE_SCALE * kib[1])
 
 
 def parse():
@@ -489,7 +497,7 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(lanes),
             "flop_per_atom": flop_atom,
             "avg_launch_us": avg_s * 1e6,
             "timing": "HIP events around 200 back-to-back launches on the library stream",
