@@ -490,8 +490,7 @@ hipError_t launch_partials_population(nep_ctx ctx, nep_dataset ds, int n_pop, co
                 (const int*)ds->cnt_r.ptr, (const int*)ds->cnt_a.ptr, (const int*)ds->rev.ptr,
                 Box{}, (const double*)ds->boxes.ptr, (const int*)ds->struct_of.ptr, Z,
                 (size_t)ctx->n_par, (float)ctx->hyper.rc_radial, (float)ctx->hyper.rc_angular,
-                reinterpret_cast<Partial3*>(ds->pin.ptr), (size_t)ds->cap * ds->N, ds->fown.ptr,
-                ds->U.ptr);
+                ds->pin.ptr, (size_t)ds->cap * ds->N, ds->fown.ptr, ds->U.ptr);
   return hipGetLastError();
 }
 

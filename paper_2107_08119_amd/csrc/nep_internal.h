@@ -260,7 +260,7 @@ struct nep_dataset_s {
   unsigned long long serial = 0;  // unique per dataset created by the process
   bool pop_tuned = false;
   // population workspace
-  nep::DevBuf<float4> pin;          // [pop][cap][N] (dataset evaluation: Partial3 [cap][N])
+  nep::DevBuf<nep::Partial3> pin;   // [pop][cap][N] partial forces
   nep::DevBuf<float> fown;          // [pop][3][N]
   nep::DevBuf<float> U;             // [pop][N]
   nep::DevBuf<double> atom_terms;   // [10][N] per-atom U and W (forward)

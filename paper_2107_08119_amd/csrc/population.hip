@@ -142,7 +142,7 @@ template <int L>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_pop_partials(
     int N, const float4* __restrict__ rec, const int* __restrict__ n_ang,
     const int* __restrict__ n_in, const float* __restrict__ desc, const float* __restrict__ Z,
-    int n_par, float rc_r, float rc_a, float4* __restrict__ pin, size_t pstride,
+    int n_par, float rc_r, float rc_a, Partial3* __restrict__ pin, size_t pstride,
     float* __restrict__ fown, float* __restrict__ U) {
   __shared__ float4 rows[NetRows<NDES, NNEU>::kFloat4];
   __shared__ float b2;
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     fx += px;
     fy += py;
     fz += pz;
-    pin[(size_t)(unsigned)__float_as_int(p.w)] = make_float4(px, py, pz, 0.f);
+    pin[(size_t)(unsigned)__float_as_int(p.w)] = Partial3{px, py, pz};
   }
   fx = group_sum<L>(fx);
   fy = group_sum<L>(fy);
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 template <int L>
 __global__ __launch_bounds__(kBlock) void k_pop_struct(
     int N, int S, const int* __restrict__ off, const float4* __restrict__ rec,
-    const int* __restrict__ n_in, const float4* __restrict__ pin, size_t pstride,
+    const int* __restrict__ n_in, const Partial3* __restrict__ pin, size_t pstride,
     const float* __restrict__ fown, const float* __restrict__ U, const double* __restrict__ f_tar,
     const double* __restrict__ e_tar, const double* __restrict__ w_tar,
     const int* __restrict__ has_v, double* __restrict__ sq) {
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_pop_struct(
     for (int t = lane; t < ni; t += L) {
       const size_t idx = (size_t)t * N + i;
       const float4 r = rec[idx];
-      const float4 p = pin[idx];
+      const Partial3 p = pin[idx];
       f0 -= p.x;
       f1 -= p.y;
       f2 -= p.z;
@@ -307,7 +307,7 @@ void launch_pop(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z, bool fir
                 ds->pin.ptr, pstride, ds->fown.ptr, ds->U.ptr);
   launch_kernel(ctx, false, false, k_pop_struct<4>, dim3(n_pop, S), dim3(kBlock), N, S,
                 (const int*)ds->off.ptr, (const float4*)ds->prec.ptr, (const int*)ds->pn_in.ptr,
-                (const float4*)ds->pin.ptr, pstride, (const float*)ds->fown.ptr,
+                (const Partial3*)ds->pin.ptr, pstride, (const float*)ds->fown.ptr,
                 (const float*)ds->U.ptr, (const double*)ds->f_tar.ptr,
                 (const double*)ds->e_tar.ptr, (const double*)ds->w_tar.ptr,
                 (const int*)ds->has_v.ptr, ds->struct_sq.ptr);

@@ -615,7 +615,7 @@ nep_status nep_dataset_compute(nep_ctx ctx, nep_dataset ds, const float* z_dev,
                     dim3(blocks_for((size_t)N * kLanes, kBlock)), dim3(kBlock), N,
                     (const double*)ds->pos.ptr, (const double*)ds->boxes.ptr,
                     (const int*)ds->struct_of.ptr, (const uint32_t*)ds->nl.ptr,
-                    (const int*)ds->cnt_r.ptr, reinterpret_cast<const Partial3*>(ds->pin.ptr),
+                    (const int*)ds->cnt_r.ptr, (const Partial3*)ds->pin.ptr,
                     (const float*)ds->fown.ptr, (const float*)ds->U.ptr, ds->atom_terms.ptr,
                     forces_dev);
       launch_kernel(ctx, false, true, k_ds_totals, dim3(S), dim3(kBlock), N,
