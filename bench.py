@@ -182,34 +182,52 @@ def spectral_rate(ctx, nep, torch, p, v, n, box, dt, rebuild, mass, fe, n_lags=2
 
 
 def paper_model_rate(nep, I, torch, steps=100):
-    """The paper's speed test (Sec. III D) in kind: 8000-atom bulk Si, 100 MD
-    steps, with the general-Si model sizes of Sec. III B (r_c 5/5 A, n_max
-    15/15, l_max 4, 50 neurons: an 80-50-1 network, 4101 parameters), random
-    parameters (the work does not depend on their values); NVE, no thermostat."""
-    h = nep.hyper(5.0, 5.0, 15, 15, 4, 50)
-    z = I.random_parameters(nep.num_params(h), seed=1, std=0.02)
+    """The paper's speed test (Sec. III D) in kind, for the three models of
+    Table I: 100 MD steps (NVE here) of bulk Si (8000 atoms, 80-50-1:
+    r_c 5/5 A, n_max 15/15, 50 neurons), 2D silicene (6000 atoms, 65-40-1:
+    r_c 5.5/5.5 A, n_max 12/12, 40 neurons) and bulk PbTe (8000 atoms,
+    41-40-1: r_c 8/4 A, n_max 12/6, 40 neurons, sqrt(Z_i Z_j) weights and
+    per-atom masses); l_max 4 throughout, random parameters (the work does
+    not depend on their values)."""
+    cases = []
     pos, box = I.diamond_supercell(10, 10, 10)
-    vel = I.maxwell_boltzmann(len(pos), 300.0, seed=2)
-    ctx = nep.Context(0)
-    ctx.load_params(h, z)
-    p, v = nep.soa(pos), nep.soa(vel)
-    ctx.build_neighbors(p, box, skin=0.5, max_neighbors=96)
-    ctx.md_step(10, 1.0, 10, I.MASS_SI, p, v)
-    ctx.synchronize()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.md_step(steps, 1.0, 10, I.MASS_SI, p, v)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    ctx.synchronize()
-    ms = nep.time_partials(ctx, p, reps=50)
-    rate = len(pos) * steps / t
-    return {"workload": "8000-atom Si diamond (10x10x10 cells), NEP 80-50-1 (r_c 5/5 A, "
-                        "n_max 15/15, l_max 4, 50 neurons), %d NVE steps, dt 1 fs, rebuild every "
-                        "10 steps, one-wave-per-atom kernel" % steps,
-            "atom_steps_per_s": rate, "ms_per_step": t / steps * 1e3, "k_partials_us": ms * 1e3,
-            "paper_v100_atom_steps_per_s": ">1e7 (context: another GPU)",
-            "ratio_to_1e7": rate / 1e7}
+    cases.append(("si_80_50_1_8000", nep.hyper(5.0, 5.0, 15, 15, 4, 50), pos, box, None,
+                  I.MASS_SI, 0.02))
+    pos, box = I.silicene_sheet(50, 30)
+    cases.append(("silicene_65_40_1_6000", nep.hyper(5.5, 5.5, 12, 12, 4, 40), pos, box, None,
+                  I.MASS_SI, 0.02))
+    pos, box, Z, masses = I.rocksalt_supercell(10, 10, 10)
+    cases.append(("pbte_41_40_1_8000", nep.hyper(8.0, 4.0, 12, 6, 4, 40), pos, box, (Z, masses),
+                  150.0, 0.05))
+    out = {"workload": "the paper's speed test in kind: %d NVE steps, dt 1 fs, rebuild every 10 "
+                       "steps, for the three models of Table I (one-wave-per-atom kernel with "
+                       "each model's sizes compiled in)" % steps,
+           "paper_v100_atom_steps_per_s": ">1e7 for each (context: another GPU)"}
+    for name, h, pos, box, species, mass, std in cases:
+        z = I.random_parameters(nep.num_params(h), seed=1, std=std)
+        if species is not None:
+            z[:h.n_neuron * nep.num_descriptors(h)] *= np.float32(1.0 / 300.0)
+        vel = I.maxwell_boltzmann(len(pos), 300.0, seed=2,
+                                  mass=mass if species is None else species[1])
+        ctx = nep.Context(0)
+        ctx.load_params(h, z)
+        p, v = nep.soa(pos), nep.soa(vel)
+        ctx.build_neighbors(p, box, skin=0.5, max_neighbors=128)
+        if species is not None:
+            ctx.set_species(species[0], species[1])
+        ctx.md_step(10, 1.0, 10, mass, p, v)
+        ctx.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.md_step(steps, 1.0, 10, mass, p, v)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ctx.synchronize()
+        ms = nep.time_partials(ctx, p, reps=50)
+        rate = len(pos) * steps / t
+        out[name] = {"atoms": len(pos), "atom_steps_per_s": rate, "ms_per_step": t / steps * 1e3,
+                     "k_partials_us": ms * 1e3, "ratio_to_1e7": rate / 1e7}
+    return out
 
 
 def pbte_rate(nep, I, torch, steps=100):
@@ -526,7 +544,7 @@ def main():
         "mean_Jx_eV_A_per_fs": float(th_h[:k_h, 2].mean().item())}
     line["hnemd_spectral_64k"] = spectral_rate(ctx, nep, torch, p, v, n, box, dt, rebuild, mass,
                                                fe)
-    line["paper_model_8k"] = paper_model_rate(nep, I, torch)
+    line["paper_models"] = paper_model_rate(nep, I, torch)
     line["autograd_256"] = autograd_rate(nep, I, torch, z)
     line["pbte_64k"] = pbte_rate(nep, I, torch)
     if not args.no_disordered:

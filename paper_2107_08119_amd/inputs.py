@@ -86,6 +86,30 @@ def rocksalt_supercell(n1: int, n2: int, n3: int, a: float = PBTE_A):
     return frac * a, box, Z, masses
 
 
+# Buckled honeycomb silicene (2D): in-plane lattice constant and buckling
+# height are standard literature values, not the paper's.
+SILICENE_A = 3.86  # Angstrom
+SILICENE_BUCKLE = 0.44  # Angstrom
+
+
+def silicene_sheet(n1: int, n2: int, a: float = SILICENE_A, buckle: float = SILICENE_BUCKLE,
+                   height: float = 20.0):
+    """Rectangular 4-atom cells (a x sqrt(3) a) of buckled silicene repeated
+    n1 x n2 in the plane, one sheet in a box of the given height (vacuum
+    along z, periodic in all three directions)."""
+    r3 = math.sqrt(3.0)
+    d = a / r3  # in-plane nearest-neighbour distance
+    basis = np.array([[0.0, 0.0, 0.5 * buckle],
+                      [0.5 * a, 0.5 * d, -0.5 * buckle],
+                      [0.5 * a, 0.5 * r3 * a, 0.5 * buckle],
+                      [0.0, 0.5 * r3 * a + 0.5 * d, -0.5 * buckle]])
+    cells = np.array([[i * a, j * r3 * a, 0.0] for i in range(n1) for j in range(n2)])
+    pos = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3)
+    pos[:, 2] += 0.5 * height
+    box = np.diag([n1 * a, n2 * r3 * a, height]).astype(np.float64)
+    return pos, box
+
+
 def wrap_positions(pos: np.ndarray, box: np.ndarray) -> np.ndarray:
     """Map positions into the cell spanned by the box rows (fractional in [0,1))."""
     frac = pos @ np.linalg.inv(box)

@@ -89,6 +89,25 @@ def test_paper_model_md_matches_oracle():
     assert rel(nep.aos(v), v_ref) < TOL
 
 
+def test_silicene_model_matches_oracle():
+    """The 2D-silicene model of Table I (r_c 5.5/5.5 A, n_max 12/12, l_max 4,
+    40 neurons: 65-40-1, 2681 parameters) on a jittered buckled sheet with
+    vacuum along z."""
+    nep = nep_mod()
+    h = nep.hyper(5.5, 5.5, 12, 12, 4, 40)
+    oh = O.hyper(5.5, 5.5, 12, 12, 4, 40)
+    assert O.n_par(oh) == 2681
+    pos, box = I.silicene_sheet(6, 4)
+    rng = np.random.default_rng(14)
+    pos = pos + rng.normal(0.0, 0.05, pos.shape)
+    z = I.random_parameters(2681, 10, std=0.05)
+    vel = I.maxwell_boltzmann(len(pos), 300.0, 6)
+    out, _ = evaluate(h, z, pos, box, vel)
+    ref = O.nep_eval(oh, z, pos, box, vel=vel)
+    for k in ("U", "F", "W", "J"):
+        assert rel(out[k], ref[k]) < TOL, k
+
+
 def test_runtime_sized_kernel_matches_oracle():
     """A size without a compile-time instantiation (n_max 6/3, l_max 3,
     20 neurons, r_c 5/4.5 A) runs the runtime-sized kernel."""
