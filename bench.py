@@ -38,12 +38,13 @@ PEAK_HBM_GBS = 8000.0
 # counted from its arithmetic (a fused multiply-add counts 2, a square root,
 # reciprocal or exponential 1):
 #   every list slot (geometry in both loops)                   29
-#   every pair inside r_c^R (radial basis, sum, derivative)   227
+#   every pair inside r_c^R (f_c T_n sums, partial force from
+#                            T_n, T_n' sums)                   181
 #   every pair inside r_c^A (basis, harmonics, moments,
 #                            partial force from T_n, T_n' sums)  1177
 #   every atom (angular invariants, 30-neuron network with
-#               derivative, moment scaling and n = 0 fold)    4366
-FLOP_SLOT, FLOP_RADIAL, FLOP_ANGULAR, FLOP_ATOM = 29, 227, 1177, 4366
+#               derivative, moment scaling, n = 0 folds)      4390
+FLOP_SLOT, FLOP_RADIAL, FLOP_ANGULAR, FLOP_ATOM = 29, 181, 1177, 4390
 # Algorithmic HBM bytes of the same kernel per atom: own position 24, counts 8,
 # list 4 per slot, partial force written 12 per slot, site energy 4.
 BYTE_ATOM, BYTE_SLOT = 36, 16

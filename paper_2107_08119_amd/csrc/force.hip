@@ -198,6 +198,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
 #pragma unroll
   for (int a = 0; a < NR; ++a) q[a] = group_sum<L>(q[a]);
+  radial_finish<NR>(q);
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -209,6 +210,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   network<NDES, NNEU, L>(q, sw4, sb2, lane, dq, u);
   if (active && lane == 0) U[i] = u;
   angular_coefficients<NR, NA, LMAX>(dq, c);
+  const float dqs = radial_dq_sum<NR>(dq);
 
   // partial forces p_ij = dU_i/dr_ij for this lane's pairs
   float fx = 0.f, fy = 0.f, fz = 0.f;
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     float dx, dy, dz;
     pair(k, dx, dy, dz, dst, ang, rad);
     float px, py, pz;
-    pair_force<NR, NA, LMAX>(dx, dy, dz, rad, ang, rcr_inv, rca_inv, dq, c, px, py, pz);
+    pair_force<NR, NA, LMAX>(dx, dy, dz, rad, ang, rcr_inv, rca_inv, dq, dqs, c, px, py, pz);
     fx += px;
     fy += py;
     fz += pz;

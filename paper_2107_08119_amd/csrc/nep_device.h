@@ -95,6 +95,22 @@ __device__ __forceinline__ void radial_basis(float r, float rc_inv, float* g, fl
   }
 }
 
+// f_c(r) and T_n(x) for n < NB (T_0 = 1), the factors of g_n = f_c (T_n + 1)/2.
+template <int NB>
+__device__ __forceinline__ void chebyshev_values(float r, float rc_inv, float& fc, float* T) {
+  const float t = r * rc_inv;
+  float sy, cy;
+  sincos_quarter_turn(kPi * (t - 0.5f), sy, cy);
+  (void)cy;
+  fc = 0.5f * (1.f - sy);
+  const float tm1 = t - 1.f;
+  const float x = 2.f * tm1 * tm1 - 1.f;
+  T[0] = 1.f;
+  if constexpr (NB > 1) T[1] = x;
+#pragma unroll
+  for (int n = 2; n < NB; ++n) T[n] = 2.f * x * T[n - 1] - T[n - 2];
+}
+
 // The pieces of g_n and g_n' without the products: T_n(x), dT_n/dx = n U_{n-1}(x)
 // for n = 1..NB-1 (entry 0 unused), f_c, f_c' and dx/dr, so that
 //   g_n = f_c (T_n + 1) / 2,  g_n' = f_c' (T_n + 1) / 2 + f_c (dx/dr) T_n' / 2.

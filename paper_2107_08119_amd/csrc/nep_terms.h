@@ -28,8 +28,10 @@ struct Model {
   static constexpr int kNDES = NR + NA * LMAX;
 };
 
-// Add pair (dx, dy, dz) to the radial sums q[0..NR) (when rad) and to the
-// angular moments c[NA][NLM] (when ang).
+// Add pair (dx, dy, dz) to the radial sums (when rad) and to the angular
+// moments c[NA][NLM] (when ang).  The radial sums are kept as
+// R_n = sum_j f_c T_n (R_0 = sum_j f_c); radial_finish turns them into
+// q_n = sum_j g_n = (R_n + R_0) / 2 once they are complete.
 template <int NR, int NA, int LMAX>
 __device__ __forceinline__ void pair_descriptor(float dx, float dy, float dz, bool rad, bool ang,
                                                 float rcr_inv, float rca_inv, float* q,
@@ -39,10 +41,11 @@ __device__ __forceinline__ void pair_descriptor(float dx, float dy, float dz, bo
   const float rinv = __builtin_amdgcn_rsqf(r2);
   const float r = r2 * rinv;
   if (rad) {
-    float g[NR];
-    radial_basis<NR, false>(r, rcr_inv, g, nullptr);
+    float fc, T[NR];
+    chebyshev_values<NR>(r, rcr_inv, fc, T);
+    q[0] += fc;
 #pragma unroll
-    for (int a = 0; a < NR; ++a) q[a] += g[a];
+    for (int a = 1; a < NR; ++a) q[a] += fc * T[a];
   }
   if (ang) {
     float g[NA];
@@ -59,6 +62,23 @@ __device__ __forceinline__ void pair_descriptor(float dx, float dy, float dz, bo
     NEP_YLM_TABLE(NEP_ACC)
 #undef NEP_ACC
   }
+}
+
+// q_n = (R_n + R_0) / 2 from the complete sums R_n of pair_descriptor.
+template <int NR>
+__device__ __forceinline__ void radial_finish(float* q) {
+#pragma unroll
+  for (int a = 1; a < NR; ++a) q[a] = 0.5f * (q[a] + q[0]);
+}
+
+// sum_n dU/dq_n over the radial components, the constant part of
+// sum_n dU/dq_n g_n' (pair_force's dq_sum).
+template <int NR>
+__device__ __forceinline__ float radial_dq_sum(const float* dq) {
+  float s = 0.f;
+#pragma unroll
+  for (int a = 0; a < NR; ++a) s += dq[a];
+  return s;
 }
 
 // The 24 harmonics Yhat_lm (l = 1..4) of the unit vector (x, y, z).
@@ -175,10 +195,14 @@ __device__ __forceinline__ void angular_coefficients(const float* dq,
 }
 
 // Partial force dU_i/dr_ij of pair (dx, dy, dz) from dq (radial part, when
-// rad) and the angular coefficients a as left by angular_coefficients (when ang).
+// rad; dq_sum = radial_dq_sum(dq)) and the angular coefficients a as left by
+// angular_coefficients (when ang).  Radial part: sum_n dU/dq_n g_n' =
+// f_c' (S_1 + dq_sum) / 2 + f_c (dx/dr) S_2 / 2 with S_1 = sum_n dU/dq_n T_n
+// and S_2 = sum_n dU/dq_n T_n'.
 template <int NR, int NA, int LMAX>
 __device__ __forceinline__ void pair_force(float dx, float dy, float dz, bool rad, bool ang,
                                            float rcr_inv, float rca_inv, const float* dq,
+                                           float dq_sum,
                                            const float (&c)[NA][Model<NR, NA, LMAX>::kNLM],
                                            float& px, float& py, float& pz) {
   constexpr int NLM = Model<NR, NA, LMAX>::kNLM;
@@ -190,11 +214,15 @@ __device__ __forceinline__ void pair_force(float dx, float dy, float dz, bool ra
   py = 0.f;
   pz = 0.f;
   if (rad) {
-    float g[NR], dg[NR];
-    radial_basis<NR, true>(r, rcr_inv, g, dg);
-    float f = 0.f;
+    float fc, dfc, dxdr, T[NR], dT[NR];
+    chebyshev_terms<NR>(r, rcr_inv, fc, dfc, dxdr, T, dT);
+    float s1 = dq[0], s2 = 0.f;
 #pragma unroll
-    for (int a = 0; a < NR; ++a) f += dq[a] * dg[a];
+    for (int a = 1; a < NR; ++a) {
+      s1 += dq[a] * T[a];
+      s2 += dq[a] * dT[a];
+    }
+    const float f = 0.5f * (dfc * (s1 + dq_sum) + fc * dxdr * s2);
     px += f * x;
     py += f * y;
     pz += f * z;

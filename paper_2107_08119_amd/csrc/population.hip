@@ -114,6 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_ds_descriptors(int N, const float4* 
   }
 #pragma unroll
   for (int a = 0; a < NR; ++a) q[a] = group_sum<L>(q[a]);
+  radial_finish<NR>(q);
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -187,11 +188,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   network<NDES, NNEU, L>(q, rows, b2, lane, dq, u);
   if (active && lane == 0) U[i] = u;
   angular_coefficients<NR, NA, LMAX>(dq, c);
+  const float dqs = radial_dq_sum<NR>(dq);
   float fx = 0.f, fy = 0.f, fz = 0.f;
   for (int t = lane; t < ni; t += L) {
     const float4 p = rec[(size_t)t * N + i];
     float px, py, pz;
-    pair_force<NR, NA, LMAX>(p.x, p.y, p.z, true, t < na, rcr_inv, rca_inv, dq, c, px, py, pz);
+    pair_force<NR, NA, LMAX>(p.x, p.y, p.z, true, t < na, rcr_inv, rca_inv, dq, dqs, c, px, py,
+                             pz);
     fx += px;
     fy += py;
     fz += pz;
