@@ -35,26 +35,27 @@ KB = 1.380649e-23  # J/K
 KAPPA_UNIT = EV / 1.0e-15 * 1.0e10 * 1.0e-3
 
 
-def virial_velocity_correlation(W, v, n_lags):
+def virial_velocity_correlation(W, v, n_lags, lags=None):
     """K[k, mu] = mean over origins t0 = 0 .. S-1-k of
     sum_i sum_nu W[t0, i, mu, nu] v[t0 + k, i, nu], for k = 0 .. n_lags-1.
 
     W: [S, N, 3, 3] per-atom virials, v: [S, N, 3] velocities at the S
-    sample times.  Lags with no origin are zero.  Returns (K, counts)."""
-    W = np.asarray(W, np.float64)
-    v = np.asarray(v, np.float64)
+    sample times (float32 inputs are widened one sample at a time).  Lags
+    with no origin are zero.  With `lags` given, only those rows are
+    computed (the others stay zero).  Returns (K, counts)."""
     S = W.shape[0]
     K = np.zeros((n_lags, 3))
     counts = np.zeros(n_lags, dtype=np.int64)
+    want = np.zeros(n_lags, dtype=bool)
+    want[list(range(n_lags)) if lags is None else list(lags)] = True
     for t in range(S):  # a sample at time t closes lag k with the origin t - k
+        vt = np.asarray(v[t], np.float64)
         for k in range(min(t + 1, n_lags)):
+            if not want[k]:
+                continue
             o = t - k
-            acc = np.zeros(3)
-            for i in range(W.shape[1]):
-                for mu in range(3):
-                    for nu in range(3):
-                        acc[mu] += W[o, i, mu, nu] * v[t, i, nu]
-            K[k] += acc
+            # sum over atoms i and components nu of W[o, i, mu, nu] v[t, i, nu]
+            K[k] += np.einsum("inm,im->n", np.asarray(W[o], np.float64), vt)
             counts[k] += 1
     nz = counts > 0
     K[nz] /= counts[nz, None]

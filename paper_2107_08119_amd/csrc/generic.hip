@@ -4,13 +4,15 @@
 //
 // The terms are those of nep_terms.h (factorised angular descriptor, network,
 // partial force of Sec. II D), with the per-atom sums done by the wave:
-//   * radial q_n: each lane adds its pairs, then a fixed-order wave sum;
+//   * radial q_n: each lane adds f_c T_n of its pairs, then a fixed-order
+//     wave sum gives R_n and q_n = (R_n + R_0)/2 (g_n = f_c (T_n + 1)/2);
 //   * angular moments c_nlm = sum_j g_n(r_ij) Yhat_lm(u_ij): the lanes write
 //     their pairs' g_n and Yhat_lm to LDS and lane k accumulates outputs
 //     (n, lm) = k, k + 64, ... over the pairs in index order;
 //   * network: lane mu evaluates neuron mu; dU/dq_v is formed by lane v from
 //     the neurons' w2 sech^2 in LDS;
-//   * partial forces: lane p evaluates pair p from dU/dq and a_nlm in LDS.
+//   * partial forces: lane p evaluates pair p from dU/dq and a_nlm in LDS,
+//     as sums over T_n and T_n' (the n = 0 terms folded per atom).
 // Every sum has a fixed order, so results are reproducible bit for bit.
 #include "nep_terms.h"
 
@@ -128,11 +130,13 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
       const float r2 = pair_r2(dx, dy, dz);
       const float rinv = __builtin_amdgcn_rsqf(r2);
       const float r = r2 * rinv;
-      if (r2 < rcr2) {
-        float gr[kMaxR];
-        radial_basis_n<kMaxR>(r, rcr_inv, NR, gr, nullptr);
+      if (r2 < rcr2) {  // entries a >= NR are never read
+        float fc, T[kMaxR];
+        chebyshev_values<kMaxR>(r, rcr_inv, fc, T);
+        const float wf = wij * fc;
+        qr[0] += wf;
 #pragma unroll
-        for (int a = 0; a < kMaxR; ++a) qr[a] += wij * gr[a];
+        for (int a = 1; a < kMaxR; ++a) qr[a] += wf * T[a];
       }
       if (s < ca && r2 < rca2) {
         radial_basis_n<kMaxA>(r, rca_inv, NA, g, nullptr);
@@ -160,11 +164,13 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
     }
     wave_lds_sync();
   }
-  // radial components and angular moments to LDS
+  // radial components q_0 = R_0, q_n = (R_n + R_0)/2, and angular moments to LDS
+  const float r0 = wave_sum(qr[0]);
+  if (lane == 0) s_q[wave][0] = r0;
 #pragma unroll
-  for (int a = 0; a < kMaxR; ++a) {
+  for (int a = 1; a < kMaxR; ++a) {
     const float v = wave_sum(qr[a]);
-    if (lane == 0 && a < NR) s_q[wave][a] = v;
+    if (lane == 0 && a < NR) s_q[wave][a] = 0.5f * (v + r0);
   }
 #pragma unroll
   for (int r = 0; r < (kMaxA * kMaxLM + 63) / 64; ++r) {
@@ -217,6 +223,17 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
     }
   }
   wave_lds_sync();
+  // row 0 becomes a'_0lm = 2 a_0lm + sum_{n>=1} a_nlm, the constant part of
+  // sum_n a_nlm (T_n + 1)
+  if (lane < NLM) {
+    float s0 = 2.f * s_c[wave][lane];
+    for (int a = 1; a < NA; ++a) s0 += s_c[wave][a * NLM + lane];
+    s_c[wave][lane] = s0;
+  }
+  // sum_n dU/dq_n over the radial components
+  float dqs = 0.f;
+  for (int a = 0; a < NR; ++a) dqs += s_dq[wave][a];
+  wave_lds_sync();
 
   // ---- partial forces: lane p is pair p
   float fx = 0.f, fy = 0.f, fz = 0.f;
@@ -234,39 +251,53 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
       const float x = dx * rinv, y = dy * rinv, z = dz * rinv;
       float px = 0.f, py = 0.f, pz = 0.f;
       if (r2 < rcr2) {
-        float g[kMaxR], dg[kMaxR];
-        radial_basis_n<kMaxR>(r, rcr_inv, NR, g, dg);
-        float f = 0.f;
+        // sum_n dU/dq_n g_n' = f_c' (S_1 + sum_n dU/dq_n)/2 + f_c (dx/dr) S_2/2
+        float fc, dfc, dxdr, T[kMaxR], dT[kMaxR];
+        chebyshev_terms<kMaxR>(r, rcr_inv, fc, dfc, dxdr, T, dT);
+        float s1 = s_dq[wave][0], s2 = 0.f;
 #pragma unroll
-        for (int a = 0; a < kMaxR; ++a)
-          if (a < NR) f += s_dq[wave][a] * dg[a];
+        for (int a = 1; a < kMaxR; ++a)
+          if (a < NR) {
+            s1 += s_dq[wave][a] * T[a];
+            s2 += s_dq[wave][a] * dT[a];
+          }
+        const float f = 0.5f * (dfc * (s1 + dqs) + fc * dxdr * s2);
         px += f * x;
         py += f * y;
         pz += f * z;
       }
       if (s < ca && r2 < rca2) {
-        float g[kMaxA], dg[kMaxA];
-        radial_basis_n<kMaxA>(r, rca_inv, NA, g, dg);
+        float fc, dfc, dxdr, T[kMaxA], dT[kMaxA];
+        chebyshev_terms<kMaxA>(r, rca_inv, fc, dfc, dxdr, T, dT);
         const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
         const float xyz = xy * z;
         (void)xyz;
-        float sb = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        // per lm: At = a'_0 + sum_{n>=1} a_n T_n, D = sum_{n>=1} a_n T_n';
+        // A = f_c At/2 multiplies the harmonic's gradient and
+        // B = f_c' At/2 + f_c (dx/dr) D/2 the harmonic
+        float st = 0.f, sd = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
         const float* aw = s_c[wave];
 #define NEP_PF(idx, YV, GX, GY, GZ)                     \
   if ((idx) < NLM) {                                    \
-    float A = 0.f, B = 0.f;                             \
-    for (int a = 0; a < NA; ++a) {                      \
+    float At = aw[(idx)], D = 0.f;                      \
+    for (int a = 1; a < NA; ++a) {                      \
       const float c = aw[a * NLM + (idx)];              \
-      A += c * g[a];                                    \
-      B += c * dg[a];                                   \
+      At += c * T[a];                                   \
+      D += c * dT[a];                                   \
     }                                                   \
-    sb += B * (YV);                                     \
-    gx += A * (GX);                                     \
-    gy += A * (GY);                                     \
-    gz += A * (GZ);                                     \
+    st += At * (YV);                                    \
+    sd += D * (YV);                                     \
+    gx += At * (GX);                                    \
+    gy += At * (GY);                                    \
+    gz += At * (GZ);                                    \
   }
         NEP_YLM_TABLE(NEP_PF)
 #undef NEP_PF
+        const float hf = 0.5f * fc;
+        const float sb = 0.5f * (dfc * st + fc * dxdr * sd);
+        gx *= hf;
+        gy *= hf;
+        gz *= hf;
         const float ug = x * gx + y * gy + z * gz;
         px += sb * x + (gx - x * ug) * rinv;
         py += sb * y + (gy - y * ug) * rinv;

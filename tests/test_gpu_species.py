@@ -141,3 +141,22 @@ def test_species_calls_and_errors():
     ref_one = O.nep_eval(oh, z, pos, box)["U"]
     assert rel(u_sp, ref_sp) < TOL
     assert rel(u_one, ref_one) < TOL
+
+
+def test_pbte_full_size_64k_sampled():
+    """The 64,000-atom PbTe system of the benchmark (20x20x20 rock-salt cells,
+    41-40-1 model with the benchmark's parameters, 128-slot lists, cell-list
+    build), jittered by N(0, 0.05^2) A: 300 sampled atoms against the oracle."""
+    nep = nep_mod()
+    h, oh = pbte_hyper()
+    pos, box, Z, masses = I.rocksalt_supercell(20, 20, 20)
+    rng = np.random.default_rng(11)
+    pos = I.wrap_positions(pos + rng.normal(0.0, 0.05, pos.shape), box)
+    vel = I.maxwell_boltzmann(len(pos), 300.0, 2, masses)
+    z = damp_input_weights(I.random_parameters(nep.num_params(h), 1, std=0.05), 40, 41,
+                           1.0 / 300.0)
+    out, _ = evaluate(h, z, pos, box, vel, Z)
+    sel = np.sort(rng.choice(len(pos), 300, replace=False))
+    ref = O.nep_eval(oh, z, pos, box, vel=vel, Z=Z, sel=sel)
+    for k in ("U", "F", "W", "J"):
+        assert rel(out[k][sel], ref[k]) < TOL, k

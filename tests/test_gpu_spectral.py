@@ -103,3 +103,38 @@ def test_correlation_errors():
         corr.spectrum(1.0, 300.0, 1.0e3, 1e-4, [1.0])
     K, n = corr.get()
     assert n == 0 and not K.any()
+
+
+def test_full_size_ring_sampled_lags():
+    """The benchmark's configuration: HNEMD of the 64,000-atom diamond with
+    F_e = 1e-4 1/A along x, W_i and v_i sampled every 2 steps into a
+    250-lag ring, 256 samples (the ring wraps); lags 0, 1, 7, 128 and 249
+    against the oracle over the recorded series."""
+    import torch
+    nep = nep_mod()
+    pos, box = I.nve_cell()
+    n = len(pos)
+    vel = I.maxwell_boltzmann(n, 300.0, 2)
+    z = I.random_parameters(931, 1, std=0.1)
+    ctx = nep.Context(0)
+    ctx.load_params(nep.hyper(), z)
+    p, v = nep.soa(pos), nep.soa(vel)
+    ctx.build_neighbors(p, box, skin=0.5, max_neighbors=64)
+    W = torch.empty((9, n), dtype=torch.float32, device="cuda")
+    lags, samples = 250, 256
+    corr = nep.Correlation(ctx, n, lags)
+    Ws = np.empty((samples, n, 3, 3), np.float32)
+    vs = np.empty((samples, n, 3), np.float64)
+    for t in range(samples):
+        ctx.md_step(2, 1.0, 10, I.MASS_SI, p, v, W=W, fe=(1e-4, 0.0, 0.0))
+        corr.sample(W, v)
+        Ws[t] = W.cpu().numpy().T.reshape(n, 3, 3)
+        vs[t] = v.cpu().numpy().T
+    K, n_s = corr.get()
+    corr.close()
+    assert n_s == samples
+    pick = [0, 1, 7, 128, 249]
+    K_ref, counts = SP.virial_velocity_correlation(Ws, vs, lags, lags=pick)
+    assert counts[pick].tolist() == [samples - k for k in pick]
+    for k in pick:
+        assert rel(K[k], K_ref[k]) < 1e-9, k
