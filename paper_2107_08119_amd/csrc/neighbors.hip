@@ -175,7 +175,7 @@ __global__ void k_permute(int n, const int* __restrict__ members, const double* 
                           int* __restrict__ wrap_out, const int* __restrict__ perm,
                           int* __restrict__ perm_out, const int* __restrict__ cell_of,
                           int* __restrict__ cell_out, CellRec* __restrict__ rec,
-                          int* __restrict__ flags) {
+                          int* __restrict__ iperm_out, int* __restrict__ flags) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int o = members[k];
@@ -195,7 +195,9 @@ __global__ void k_permute(int n, const int* __restrict__ members, const double* 
   wrap_out[k] = w0;
   wrap_out[n + k] = w1;
   wrap_out[2 * n + k] = w2;
-  perm_out[k] = perm[o];
+  const int caller = perm[o];
+  perm_out[k] = caller;
+  iperm_out[caller] = k;  // caller index -> new internal index
   cell_out[k] = cell_of[o];
   if (w0 < -127 || w0 > 127 || w1 < -127 || w1 > 127 || w2 < -127 || w2 > 127)
     flags[kFlagImage] = 1;
@@ -507,13 +509,23 @@ __global__ void k_reverse(int n, int cap, int width, const uint32_t* __restrict_
     const int t1 = angular ? cnt_a[j] : cnt_r[j];
     int found = -1;
     if (nl_rm && (cap & 3) == 0) {  // j's entries are contiguous: 4 per load
+      // 16 entries per round, their four loads issued together (no load
+      // waits on the previous compare); loads stay below t1 <= cap
       const uint4* row4 = reinterpret_cast<const uint4*>(nl_rm + (size_t)j * cap);
-      for (int u4 = t0 & ~3; u4 < t1 && found < 0; u4 += 4) {
-        const uint4 v = row4[u4 >> 2];
-        if (v.x == target && u4 >= t0) found = u4;
-        else if (v.y == target && u4 + 1 >= t0 && u4 + 1 < t1) found = u4 + 1;
-        else if (v.z == target && u4 + 2 >= t0 && u4 + 2 < t1) found = u4 + 2;
-        else if (v.w == target && u4 + 3 >= t0 && u4 + 3 < t1) found = u4 + 3;
+      for (int u16 = t0 & ~3; u16 < t1 && found < 0; u16 += 16) {
+        uint4 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          v[q] = u16 + 4 * q < t1 ? row4[(u16 >> 2) + q] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int u4 = u16 + 4 * q;
+          if (found >= 0 || u4 >= t1) continue;
+          if (v[q].x == target && u4 >= t0) found = u4;
+          else if (v[q].y == target && u4 + 1 >= t0 && u4 + 1 < t1) found = u4 + 1;
+          else if (v[q].z == target && u4 + 2 >= t0 && u4 + 2 < t1) found = u4 + 2;
+          else if (v[q].w == target && u4 + 3 >= t0 && u4 + 3 < t1) found = u4 + 3;
+        }
       }
     } else if (nl_rm) {
       const uint32_t* row = nl_rm + (size_t)j * cap;
@@ -715,7 +727,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
                   have_vel ? (const double*)s.vel_s.ptr : (const double*)nullptr,
                   have_vel ? s.vel_t.ptr : (double*)nullptr, (const int*)s.wrap.ptr, s.wrap_t.ptr,
                   (const int*)s.perm.ptr, s.perm_t.ptr, (const int*)s.cell_of.ptr, s.cell_t.ptr,
-                  s.cell_rec.ptr, ctx->flags.ptr);
+                  s.cell_rec.ptr, s.iperm.ptr, ctx->flags.ptr);
     s.pos_s.swap(s.pos_t);
     if (have_vel) s.vel_s.swap(s.vel_t);
     s.wrap.swap(s.wrap_t);
@@ -734,8 +746,9 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
                   (const int*)s.wrap.ptr, rc2_r, rc2_a, s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr,
                   ctx->flags.ptr);
   }
-  // caller index -> internal index, for the coalesced copies back
-  if (n > 0)
+  // caller index -> internal index, for the coalesced copies back (the cell
+  // path's k_permute writes it)
+  if (n > 0 && !s.use_cells)
     launch_kernel(ctx, false, false, k_invert_perm, dim3(blocks_for(n, kBlock)), blk, n,
                   (const int*)s.perm.ptr, s.iperm.ptr);
   const int width = s.cap < 40 ? s.cap : 40;
