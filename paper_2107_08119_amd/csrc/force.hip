@@ -181,15 +181,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 
   float q[NDES];
   float c[NA][NLM];
-#pragma unroll
-  for (int v = 0; v < NDES; ++v) q[v] = 0.f;
-#pragma unroll
-  for (int a = 0; a < NA; ++a)
-#pragma unroll
-    for (int m = 0; m < NLM; ++m) c[a][m] = 0.f;
 
-  // descriptor sums over this lane's share of the pairs
-  for (int k = lane; k < n_work; k += L) {
+  // descriptor sums over this lane's share of the pairs; the first work item
+  // (a dummy pair when the lane has none) starts them
+  {
+    int dst = 0;
+    bool ang = false, rad = false;
+    float dx = 1.f, dy = 0.f, dz = 0.f;
+    if (lane < n_work) pair(lane, dx, dy, dz, dst, ang, rad);
+    pair_descriptor_first<NR, NA, LMAX>(dx, dy, dz, rad, ang, rcr_inv, rca_inv, q, c);
+  }
+  for (int k = lane + L; k < n_work; k += L) {
     int dst;
     bool ang, rad;
     float dx, dy, dz;

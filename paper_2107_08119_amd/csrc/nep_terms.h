@@ -64,6 +64,45 @@ __device__ __forceinline__ void pair_descriptor(float dx, float dy, float dz, bo
   }
 }
 
+// The sums of pair_descriptor started from one pair instead of from zero:
+// q[0..NR) and c are assigned the pair's terms, weighted 0 where the pair
+// is not inside the cutoff (rad, ang false), so a lane whose first work item
+// is a dummy pair passes zeros on.  The terms are evaluated for every lane
+// (finite for any r > 0).
+template <int NR, int NA, int LMAX>
+__device__ __forceinline__ void pair_descriptor_first(float dx, float dy, float dz, bool rad,
+                                                      bool ang, float rcr_inv, float rca_inv,
+                                                      float* q,
+                                                      float (&c)[NA][Model<NR, NA, LMAX>::kNLM]) {
+  constexpr int NLM = Model<NR, NA, LMAX>::kNLM;
+  const float r2 = pair_r2(dx, dy, dz);
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float r = r2 * rinv;
+  {
+    float fc, T[NR];
+    chebyshev_values<NR>(r, rcr_inv, fc, T);
+    const float w = rad ? fc : 0.f;
+    q[0] = w;
+#pragma unroll
+    for (int a = 1; a < NR; ++a) q[a] = w * T[a];
+  }
+  float g[NA];
+  radial_basis<NA, false>(r, rca_inv, g, nullptr);
+#pragma unroll
+  for (int a = 0; a < NA; ++a) g[a] = ang ? g[a] : 0.f;
+  const float x = dx * rinv, y = dy * rinv, z = dz * rinv;
+  const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+  const float xyz = xy * z;
+  (void)xyz;
+#define NEP_SET(idx, YV, GX, GY, GZ)                                       \
+  if constexpr ((idx) < NLM) {                                             \
+    const float yv = (YV);                                                 \
+    _Pragma("unroll") for (int a = 0; a < NA; ++a) c[a][idx] = g[a] * yv; \
+  }
+  NEP_YLM_TABLE(NEP_SET)
+#undef NEP_SET
+}
+
 // q_n = (R_n + R_0) / 2 from the complete sums R_n of pair_descriptor.
 template <int NR>
 __device__ __forceinline__ void radial_finish(float* q) {
