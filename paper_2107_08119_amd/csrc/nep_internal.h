@@ -20,20 +20,19 @@ struct Box {
   double hinv[9];
 };
 
-// Packed neighbour entry: atom index in the low 23 bits, lattice image code
-// (n0+3) + 7 (n1+3) + 49 (n2+3) in the high 9 bits.
+// Packed neighbour entry: atom index in the low 23 bits, lattice image
+// n0+3, n1+3, n2+3 (each 0..6) in three 3-bit fields of the high 9 bits.
 constexpr int kAtomBits = 23;
 constexpr uint32_t kAtomMask = (1u << kAtomBits) - 1u;
 constexpr int kMaxAtoms = (1 << kAtomBits) - 1;
 
 __host__ __device__ inline uint32_t pack_entry(int j, int n0, int n1, int n2) {
-  return (uint32_t)j | ((uint32_t)((n0 + 3) + 7 * (n1 + 3) + 49 * (n2 + 3)) << kAtomBits);
+  return (uint32_t)j | ((uint32_t)((n0 + 3) | ((n1 + 3) << 3) | ((n2 + 3) << 6)) << kAtomBits);
 }
 __host__ __device__ inline void unpack_image(uint32_t e, int& n0, int& n1, int& n2) {
-  int code = (int)(e >> kAtomBits);
-  n0 = code % 7 - 3;
-  n1 = (code / 7) % 7 - 3;
-  n2 = code / 49 - 3;
+  n0 = (int)((e >> kAtomBits) & 7u) - 3;
+  n1 = (int)((e >> (kAtomBits + 3)) & 7u) - 3;
+  n2 = (int)(e >> (kAtomBits + 6)) - 3;
 }
 
 // A device array owned by the context that only grows.
