@@ -25,7 +25,7 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
   return __builtin_bit_cast(
-      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
 
 // Sum over aligned groups of L consecutive lanes; every lane gets the sum.

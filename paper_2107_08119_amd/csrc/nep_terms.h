@@ -179,9 +179,8 @@ template <int NDES, int NNEU, int L>
 __device__ __forceinline__ void network(const float* q, const float4* rows, float b2, int lane,
                                         float* dq, float& u) {
   constexpr int RS = NetRows<NDES, NNEU>::RS;
-#pragma unroll
-  for (int v = 0; v < NDES; ++v) dq[v] = 0.f;
-  u = 0.f;
+  static_assert(L <= NNEU, "every lane has a first neuron");
+  // the lane's first neuron (mu = lane) starts the sums u and dq
   for (int mu = lane; mu < NNEU; mu += L) {
     float w[RS];
 #pragma unroll
@@ -200,10 +199,16 @@ __device__ __forceinline__ void network(const float* q, const float4* rows, floa
     const float inv = __builtin_amdgcn_rcpf(1.f + ea);
     const float th = copysignf((1.f - ea) * inv, act);
     const float sech2 = 4.f * ea * inv * inv;
-    u += w[NDES + 1] * th;
     const float gmu = w[NDES + 1] * sech2;
+    if (mu == lane) {
+      u = w[NDES + 1] * th;
 #pragma unroll
-    for (int v = 0; v < NDES; ++v) dq[v] += gmu * w[v];
+      for (int v = 0; v < NDES; ++v) dq[v] = gmu * w[v];
+    } else {
+      u += w[NDES + 1] * th;
+#pragma unroll
+      for (int v = 0; v < NDES; ++v) dq[v] += gmu * w[v];
+    }
   }
   u = group_sum<L>(u) - b2;
 #pragma unroll
