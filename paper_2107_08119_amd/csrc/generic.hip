@@ -74,17 +74,32 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
   const int NNEU = S::kFixed ? TNEU : nneu_rt;
   const int NLM = (LMAX + 1) * (LMAX + 1) - 1;
   const int NDES = NR + NA * LMAX;
-  const int RS = NDES + 1;  // LDS row of neuron mu: w1[mu][:] (padded)
-  __shared__ float s_w1[kMaxNeu * (kMaxDes + 1)];
+  // Compiled shapes with l_max = 4 read LDS four floats at a time: the
+  // network rows, the descriptor and the neurons' w2 sech^2 are padded with
+  // zeros to multiples of 4, and the harmonics rows hold 24 floats.
+  constexpr bool kVec = S::kFixed && TL == 4;
+  constexpr int kDes4 = ((kMaxDes + 3) / 4) * 4;
+  constexpr int kRS = kVec ? kDes4 + (kDes4 % 32 == 0 ? 4 : 0) : kMaxDes + 1;
+  constexpr int kNeuRows = kVec ? ((kMaxNeu + 3) / 4) * 4 : kMaxNeu;
+  constexpr int kYS = kVec ? kMaxLM : kMaxLM + 1;
+  const int RS = kVec ? kRS : NDES + 1;  // LDS row of neuron mu: w1[mu][:] (padded)
+  __shared__ __align__(16) float s_w1[kNeuRows * kRS];
   __shared__ float s_b1[kMaxNeu], s_w2[kMaxNeu];
-  __shared__ float s_g[kWaves][64][kMaxA + 1];   // angular g_n of each lane's pair
-  __shared__ float s_y[kWaves][64][kMaxLM + 1];  // Yhat_lm of each lane's pair
-  __shared__ float s_q[kWaves][kMaxDes];
+  __shared__ float s_g[kWaves][64][kMaxA + 1];           // angular g_n of each lane's pair
+  __shared__ __align__(16) float s_y[kWaves][64][kYS];   // Yhat_lm of each lane's pair
+  __shared__ __align__(16) float s_q[kWaves][kDes4];
   __shared__ float s_dq[kWaves][kMaxDes];
   __shared__ float s_c[kWaves][kMaxA * kMaxLM];  // c_nlm, then a_nlm
-  __shared__ float s_gmu[kWaves][kMaxNeu];
-  for (int t = threadIdx.x; t < NNEU * NDES; t += blockDim.x)
-    s_w1[(t / NDES) * RS + t % NDES] = z[t];
+  __shared__ __align__(16) float s_gmu[kWaves][kNeuRows];
+  if constexpr (kVec) {
+    for (int t = threadIdx.x; t < kNeuRows * kRS; t += blockDim.x) {
+      const int mu = t / kRS, v = t % kRS;
+      s_w1[t] = mu < NNEU && v < NDES ? z[mu * NDES + v] : 0.f;
+    }
+  } else {
+    for (int t = threadIdx.x; t < NNEU * NDES; t += blockDim.x)
+      s_w1[(t / NDES) * RS + t % NDES] = z[t];
+  }
   for (int t = threadIdx.x; t < NNEU; t += blockDim.x) {
     s_b1[t] = z[NNEU * NDES + t];
     s_w2[t] = z[NNEU * (NDES + 1) + t];
@@ -103,11 +118,15 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
   const float rcr2 = rc_r * rc_r, rca2 = rc_a * rc_a;
   const int nout = NA * NLM;  // angular moments, lane k owns k, k + 64, ...
   float qr[kMaxR];
-  float cacc[(kMaxA * kMaxLM + 63) / 64];
+  constexpr int kR4 = (kMaxA * 6 + 63) / 64;  // rounds of the four-output groups
+  float cacc[kVec ? 1 : (kMaxA * kMaxLM + 63) / 64];
+  float4 cacc4[kVec ? kR4 : 1];
 #pragma unroll
   for (int a = 0; a < kMaxR; ++a) qr[a] = 0.f;
 #pragma unroll
-  for (int r = 0; r < (kMaxA * kMaxLM + 63) / 64; ++r) cacc[r] = 0.f;
+  for (int r = 0; r < (kVec ? 1 : (kMaxA * kMaxLM + 63) / 64); ++r) cacc[r] = 0.f;
+#pragma unroll
+  for (int r = 0; r < (kVec ? kR4 : 1); ++r) cacc4[r] = make_float4(0.f, 0.f, 0.f, 0.f);
   auto wave_lds_sync = [] {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -152,14 +171,34 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
     wave_lds_sync();
     // pairs past the list's angular part have g = 0: skip them
     const int np = max(0, min(64, min(cr, ca) - base));
+    if constexpr (kVec) {  // lane k owns outputs (n, 4 m4 .. 4 m4 + 3), k = 6 n + m4
 #pragma unroll
-    for (int r = 0; r < (kMaxA * kMaxLM + 63) / 64; ++r) {
-      const int k = lane + 64 * r;
-      if (k < nout) {
-        const int a = k / NLM, m = k % NLM;
-        float acc = cacc[r];
-        for (int p = 0; p < np; ++p) acc += s_g[wave][p][a] * s_y[wave][p][m];
-        cacc[r] = acc;
+      for (int r = 0; r < kR4; ++r) {
+        const int k = lane + 64 * r;
+        if (k < NA * 6) {
+          const int a = k / 6, m4 = k % 6;
+          float4 acc = cacc4[r];
+          for (int p = 0; p < np; ++p) {
+            const float gv = s_g[wave][p][a];
+            const float4 y4 = *reinterpret_cast<const float4*>(&s_y[wave][p][4 * m4]);
+            acc.x += gv * y4.x;
+            acc.y += gv * y4.y;
+            acc.z += gv * y4.z;
+            acc.w += gv * y4.w;
+          }
+          cacc4[r] = acc;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < (kMaxA * kMaxLM + 63) / 64; ++r) {
+        const int k = lane + 64 * r;
+        if (k < nout) {
+          const int a = k / NLM, m = k % NLM;
+          float acc = cacc[r];
+          for (int p = 0; p < np; ++p) acc += s_g[wave][p][a] * s_y[wave][p][m];
+          cacc[r] = acc;
+        }
       }
     }
     wave_lds_sync();
@@ -172,10 +211,24 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
     const float v = wave_sum(qr[a]);
     if (lane == 0 && a < NR) s_q[wave][a] = 0.5f * (v + r0);
   }
+  if constexpr (kVec) {
 #pragma unroll
-  for (int r = 0; r < (kMaxA * kMaxLM + 63) / 64; ++r) {
-    const int k = lane + 64 * r;
-    if (k < nout) s_c[wave][k] = cacc[r];
+    for (int r = 0; r < kR4; ++r) {
+      const int k = lane + 64 * r;
+      if (k < NA * 6) {
+        s_c[wave][4 * k] = cacc4[r].x;  // (n, 4 m4 + c) is n 24 + 4 m4 + c = 4 k + c
+        s_c[wave][4 * k + 1] = cacc4[r].y;
+        s_c[wave][4 * k + 2] = cacc4[r].z;
+        s_c[wave][4 * k + 3] = cacc4[r].w;
+      }
+    }
+    for (int v = NDES + lane; v < kDes4; v += 64) s_q[wave][v] = 0.f;  // padding
+  } else {
+#pragma unroll
+    for (int r = 0; r < (kMaxA * kMaxLM + 63) / 64; ++r) {
+      const int k = lane + 64 * r;
+      if (k < nout) s_c[wave][k] = cacc[r];
+    }
   }
   wave_lds_sync();
   // angular components q_nl = sum_m c_nlm^2
@@ -194,12 +247,26 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
   float u = 0.f;
   if (lane < NNEU) {
     float act = -s_b1[lane];
-    for (int v = 0; v < NDES; ++v) act += s_w1[lane * RS + v] * s_q[wave][v];
+    if constexpr (kVec) {
+#pragma unroll 4
+      for (int v4 = 0; v4 < kDes4 / 4; ++v4) {
+        const float4 w4 = *reinterpret_cast<const float4*>(&s_w1[lane * kRS + 4 * v4]);
+        const float4 q4 = *reinterpret_cast<const float4*>(&s_q[wave][4 * v4]);
+        act += w4.x * q4.x;
+        act += w4.y * q4.y;
+        act += w4.z * q4.z;
+        act += w4.w * q4.w;
+      }
+    } else {
+      for (int v = 0; v < NDES; ++v) act += s_w1[lane * RS + v] * s_q[wave][v];
+    }
     const float ea = __expf(-2.f * fabsf(act));
     const float inv = __builtin_amdgcn_rcpf(1.f + ea);
     const float th = copysignf((1.f - ea) * inv, act);
     u = s_w2[lane] * th;
     s_gmu[wave][lane] = s_w2[lane] * (4.f * ea * inv * inv);
+  } else if (kVec && lane < kNeuRows) {
+    s_gmu[wave][lane] = 0.f;  // padding (its w1 row is zero too)
   }
   u = wave_sum(u) - b2;
   if (lane == 0) U[i] = u;
@@ -207,7 +274,18 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
   // dU/dq_v: lane v (two rounds for up to 128 descriptor components)
   for (int v = lane; v < NDES; v += 64) {
     float d = 0.f;
-    for (int mu = 0; mu < NNEU; ++mu) d += s_gmu[wave][mu] * s_w1[mu * RS + v];
+    if constexpr (kVec) {
+#pragma unroll 2
+      for (int m4 = 0; m4 < kNeuRows / 4; ++m4) {
+        const float4 g4 = *reinterpret_cast<const float4*>(&s_gmu[wave][4 * m4]);
+        d += g4.x * s_w1[(4 * m4) * kRS + v];
+        d += g4.y * s_w1[(4 * m4 + 1) * kRS + v];
+        d += g4.z * s_w1[(4 * m4 + 2) * kRS + v];
+        d += g4.w * s_w1[(4 * m4 + 3) * kRS + v];
+      }
+    } else {
+      for (int mu = 0; mu < NNEU; ++mu) d += s_gmu[wave][mu] * s_w1[mu * RS + v];
+    }
     s_dq[wave][v] = d;
   }
   wave_lds_sync();
