@@ -7,11 +7,13 @@
 // terms (factorised angular descriptor, network, partial force) are in
 // nep_terms.h.
 //
-// Pass 1 also sums the atom's own partials, sum_j p_ij, and stores every p_ij
-// in the reverse slot of atom j's list (each slot is written exactly once).
-// Pass 2 then computes, per atom, F_i = sum_j p_ij - sum_j p_ji,
-// W_i = sum_j r_ij (x) p_ji and J_i = W_i v_i (Sec. II A-B) from coalesced
-// reads of its own slots; no atomics touch forces and the result is
+// Pass 1 also sums the atom's own partials, sum_j p_ij, stores every p_ij
+// in the reverse slot of atom j's list (each slot is written exactly once)
+// and, for systems up to kPairVectorMaxAtoms atoms, the pair vector r_ij in
+// the atom's own slot.  Pass 2 then computes, per atom,
+// F_i = sum_j p_ij - sum_j p_ji, W_i = sum_j r_ij (x) p_ji and J_i = W_i v_i
+// (Sec. II A-B) from coalesced reads of its own slots (and, for larger
+// systems, the neighbours' positions); no atomics touch forces and the result is
 // reproducible bit for bit.  Totals are summed in float64 per block and the
 // block sums are added in block order by a one-block kernel.
 #include "nep_terms.h"
@@ -29,6 +31,9 @@ constexpr int stage_slots(int atoms_per_block) {
 // Outputs: U[i]; fown[c*n + i] = sum_j dU_i/dr_ij (component c); and every
 // partial force dU_i/dr_ij written to the reverse slot, pin[t*n + j] with
 // t = rev[s*n + i], where atom j finds it as its incoming partial dU_i/dr_ij.
+// With geo (systems of up to kPairVectorMaxAtoms atoms), the pair vector
+// r_ij of every slot s of atom i goes to geo[s*n + i] (float32, as used
+// here) for pass 2's virial.
 // MULTI: every atom has its own cell (struct_of[i] indexes boxes[][9]).
 // Population: blockIdx.y selects parameter vector k at zpar + k*zstride and
 // its outputs at pin + k*pstride, fown + 3nk, U + nk.
@@ -38,7 +43,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, const int* __restrict__ rev,
     Box box, const double* __restrict__ boxes, const int* __restrict__ struct_of,
     const float* __restrict__ zpar, size_t zstride, float rc_r, float rc_a,
-    Partial3* __restrict__ pin, size_t pstride, float* __restrict__ fown, float* __restrict__ U) {
+    Partial3* __restrict__ pin, size_t pstride, float* __restrict__ fown, float* __restrict__ U,
+    Partial3* __restrict__ geo) {
   constexpr int NLM = Model<NR, NA, LMAX>::kNLM;
   constexpr int NDES = Model<NR, NA, LMAX>::kNDES;
   __shared__ float4 sw4[NetRows<NDES, NNEU>::kFloat4];
@@ -106,6 +112,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       const int dst = rv[t] * n + (int)(e[t] & kAtomMask);
       v[t] = make_float4(dx, dy, dz, __int_as_float(dst));
       const float r2 = pair_r2(dx, dy, dz);
+      if (geo && sl < cra) geo[(size_t)sl * n + ia] = Partial3{dx, dy, dz};
       if (sl < cra) {
         if (sl < caa && r2 < rca2)
           ma |= 1ull << sl;
@@ -221,6 +228,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     bool ang, rad;
     float dx, dy, dz;
     pair(k, dx, dy, dz, dst, ang, rad);
+    if (geo && k >= n_in) geo[(size_t)(KS + (k - n_in)) * n + i] = Partial3{dx, dy, dz};
     float px, py, pz;
     pair_force<NR, NA, LMAX>(dx, dy, dz, rad, ang, rcr_inv, rca_inv, dq, dqs, c, px, py, pz);
     fx += px;
@@ -276,12 +284,15 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int nblocks, const double* 
 //         (E_pot, E_kin, J (3)) with the kicked velocities.
 // MODE 2: MODE 1, then the next step's first half-kick v += kick F and drift
 //         pos_next = pos + dt v (a separate array: pos is still being read).
-template <int L, int MODE>
+// GEO: r_ij from pass 1's pair vectors geo[s*n + i]; otherwise formed again
+// from the list entry and the neighbour's position (the same float32 value).
+template <int L, int MODE, bool GEO>
 __global__ __launch_bounds__(kBlock) void k_gather(
     int n, const double* __restrict__ pos, double* __restrict__ vel,
-    const uint32_t* __restrict__ nl, const int* __restrict__ cnt_r,
-    const Partial3* __restrict__ pin, const float* __restrict__ fown, const float* __restrict__ U,
-    Box box, float* __restrict__ U_out,
+    const uint32_t* __restrict__ nl, const Partial3* __restrict__ geo,
+    const int* __restrict__ cnt_r, const Partial3* __restrict__ pin,
+    const float* __restrict__ fown, const float* __restrict__ U, Box box,
+    float* __restrict__ U_out,
     float* __restrict__ F, float* __restrict__ W, float* __restrict__ J, double kick,
     double ekin_factor, double dt,
     double* __restrict__ pos_next, float fe0, float fe1, float fe2,
@@ -304,28 +315,39 @@ __global__ __launch_bounds__(kBlock) void k_gather(
   // (5 measured best of 3, 5, 7, 9 on the 64,000-atom step)
   constexpr int B = 5;
   for (int s0 = lane; s0 < cr; s0 += B * L) {
+    Partial3 rg[B], p[B];
     uint32_t e[B];
-    Partial3 p[B];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int s = s0 + u * L;
       const size_t idx = s < cr ? (size_t)s * n + i : (size_t)i;  // slot 0 when past the end
-      e[u] = nl[idx];
+      if constexpr (GEO)
+        rg[u] = geo[idx];
+      else
+        e[u] = nl[idx];
       p[u] = pin[idx];
     }
     double pj[B][3];
+    if constexpr (!GEO) {
 #pragma unroll
-    for (int u = 0; u < B; ++u) {
-      const int j = (int)(e[u] & kAtomMask);
-      pj[u][0] = pos[j];
-      pj[u][1] = pos[n + j];
-      pj[u][2] = pos[2 * n + j];
+      for (int u = 0; u < B; ++u) {
+        const int j = (int)(e[u] & kAtomMask);
+        pj[u][0] = pos[j];
+        pj[u][1] = pos[n + j];
+        pj[u][2] = pos[2 * n + j];
+      }
     }
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       if (s0 + u * L >= cr) break;
       float dx, dy, dz;
-      image_displacement(e[u], pj[u][0], pj[u][1], pj[u][2], xi, yi, zi, H, dx, dy, dz);
+      if constexpr (GEO) {
+        dx = rg[u].x;
+        dy = rg[u].y;
+        dz = rg[u].z;
+      } else {
+        image_displacement(e[u], pj[u][0], pj[u][1], pj[u][2], xi, yi, zi, H, dx, dy, dz);
+      }
       const Partial3 pji = p[u];
       f0 -= pji.x;
       f1 -= pji.y;
@@ -464,7 +486,8 @@ void launch_partials_shape(nep_ctx ctx, const double* pos, bool first, bool last
                 pos, (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr, (const int*)s.cnt_a.ptr,
                 (const int*)s.rev.ptr, s.box, (const double*)nullptr, (const int*)nullptr,
                 (const float*)ctx->z.ptr, (size_t)0, (float)ctx->hyper.rc_radial,
-                (float)ctx->hyper.rc_angular, ctx->p.ptr, (size_t)0, ctx->fown.ptr, ctx->U.ptr);
+                (float)ctx->hyper.rc_angular, ctx->p.ptr, (size_t)0, ctx->fown.ptr, ctx->U.ptr,
+                s.n <= kPairVectorMaxAtoms ? ctx->geo.ptr : (Partial3*)nullptr);
 }
 
 hipError_t launch_partials(nep_ctx ctx, const double* pos, int variant) {
@@ -494,7 +517,8 @@ hipError_t launch_partials_population(nep_ctx ctx, nep_dataset ds, int n_pop, co
                 (const int*)ds->cnt_r.ptr, (const int*)ds->cnt_a.ptr, (const int*)ds->rev.ptr,
                 Box{}, (const double*)ds->boxes.ptr, (const int*)ds->struct_of.ptr, Z,
                 (size_t)ctx->n_par, (float)ctx->hyper.rc_radial, (float)ctx->hyper.rc_angular,
-                ds->pin.ptr, (size_t)ds->cap * ds->N, ds->fown.ptr, ds->U.ptr);
+                ds->pin.ptr, (size_t)ds->cap * ds->N, ds->fown.ptr, ds->U.ptr,
+                (Partial3*)nullptr);
   return hipGetLastError();
 }
 
@@ -505,7 +529,9 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
   if (s.n == 0) return hipSuccess;
   const unsigned nb = blocks_for((size_t)s.n * kLanes, kBlock);
   const double ekin_factor = 0.5 * mass / kAccel;
+  const bool use_geo = s.n <= kPairVectorMaxAtoms;
   const uint32_t* nl = s.nl.ptr;
+  const Partial3* geo = ctx->geo.ptr;
   const int* cnt = s.cnt_r.ptr;
   const Partial3* p = ctx->p.ptr;
   const float* fown = ctx->fown.ptr;
@@ -513,17 +539,26 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
   const bool per_atom = ctx->species_on() && ctx->have_masses;
   const double* mass_c = per_atom ? (const double*)ctx->masses.ptr : (const double*)nullptr;
   auto go = [&](auto kernel) {
-    launch_kernel(ctx, true, last, kernel, dim3(nb), dim3(kBlock), s.n, pos, vel, nl, cnt, p, fown,
-                  U, s.box, U_out, F_out, W_out, J_out, kick, ekin_factor, dt, pos_next,
+    launch_kernel(ctx, true, last, kernel, dim3(nb), dim3(kBlock), s.n, pos, vel, nl, geo, cnt, p,
+                  fown, U, s.box, U_out, F_out, W_out, J_out, kick, ekin_factor, dt, pos_next,
                   (float)fe[0], (float)fe[1], (float)fe[2], mass_c, (const int*)s.perm.ptr, mass,
                   block_out);
   };
-  if (mode == 0)
-    go(k_gather<kLanes, 0>);
-  else if (mode == 1)
-    go(k_gather<kLanes, 1>);
-  else
-    go(k_gather<kLanes, 2>);
+  if (use_geo) {
+    if (mode == 0)
+      go(k_gather<kLanes, 0, true>);
+    else if (mode == 1)
+      go(k_gather<kLanes, 1, true>);
+    else
+      go(k_gather<kLanes, 2, true>);
+  } else {
+    if (mode == 0)
+      go(k_gather<kLanes, 0, false>);
+    else if (mode == 1)
+      go(k_gather<kLanes, 1, false>);
+    else
+      go(k_gather<kLanes, 2, false>);
+  }
   return hipGetLastError();
 }
 

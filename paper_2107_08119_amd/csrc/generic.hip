@@ -12,7 +12,9 @@
 //   * network: lane mu evaluates neuron mu; dU/dq_v is formed by lane v from
 //     the neurons' w2 sech^2 in LDS;
 //   * partial forces: lane p evaluates pair p from dU/dq and a_nlm in LDS,
-//     as sums over T_n and T_n' (the n = 0 terms folded per atom).
+//     as sums over T_n and T_n' (the n = 0 terms folded per atom), and
+//     stores the pair vector r_ij in the atom's own slot for pass 2 (systems
+//     of up to kPairVectorMaxAtoms atoms).
 // Every sum has a fixed order, so results are reproducible bit for bit.
 #include "nep_terms.h"
 
@@ -64,7 +66,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
     const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, const int* __restrict__ rev,
     Box box, const float* __restrict__ z, int nr_rt, int na_rt, int lmax_rt, int nneu_rt,
     float rc_r, float rc_a, const float* __restrict__ wsp, const int* __restrict__ perm,
-    Partial3* __restrict__ pin, float* __restrict__ fown, float* __restrict__ U) {
+    Partial3* __restrict__ pin, float* __restrict__ fown, float* __restrict__ U,
+    Partial3* __restrict__ geo) {
   using S = Shape<TR, TA, TL, TNEU>;
   constexpr int kMaxR = S::MR, kMaxA = S::MA, kMaxLM = S::MLM, kMaxNeu = S::MNEU;
   constexpr int kMaxDes = S::MDES;
@@ -322,6 +325,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
       int j;
       float dx, dy, dz;
       displacement(nl[idx], pos, n, xi, yi, zi, box.h, j, dx, dy, dz);
+      if (geo) geo[idx] = Partial3{dx, dy, dz};  // r_ij for pass 2's virial
       const int dst = rev[idx] * n + j;
       const float r2 = pair_r2(dx, dy, dz);
       const float rinv = __builtin_amdgcn_rsqf(r2);
@@ -425,7 +429,8 @@ void launch_shape(nep_ctx ctx, const double* pos) {
                 h.n_max_angular + 1, h.l_max, h.n_neuron, (float)h.rc_radial,
                 (float)h.rc_angular,
                 ctx->species_on() ? (const float*)ctx->species_w.ptr : (const float*)nullptr,
-                (const int*)s.perm.ptr, ctx->p.ptr, ctx->fown.ptr, ctx->U.ptr);
+                (const int*)s.perm.ptr, ctx->p.ptr, ctx->fown.ptr, ctx->U.ptr,
+                s.n <= kPairVectorMaxAtoms ? ctx->geo.ptr : (Partial3*)nullptr);
 }
 
 bool is_shape(const nep_hyper& h, int nr, int na, int lmax, int nneu) {

@@ -41,6 +41,7 @@ nep_status size_system_buffers(nep_ctx ctx) {
   hipError_t e;
   System& sm = ctx->sys;
   if ((e = ctx->p.ensure((size_t)s.cap * s.n)) != hipSuccess ||
+      (s.n <= kPairVectorMaxAtoms && (e = ctx->geo.ensure((size_t)s.cap * s.n)) != hipSuccess) ||
       (e = ctx->U.ensure((size_t)s.n)) != hipSuccess ||
       (e = ctx->fown.ensure((size_t)3 * s.n)) != hipSuccess ||
       (e = ctx->F.ensure((size_t)3 * s.n)) != hipSuccess ||
@@ -113,6 +114,7 @@ void nep_destroy(nep_ctx ctx) {
   ctx->sys.release();
   ctx->z.release();
   ctx->p.release();
+  ctx->geo.release();
   ctx->species_w.release();
   ctx->masses.release();
   ctx->fown.release();

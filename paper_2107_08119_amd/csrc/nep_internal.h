@@ -35,6 +35,13 @@ __host__ __device__ inline void unpack_image(uint32_t e, int& n0, int& n1, int& 
   n2 = (int)(e >> (kAtomBits + 6)) - 3;
 }
 
+// Pass 1 hands pass 2 the pair vectors r_ij (12 bytes per list slot) for
+// systems of up to 2^17 atoms, whose vectors stay in the chip's last-level
+// cache between the two passes; for larger systems writing them to HBM costs
+// pass 1 more than it saves pass 2, which then forms r_ij again from the
+// list and the positions.
+constexpr int kPairVectorMaxAtoms = 1 << 17;
+
 // A device array owned by the context that only grows.
 template <class T>
 struct DevBuf {
@@ -200,6 +207,7 @@ struct nep_ctx_s {
   bool have_list = false;
   nep::System sys;
   nep::DevBuf<nep::Partial3> p;   // incoming partial forces dU_j/dr_ji at i's slots, [cap][n]
+  nep::DevBuf<nep::Partial3> geo; // pair vectors r_ij of i's slots from pass 1, [cap][n]
   nep::DevBuf<float> fown;        // sum_j dU_i/dr_ij, [3][n]
   nep::DevBuf<float> U;           // [n]
   nep::DevBuf<float> F;           // [3][n]
