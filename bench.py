@@ -46,8 +46,9 @@ PEAK_HBM_GBS = 8000.0
 #               derivative, moment scaling, n = 0 folds)      4390
 FLOP_SLOT, FLOP_RADIAL, FLOP_ANGULAR, FLOP_ATOM = 29, 181, 1177, 4390
 # Algorithmic HBM bytes of the same kernel per atom: own position 24, counts 8,
-# list 4 per slot, partial force written 12 per slot, site energy 4.
-BYTE_ATOM, BYTE_SLOT = 36, 16
+# list 4 per slot, partial force written 12 per slot, pair vector written 12
+# per slot (for pass 2), site energy 4.
+BYTE_ATOM, BYTE_SLOT = 36, 28
 # Measured HBM traffic of one k_partials launch of this workload: rocprofv3
 # --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this bench (KiB per dispatch;
 # profiles/k_partials_nve64k_counters.md), each scaled by what the counter
@@ -56,11 +57,11 @@ BYTE_ATOM, BYTE_SLOT = 36, 16
 # tile shape (lanes per atom: FETCH_SIZE, WRITE_SIZE).  They hold only for the
 # kernel sources they were taken with (hash below); otherwise, or for a tile
 # without an entry, the bench reports traffic null.
-COUNTERS = {"sources_sha256": "90d55761de7a794272e74d465fe3fcea0acb935dc7ef080def3b862ba43cb6c5",
+COUNTERS = {"sources_sha256": "aca0339d1a151dea4584822e93022ad841d4deff77c480c67f2424b51d21293d",
             "kib": {
-                    "2": [12494.88, 56837.37],
-                    "4": [11040.80, 55239.64],
-                    "8": [10666.91, 56394.86]}}
+                    "2": [12132.65, 83860.66],
+                    "4": [11233.32, 78602.53],
+                    "8": [10920.66, 76293.80]}}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ["force.hip", "nep_terms.h", "nep_device.h", "nep_internal.h"]
 
