@@ -312,8 +312,9 @@ __global__ __launch_bounds__(kBlock) void k_gather(
 #pragma unroll
   for (int k = 0; k < 9; ++k) w[k] = 0.f;
   // B slots per lane at a time, all their loads issued before any use
-  // (5 measured best of 3, 5, 7, 9 on the 64,000-atom step)
-  constexpr int B = 5;
+  // (measured best on the 64,000-atom step: 9 of 9, 13, 17 with pair vectors
+  // and 2 lanes per atom; 5 of 3, 5, 7, 9 otherwise with 4 lanes)
+  constexpr int B = GEO && L == 2 ? 9 : 5;
   for (int s0 = lane; s0 < cr; s0 += B * L) {
     Partial3 rg[B], p[B];
     uint32_t e[B];
@@ -476,7 +477,13 @@ bool have_force_variant(const nep_hyper& h) { return is_default_variant(h) || ge
 
 bool have_training_variant(const nep_hyper& h) { return is_default_variant(h); }
 
-size_t gather_blocks(int n) { return blocks_for((size_t)n * kLanes, kBlock); }
+// Pass-2 tile: 2 lanes per atom with pair vectors from pass 1 on systems of
+// 2^15 atoms or more, else 4 (the fastest of 1, 2, 4, 8 and 16 on the
+// 64,000-atom step for each source of r_ij; below 2^15 atoms 4 lanes give
+// the launch more waves, 1-2% faster on the 6,000-8,000-atom cells).
+inline int gather_lanes(int n) { return n >= (1 << 15) && n <= kPairVectorMaxAtoms ? 2 : 4; }
+
+size_t gather_blocks(int n) { return blocks_for((size_t)n * gather_lanes(n), kBlock); }
 
 template <int L>
 void launch_partials_shape(nep_ctx ctx, const double* pos, bool first, bool last) {
@@ -527,9 +534,9 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
                          double mass, double dt, double* pos_next, const double* fe, bool last) {
   const System& s = ctx->sys;
   if (s.n == 0) return hipSuccess;
-  const unsigned nb = blocks_for((size_t)s.n * kLanes, kBlock);
+  const unsigned nb = (unsigned)gather_blocks(s.n);
   const double ekin_factor = 0.5 * mass / kAccel;
-  const bool use_geo = s.n <= kPairVectorMaxAtoms;
+  const bool use_geo = s.n <= kPairVectorMaxAtoms;  // pass 1 wrote the pair vectors
   const uint32_t* nl = s.nl.ptr;
   const Partial3* geo = ctx->geo.ptr;
   const int* cnt = s.cnt_r.ptr;
@@ -544,13 +551,20 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
                   (float)fe[0], (float)fe[1], (float)fe[2], mass_c, (const int*)s.perm.ptr, mass,
                   block_out);
   };
-  if (use_geo) {
+  if (use_geo && gather_lanes(s.n) == 2) {
     if (mode == 0)
-      go(k_gather<kLanes, 0, true>);
+      go(k_gather<2, 0, true>);
     else if (mode == 1)
-      go(k_gather<kLanes, 1, true>);
+      go(k_gather<2, 1, true>);
     else
-      go(k_gather<kLanes, 2, true>);
+      go(k_gather<2, 2, true>);
+  } else if (use_geo) {
+    if (mode == 0)
+      go(k_gather<4, 0, true>);
+    else if (mode == 1)
+      go(k_gather<4, 1, true>);
+    else
+      go(k_gather<4, 2, true>);
   } else {
     if (mode == 0)
       go(k_gather<kLanes, 0, false>);
