@@ -160,3 +160,30 @@ def test_pbte_full_size_64k_sampled():
     ref = O.nep_eval(oh, z, pos, box, vel=vel, Z=Z, sel=sel)
     for k in ("U", "F", "W", "J"):
         assert rel(out[k][sel], ref[k]) < TOL, k
+
+
+def test_pbte_md_full_size_64k_matches_oracle():
+    """The benchmark's 64,000-atom PbTe run (sqrt(Z_i Z_j) weights, per-atom
+    masses, 128-slot cell lists): 3 NVE steps with a rebuild after 2, against
+    the oracle's velocity Verlet."""
+    nep = nep_mod()
+    h, oh = pbte_hyper()
+    pos, box, Z, masses = I.rocksalt_supercell(20, 20, 20)
+    rng = np.random.default_rng(12)
+    pos = I.wrap_positions(pos + rng.normal(0.0, 0.05, pos.shape), box)
+    vel = I.maxwell_boltzmann(len(pos), 300.0, 2, masses)
+    z = damp_input_weights(I.random_parameters(nep.num_params(h), 1, std=0.05), 40, 41,
+                           1.0 / 300.0)
+    ctx = nep.Context(0)
+    ctx.load_params(h, z)
+    p, v = nep.soa(pos), nep.soa(vel)
+    ctx.build_neighbors(p, box, skin=0.5, max_neighbors=128)
+    ctx.set_species(Z, masses)
+    th = ctx.md_step(3, 1.0, 2, 150.0, p, v).cpu().numpy()  # 150 amu: reference only
+    ctx.synchronize()
+    th_ref, p_ref, v_ref = O.md_nve(oh, z, pos, box, vel, masses, 1.0, 3, Z=Z)
+    assert rel(th[:, 0], th_ref[:, 0]) < TOL
+    assert rel(th[:, 1], th_ref[:, 1]) < TOL
+    assert rel(nep.aos(v), v_ref) < TOL
+    d = I.wrap_positions(nep.aos(p) - p_ref + 0.5 * np.diag(box), box) - 0.5 * np.diag(box)
+    assert np.abs(d).max() < 1e-6
