@@ -133,3 +133,43 @@ def test_unsupported_sizes_are_refused():
     ctx.load_params(h, np.zeros(4101, np.float32))
     with pytest.raises(nep.NepError, match="ENOTIMPL"):
         ctx.dataset_create(I.labelled_set(2, 8, 16, seed=1))
+
+
+@pytest.mark.parametrize("model", ["si_80_50_1", "silicene_65_40_1", "pbte_41_40_1"])
+def test_table_one_models_at_speed_test_size(model):
+    """The benchmark's speed-test cells of the three Table I models (8,000-atom
+    diamond, 6,000-atom silicene sheet, 8,000-atom rock-salt PbTe with
+    sqrt(Z_i Z_j) weights; 128-slot cell lists), jittered by N(0, 0.05^2) A:
+    300 sampled atoms against the oracle."""
+    nep = nep_mod()
+    Z = None
+    if model == "si_80_50_1":
+        pos, box = I.diamond_supercell(10, 10, 10)
+        sizes, std = (5.0, 5.0, 15, 15, 4, 50), 0.02
+    elif model == "silicene_65_40_1":
+        pos, box = I.silicene_sheet(50, 30)
+        sizes, std = (5.5, 5.5, 12, 12, 4, 40), 0.02
+    else:
+        pos, box, Z, _ = I.rocksalt_supercell(10, 10, 10)
+        sizes, std = (8.0, 4.0, 12, 6, 4, 40), 0.05
+    h, oh = nep.hyper(*sizes), O.hyper(*sizes)
+    rng = np.random.default_rng(21)
+    pos = I.wrap_positions(pos + rng.normal(0.0, 0.05, pos.shape), box)
+    z = I.random_parameters(nep.num_params(h), 1, std=std)
+    if Z is not None:  # O(1) activations with the weighted descriptors
+        z[:40 * 41] *= np.float32(1.0 / 300.0)
+    vel = I.maxwell_boltzmann(len(pos), 300.0, 2)
+    ctx = nep.Context(0)
+    ctx.load_params(h, z)
+    p = nep.soa(pos)
+    ctx.build_neighbors(p, box, skin=0.5, max_neighbors=128)
+    if Z is not None:
+        ctx.set_species(Z)
+    o = ctx.compute(p, nep.soa(vel))
+    ctx.synchronize()
+    out = {"U": o["U"].cpu().numpy(), "F": nep.aos(o["F"]),
+           "W": nep.aos(o["W"]).reshape(-1, 3, 3), "J": nep.aos(o["J"])}
+    sel = np.sort(rng.choice(len(pos), 300, replace=False))
+    ref = O.nep_eval(oh, z, pos, box, vel=vel, Z=Z, sel=sel)
+    for k in ("U", "F", "W", "J"):
+        assert rel(out[k][sel], ref[k]) < TOL, k
