@@ -435,45 +435,59 @@ __global__ __launch_bounds__(NT) void k_build_cells(
     scan(std::false_type{});
 }
 
-// One thread per atom: every atom j and every image m in [-k, k]^3 of the
-// wrapped frame (boxes thinner than three cut-off widths).
-__global__ void k_build_all_pairs(int n, int cap, const double* __restrict__ pos, Box box, int k0,
-                                  int k1, int k2, const int* __restrict__ wrap, double rc2_r,
-                                  double rc2_a, uint32_t* __restrict__ nl,
-                                  int* __restrict__ cnt_r, int* __restrict__ cnt_a,
-                                  int* __restrict__ flags) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// One 64-lane wave per atom (4 atoms per block): every atom j and every image
+// m in [-k, k]^3 of the wrapped frame (boxes thinner than three cut-off
+// widths).  Candidate c = j (2k+1)^3 + image (m2 fastest) is tested by lane
+// c mod 64; a ballot and a population count give each kept entry the slot of
+// the serial order (angular-range entries first, then the radial-only ones).
+__global__ __launch_bounds__(256) void k_build_all_pairs(
+    int n, int cap, const double* __restrict__ pos, Box box, int k0, int k1, int k2,
+    const int* __restrict__ wrap, double rc2_r, double rc2_a, uint32_t* __restrict__ nl,
+    int* __restrict__ cnt_r, int* __restrict__ cnt_a, int* __restrict__ flags) {
+  const int lane = (int)threadIdx.x % 64;
+  const int i = (int)blockIdx.x * 4 + (int)threadIdx.x / 64;
+  if (i >= n) return;  // whole waves leave together
   const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
   const int wi0 = wrap[i], wi1 = wrap[n + i], wi2 = wrap[2 * n + i];
+  const int d1 = 2 * k1 + 1, d2 = 2 * k2 + 1;
+  const int nimg = (2 * k0 + 1) * d1 * d2;
+  const long long total = (long long)n * nimg;
+  const unsigned long long below = (1ull << lane) - 1ull;
   int count = 0;
   bool overflow = false, bad_image = false;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int j = 0; j < n; ++j) {
-      const int wj0 = wrap[j], wj1 = wrap[n + j], wj2 = wrap[2 * n + j];
-      for (int m0 = -k0; m0 <= k0; ++m0)
-        for (int m1 = -k1; m1 <= k1; ++m1)
-          for (int m2 = -k2; m2 <= k2; ++m2) {
-            const int n0 = m0 + wi0 - wj0, n1 = m1 + wi1 - wj1, n2 = m2 + wi2 - wj2;
-            if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
-            const double r2 = list_r2(pos[j], pos[n + j], pos[2 * n + j], xi, yi, zi, n0, n1, n2, box.h);
-            const bool in_a = r2 < rc2_a;
-            const bool keep = pass == 0 ? in_a : (!in_a && r2 < rc2_r);
-            if (!keep) continue;
-            if (n0 < -3 || n0 > 3 || n1 < -3 || n1 > 3 || n2 < -3 || n2 > 3) {
-              bad_image = true;
-              continue;
-            }
-            if (count < cap)
-              nl[(size_t)count * n + i] = pack_entry(j, n0, n1, n2);
-            else
-              overflow = true;
-            ++count;
+    for (long long base = 0; base < total; base += 64) {
+      const long long c = base + lane;
+      bool keep = false;
+      uint32_t entry = 0;
+      if (c < total) {
+        const int j = (int)(c / nimg), im = (int)(c % nimg);
+        const int m0 = im / (d1 * d2) - k0, m1 = (im / d2) % d1 - k1, m2 = im % d2 - k2;
+        const int n0 = m0 + wi0 - wrap[j], n1 = m1 + wi1 - wrap[n + j], n2 = m2 + wi2 - wrap[2 * n + j];
+        if (!(j == i && n0 == 0 && n1 == 0 && n2 == 0)) {
+          const double r2 = list_r2(pos[j], pos[n + j], pos[2 * n + j], xi, yi, zi, n0, n1, n2, box.h);
+          const bool in_a = r2 < rc2_a;
+          keep = pass == 0 ? in_a : (!in_a && r2 < rc2_r);
+          if (keep && (n0 < -3 || n0 > 3 || n1 < -3 || n1 > 3 || n2 < -3 || n2 > 3)) {
+            bad_image = true;
+            keep = false;
           }
+          entry = pack_entry(j, n0, n1, n2);
+        }
+      }
+      const unsigned long long b = __ballot(keep);
+      if (keep) {
+        const int slot = count + __popcll(b & below);
+        if (slot < cap)
+          nl[(size_t)slot * n + i] = entry;
+        else
+          overflow = true;
+      }
+      count += __popcll(b);
     }
-    if (pass == 0) cnt_a[i] = min(count, cap);
+    if (pass == 0 && lane == 0) cnt_a[i] = min(count, cap);
   }
-  cnt_r[i] = min(count, cap);
+  if (lane == 0) cnt_r[i] = min(count, cap);
   if (overflow) flags[kFlagOverflow] = 1;
   if (bad_image) flags[kFlagImage] = 1;
 }
@@ -741,7 +755,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
   } else {
     launch_kernel(ctx, true, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, s.pos_s.ptr, s.box,
                   1, 1, 1, 0, wrap_in_place ? 1 : 0, s.wrap.ptr, (int*)nullptr, (int*)nullptr);
-    launch_kernel(ctx, false, false, k_build_all_pairs, dim3(blocks_for(n, 64)), dim3(64), n,
+    launch_kernel(ctx, false, false, k_build_all_pairs, dim3(blocks_for(n, 4)), dim3(256), n,
                   s.cap, (const double*)s.pos_s.ptr, s.box, s.kimg[0], s.kimg[1], s.kimg[2],
                   (const int*)s.wrap.ptr, rc2_r, rc2_a, s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr,
                   ctx->flags.ptr);
