@@ -120,7 +120,7 @@ def disordered_rate(args, nep, I, torch, z):
     W = torch.empty((9, n), dtype=torch.float32, device="cuda")
     J = torch.empty((3, n), dtype=torch.float32, device="cuda")
     K = args.disordered_steps
-    thermo = torch.empty((K, 5), dtype=torch.float64, device="cuda")
+    thermo = torch.empty((max(K, 20), 5), dtype=torch.float64, device="cuda")
     ctx.md_step(20, 1.0, 10, I.MASS_SI, p, v, thermo, W, J)
     lanes, _ = ctx.autotune(p, reps=5)
     ctx.synchronize()

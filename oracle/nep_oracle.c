@@ -922,13 +922,22 @@ void or_snes_utilities(int n_pop, double* u) {
   for (int k = 0; k < n_pop; ++k) u[k] = u[k] / tot - 1.0 / n_pop;
 }
 
-/* Sort individuals by loss, smallest first; equal losses keep index order. */
+/* a ranks after b: larger loss, or a NaN loss after any number. */
+static int or_ranks_after(double a, double b) {
+  if (isnan(a)) return !isnan(b);
+  if (isnan(b)) return 0;
+  return a > b;
+}
+
+/* Sort individuals by loss, smallest first (Sec. II E 2, step (b)); NaN
+ * losses rank last; equal losses (and NaNs among themselves) keep index
+ * order. */
 void or_snes_order(int n_pop, const double* loss, int* order) {
   for (int k = 0; k < n_pop; ++k) order[k] = k;
   for (int a = 1; a < n_pop; ++a) { /* insertion sort is stable */
     int v = order[a];
     int b = a - 1;
-    while (b >= 0 && loss[order[b]] > loss[v]) {
+    while (b >= 0 && or_ranks_after(loss[order[b]], loss[v])) {
       order[b + 1] = order[b];
       --b;
     }

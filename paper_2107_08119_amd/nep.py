@@ -114,18 +114,36 @@ def lib() -> C.CDLL:
 
 
 def _ptr(t):
-    return None if t is None else C.c_void_p(t.data_ptr())
+    """Device address of a tensor handed to the library (None for NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise TypeError("the library needs CUDA tensors, got one on %s" % t.device)
+    return C.c_void_p(t.data_ptr())
 
 
-def _require(t, dtype, shape=None, name="tensor"):
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError("%s must be a CUDA tensor" % name)
+def _require(t, dtype, shape=None, name="tensor", min_rows=None):
+    """Check a buffer handed to the library before any call is made: a tensor of
+    `dtype`, contiguous, of exactly `shape` (None entries match any size), or
+    with at least `min_rows` rows where given.  The library writes exactly the
+    documented extent of each output, so a smaller buffer would be written past
+    its end.  That the tensor lives on the GPU is checked by _ptr."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a tensor" % name)
     if t.dtype != dtype:
-        raise TypeError("%s must be %s" % (name, dtype))
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
-    if shape is not None and tuple(t.shape) != tuple(shape):
-        raise ValueError("%s must have shape %s, got %s" % (name, shape, tuple(t.shape)))
+    if shape is not None:
+        ok = t.dim() == len(shape) and all(
+            want is None or got == want for got, want in zip(t.shape, shape))
+        if ok and min_rows is not None:
+            ok = t.shape[0] >= min_rows
+        if not ok:
+            want = tuple("*" if w is None else w for w in shape)
+            if min_rows is not None:
+                want = ">= %d rows of %s" % (min_rows, want)
+            raise ValueError("%s must have shape %s, got %s" % (name, want, tuple(t.shape)))
     return t
 
 
@@ -221,6 +239,14 @@ class Context:
                 out["W"] = torch.empty((9, n), dtype=torch.float32, device=dev)
             if J:
                 out["J"] = torch.empty((3, n), dtype=torch.float32, device=dev)
+        _require(out["F"], torch.float32, (3, n), "F")
+        for key, shape in (("U", (n,)), ("W", (9, n)), ("J", (3, n))):
+            if out.get(key) is not None:
+                _require(out[key], torch.float32, shape, key)
+        if out.get("J") is not None and vel is None:
+            raise ValueError("J needs vel")
+        if out.get("totals") is not None:
+            _require(out["totals"], torch.float64, (13,), "totals")
         self._check(self._lib.nep_compute(
             self._h, _ptr(pos), _ptr(vel), _ptr(out.get("U")), _ptr(out["F"]),
             _ptr(out.get("W")), _ptr(out.get("J")), _ptr(out.get("totals"))))
@@ -266,12 +292,18 @@ class Context:
             self._h, len(n_atoms), *[a.ctypes.data for a in arrays], max_neighbors, C.byref(h)))
         return Dataset(self, h, len(n_atoms), int(n_atoms.sum()))
 
+    def _n_par(self) -> int:
+        if self.hyper is None:
+            raise NepError(NEP_ESTATE, "no parameters loaded")
+        return num_params(self.hyper)
+
     def eval_population(self, ds: "Dataset", Z: torch.Tensor,
                         lam=(1.0, 1.0, 1.0, 0.05, 0.05), out: torch.Tensor | None = None):
-        _require(Z, torch.float32, None, "Z")
+        _require(Z, torch.float32, (None, self._n_par()), "Z")
         n_pop = Z.shape[0]
         if out is None:
             out = torch.empty((n_pop, 6), dtype=torch.float64, device=Z.device)
+        _require(out, torch.float64, (n_pop, 6), "out")
         lam = np.ascontiguousarray(lam, np.float64)
         self._check(self._lib.snes_eval_population(self._h, ds._h, n_pop, _ptr(Z),
                                                    lam.ctypes.data, _ptr(out)))
@@ -286,13 +318,18 @@ class Context:
             r = torch.empty((n_pop, n_par), dtype=torch.float32, device=m.device)
         if Z is None:
             Z = torch.empty((n_pop, n_par), dtype=torch.float32, device=m.device)
+        _require(r, torch.float32, (n_pop, n_par), "r")
+        _require(Z, torch.float32, (n_pop, n_par), "Z")
         self._check(self._lib.snes_sample(self._h, n_par, n_pop, _ptr(m), _ptr(s), seed,
                                           generation, _ptr(r), _ptr(Z)))
         return r, Z
 
     def snes_update(self, m: torch.Tensor, s: torch.Tensor, r: torch.Tensor,
                     loss: torch.Tensor, eta_m: float = 0.0, eta_s: float = 0.0) -> None:
+        _require(r, torch.float32, (None, None), "r")
         n_pop, n_par = r.shape
+        _require(m, torch.float32, (n_par,), "m")
+        _require(s, torch.float32, (n_par,), "s")
         _require(loss, torch.float64, (n_pop, 6), "loss")
         self._check(self._lib.snes_update(self._h, n_par, n_pop, _ptr(m), _ptr(s), _ptr(r),
                                           _ptr(loss), eta_m, eta_s))
@@ -301,7 +338,7 @@ class Context:
         """Time the population kernel shapes on this dataset and keep the
         fastest; returns (lanes per atom chosen, ms per evaluation of the
         2-, 4- and 8-lane shapes)."""
-        _require(Z, torch.float32, None, "Z")
+        _require(Z, torch.float32, (None, self._n_par()), "Z")
         lanes = C.c_int(0)
         ms = (C.c_double * 3)()
         self._check(self._lib.snes_autotune(self._h, ds._h, Z.shape[0], _ptr(Z), reps,
@@ -317,15 +354,15 @@ class Context:
                  eta_s: float = 0.0, best: torch.Tensor | None = None):
         """n_gen SNES generations on the device (sample, evaluate, update per
         generation, replayed as a HIP graph); returns best [n_gen][6]."""
+        _require(r, torch.float32, (None, None), "r")
         n_pop, n_par = r.shape
         _require(m, torch.float32, (n_par,), "m")
         _require(s, torch.float32, (n_par,), "s")
-        _require(r, torch.float32, (n_pop, n_par), "r")
         _require(Z, torch.float32, (n_pop, n_par), "Z")
         _require(loss, torch.float64, (n_pop, 6), "loss")
         if best is None:
             best = torch.empty((max(n_gen, 1), 6), dtype=torch.float64, device=m.device)
-        _require(best, torch.float64, None, "best")
+        _require(best, torch.float64, (None, 6), "best", min_rows=n_gen)
         lam = np.ascontiguousarray(lam, np.float64)
         self._check(self._lib.snes_run(self._h, ds._h, n_par, n_pop, _ptr(m), _ptr(s), seed,
                                        generation, n_gen, lam.ctypes.data, eta_m, eta_s, _ptr(r),
@@ -343,7 +380,7 @@ class Context:
         self._check(self._lib.nep_dataset_set_positions(self._h, ds._h, _ptr(pos)))
 
     def dataset_compute(self, ds: "Dataset", z: torch.Tensor, virial: bool = False) -> dict:
-        _require(z, torch.float32, None, "z")
+        _require(z, torch.float32, (self._n_par(),), "z")
         dev = z.device
         out = {"E": torch.empty(ds.n_struct, dtype=torch.float64, device=dev),
                "F": torch.empty((3, ds.n_atoms), dtype=torch.float32, device=dev)}
@@ -355,11 +392,16 @@ class Context:
 
     def dataset_backward(self, ds: "Dataset", z: torch.Tensor, gE=None, gF=None, F=None,
                          want_pos: bool = False) -> dict:
+        _require(z, torch.float32, (self._n_par(),), "z")
         dev = z.device
         if gE is not None:
             _require(gE, torch.float64, (ds.n_struct,), "gE")
         if gF is not None:
             _require(gF, torch.float32, (3, ds.n_atoms), "gF")
+        if F is not None:
+            _require(F, torch.float32, (3, ds.n_atoms), "F")
+        elif want_pos:
+            raise ValueError("the position gradient needs the forces F of the same z")
         out = {"z": torch.empty(z.shape[0], dtype=torch.float64, device=dev),
                "z32": torch.empty(z.shape[0], dtype=torch.float32, device=dev)}
         if want_pos:
@@ -380,6 +422,11 @@ class Context:
         _require(vel, torch.float64, (3, n), "vel")
         if thermo is None:
             thermo = torch.empty((max(n_steps, 1), 5), dtype=torch.float64, device=pos.device)
+        _require(thermo, torch.float64, (None, 5), "thermo", min_rows=n_steps)
+        if W is not None:
+            _require(W, torch.float32, (9, n), "W")
+        if J is not None:
+            _require(J, torch.float32, (3, n), "J")
         if fe is None:
             self._check(self._lib.nep_md_step(self._h, n_steps, dt, rebuild_every, mass,
                                               _ptr(pos), _ptr(vel), _ptr(thermo), _ptr(W),
@@ -422,8 +469,8 @@ class Correlation:
 
     def sample(self, W: torch.Tensor, vel: torch.Tensor) -> None:
         """W [9][N] float32 and vel [3][N] float64 device tensors (caller order)."""
-        assert W.dtype == torch.float32 and W.is_contiguous() and W.numel() == 9 * self.n_atoms
-        assert vel.dtype == torch.float64 and vel.is_contiguous() and vel.numel() == 3 * self.n_atoms
+        _require(W, torch.float32, (9, self.n_atoms), "W")
+        _require(vel, torch.float64, (3, self.n_atoms), "vel")
         self.ctx._check(self.ctx._lib.nep_vvcf_sample(self.ctx._h, self._h, _ptr(W), _ptr(vel)))
 
     def get(self):

@@ -644,6 +644,54 @@ def test_snes_order_is_stable():
     np.testing.assert_array_equal(order, [4, 1, 3, 2, 0])
 
 
+def test_snes_order_ranks_nan_last():
+    nan = float("nan")
+    np.testing.assert_array_equal(O.snes_order([nan, 1.0, nan, 0.5, 1.0]), [3, 1, 4, 0, 2])
+
+
+def test_snes_scale_rate_uses_the_natural_log():
+    """eta_s = (3 + log N_par) / (5 sqrt N_par) (Sec. II E 2, step (d)) with the natural
+    log, evaluated by hand for the 29-30-1 model (N_par 931) and the general-Si model of
+    Table I (N_par 4101); a base-10 log would give 0.0391 and 0.0242."""
+    assert O.snes_eta_s(931) == pytest.approx(0.064474075, rel=1e-8)
+    assert O.snes_eta_s(4101) == pytest.approx(0.035350262, rel=1e-8)
+
+
+def test_snes_utility_of_the_best_of_fifty():
+    """u_1 for P = 50: ln 26 / (25 ln 26 - ln 25!) - 1/50 = 3.258097 / 23.449032 - 0.02."""
+    assert O.snes_utilities(50)[0] == pytest.approx(0.118945080, rel=1e-8)
+
+
+def test_snes_one_generation_by_hand():
+    """One update of m and s (Sec. II E 2, steps (b)-(d)) for P = 4 individuals and three
+    parameters, worked out by hand.
+
+    Losses (0.3, 0.1, 0.4, 0.2) rank the individuals 1, 3, 0, 2 (best first).  For P = 4
+    the utilities are max(0, ln 3 - ln k) / (ln 3 + ln 1.5) - 1/4:
+    u = (0.480422710, 0.019577290, -0.25, -0.25).  With r_1 = (2, 1, 0), r_3 = (-1, 2, 0),
+    r_0 = (1, 0, 2), r_2 = (0, -1, 1):
+      grad_m = 0.480422710 r_1 + 0.019577290 r_3 - 0.25 (r_0 + r_2)
+             = (0.691268131, 0.769577290, -0.75),
+      grad_s = sum_k u_k (r_k^2 - 1) = (1.691268131, 0.308731869, -1.25).
+    m = (0.5, -0.25, 0), s = (0.1, 0.2, 0.4), eta_m = 1:
+      m' = m + s grad_m = (0.569126813, -0.096084542, -0.3);
+    with eta_s = 0.5, s' = s exp(eta_s/2 grad_s) = (0.152625502, 0.216047941, 0.292646252);
+    with the default eta_s = (3 + ln 3)/(5 sqrt 3) = 0.473266982,
+      s' = (0.149213903, 0.215158220, 0.297576901).
+    Dropping the 1/2 in the exponent would give s'_0 = 0.233; a base-10 log in eta_s
+    would give s'_0 = 0.140."""
+    r = np.array([[1, 0, 2], [2, 1, 0], [0, -1, 1], [-1, 2, 0]], np.float32)
+    loss = [0.3, 0.1, 0.4, 0.2]
+    m0 = np.array([0.5, -0.25, 0.0], np.float32)
+    s0 = np.array([0.1, 0.2, 0.4], np.float32)
+    m, s = O.snes_update(m0, s0, r, loss, eta_m=1.0, eta_s=0.5)
+    np.testing.assert_allclose(m, [0.569126813, -0.096084542, -0.3], rtol=1e-6)
+    np.testing.assert_allclose(s, [0.152625502, 0.216047941, 0.292646252], rtol=1e-6)
+    m, s = O.snes_update(m0, s0, r, loss)
+    np.testing.assert_allclose(m, [0.569126813, -0.096084542, -0.3], rtol=1e-6)
+    np.testing.assert_allclose(s, [0.149213903, 0.215158220, 0.297576901], rtol=1e-6)
+
+
 def test_snes_minimises_a_quadratic():
     n_par, n_pop = 40, 20
     rng = np.random.default_rng(0)
