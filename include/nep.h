@@ -33,6 +33,8 @@
 #ifndef NEP_H_
 #define NEP_H_
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -163,6 +165,39 @@ nep_status nep_set_species(nep_ctx ctx, int n, const int* atomic_numbers_host,
  * [13] float64 = (sum U, sum W (9, row-major), sum J (3)). */
 nep_status nep_compute(nep_ctx ctx, const double* pos_dev, const double* vel_dev, float* U_dev,
                        float* F_dev, float* W_dev, float* J_dev, double* totals_dev);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the work of
+ * nep_build_neighbors followed by nep_compute in one call that makes no
+ * hipMalloc, hipFree or other allocation.  The neighbour list, partial forces
+ * and block sums live in a static workspace of nep_static_workspace_bytes()
+ * bytes (32 MiB) on each device, reserved while the library is loaded there
+ * and located at nep_create.
+ *   n_atoms, pos_dev [3][N] float64, box_host [9] (rows a, b, c in Angstrom,
+ *   host), skin, max_neighbors: as for nep_build_neighbors;
+ *   vel_dev [3][N] float64 or NULL; U_dev [N], F_dev [3][N], W_dev [9][N],
+ *   J_dev [3][N] float32 and totals_dev [13] float64: as for nep_compute
+ *   (F_dev required; J_dev needs vel_dev; totals_dev NULL keeps the totals in
+ *   the context).
+ * The context's parameters and stream are used; its own neighbour list,
+ * species, masses and the MD state kept by nep_md_step are left as they
+ * were.  One species (nep_set_species does not apply).  All arrays are
+ * caller-owned; nothing is kept after the call except in the workspace.
+ * NEP_EINVAL when the system needs more than the workspace (about
+ * 36 * max_neighbors + 300 bytes per atom, plus 12 bytes per list cell; e.g.
+ * 8,000 atoms with 64 slots fit) and for the arguments nep_build_neighbors
+ * rejects; NEP_EDEVICE if the workspace could not be located on this device.
+ * Device errors (list overflow, non-finite values) are latched as for the
+ * other calls and reported by nep_synchronize.  Every call on one device
+ * shares its workspace, which keeps the last call's contents: calls that
+ * overlap on one GPU (different streams or host threads) race. */
+nep_status nep_evaluate_static(nep_ctx ctx, int n_atoms, const double* pos_dev,
+                               const double* box_host, double skin, int max_neighbors,
+                               const double* vel_dev, float* U_dev, float* F_dev, float* W_dev,
+                               float* J_dev, double* totals_dev);
+
+/* Size in bytes of the per-device static workspace of nep_evaluate_static. */
+size_t nep_static_workspace_bytes(void);
 
 /* n_steps of velocity-Verlet NVE for atoms of mass mass_amu:
  *   v += dt/2 F/m;  r += dt v;  (rebuild the list every rebuild_every steps,

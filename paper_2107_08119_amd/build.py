@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnep.so")
 SOURCES = ["nep_api.hip", "neighbors.hip", "force.hip", "generic.hip", "snes.hip",
-           "population.hip", "backward.hip", "spectral.hip"]
+           "population.hip", "backward.hip", "spectral.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -21,11 +21,11 @@ nep_status check_hip(nep_ctx ctx, hipError_t e, const char* what) {
               std::string(what) + ": " + hipGetErrorString(e));
 }
 
-namespace {
-
 int n_des_of(const nep_hyper& h) {
   return (h.n_max_radial + 1) + (h.n_max_angular + 1) * h.l_max;
 }
+
+namespace {
 
 bool hyper_valid(const nep_hyper* h) {
   return h && std::isfinite(h->rc_radial) && std::isfinite(h->rc_angular) && h->rc_angular > 0 &&
@@ -56,14 +56,11 @@ nep_status size_system_buffers(nep_ctx ctx) {
   return NEP_OK;
 }
 
-// One force evaluation of the internal state (positions sys.pos_s, velocities
-// sys.vel_s when vel is true): pass 1 and pass 2 into the internal U, F, W, J,
-// with the totals (13 values, or 5 thermo values in the MD modes) in out.
-// MD modes: block sums go to block_out and are reduced later (out unused).
+}  // namespace
+
 hipError_t evaluate_internal(nep_ctx ctx, bool vel, double* out, int mode, double kick,
-                             double mass, bool want_w = false, bool want_j = false,
-                             double* block_out = nullptr, double dt = 0.0,
-                             double* pos_next = nullptr, const double* fe = nullptr) {
+                             double mass, bool want_w, bool want_j, double* block_out, double dt,
+                             double* pos_next, const double* fe) {
   static const double kNoField[3] = {0.0, 0.0, 0.0};
   if (!fe) fe = kNoField;
   System& s = ctx->sys;
@@ -80,7 +77,21 @@ hipError_t evaluate_internal(nep_ctx ctx, bool vel, double* out, int mode, doubl
   });
 }
 
-}  // namespace
+nep_status check_box(nep_ctx ctx, const double* box_host, double skin, System& probe) {
+  if (!box_host) return fail(ctx, NEP_EINVAL, "box_host is NULL");
+  if (!(skin >= 0.0) || !std::isfinite(skin)) return fail(ctx, NEP_EINVAL, "skin must be >= 0");
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(box_host[k])) return fail(ctx, NEP_EINVAL, "box has non-finite entries");
+  prepare_system_geometry(probe, box_host, ctx->hyper.rc_radial, ctx->hyper.rc_angular, skin);
+  const double* h = probe.box.h;
+  const double det = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) +
+                     h[2] * (h[3] * h[7] - h[4] * h[6]);
+  if (!(std::fabs(det) > 0.0)) return fail(ctx, NEP_EINVAL, "box is singular");
+  if (!probe.use_cells && (probe.kimg[0] > 2 || probe.kimg[1] > 2 || probe.kimg[2] > 2))
+    return fail(ctx, NEP_EINVAL, "box thinner than half the list cutoff along a cell vector");
+  return NEP_OK;
+}
+
 }  // namespace nep
 
 using namespace nep;
@@ -103,6 +114,7 @@ nep_status nep_create(nep_ctx* out, int device, void* hip_stream) {
     nep_destroy(ctx);
     return e == hipErrorOutOfMemory ? NEP_ENOMEM : NEP_EDEVICE;
   }
+  scratch_setup(device);
   *out = ctx;
   return NEP_OK;
 }
@@ -205,21 +217,12 @@ nep_status nep_build_neighbors(nep_ctx ctx, int n_atoms, const double* pos_dev,
   if (n_atoms < 0 || n_atoms > kMaxAtoms)
     return fail(ctx, NEP_EINVAL, "n_atoms must be in [0, 2^23)");
   if (n_atoms > 0 && !pos_dev) return fail(ctx, NEP_EINVAL, "pos_dev is NULL");
-  if (!box_host) return fail(ctx, NEP_EINVAL, "box_host is NULL");
-  if (!(skin >= 0.0) || !std::isfinite(skin)) return fail(ctx, NEP_EINVAL, "skin must be >= 0");
   if (max_neighbors < 1 || (size_t)max_neighbors * (size_t)(n_atoms > 0 ? n_atoms : 1) >= (1ull << 31))
     return fail(ctx, NEP_EINVAL, "need 1 <= max_neighbors and max_neighbors * n_atoms < 2^31");
-  for (int k = 0; k < 9; ++k)
-    if (!std::isfinite(box_host[k])) return fail(ctx, NEP_EINVAL, "box has non-finite entries");
   System& s = ctx->sys;
   System probe;
-  prepare_system_geometry(probe, box_host, ctx->hyper.rc_radial, ctx->hyper.rc_angular, skin);
-  const double det = probe.box.h[0] * (probe.box.h[4] * probe.box.h[8] - probe.box.h[5] * probe.box.h[7]) -
-                     probe.box.h[1] * (probe.box.h[3] * probe.box.h[8] - probe.box.h[5] * probe.box.h[6]) +
-                     probe.box.h[2] * (probe.box.h[3] * probe.box.h[7] - probe.box.h[4] * probe.box.h[6]);
-  if (!(std::fabs(det) > 0.0)) return fail(ctx, NEP_EINVAL, "box is singular");
-  if (!probe.use_cells && (probe.kimg[0] > 2 || probe.kimg[1] > 2 || probe.kimg[2] > 2))
-    return fail(ctx, NEP_EINVAL, "box thinner than half the list cutoff along a cell vector");
+  nep_status chk = check_box(ctx, box_host, skin, probe);
+  if (chk != NEP_OK) return chk;
   DeviceGuard guard(ctx->device);
   for (int k = 0; k < 9; ++k) s.box.h[k] = probe.box.h[k];
   for (int k = 0; k < 9; ++k) s.box.hinv[k] = probe.box.hinv[k];

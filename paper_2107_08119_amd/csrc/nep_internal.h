@@ -42,13 +42,21 @@ __host__ __device__ inline void unpack_image(uint32_t e, int& n0, int& n1, int& 
 // list and the positions.
 constexpr int kPairVectorMaxAtoms = 1 << 17;
 
-// A device array owned by the context that only grows.
+// A device array owned by the context that only grows, or (view) a fixed
+// range of memory owned elsewhere, which it never frees or grows.
 template <class T>
 struct DevBuf {
   T* ptr = nullptr;
   size_t size = 0;
+  bool view = false;
+  void set_view(T* p, size_t n) {
+    ptr = p;
+    size = n;
+    view = true;
+  }
   hipError_t ensure(size_t need) {
     if (ptr && need <= size) return hipSuccess;
+    if (view) return hipErrorOutOfMemory;
     if (ptr) {
       hipError_t e = hipFree(ptr);
       ptr = nullptr;
@@ -65,9 +73,10 @@ struct DevBuf {
     return hipSuccess;
   }
   void release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr && !view) (void)hipFree(ptr);
     ptr = nullptr;
     size = 0;
+    view = false;
   }
   void swap(DevBuf& o) {
     T* p = ptr;
@@ -76,6 +85,9 @@ struct DevBuf {
     size_t z = size;
     size = o.size;
     o.size = z;
+    bool v = view;
+    view = o.view;
+    o.view = v;
   }
 };
 
@@ -407,5 +419,20 @@ struct DeviceGuard {
 // helpers (nep_api.hip)
 nep_status fail(nep_ctx ctx, nep_status code, const std::string& msg);
 nep_status check_hip(nep_ctx ctx, hipError_t e, const char* what);
+int n_des_of(const nep_hyper& h);
+// One force evaluation of the internal state (positions sys.pos_s, velocities
+// sys.vel_s when vel is true): pass 1 and pass 2 into the internal U, F, W, J,
+// with the totals (13 values, or 5 thermo values in the MD modes) in out.
+// MD modes: block sums go to block_out and are reduced later (out unused).
+hipError_t evaluate_internal(nep_ctx ctx, bool vel, double* out, int mode, double kick,
+                             double mass, bool want_w = false, bool want_j = false,
+                             double* block_out = nullptr, double dt = 0.0,
+                             double* pos_next = nullptr, const double* fe = nullptr);
+// noalloc.hip: locate the static workspace of nep_evaluate_static on the
+// current device (once per device, at context creation).
+void scratch_setup(int device);
+// Check a box and its list geometry for a neighbour build (as
+// nep_build_neighbors does); fills `probe` on success.
+nep_status check_box(nep_ctx ctx, const double* box_host, double skin, System& probe);
 
 }  // namespace nep

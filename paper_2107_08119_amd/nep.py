@@ -30,6 +30,7 @@ EXPORTED = [
     "nep_dataset_compute", "nep_dataset_backward", "snes_autotune", "snes_run",
     "snes_set_tile", "nep_autotune", "nep_set_tile", "nep_md_step_driven", "nep_set_species",
     "nep_vvcf_create", "nep_vvcf_destroy", "nep_vvcf_sample", "nep_vvcf_get", "nep_vvcf_spectrum",
+    "nep_evaluate_static", "nep_static_workspace_bytes",
 ]
 
 
@@ -105,9 +106,14 @@ def lib() -> C.CDLL:
         L.nep_dataset_get_positions.argtypes = [vp, vp, vp]
         L.nep_dataset_compute.argtypes = [vp, vp, vp, vp, vp, vp]
         L.nep_dataset_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.nep_evaluate_static.argtypes = [vp, ip, vp, C.POINTER(C.c_double), dp, ip, vp, vp,
+                                          vp, vp, vp, vp]
+        L.nep_static_workspace_bytes.argtypes = []
+        L.nep_static_workspace_bytes.restype = C.c_size_t
         for name in EXPORTED:
             if name not in ("nep_destroy", "nep_last_error", "nep_num_descriptors",
-                            "nep_num_params", "nep_dataset_destroy", "nep_vvcf_destroy"):
+                            "nep_num_params", "nep_dataset_destroy", "nep_vvcf_destroy",
+                            "nep_static_workspace_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -250,6 +256,32 @@ class Context:
         self._check(self._lib.nep_compute(
             self._h, _ptr(pos), _ptr(vel), _ptr(out.get("U")), _ptr(out["F"]),
             _ptr(out.get("W")), _ptr(out.get("J")), _ptr(out.get("totals"))))
+        return out
+
+    def evaluate_static(self, pos: torch.Tensor, box, out: dict, vel: torch.Tensor | None = None,
+                        skin: float = 0.5, max_neighbors: int = 64) -> dict:
+        """nep_evaluate_static: list build and one evaluation of the system at
+        `pos` in the library's static workspace (no device allocation in the
+        call).  `out` holds the caller's output tensors: "F" [3][N] float32
+        (required), and optionally "U" [N], "W" [9][N], "J" [3][N] float32 and
+        "totals" [13] float64.  The context's own list is left as it was."""
+        n = pos.shape[1] if pos.dim() == 2 else 0
+        _require(pos, torch.float64, (3, n), "pos")
+        if vel is not None:
+            _require(vel, torch.float64, (3, n), "vel")
+        _require(out["F"], torch.float32, (3, n), "F")
+        for key, shape in (("U", (n,)), ("W", (9, n)), ("J", (3, n))):
+            if out.get(key) is not None:
+                _require(out[key], torch.float32, shape, key)
+        if out.get("J") is not None and vel is None:
+            raise ValueError("J needs vel")
+        if out.get("totals") is not None:
+            _require(out["totals"], torch.float64, (13,), "totals")
+        b = np.ascontiguousarray(box, dtype=np.float64).reshape(9)
+        self._check(self._lib.nep_evaluate_static(
+            self._h, n, _ptr(pos), b.ctypes.data_as(C.POINTER(C.c_double)), skin, max_neighbors,
+            _ptr(vel), _ptr(out.get("U")), _ptr(out["F"]), _ptr(out.get("W")),
+            _ptr(out.get("J")), _ptr(out.get("totals"))))
         return out
 
     def autotune(self, pos: torch.Tensor, reps: int = 20):

@@ -37,6 +37,8 @@ def test_host_only_calls():
     assert nep.num_params(nep.hyper(5.0, 5.0, 15, 15, 4, 50)) == 4101
     bad = nep.hyper(4.0, 5.0)  # angular cutoff beyond the radial one
     assert nep.num_params(bad) == 0
+    # the fixed size of the static workspace of nep_evaluate_static
+    assert nep.lib().nep_static_workspace_bytes() == 32 << 20
     # context creation without a visible device fails cleanly
     import torch
     if not torch.cuda.is_available():
