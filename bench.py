@@ -321,8 +321,8 @@ def snes_rate(args, ctx, nep, I, torch):
         "gen_per_s": 1.0 / t_gen,
         "ms_per_gen": t_gen * 1e3,
         "generations": G,
-        "tile_lanes_per_atom": lanes,
-        "tile_ms_per_eval": {"2": tile_ms[0], "4": tile_ms[1], "8": tile_ms[2]},
+        "tile_atoms_per_wave": lanes,
+        "tile_ms_per_eval": {"16": tile_ms[0], "32": tile_ms[1], "64": tile_ms[2]},
         "launch": "snes_run: sample, population loss and update of a generation captured as "
                   "one HIP graph, replayed per generation",
         "best_loss_last_gen": best,

@@ -295,30 +295,35 @@ void nep_dataset_destroy(nep_dataset ds);
  *   L_v = sqrt(sum_{s with virial} sum_6 ((W_s - W_s^tar)/N_s)^2 / (6 N_v)),
  *   L_1 = mean |z|,  L_2 = sqrt(mean z^2),
  * where U_s and W_s = sum_i W_i are the NEP energy and virial of structure s.
- * All individuals are evaluated by the same launches (pass 1 of every
- * individual on every atom, then one block per structure and individual),
- * reusing pair records and descriptors cached when the dataset's positions
- * were set; sums are float64 in a fixed order.  The kernels use the tile
- * shape chosen by snes_autotune (4 lanes per atom until then).  The dataset
- * must belong to ctx and match its hyperparameters.  NEP_EINVAL if the
- * dataset exceeds one launch (more than 65535 structures or about 2 million
- * atoms). */
+ * All individuals are evaluated by the same two launches, on the matrix
+ * cores: the network and dU/dq of every (individual, atom), then one block
+ * per tile of whole structures that contracts the descriptor derivatives
+ * cached when the dataset's positions were set (Sec. II D) with every
+ * individual's dU/dq, gathers the forces in LDS and forms the squared errors.
+ * Sums are float64 in a fixed order; the result of an individual does not
+ * depend on the rest of the population.  The network kernel uses the shape
+ * chosen by snes_autotune (32 atoms per wave until then).  The dataset must
+ * belong to ctx and match its hyperparameters.  NEP_EINVAL if a structure has
+ * more than 13,312 atoms (the forces of one individual on one structure must
+ * fit in 160 KB of LDS); more than 52 individuals per 256-atom structure
+ * take one more contraction launch per 52. */
 nep_status snes_eval_population(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z_dev,
                                 const double* lambda_host, double* loss_dev);
 
 /* Tile-shape autotuner for snes_eval_population on this dataset: times each
- * compiled shape of the population kernels (2, 4 and 8 lanes per atom; 128,
- * 64 and 32 atoms per block) over `reps` evaluations (1..1000) of Z_dev
- * [n_pop][N_par] with HIP events on the context's stream, and keeps the
- * fastest for later calls on the dataset.  Host outputs (either may be NULL):
- * *lanes_out = chosen lanes per atom; ms_out[3] = mean ms per evaluation of
- * the shapes in the order above.  Waits for the stream. */
+ * compiled shape of the network kernel (16, 32 and 64 atoms per wave, i.e.
+ * weight fragments reused over 1, 2 or 4 matrix tiles) over `reps`
+ * evaluations (1..1000) of Z_dev [n_pop][N_par] with HIP events on the
+ * context's stream, and keeps the fastest for later calls on the dataset.
+ * Host outputs (either may be NULL): *atoms_out = chosen atoms per wave;
+ * ms_out[3] = mean ms per evaluation of the shapes in the order above.
+ * Waits for the stream. */
 nep_status snes_autotune(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z_dev, int reps,
-                         int* lanes_out, double* ms_out);
+                         int* atoms_out, double* ms_out);
 
-/* Use `lanes` (2, 4 or 8) lanes per atom in the population kernels of this
+/* Use `atoms` (16, 32 or 64) atoms per wave in the network kernel of this
  * dataset, e.g. to reproduce a tuned choice.  NEP_EINVAL for other values. */
-nep_status snes_set_tile(nep_ctx ctx, nep_dataset ds, int lanes);
+nep_status snes_set_tile(nep_ctx ctx, nep_dataset ds, int atoms);
 
 /* Draw the population of generation `generation` (Sec. II E 2, step 2a):
  * r_dev [n_pop][n_par] standard normal (float32) and Z_dev = m + s . r

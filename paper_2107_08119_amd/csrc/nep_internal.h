@@ -275,13 +275,33 @@ struct nep_dataset_s {
   nep::DevBuf<int> pn_ang;     // [N] pairs inside r_c^A (they come first)
   nep::DevBuf<int> pn_in;      // [N] pairs inside a cutoff
   nep::DevBuf<float> desc;     // [N][152] q_i (29) and c_nlm (120), padded
-  int pop_variant = 1;         // population kernel shape: 0, 1, 2 = 2, 4, 8 lanes per atom
+  std::vector<int> off_host;   // [S+1] first atom of each structure
+  // Population operands (geometry only, rebuilt with the positions): the
+  // padded descriptors, and per atom the derivatives of its descriptor with
+  // respect to its pair vectors in matrix-core fragment order (see
+  // population.hip); structures grouped into tiles of at most tile_max atoms.
+  nep::DevBuf<float> qpad;       // [N][32]
+  nep::DevBuf<float> pfrag;      // [chunks][64]
+  nep::DevBuf<float4> ppair;     // [sum of pairs] unit vector and receiver index in its tile
+  nep::DevBuf<int4> pmeta;       // [N] first chunk, first pair, pairs, angular pairs
+  nep::DevBuf<int> tile_off;     // [T+1] first atom of each tile
+  nep::DevBuf<int> tile_s0;      // [T+1] first structure of each tile
+  nep::DevBuf<int> tile_order;   // [T] tiles by decreasing work
+  nep::DevBuf<int> stile0;       // [S] first atom of the tile holding structure s
+  nep::DevBuf<float2> pnorm;     // [N] largest row 1-norm of the force rows, of the virial rows
+  nep::DevBuf<int> tile_deg;     // [T] most additions into one force component of the tile
+  int n_tiles = 0, tile_max = 0;
+  int tile_kc = 0;               // individuals per contraction launch the tiles were sized for
+  int pop_variant = 1;         // network kernel shape: 0, 1, 2 = 16, 32, 64 atoms per wave
   unsigned long long serial = 0;  // unique per dataset created by the process
   bool pop_tuned = false;
   // population workspace
-  nep::DevBuf<nep::Partial3> pin;   // [pop][cap][N] partial forces
-  nep::DevBuf<float> fown;          // [pop][3][N]
+  nep::DevBuf<nep::Partial3> pin;   // [cap][N] partial forces (nep_dataset_compute)
+  nep::DevBuf<float> fown;          // [3][N]
   nep::DevBuf<float> U;             // [pop][N]
+  nep::DevBuf<float> dq;            // [pop][N][32] dU/dq of every individual
+  nep::DevBuf<float> dqmax;         // [N][pop] largest |dU/dq| of every atom and individual
+  nep::DevBuf<int2> tscale;         // [T][pop] fixed-point exponents of forces and virials
   nep::DevBuf<double> atom_terms;   // [10][N] per-atom U and W (forward)
   nep::DevBuf<double> struct_sq;    // [pop][S][3] squared errors per structure
   // backward workspace
@@ -293,6 +313,16 @@ struct nep_dataset_s {
     pn_ang.release();
     pn_in.release();
     desc.release();
+    qpad.release();
+    pfrag.release();
+    ppair.release();
+    pmeta.release();
+    tile_off.release();
+    tile_s0.release();
+    tile_order.release();
+    stile0.release();
+    pnorm.release();
+    tile_deg.release();
   }
 };
 
@@ -302,11 +332,14 @@ namespace nep {
 // Pair records and per-atom descriptors of a dataset's current positions.
 hipError_t prepare_dataset_geometry(nep_ctx ctx, nep_dataset ds);
 // Loss sums sq[k][s][3] of n_pop individuals (Z [n_pop][N_par]) with the
-// given kernel variant (0..population_variants()-1).
+// given network-kernel shape (0..population_variants()-1).
 hipError_t launch_population(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z, int variant,
                              bool first);
 int population_variants();
-int population_lanes(int variant);
+int population_atoms(int variant);
+// Largest structure snes_eval_population handles (its forces for one
+// individual must fit the contraction kernel's LDS).
+int population_max_structure();
 
 // neighbours.hip
 // Build the list of the internal positions sys.pos_s; on the cell path the

@@ -1,4 +1,6 @@
-// Population evaluation over a training set (Sec. II E) on gfx950.
+// Population evaluation over a training set (Sec. II E) on gfx950: the loss
+// of every parameter vector of a population over every structure, in two
+// launches per population, with the dense contractions on the matrix cores.
 //
 // Training positions do not change between generations, so everything that
 // depends on geometry alone is computed once per dataset:
@@ -6,13 +8,37 @@
 //     the angular list part first, then the rest inside r_c^R), each as a
 //     record (float32 displacement r_ij, index of its reverse record);
 //   * every atom's descriptor q_i and angular moments c_nlm (factorised form
-//     of Eq. qinl), 149 floats.
-// A generation then needs, per (atom, individual), only the network (Eqs.
-// nn1, nn2), the coefficients a_nlm = 2 dU/dq_nl c_nlm and the partial forces
-// (Sec. II D), followed by one block per (structure, individual) that forms
-// F_i = sum_j p_ij - sum_j p_ji, the structure's energy and virial (Sec.
-// II A) and the squared errors of the loss (Sec. II E), summed in float64 in
-// a fixed order.
+//     of Eq. qinl);
+//   * per pair, the derivative of atom i's descriptor with respect to r_ij,
+//     D_ij[b][nu] = dq^i_nu / d(r_ij)_b (Sec. II D).  It depends on geometry
+//     only (the angular part through c_nlm), so the partial force of any
+//     parameter vector is the contraction p_ij = sum_nu D_ij[.][nu] dU/dq_nu.
+//     Its radial part is g_n'(r) r_ij/r, stored as the scalars g_n'; the
+//     angular part is 3 x 20 numbers per angular pair;
+//   * per atom, G_i = sum_j D_ij (3 x 29: sum_j p_ij = G_i dU/dq) and
+//     V_i[a][b] = -sum_j (r_ij)_a D_ij[b] (9 x 29: the structure's virial is
+//     sum_i V_i dU/dq, since summing W_i = sum_j r_ij (x) p_ji over a
+//     structure visits every pair in both directions, r_ji = -r_ij).
+// These operands are stored in the fragment order of the 16x16x4 float32
+// matrix instruction, so one wave-wide load fetches one step's operand.
+//
+// A generation then runs:
+//   * the network kernel: per individual k, act^T = W1_k Q^T (rows neurons,
+//     columns atoms), tanh, U_i, and dU/dq = (w2 sech^2(act)) W1_k as two
+//     products on the matrix cores (Eqs. nn1, nn2 and their input gradient);
+//   * the contraction kernel: one block per tile of whole structures keeps
+//     the forces of every atom of the tile for every individual in LDS.  Wave
+//     w owns the individuals k = w mod 4, sixteen per matrix tile, and for
+//     each atom i multiplies D_i (rows: pair components) by dU/dq_i (columns:
+//     individuals); each product element p_ij goes to F_j with an LDS add
+//     (F_i = sum_j p_ij - sum_j p_ji, Sec. II A), G_i and V_i give the own
+//     force and the virial.  No partial force goes to memory.  At the end of
+//     each structure the wave forms its energy, force and virial errors in
+//     float64 in a fixed order (Sec. II E).  Only wave w touches the forces
+//     of its individuals, so the sums do not depend on scheduling.
+#include <algorithm>
+#include <vector>
+
 #include "nep_terms.h"
 
 namespace nep {
@@ -136,198 +162,676 @@ __global__ __launch_bounds__(kBlock) void k_ds_descriptors(int N, const float4* 
     d4[t] = make_float4(d[4 * t], d[4 * t + 1], d[4 * t + 2], d[4 * t + 3]);
 }
 
-// Pass 1 of every individual k = blockIdx.x on the atoms of block y: network,
-// coefficients and partial forces, written to the reverse records of
-// pin + k pstride; fown = sum_j p_ij and U per atom.
-template <int L>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_pop_partials(
-    int N, const float4* __restrict__ rec, const int* __restrict__ n_ang,
-    const int* __restrict__ n_in, const float* __restrict__ desc, const float* __restrict__ Z,
-    int n_par, float rc_r, float rc_a, Partial3* __restrict__ pin, size_t pstride,
-    float* __restrict__ fown, float* __restrict__ U) {
-  __shared__ float4 rows[NetRows<NDES, NNEU>::kFloat4];
-  __shared__ float b2;
-  // logical (individual, atom block), contiguous atom blocks per XCD
-  const unsigned lb = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
-  const size_t k = lb % gridDim.x;
-  const unsigned by = lb / gridDim.x;
-  load_net_rows<NDES, NNEU>(Z + k * (size_t)n_par, rows, &b2);
-  pin += k * pstride;
-  fown += k * 3 * (size_t)N;
-  U += k * (size_t)N;
-  __syncthreads();
-  const int gid = (int)by * blockDim.x + threadIdx.x;
-  const int i = gid / L;
-  const int lane = gid % L;
-  const bool active = i < N;
-  const int ii = active ? i : 0;
-  const int na = active ? n_ang[i] : 0, ni = active ? n_in[i] : 0;
-  const float rcr_inv = 1.f / rc_r, rca_inv = 1.f / rc_a;
-  float q[NDES];
-  float c[NA][NLM];
-  {
-    const float4* d4 = reinterpret_cast<const float4*>(desc + (size_t)ii * kDescRow);
-    float d[kDescRow];
+// ------------------------------------------------- population operands
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// D[16x4] x B[4x16] + C on the matrix cores: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16] and holds C[4 (l/16) + r][l%16] in element r.
+__device__ __forceinline__ f32x4 mma(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Padded descriptor order of the population kernels: radial components at
+// 0..8, zeros at 9..11, angular components nu = 9..28 at nu + 3 = 12..31, so
+// that a lane's K steps of the angular product (K index 12 + 4 s + l/16) are
+// a subset of those of the full product (4 s + l/16).
+constexpr int kQ = 32;
+constexpr int kAng0 = 12;
+__host__ __device__ constexpr int padded(int v) { return v < NR ? v : v + (kAng0 - NR); }
+
+// Fragment chunks (64 floats) per atom: the own-force/virial tile (8 K steps
+// over the padded descriptor), ns radial tiles of 16 pairs (3 K steps: the
+// nine g_n' and three zeros), na angular tiles of 16 pair components (5 K
+// steps over the angular part).
+constexpr int kGSteps = 8, kSSteps = 3, kASteps = 5;
+__host__ __device__ inline int radial_tiles(int pairs) { return (pairs + 15) / 16; }
+__host__ __device__ inline int angular_tiles(int ang) { return (3 * ang + 15) / 16; }
+__host__ __device__ inline int atom_chunks(int pairs, int ang) {
+  return kGSteps + kSSteps * radial_tiles(pairs) + kASteps * angular_tiles(ang);
+}
+
+// Fixed-point accumulators of a tile in LDS (162,816 bytes): forces
+// [atom][3][KC] and structure virials [structure][9][KC], 32-bit integers.
+constexpr int kLdsInts = 40704;
+
+__global__ void k_pop_qpad(int N, const float* __restrict__ desc, float* __restrict__ qpad) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)N * kQ) return;
+  const int i = (int)(t / kQ), v = (int)(t % kQ);
+  float q = 0.f;
+  if (v < NR)
+    q = desc[(size_t)i * kDescRow + v];
+  else if (v >= kAng0)
+    q = desc[(size_t)i * kDescRow + v - (kAng0 - NR)];
+  qpad[t] = q;
+}
+
+// One thread per (atom i, descriptor component nu < 29): D_ij[.][nu] for
+// every pair of i, written into i's radial or angular fragment chunks, and
+// row nu of G_i and V_i.  The thread of nu = 0 also writes the pair records
+// (r_ij/r_ij, receiver index within the tile).  pfrag must be zero before.
+__global__ __launch_bounds__(kBlock) void k_pop_geo(
+    int N, const float4* __restrict__ rec, const int4* __restrict__ pmeta,
+    const float* __restrict__ desc, const int* __restrict__ struct_of,
+    const int* __restrict__ stile0, float rc_r, float rc_a, float* __restrict__ pfrag,
+    float4* __restrict__ ppair) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / 32, v = gid % 32;
+  if (i >= N || v >= NDES) return;
+  const int4 m = pmeta[i];
+  const size_t dbase = (size_t)(unsigned)m.x;
+  const int P = m.z, A = m.w;
+  const int ns = radial_tiles(P);
+  const int t0 = stile0[struct_of[i]];
+  float G[3] = {0.f, 0.f, 0.f};
+  float V[9];
 #pragma unroll
-    for (int t = 0; t < kDescRow / 4; ++t) {
-      const float4 v = d4[t];
-      d[4 * t] = v.x;
-      d[4 * t + 1] = v.y;
-      d[4 * t + 2] = v.z;
-      d[4 * t + 3] = v.w;
+  for (int q = 0; q < 9; ++q) V[q] = 0.f;
+  if (v < NR) {
+    const float rcr_inv = 1.f / rc_r;
+    for (int p = 0; p < P; ++p) {
+      const float4 e = rec[(size_t)p * N + i];
+      const float r2 = pair_r2(e.x, e.y, e.z);
+      const float rinv = __builtin_amdgcn_rsqf(r2);
+      const float r = r2 * rinv;
+      float fc, dfc, dxdr, T[NR], dT[NR];
+      chebyshev_terms<NR>(r, rcr_inv, fc, dfc, dxdr, T, dT);
+      const float gp = 0.5f * (dfc * (T[v] + 1.f) + fc * dxdr * dT[v]);
+      const size_t chunk = dbase + kGSteps + (size_t)kSSteps * (p / 16) + v / 4;
+      pfrag[chunk * 64 + (v % 4) * 16 + p % 16] = gp;
+      const float d[3] = {gp * e.x * rinv, gp * e.y * rinv, gp * e.z * rinv};
+      const float rv[3] = {e.x, e.y, e.z};
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        G[b] += d[b];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) V[3 * a + b] -= rv[a] * d[b];
+      }
+      if (v == 0) {
+        const int j = (int)((unsigned)__float_as_int(e.w) % (unsigned)N);
+        ppair[(size_t)m.y + p] =
+            make_float4(e.x * rinv, e.y * rinv, e.z * rinv, __int_as_float(j - t0));
+      }
     }
-#pragma unroll
-    for (int v = 0; v < NDES; ++v) q[v] = d[v];
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-      for (int m = 0; m < NLM; ++m) c[a][m] = d[NDES + a * NLM + m];
+  } else {
+    const int n = (v - NR) / LMAX, l = (v - NR) % LMAX + 1;
+    const float rca_inv = 1.f / rc_a;
+    const float* c = desc + (size_t)i * kDescRow + NDES + n * NLM;
+    for (int a = 0; a < A; ++a) {
+      const float4 e = rec[(size_t)a * N + i];
+      const float r2 = pair_r2(e.x, e.y, e.z);
+      const float rinv = __builtin_amdgcn_rsqf(r2);
+      const float r = r2 * rinv;
+      float g[NA], dg[NA];
+      radial_basis<NA, true>(r, rca_inv, g, dg);
+      const float x = e.x * rinv, y = e.y * rinv, z = e.z * rinv;
+      const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+      const float xyz = xy * z;
+      (void)xyz;
+      // s_y = sum_m c_nlm Yhat_lm, s_g = sum_m c_nlm grad Yhat_lm (l fixed)
+      float sy = 0.f, sgx = 0.f, sgy = 0.f, sgz = 0.f;
+#define NEP_DG(idx, YV, GX, GY, GZ)                      \
+  if ((idx) >= l * l - 1 && (idx) < (l + 1) * (l + 1) - 1) { \
+    const float cm = c[idx];                              \
+    sy += cm * (YV);                                      \
+    sgx += cm * (GX);                                     \
+    sgy += cm * (GY);                                     \
+    sgz += cm * (GZ);                                     \
   }
-  float dq[NDES];
-  float u;
-  network<NDES, NNEU, L>(q, rows, b2, lane, dq, u);
-  if (active && lane == 0) U[i] = u;
-  angular_coefficients<NR, NA, LMAX>(dq, c);
-  const float dqs = radial_dq_sum<NR>(dq);
-  float fx = 0.f, fy = 0.f, fz = 0.f;
-  for (int t = lane; t < ni; t += L) {
-    const float4 p = rec[(size_t)t * N + i];
-    float px, py, pz;
-    pair_force<NR, NA, LMAX>(p.x, p.y, p.z, true, t < na, rcr_inv, rca_inv, dq, dqs, c, px, py,
-                             pz);
-    fx += px;
-    fy += py;
-    fz += pz;
-    pin[(size_t)(unsigned)__float_as_int(p.w)] = Partial3{px, py, pz};
+      NEP_YLM_TABLE(NEP_DG)
+#undef NEP_DG
+      // d/dr_ij [g_n(r) Yhat(r/|r|)] = g_n' Yhat u + g_n (grad Yhat - u (u.grad Yhat)) / r
+      const float ug = x * sgx + y * sgy + z * sgz;
+      const float d[3] = {2.f * (dg[n] * sy * x + g[n] * (sgx - x * ug) * rinv),
+                          2.f * (dg[n] * sy * y + g[n] * (sgy - y * ug) * rinv),
+                          2.f * (dg[n] * sy * z + g[n] * (sgz - z * ug) * rinv)};
+      const float rv[3] = {e.x, e.y, e.z};
+      const int kap = v - NR;  // K index within the angular product
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int row = 3 * a + b;
+        const size_t chunk =
+            dbase + kGSteps + (size_t)kSSteps * ns + (size_t)kASteps * (row / 16) + kap / 4;
+        pfrag[chunk * 64 + (kap % 4) * 16 + row % 16] = d[b];
+        G[b] += d[b];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) V[3 * q + b] -= rv[q] * d[b];
+      }
+    }
   }
-  fx = group_sum<L>(fx);
-  fy = group_sum<L>(fy);
-  fz = group_sum<L>(fz);
-  if (active && lane == 0) {
-    fown[i] = fx;
-    fown[N + i] = fy;
-    fown[2 * N + i] = fz;
+  // own-force / virial tile: rows 0..2 = G, rows 3..11 = V (row-major ab)
+  const int kap = padded(v);
+  float* gt = pfrag + (dbase + kap / 4) * 64 + (kap % 4) * 16;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) gt[b] = G[b];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) gt[3 + q] = V[q];
+}
+
+// The largest of a and b, NaN if either is NaN (so a non-finite dU/dq reaches
+// the bound and marks the individual).
+__device__ __forceinline__ float max_nan(float a, float b) { return (b > a || b != b) ? b : a; }
+
+// dU/dq of every individual on atoms [64 CT w, 64 CT w + 16 CT) for wave w:
+// act^T = W1_k Q^T (rows: neurons in two tiles of 16; columns: atoms), the
+// neurons' tanh, U_i, and dU/dq_i = sum_mu w2_mu sech^2(act_mu) W1_k[mu] as
+// a product whose K order (neurons) follows what each lane already holds,
+// so G = w2 sech^2 never moves between lanes.  dq [k][N][32] (padded order,
+// zeros at 9..11), U [k][N], dqmax [N][n_pop] = max_nu |dU/dq_nu|.
+template <int CT>
+__global__ __launch_bounds__(kBlock) void k_pop_net(int N, int n_pop, int n_par,
+                                                    const float* __restrict__ qpad,
+                                                    const float* __restrict__ Z,
+                                                    float* __restrict__ dq,
+                                                    float* __restrict__ U,
+                                                    float* __restrict__ dqmax) {
+  const int l = threadIdx.x & 63, col = l & 15, h = l >> 4;
+  const int a0 = (blockIdx.x * (kBlock / 64) + threadIdx.x / 64) * 16 * CT;
+  if (a0 >= N) return;  // whole waves leave together
+  // Q^T fragments: B[kappa = 4 s + h][atom = col]
+  float qb[CT][8];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int a = a0 + 16 * ct + col;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) qb[ct][s] = a < N ? qpad[(size_t)a * kQ + 4 * s + h] : 0.f;
+  }
+  for (int k = 0; k < n_pop; ++k) {
+    const float* z = Z + (size_t)k * n_par;
+    // W1 as the first product's A[mu = 16 mt + col][kappa = 4 s + h]
+    float wa[2][8];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int mu = 16 * mt + col, kp = 4 * s + h;
+        const int nu = kp < NR ? kp : kp - (kAng0 - NR);
+        wa[mt][s] = (mu < NNEU && (kp < NR || kp >= kAng0)) ? z[mu * NDES + nu] : 0.f;
+      }
+    // bias and output weight of the lane's neurons mu = 16 mt + 4 h + r
+    float b1[2][4], w2[2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int mu = 16 * mt + 4 * h + r;
+        b1[mt][r] = mu < NNEU ? z[NNEU * NDES + mu] : 0.f;
+        w2[mt][r] = mu < NNEU ? z[NNEU * (NDES + 1) + mu] : 0.f;
+      }
+    const float b2 = z[NNEU * (NDES + 2)];
+    // W1 as the second product's B[kappa][nu' = 16 nt + col]; K step s of
+    // lane group h holds neuron 16 (s / 4) + 4 h + s % 4
+    float wb[2][8];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int mu = 16 * (s / 4) + 4 * h + (s % 4), kp = 16 * nt + col;
+        const int nu = kp < NR ? kp : kp - (kAng0 - NR);
+        wb[nt][s] = (mu < NNEU && (kp < NR || kp >= kAng0)) ? z[mu * NDES + nu] : 0.f;
+      }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      f32x4 act[2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        act[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) act[mt] = mma(wa[mt][s], qb[ct][s], act[mt]);
+      }
+      float gm[2][4];
+      float u = 0.f;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float x = act[mt][r] - b1[mt][r];
+          // tanh and 1 - tanh^2 from e = exp(-2|x|) (no cancellation)
+          const float ea = __expf(-2.f * fabsf(x));
+          const float inv = __builtin_amdgcn_rcpf(1.f + ea);
+          const float th = copysignf((1.f - ea) * inv, x);
+          u += w2[mt][r] * th;
+          gm[mt][r] = w2[mt][r] * (4.f * ea * inv * inv);
+        }
+      u += __shfl_xor(u, 16, 64);
+      u += __shfl_xor(u, 32, 64);
+      const int a = a0 + 16 * ct + col;
+      if (h == 0 && a < N) U[(size_t)k * N + a] = u - b2;
+      f32x4 o[2];
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        o[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) o[nt] = mma(gm[s / 4][s % 4], wb[nt][s], o[nt]);
+      }
+      float mx[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ar = a0 + 16 * ct + 4 * h + r;
+        if (ar < N) {
+          dq[((size_t)k * N + ar) * kQ + col] = o[0][r];
+          dq[((size_t)k * N + ar) * kQ + 16 + col] = o[1][r];
+        }
+        mx[r] = max_nan(fabsf(o[0][r]), fabsf(o[1][r]));
+      }
+      // largest |dU/dq| of each atom: over the 16 lanes of its row group
+#pragma unroll
+      for (int d = 1; d < 16; d <<= 1)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) mx[r] = max_nan(mx[r], __shfl_xor(mx[r], d, 64));
+      if (col < 4) {
+        const int ar = a0 + 16 * ct + 4 * h + col;
+        const float v = col == 0 ? mx[0] : col == 1 ? mx[1] : col == 2 ? mx[2] : mx[3];
+        if (ar < N) dqmax[(size_t)ar * n_pop + k] = v;
+      }
+    }
   }
 }
 
-// Pass 2 and the loss sums of individual k = blockIdx.x on structure
-// s = blockIdx.y: per atom F_i = sum_j p_ij - sum_j p_ji and
-// W_i = sum_j r_ij (x) p_ji; per structure
-// sq[(k S + s) 3 + (0, 1, 2)] = (((U_s - E_s)/N_s)^2, sum_i |F_i - F_i^tar|^2,
-// sum over xx yy zz xy yz zx of ((W_s - W_s^tar)/N_s)^2, or 0 without a target).
-template <int L>
-__global__ __launch_bounds__(kBlock) void k_pop_struct(
-    int N, int S, const int* __restrict__ off, const float4* __restrict__ rec,
-    const int* __restrict__ n_in, const Partial3* __restrict__ pin, size_t pstride,
-    const float* __restrict__ fown, const float* __restrict__ U, const double* __restrict__ f_tar,
+// Per atom: the largest 1-norm (over the K index) of its force rows (own
+// force rows of the first tile, radial and angular rows) and of its virial
+// rows.  A force contribution of individual k is at most the first times
+// max |dU/dq_i|; a virial contribution the second.
+__global__ void k_pop_norms(int N, const int4* __restrict__ pmeta, const float* __restrict__ pfrag,
+                            float2* __restrict__ pnorm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int4 m = pmeta[i];
+  const float* f = pfrag + (size_t)(unsigned)m.x * 64;
+  const int P = m.z, A = m.w, ns = radial_tiles(P), na = angular_tiles(A);
+  float fmax = 0.f, vmax = 0.f;
+#pragma unroll 1
+  for (int row = 0; row < 12; ++row) {
+    float s = 0.f;
+    for (int q = 0; q < kGSteps; ++q)
+      for (int hh = 0; hh < 4; ++hh) s += fabsf(f[64 * q + 16 * hh + row]);
+    if (row < 3)
+      fmax = fmaxf(fmax, s);
+    else
+      vmax = fmaxf(vmax, s);
+  }
+  const float* fs = f + 64 * kGSteps;
+#pragma unroll 1
+  for (int p = 0; p < P; ++p) {
+    float s = 0.f;
+    for (int q = 0; q < kSSteps; ++q)
+      for (int hh = 0; hh < 4; ++hh) s += fabsf(fs[64 * (kSSteps * (p / 16) + q) + 16 * hh + p % 16]);
+    fmax = fmaxf(fmax, s);
+  }
+  const float* fa = fs + 64 * kSSteps * ns;
+#pragma unroll 1
+  for (int row = 0; row < 3 * A; ++row) {
+    float s = 0.f;
+    for (int q = 0; q < kASteps; ++q)
+      for (int hh = 0; hh < 4; ++hh)
+        s += fabsf(fa[64 * (kASteps * (row / 16) + q) + 16 * hh + row % 16]);
+    fmax = fmaxf(fmax, s);
+  }
+  (void)na;
+  pnorm[i] = make_float2(fmax, vmax);
+}
+
+// Fixed-point exponents of tile t = blockIdx.x for individuals k: a force
+// component of the tile receives at most tile_deg[t] contributions, each at
+// most max_i pnorm_i.x dqmax_i^k, and a structure's virial component at most
+// sum_i pnorm_i.y dqmax_i^k; values are stored as round(x 2^e) in 32 bits
+// with e chosen so that these bounds stay below 2^30.  A non-finite bound
+// (a non-finite dU/dq) gives e = kBadScale.
+constexpr int kBadScale = -1000;
+__device__ __forceinline__ int fixed_exponent(float bound) {
+  if (!(bound <= 3.0e38f)) return kBadScale;  // NaN or infinite
+  if (bound <= 0.f) return 30;
+  int e;
+  (void)frexpf(bound, &e);  // bound < 2^e
+  const int s = 30 - e;
+  return s < -100 ? -100 : (s > 100 ? 100 : s);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pop_scale(int n_pop, const int* __restrict__ tile_off,
+                                                      const int* __restrict__ tile_deg,
+                                                      const float2* __restrict__ pnorm,
+                                                      const float* __restrict__ dqmax,
+                                                      int2* __restrict__ tscale) {
+  __shared__ float sf[kBlock], sv[kBlock];
+  const int t = blockIdx.x;
+  const int a0 = tile_off[t], a1 = tile_off[t + 1];
+  const int kl = threadIdx.x & 63, part = threadIdx.x >> 6;
+  for (int k0 = 0; k0 < n_pop; k0 += 64) {
+    const int k = k0 + kl;
+    float bf = 0.f, bv = 0.f;
+    if (k < n_pop) {
+#pragma unroll 8
+      for (int i = a0 + part; i < a1; i += kBlock / 64) {
+        const float2 pn = pnorm[i];
+        const float d = dqmax[(size_t)i * n_pop + k];
+        bf = max_nan(bf, pn.x * d);
+        bv += pn.y * d;
+      }
+    }
+    sf[threadIdx.x] = bf;
+    sv[threadIdx.x] = bv;
+    __syncthreads();
+    if (part == 0 && k < n_pop) {
+      for (int p = 1; p < kBlock / 64; ++p) {
+        bf = max_nan(bf, sf[64 * p + kl]);
+        bv += sv[64 * p + kl];
+      }
+      tscale[(size_t)t * n_pop + k] =
+          make_int2(fixed_exponent((float)tile_deg[t] * bf), fixed_exponent(bv));
+    }
+    __syncthreads();
+  }
+}
+
+// Operands of one owner atom in the contraction kernel, all requested
+// before the atom's first product.  Atoms with at most kFastPairs pairs and
+// kFastAng angular pairs (two radial and three angular tiles) are fetched
+// whole; others read their further tiles as they are used.
+constexpr int kFastPairs = 32, kFastAng = 16;
+constexpr int kFastS = 2, kFastA = 3;
+constexpr int kCols = 4;  // column tiles of 16 individuals per wave
+struct AtomOps {
+  float b[kCols][8];   // dU/dq of the lane's individuals, K index 4 q + h
+  float g[kGSteps];    // own-force / virial tile
+  float s[kFastS][kSSteps];
+  float a[kFastA][kASteps];
+  float4 ps[kFastS][4];  // pair records (unit vector, receiver) of the lane's radial rows
+  float pw[kFastA][4];   // receiver (record .w) of the pair of each angular row
+};
+
+__device__ __forceinline__ bool fast_atom(int4 m) { return m.z <= kFastPairs && m.w <= kFastAng; }
+
+// Every load is issued unconditionally (the operand arrays carry kPadChunks
+// chunks and kPadPairs pair records of padding, so a tile or pair past the
+// atom's own reads a neighbour's data or padding) and masked at use: with no
+// branch between the loads, each operand waits only for itself.
+constexpr int kPadChunks = 64, kPadPairs = 64;
+__device__ __forceinline__ void fetch_atom(AtomOps& o, int4 m, int i, const float* const (&dqk)[kCols],
+                                           const float* pfrag, const float4* ppair, int l,
+                                           int h) {
+#pragma unroll
+  for (int c = 0; c < kCols; ++c)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o.b[c][q] = dqk[c][(size_t)i * kQ + 4 * q];
+  const float* fr = pfrag + (size_t)(unsigned)m.x * 64 + l;
+  const int ns = radial_tiles(m.z);
+#pragma unroll
+  for (int q = 0; q < kGSteps; ++q) o.g[q] = fr[64 * q];
+#pragma unroll
+  for (int tt = 0; tt < kFastS; ++tt)
+#pragma unroll
+    for (int q = 0; q < kSSteps; ++q) o.s[tt][q] = fr[64 * (kGSteps + kSSteps * tt + q)];
+  const float* fa = fr + 64 * (kGSteps + kSSteps * ns);
+#pragma unroll
+  for (int tt = 0; tt < kFastA; ++tt)
+#pragma unroll
+    for (int q = 0; q < kASteps; ++q) o.a[tt][q] = fa[64 * (kASteps * tt + q)];
+  const float4* pp = ppair + (size_t)m.y;
+#pragma unroll
+  for (int tt = 0; tt < kFastS; ++tt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o.ps[tt][r] = pp[16 * tt + 4 * h + r];
+#pragma unroll
+  for (int tt = 0; tt < kFastA; ++tt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o.pw[tt][r] = pp[(16 * tt + 4 * h + r) / 3].w;
+}
+
+// Forces, energies, virials and squared errors of individuals k0 .. k0+KC-1
+// (KC <= 64) on the tile of structures tile_order[blockIdx.x].
+// Phase 1: the waves take the tile's atoms in turn; for each atom and each
+// column tile of 16 individuals they multiply the atom's operands by dU/dq
+// and add every product element, as round(x 2^e) with the tile's exponent e
+// of the individual, into 32-bit LDS accumulators of forces [atom][3][KC]
+// and structure virials [structure][9][KC].  Integer sums do not depend on
+// their order, so results are the same for any schedule.
+// Phase 2: one unit per (structure, individual): lanes over the atoms form
+// the energy, force and virial errors in float64 in a fixed order.
+constexpr int kContractWaves = 8;
+__global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
+    int N, int S, int k0, int KC, int n_pop, const int* __restrict__ tile_order,
+    const int* __restrict__ tile_off, const int* __restrict__ tile_s0,
+    const int* __restrict__ off, const int* __restrict__ struct_of,
+    const int4* __restrict__ pmeta, const float* __restrict__ pfrag,
+    const float4* __restrict__ ppair, const float* __restrict__ dq, const float* __restrict__ U,
+    const int2* __restrict__ tscale, const double* __restrict__ f_tar,
     const double* __restrict__ e_tar, const double* __restrict__ w_tar,
     const int* __restrict__ has_v, double* __restrict__ sq) {
-  __shared__ double sw[kBlock / 64][8];
-  __shared__ double tot[8];
-  // logical (individual, structure), contiguous structures per XCD
-  const unsigned lb = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
-  const size_t k = lb % gridDim.x;
-  const int s = (int)(lb / gridDim.x);
-  pin += k * pstride;
-  fown += k * 3 * (size_t)N;
-  U += k * (size_t)N;
-  const int a0 = off[s], a1 = off[s + 1];
-  const int lane = threadIdx.x % L;
-  double acc[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  for (int base = a0; base < a1; base += kBlock / L) {
-    const int i = base + (int)threadIdx.x / L;
-    const bool active = i < a1;
-    const int ni = active ? n_in[i] : 0;
-    float f0 = 0.f, f1 = 0.f, f2 = 0.f;
-    float w[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) w[q] = 0.f;
-    for (int t = lane; t < ni; t += L) {
-      const size_t idx = (size_t)t * N + i;
-      const float4 r = rec[idx];
-      const Partial3 p = pin[idx];
-      f0 -= p.x;
-      f1 -= p.y;
-      f2 -= p.z;
-      w[0] += r.x * p.x;
-      w[1] += r.x * p.y;
-      w[2] += r.x * p.z;
-      w[3] += r.y * p.x;
-      w[4] += r.y * p.y;
-      w[5] += r.y * p.z;
-      w[6] += r.z * p.x;
-      w[7] += r.z * p.y;
-      w[8] += r.z * p.z;
-    }
-    f0 = group_sum<L>(f0);
-    f1 = group_sum<L>(f1);
-    f2 = group_sum<L>(f2);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) w[q] = group_sum<L>(w[q]);
-    if (active && lane == 0) {
-      const double F0 = (double)(f0 + fown[i]) - f_tar[i];
-      const double F1 = (double)(f1 + fown[N + i]) - f_tar[N + i];
-      const double F2 = (double)(f2 + fown[2 * N + i]) - f_tar[2 * N + i];
-      acc[0] += (double)U[i];
-      acc[1] += F0 * F0 + F1 * F1 + F2 * F2;
-      acc[2] += (double)w[0];  // xx
-      acc[3] += (double)w[4];  // yy
-      acc[4] += (double)w[8];  // zz
-      acc[5] += (double)w[1];  // xy
-      acc[6] += (double)w[5];  // yz
-      acc[7] += (double)w[6];  // zx
-    }
+  __shared__ int acc[kLdsInts];
+  __shared__ int esc[2][64];
+  const int t = tile_order[blockIdx.x];
+  const int ta = tile_off[t], tb = tile_off[t + 1];
+  const int s0 = tile_s0[t], s1 = tile_s0[t + 1];
+  int* Fq = acc;                         // [atom][3][KC]
+  int* Wq = acc + (tb - ta) * 3 * KC;    // [structure][9][KC]
+  const int n_acc = ((tb - ta) * 3 + (s1 - s0) * 9) * KC;
+  for (int x = threadIdx.x; x < n_acc; x += blockDim.x) acc[x] = 0;
+  if (threadIdx.x < KC) {
+    const int2 e = tscale[(size_t)t * n_pop + k0 + threadIdx.x];
+    esc[0][threadIdx.x] = e.x;
+    esc[1][threadIdx.x] = e.y;
   }
-  const double v = block_sum<8>(acc, sw);
-  if (threadIdx.x < 8) tot[threadIdx.x] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const double ns = (double)(a1 - a0);
-    const double de = (tot[0] - e_tar[s]) / ns;
-    double dv = 0.0;
-    if (has_v[s])
-      for (int c = 0; c < 6; ++c) {
-        const double d = (tot[2 + c] - w_tar[6 * s + c]) / ns;
-        dv += d * d;
+  const int w = threadIdx.x / 64, l = threadIdx.x & 63, col = l & 15, h = l >> 4;
+  const float* dqk[kCols];
+  float sF[kCols], sW[kCols];
+  bool valid[kCols];
+#pragma unroll
+  for (int c = 0; c < kCols; ++c) {
+    const int kl = 16 * c + col;
+    valid[c] = kl < KC;
+    const int k = k0 + (valid[c] ? kl : 0);
+    dqk[c] = dq + (size_t)k * N * kQ + h;  // K index 4 q + h
+    const int eF = valid[c] ? esc[0][kl] : kBadScale, eW = valid[c] ? esc[1][kl] : kBadScale;
+    // a non-finite bound: every contribution 0 (the loss is set to NaN below)
+    sF[c] = eF == kBadScale ? 0.f : ldexpf(1.f, eF);
+    sW[c] = eW == kBadScale ? 0.f : ldexpf(1.f, eW);
+  }
+  auto add_q = [&](int* p, float x) { atomicAdd(p, __float2int_rn(x)); };
+
+  auto process = [&](const AtomOps& o, int4 m, int i) {
+    const int il = i - ta, sl = struct_of[i] - s0;
+    const int P = m.z, A = m.w;
+    const int ns = radial_tiles(P), na = angular_tiles(A);
+#pragma unroll
+    for (int c = 0; c < kCols; ++c) {  // own force (rows 0..2) and virial (rows 3..11)
+      f32x4 g = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < kGSteps; ++q) g = mma(o.g[q], o.b[c][q], g);
+      if (!valid[c]) continue;
+      const int kl = 16 * c + col;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * h + r;
+        if (row < 3)
+          add_q(&Fq[(il * 3 + row) * KC + kl], g[r] * sF[c]);
+        else if (row < 12)
+          add_q(&Wq[(sl * 9 + row - 3) * KC + kl], g[r] * sW[c]);
       }
-    double* o = sq + (k * S + s) * 3;
-    o[0] = de * de;
-    o[1] = tot[1];
-    o[2] = dv;
+    }
+    if (fast_atom(m)) {
+#pragma unroll
+      for (int tt = 0; tt < kFastS; ++tt) {
+        if (tt >= ns) break;
+#pragma unroll
+        for (int c = 0; c < kCols; ++c) {
+          f32x4 v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int q = 0; q < kSSteps; ++q) v = mma(o.s[tt][q], o.b[c][q], v);
+          if (!valid[c]) continue;
+          const int kl = 16 * c + col;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (16 * tt + 4 * h + r >= P) continue;
+            const float4 e = o.ps[tt][r];
+            int* fj = &Fq[__float_as_int(e.w) * 3 * KC + kl];
+            const float x = -v[r] * sF[c];
+            add_q(fj, e.x * x);
+            add_q(fj + KC, e.y * x);
+            add_q(fj + 2 * KC, e.z * x);
+          }
+        }
+      }
+#pragma unroll
+      for (int tt = 0; tt < kFastA; ++tt) {
+        if (tt >= na) break;
+#pragma unroll
+        for (int c = 0; c < kCols; ++c) {
+          f32x4 v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int q = 0; q < kASteps; ++q) v = mma(o.a[tt][q], o.b[c][3 + q], v);
+          if (!valid[c]) continue;
+          const int kl = 16 * c + col;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * tt + 4 * h + r;
+            if (row >= 3 * A) continue;
+            add_q(&Fq[(__float_as_int(o.pw[tt][r]) * 3 + row - 3 * (row / 3)) * KC + kl],
+                  -v[r] * sF[c]);
+          }
+        }
+      }
+      return;
+    }
+    // atoms with more pairs: the further operands read as they are used
+    const float* fs = pfrag + (size_t)(unsigned)m.x * 64 + l + 64 * kGSteps;
+    for (int tt = 0; tt < ns; ++tt) {
+      float d[kSSteps];
+#pragma unroll
+      for (int q = 0; q < kSSteps; ++q) d[q] = fs[64 * q];
+      fs += 64 * kSSteps;
+      float4 e[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int p = 16 * tt + 4 * h + r;
+        e[r] = ppair[(size_t)m.y + (p < P ? p : 0)];
+      }
+#pragma unroll
+      for (int c = 0; c < kCols; ++c) {
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < kSSteps; ++q) v = mma(d[q], o.b[c][q], v);
+        if (!valid[c]) continue;
+        const int kl = 16 * c + col;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (16 * tt + 4 * h + r >= P) continue;
+          int* fj = &Fq[__float_as_int(e[r].w) * 3 * KC + kl];
+          const float x = -v[r] * sF[c];
+          add_q(fj, e[r].x * x);
+          add_q(fj + KC, e[r].y * x);
+          add_q(fj + 2 * KC, e[r].z * x);
+        }
+      }
+    }
+    for (int tt = 0; tt < na; ++tt) {
+      float d[kASteps];
+#pragma unroll
+      for (int q = 0; q < kASteps; ++q) d[q] = fs[64 * q];
+      fs += 64 * kASteps;
+      int dst[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * tt + 4 * h + r;
+        const int p = row / 3;
+        dst[r] = row < 3 * A ? __float_as_int(ppair[(size_t)m.y + p].w) * 3 + row - 3 * p : -1;
+      }
+#pragma unroll
+      for (int c = 0; c < kCols; ++c) {
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < kASteps; ++q) v = mma(d[q], o.b[c][3 + q], v);
+        if (!valid[c]) continue;
+        const int kl = 16 * c + col;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (dst[r] >= 0) add_q(&Fq[dst[r] * KC + kl], -v[r] * sF[c]);
+      }
+    }
+  };
+
+  // Phase 1: atoms ta + w, ta + w + 8, ...; all operands of an atom are
+  // requested before its first product (the other wave on the SIMD covers
+  // the wait)
+  for (int i = ta + w; i < tb; i += kContractWaves) {
+    const int4 m = pmeta[i];
+    AtomOps o;
+    fetch_atom(o, m, i, dqk, pfrag, ppair, l, h);
+    process(o, m, i);
+  }
+  __syncthreads();
+  // Phase 2: unit (structure s, individual kl), lanes over atoms
+  const int n_units = (s1 - s0) * KC;
+  for (int u = w; u < n_units; u += kContractWaves) {
+    const int s = s0 + u / KC, kl = u % KC, k = k0 + kl;
+    const int i0 = off[s], i1 = off[s + 1];
+    const int eF = esc[0][kl], eW = esc[1][kl];
+    const double iF = eF == kBadScale ? 0.0 : ldexp(1.0, -eF);
+    const double iW = eW == kBadScale ? 0.0 : ldexp(1.0, -eW);
+    double eu = 0.0, ef = 0.0;
+    for (int i = i0 + l; i < i1; i += 64) {
+      eu += (double)U[(size_t)k * N + i];
+      const int il = i - ta;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double d = (double)Fq[(il * 3 + c) * KC + kl] * iF - f_tar[(size_t)c * N + i];
+        ef += d * d;
+      }
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+      eu += __shfl_xor(eu, d, 64);
+      ef += __shfl_xor(ef, d, 64);
+    }
+    if (l == 0) {
+      const double ns_inv = 1.0 / (double)(i1 - i0);
+      double ev = 0.0;
+      if (has_v[s]) {
+        // targets xx yy zz xy yz zx = row-major components 0, 4, 8, 1, 5, 6
+        const int comp[6] = {0, 4, 8, 1, 5, 6};
+        for (int c = 0; c < 6; ++c) {
+          const double d =
+              ((double)Wq[((s - s0) * 9 + comp[c]) * KC + kl] * iW - w_tar[6 * (size_t)s + c]) *
+              ns_inv;
+          ev += d * d;
+        }
+      }
+      const double de = (eu - e_tar[s]) * ns_inv;
+      double* o = sq + ((size_t)k * S + s) * 3;
+      if (eF == kBadScale || eW == kBadScale) {
+        o[0] = o[1] = o[2] = __builtin_nan("");
+      } else {
+        o[0] = de * de;
+        o[1] = ef;
+        o[2] = ev;
+      }
+    }
   }
 }
 
-template <int L>
-void launch_pop(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z, bool first) {
-  const int N = ds->N, S = ds->S;
-  const unsigned nb = blocks_for((size_t)N * L, kBlock);
-  const size_t pstride = (size_t)ds->cap * N;
-  launch_kernel(ctx, first, false, k_pop_partials<L>, dim3(n_pop, nb), dim3(kBlock), N,
-                (const float4*)ds->prec.ptr, (const int*)ds->pn_ang.ptr, (const int*)ds->pn_in.ptr,
-                (const float*)ds->desc.ptr, Z, ctx->n_par, (float)ds->rc_r, (float)ds->rc_a,
-                ds->pin.ptr, pstride, ds->fown.ptr, ds->U.ptr);
-  // 2 lanes per atom: 3.33 ms per generation on the 1000-structure set
-  // against 3.41 (4 lanes), 3.55 (8) and 3.81 (16); 1 lane ties with 2
-  launch_kernel(ctx, false, false, k_pop_struct<2>, dim3(n_pop, S), dim3(kBlock), N, S,
-                (const int*)ds->off.ptr, (const float4*)ds->prec.ptr, (const int*)ds->pn_in.ptr,
-                (const Partial3*)ds->pin.ptr, pstride, (const float*)ds->fown.ptr,
-                (const float*)ds->U.ptr, (const double*)ds->f_tar.ptr,
-                (const double*)ds->e_tar.ptr, (const double*)ds->w_tar.ptr,
-                (const int*)ds->has_v.ptr, ds->struct_sq.ptr);
+template <int CT>
+void launch_net(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z, bool first) {
+  const int per_block = 16 * CT * (kBlock / 64);
+  launch_kernel(ctx, first, false, k_pop_net<CT>, dim3(blocks_for(ds->N, per_block)),
+                dim3(kBlock), ds->N, n_pop, ctx->n_par, (const float*)ds->qpad.ptr, Z,
+                ds->dq.ptr, ds->U.ptr, ds->dqmax.ptr);
 }
 
 }  // namespace
 
+int population_max_structure() { return kLdsInts / 3 - 3; }
+
 hipError_t prepare_dataset_geometry(nep_ctx ctx, nep_dataset ds) {
-  const int N = ds->N, cap = ds->cap;
+  const int N = ds->N, cap = ds->cap, S = ds->S;
   const size_t ncap = (size_t)N * cap;
   hipError_t e = ds->prec.ensure(ncap);
   if (e == hipSuccess) e = ds->pcidx.ensure(ncap);
   if (e == hipSuccess) e = ds->pn_ang.ensure(N);
   if (e == hipSuccess) e = ds->pn_in.ensure(N);
   if (e == hipSuccess) e = ds->desc.ensure((size_t)kDescRow * N);
+  if (e == hipSuccess) e = ds->qpad.ensure((size_t)kQ * N);
+  if (e == hipSuccess) e = ds->pmeta.ensure(N);
+  if (e == hipSuccess) e = ds->stile0.ensure(S);
   if (e != hipSuccess) return e;
   const float rca = (float)ds->rc_a, rcr = (float)ds->rc_r;
   hipStream_t st = ctx->stream;
@@ -339,27 +843,128 @@ hipError_t prepare_dataset_geometry(nep_ctx ctx, nep_dataset ds) {
       ds->rev.ptr, ds->pcidx.ptr, ds->prec.ptr, ctx->flags.ptr);
   k_ds_descriptors<4><<<blocks_for((size_t)N * 4, kBlock), kBlock, 0, st>>>(
       N, ds->prec.ptr, ds->pn_ang.ptr, ds->pn_in.ptr, rcr, rca, ds->desc.ptr);
-  return hipGetLastError();
+  k_pop_qpad<<<blocks_for((size_t)N * kQ, kBlock), kBlock, 0, st>>>(N, ds->desc.ptr, ds->qpad.ptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // Layout of the contraction operands from the pair counts (host side).
+  std::vector<int> n_in(N), n_ang(N);
+  if ((e = hipMemcpyAsync(n_in.data(), ds->pn_in.ptr, sizeof(int) * N, hipMemcpyDeviceToHost,
+                          st)) != hipSuccess ||
+      (e = hipMemcpyAsync(n_ang.data(), ds->pn_ang.ptr, sizeof(int) * N, hipMemcpyDeviceToHost,
+                          st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return e;
+  std::vector<int4> meta(N);
+  size_t chunks = 0, pairs = 0;
+  for (int i = 0; i < N; ++i) {
+    meta[i] = make_int4((int)chunks, (int)pairs, n_in[i], n_ang[i]);
+    chunks += atom_chunks(n_in[i], n_ang[i]);
+    pairs += n_in[i];
+  }
+  if (chunks >= (1ull << 31) || pairs >= (1ull << 31)) return hipErrorInvalidValue;
+  // Tiles: consecutive whole structures whose accumulators fit the LDS for
+  // tile_kc individuals: 3 KC (atoms + 3 structures) 32-bit values.
+  const std::vector<int>& off = ds->off_host;
+  int largest = 0;
+  for (int s = 0; s < S; ++s) largest = std::max(largest, off[s + 1] - off[s]);
+  const int tile_kc = std::min(64, kLdsInts / (3 * (largest + 3)));
+  if (tile_kc < 1) return hipErrorInvalidValue;
+  const int units = kLdsInts / (3 * tile_kc);
+  std::vector<int> toff{0}, ts0{0}, st0(S);
+  int cur = 0;
+  for (int s = 0; s < S; ++s) {
+    const int ns = off[s + 1] - off[s] + 3;
+    if (cur > 0 && cur + ns > units) {
+      toff.push_back(off[s]);
+      ts0.push_back(s);
+      cur = 0;
+    }
+    st0[s] = toff.back();
+    cur += ns;
+  }
+  toff.push_back(N);
+  ts0.push_back(S);
+  const int T = (int)ts0.size() - 1;
+  std::vector<long long> work(T, 0);
+  std::vector<int> deg(T, 1);
+  int tile_max = 0;
+  for (int t = 0; t < T; ++t) {
+    tile_max = std::max(tile_max, toff[t + 1] - toff[t]);
+    for (int i = toff[t]; i < toff[t + 1]; ++i) {
+      work[t] += atom_chunks(n_in[i], n_ang[i]);
+      // a force component receives a radial and an angular part per incoming
+      // pair (as many as the receiver's own pairs) and its own force
+      deg[t] = std::max(deg[t], 2 * n_in[i] + 1);
+    }
+  }
+  std::vector<int> order(T);
+  for (int t = 0; t < T; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return work[a] > work[b]; });
+  ds->n_tiles = T;
+  ds->tile_max = tile_max;
+  ds->tile_kc = tile_kc;
+  if ((e = ds->pfrag.ensure((chunks + kPadChunks) * 64)) != hipSuccess ||
+      (e = ds->ppair.ensure(pairs + kPadPairs)) != hipSuccess ||
+      (e = ds->tile_off.ensure(T + 1)) != hipSuccess ||
+      (e = ds->tile_s0.ensure(T + 1)) != hipSuccess ||
+      (e = ds->tile_order.ensure(T)) != hipSuccess ||
+      (e = ds->tile_deg.ensure(T)) != hipSuccess || (e = ds->pnorm.ensure(N)) != hipSuccess)
+    return e;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  up(ds->pmeta.ptr, meta.data(), sizeof(int4) * N);
+  up(ds->tile_off.ptr, toff.data(), sizeof(int) * (T + 1));
+  up(ds->tile_s0.ptr, ts0.data(), sizeof(int) * (T + 1));
+  up(ds->tile_order.ptr, order.data(), sizeof(int) * T);
+  up(ds->stile0.ptr, st0.data(), sizeof(int) * S);
+  up(ds->tile_deg.ptr, deg.data(), sizeof(int) * T);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(ds->pfrag.ptr, 0, sizeof(float) * (chunks + kPadChunks) * 64, st);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(ds->ppair.ptr + pairs, 0, sizeof(float4) * kPadPairs, st);
+  if (e != hipSuccess) return e;
+  k_pop_geo<<<blocks_for((size_t)N * 32, kBlock), kBlock, 0, st>>>(
+      N, ds->prec.ptr, ds->pmeta.ptr, ds->desc.ptr, ds->struct_of.ptr, ds->stile0.ptr, rcr, rca,
+      ds->pfrag.ptr, ds->ppair.ptr);
+  k_pop_norms<<<blocks_for(N, 64), 64, 0, st>>>(N, ds->pmeta.ptr, ds->pfrag.ptr, ds->pnorm.ptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // the host vectors above are read by the copies
+  return hipStreamSynchronize(st);
 }
 
 int population_variants() { return 3; }
-int population_lanes(int variant) { return variant == 0 ? 2 : (variant == 1 ? 4 : 8); }
+int population_atoms(int variant) { return variant == 0 ? 16 : (variant == 1 ? 32 : 64); }
 
 hipError_t launch_population(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z, int variant,
                              bool first) {
   if (ds->N == 0 || n_pop == 0) return hipSuccess;
-  if (blocks_for((size_t)ds->N * 8, kBlock) > 65535 || ds->S > 65535 || n_pop > 65535)
-    return hipErrorInvalidConfiguration;
+  const int KC = ds->tile_kc;
+  if (KC < 1 || ds->n_tiles < 1) return hipErrorInvalidConfiguration;
   switch (variant) {
     case 0:
-      launch_pop<2>(ctx, ds, n_pop, Z, first);
+      launch_net<1>(ctx, ds, n_pop, Z, first);
       break;
     case 2:
-      launch_pop<8>(ctx, ds, n_pop, Z, first);
+      launch_net<4>(ctx, ds, n_pop, Z, first);
       break;
     default:
-      launch_pop<4>(ctx, ds, n_pop, Z, first);
+      launch_net<2>(ctx, ds, n_pop, Z, first);
   }
+  launch_kernel(ctx, false, false, k_pop_scale, dim3(ds->n_tiles), dim3(kBlock), n_pop,
+                (const int*)ds->tile_off.ptr, (const int*)ds->tile_deg.ptr,
+                (const float2*)ds->pnorm.ptr, (const float*)ds->dqmax.ptr, ds->tscale.ptr);
+  for (int k0 = 0; k0 < n_pop; k0 += KC)
+    launch_kernel(ctx, false, false, k_pop_contract, dim3(ds->n_tiles),
+                  dim3(64 * kContractWaves), ds->N, ds->S, k0, std::min(KC, n_pop - k0), n_pop,
+                  (const int*)ds->tile_order.ptr, (const int*)ds->tile_off.ptr,
+                  (const int*)ds->tile_s0.ptr, (const int*)ds->off.ptr,
+                  (const int*)ds->struct_of.ptr, (const int4*)ds->pmeta.ptr,
+                  (const float*)ds->pfrag.ptr, (const float4*)ds->ppair.ptr,
+                  (const float*)ds->dq.ptr, (const float*)ds->U.ptr,
+                  (const int2*)ds->tscale.ptr, (const double*)ds->f_tar.ptr,
+                  (const double*)ds->e_tar.ptr, (const double*)ds->w_tar.ptr,
+                  (const int*)ds->has_v.ptr, ds->struct_sq.ptr);
   return hipGetLastError();
 }
 

@@ -398,11 +398,13 @@ nep_status check_dataset(nep_ctx ctx, nep_dataset ds) {
   return NEP_OK;
 }
 
-// Workspace of snes_eval_population for n_pop individuals.
+// Workspace of snes_eval_population for n_pop individuals: dU/dq (32 floats
+// per atom and individual), site energies and per-structure squared errors.
 hipError_t ensure_population(nep_dataset ds, int n_pop) {
   const int N = ds->N, S = ds->S;
-  hipError_t e = ds->pin.ensure((size_t)n_pop * ds->cap * N);
-  if (e == hipSuccess) e = ds->fown.ensure((size_t)n_pop * 3 * N);
+  hipError_t e = ds->dq.ensure((size_t)n_pop * N * 32);
+  if (e == hipSuccess) e = ds->dqmax.ensure((size_t)n_pop * N);
+  if (e == hipSuccess) e = ds->tscale.ensure((size_t)n_pop * (ds->n_tiles > 0 ? ds->n_tiles : 1));
   if (e == hipSuccess) e = ds->U.ensure((size_t)n_pop * N);
   if (e == hipSuccess) e = ds->struct_sq.ensure((size_t)n_pop * 3 * S);
   return e;
@@ -420,7 +422,8 @@ hipError_t enqueue_population_loss(nep_ctx ctx, nep_dataset ds, int n_pop, const
 }
 
 bool population_fits(nep_dataset ds) {
-  return ds->S <= 65535 && blocks_for((size_t)ds->N * 8, kBlock) <= 65535;
+  return ds->tile_max <= population_max_structure() &&
+         (size_t)ds->N * 32 * 65535 < (1ull << 62);
 }
 
 }  // namespace
@@ -495,6 +498,7 @@ nep_status nep_dataset_create(nep_ctx ctx, int n_struct, const int* n_atoms_host
   ds->n_virial = n_virial;
   ds->rc_r = rc_r;
   ds->rc_a = rc_a;
+  ds->off_host = off;
   DeviceGuard guard(ctx->device);
   hipError_t e = hipSuccess;
   const size_t ncap = (size_t)N * max_neighbors;
@@ -564,6 +568,9 @@ void nep_dataset_destroy(nep_dataset ds) {
   ds->pin.release();
   ds->fown.release();
   ds->U.release();
+  ds->dq.release();
+  ds->dqmax.release();
+  ds->tscale.release();
   ds->atom_terms.release();
   ds->struct_sq.release();
   ds->grad_rec.release();
@@ -652,7 +659,7 @@ nep_status snes_eval_population(nep_ctx ctx, nep_dataset ds, int n_pop, const fl
   if (n_pop < 1 || n_pop > 65535) return fail(ctx, NEP_EINVAL, "n_pop must be in [1, 65535]");
   if (!Z_dev || !lambda_host || !loss_dev) return fail(ctx, NEP_EINVAL, "NULL argument");
   if (!population_fits(ds))
-    return fail(ctx, NEP_EINVAL, "dataset too large for one population launch");
+    return fail(ctx, NEP_EINVAL, "a structure has more atoms than the population kernels hold");
   DeviceGuard guard(ctx->device);
   hipError_t e = ensure_population(ds, n_pop);
   if (e != hipSuccess) return check_hip(ctx, e, "allocating population workspace");
@@ -700,7 +707,7 @@ nep_status snes_update(nep_ctx ctx, int n_par, int n_pop, float* m_dev, float* s
 }
 
 nep_status snes_autotune(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z_dev, int reps,
-                         int* lanes_out, double* ms_out) {
+                         int* atoms_out, double* ms_out) {
   if (!ctx) return NEP_EINVAL;
   nep_status chk = check_dataset(ctx, ds);
   if (chk != NEP_OK) return chk;
@@ -708,7 +715,7 @@ nep_status snes_autotune(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z_
   if (reps < 1 || reps > 1000) return fail(ctx, NEP_EINVAL, "reps must be in [1, 1000]");
   if (!Z_dev) return fail(ctx, NEP_EINVAL, "Z_dev is NULL");
   if (!population_fits(ds))
-    return fail(ctx, NEP_EINVAL, "dataset too large for one population launch");
+    return fail(ctx, NEP_EINVAL, "a structure has more atoms than the population kernels hold");
   DeviceGuard guard(ctx->device);
   hipError_t e = ensure_population(ds, n_pop);
   if (e != hipSuccess) return check_hip(ctx, e, "allocating population workspace");
@@ -742,19 +749,19 @@ nep_status snes_autotune(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z_
   if (e != hipSuccess) return check_hip(ctx, e, "timing population kernels");
   ds->pop_variant = best;
   ds->pop_tuned = true;
-  if (lanes_out) *lanes_out = population_lanes(best);
+  if (atoms_out) *atoms_out = population_atoms(best);
   return nep_synchronize(ctx);
 }
 
-nep_status snes_set_tile(nep_ctx ctx, nep_dataset ds, int lanes) {
+nep_status snes_set_tile(nep_ctx ctx, nep_dataset ds, int atoms) {
   if (!ctx) return NEP_EINVAL;
   if (!ds || ds->ctx != ctx) return fail(ctx, NEP_EINVAL, "dataset belongs to another context");
   for (int v = 0; v < population_variants(); ++v)
-    if (population_lanes(v) == lanes) {
+    if (population_atoms(v) == atoms) {
       ds->pop_variant = v;
       return NEP_OK;
     }
-  return fail(ctx, NEP_EINVAL, "lanes must be 2, 4 or 8");
+  return fail(ctx, NEP_EINVAL, "atoms must be 16, 32 or 64");
 }
 
 nep_status snes_run(nep_ctx ctx, nep_dataset ds, int n_par, int n_pop, float* m_dev,
@@ -771,7 +778,7 @@ nep_status snes_run(nep_ctx ctx, nep_dataset ds, int n_par, int n_pop, float* m_
   if (!m_dev || !s_dev || !r_dev || !Z_dev || !loss_dev || !lambda_host)
     return fail(ctx, NEP_EINVAL, "NULL argument");
   if (!population_fits(ds))
-    return fail(ctx, NEP_EINVAL, "dataset too large for one population launch");
+    return fail(ctx, NEP_EINVAL, "a structure has more atoms than the population kernels hold");
   if (n_gen == 0) return NEP_OK;
   if (!(eta_m > 0.0)) eta_m = 1.0;
   if (!(eta_s > 0.0)) eta_s = (3.0 + std::log((double)n_par)) / (5.0 * std::sqrt((double)n_par));
@@ -781,9 +788,9 @@ nep_status snes_run(nep_ctx ctx, nep_dataset ds, int n_par, int n_pop, float* m_
   if (e != hipSuccess) return check_hip(ctx, e, "allocating SNES workspace");
   SnesGraph& G = ctx->snes_graph;
   const std::vector<const void*> pk = {ds, m_dev, s_dev, r_dev, Z_dev, loss_dev, best_dev,
-                                       ds->pin.ptr, ds->fown.ptr, ds->U.ptr, ds->struct_sq.ptr,
-                                       ds->prec.ptr, ds->desc.ptr, ctx->gen_counter.ptr,
-                                       ctx->stream};
+                                       ds->dq.ptr, ds->U.ptr, ds->struct_sq.ptr, ds->pfrag.ptr,
+                                       ds->ppair.ptr, ds->qpad.ptr, ds->dqmax.ptr,
+                                       ds->tscale.ptr, ctx->gen_counter.ptr, ctx->stream};
   const std::vector<double> vk = {(double)ds->serial, (double)n_par, (double)n_pop,
                                   (double)(seed & 0xFFFFFFFFull), (double)(seed >> 32),
                                   lambda_host[0], lambda_host[1], lambda_host[2], lambda_host[3],

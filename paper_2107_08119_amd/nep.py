@@ -367,18 +367,18 @@ class Context:
                                           _ptr(loss), eta_m, eta_s))
 
     def snes_autotune(self, ds: "Dataset", Z: torch.Tensor, reps: int = 3):
-        """Time the population kernel shapes on this dataset and keep the
-        fastest; returns (lanes per atom chosen, ms per evaluation of the
-        2-, 4- and 8-lane shapes)."""
+        """Time the network-kernel shapes of the population evaluation on this
+        dataset and keep the fastest; returns (atoms per wave chosen, ms per
+        evaluation of the 16-, 32- and 64-atom shapes)."""
         _require(Z, torch.float32, (None, self._n_par()), "Z")
-        lanes = C.c_int(0)
+        atoms = C.c_int(0)
         ms = (C.c_double * 3)()
         self._check(self._lib.snes_autotune(self._h, ds._h, Z.shape[0], _ptr(Z), reps,
-                                            C.byref(lanes), ms))
-        return lanes.value, list(ms)
+                                            C.byref(atoms), ms))
+        return atoms.value, list(ms)
 
-    def snes_set_tile(self, ds: "Dataset", lanes: int) -> None:
-        self._check(self._lib.snes_set_tile(self._h, ds._h, lanes))
+    def snes_set_tile(self, ds: "Dataset", atoms: int) -> None:
+        self._check(self._lib.snes_set_tile(self._h, ds._h, atoms))
 
     def snes_run(self, ds: "Dataset", m: torch.Tensor, s: torch.Tensor, seed: int,
                  generation: int, n_gen: int, r: torch.Tensor, Z: torch.Tensor,

@@ -52,7 +52,7 @@ def train(ctx, n_struct=1000, n_min=8, n_max=256, data_seed=4, snes_seed=5, n_po
     loss = torch.empty((n_pop, 6), dtype=torch.float64, device=dev)
     # tile shape for this dataset, timed on the first generation's population
     ctx.snes_sample(m, s, snes_seed, 0, n_pop, r, Z)
-    lanes, _ = ctx.snes_autotune(ds, Z, reps=3)
+    atoms, _ = ctx.snes_autotune(ds, Z, reps=3)
     history = []
     t0 = time.perf_counter()
     g = 0
@@ -61,7 +61,7 @@ def train(ctx, n_struct=1000, n_min=8, n_max=256, data_seed=4, snes_seed=5, n_po
         best = ctx.snes_run(ds, m, s, snes_seed, g, n, r, Z, loss, lam)
         g += n
         b = best[n - 1].cpu().numpy()
-        rec = {"generation": g, "seconds": time.perf_counter() - t0, "lanes": lanes,
+        rec = {"generation": g, "seconds": time.perf_counter() - t0, "atoms_per_wave": atoms,
                "loss": float(b[0]), "rmse_e": float(b[1]), "rmse_f": float(b[2]),
                "rmse_v": float(b[3])}
         history.append(rec)

@@ -131,10 +131,10 @@ def test_full_size_training_set_sampled():
     assert np.all(np.isfinite(got))
 
 
-@pytest.mark.parametrize("lanes", [2, 4, 8])
-def test_population_tile_shapes_match_oracle(lanes):
-    """Every compiled tile shape of the population kernels gives the oracle's
-    losses; the autotuner picks one of them."""
+@pytest.mark.parametrize("atoms", [16, 32, 64])
+def test_population_tile_shapes_match_oracle(atoms):
+    """Every compiled shape of the population network kernel gives the
+    oracle's losses; the autotuner picks one of them."""
     import torch
     nep = nep_mod()
     ls = small_set()
@@ -144,8 +144,8 @@ def test_population_tile_shapes_match_oracle(lanes):
     ds = ctx.dataset_create(ls, max_neighbors=200)
     Zt = torch.from_numpy(Z).cuda()
     chosen, ms = ctx.snes_autotune(ds, Zt, reps=2)
-    assert chosen in (2, 4, 8) and all(t > 0 for t in ms)
-    ctx.snes_set_tile(ds, lanes)
+    assert chosen in (16, 32, 64) and all(t > 0 for t in ms)
+    ctx.snes_set_tile(ds, atoms)
     got = ctx.eval_population(ds, Zt, LAM).cpu().numpy()
     for k in range(len(Z)):
         ref = O.loss(OH, Z[k], ls, LAM, cap=200)
