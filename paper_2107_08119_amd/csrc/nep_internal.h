@@ -289,7 +289,7 @@ struct nep_dataset_s {
   nep::DevBuf<int> tile_order;   // [T] tiles by decreasing work
   nep::DevBuf<int> stile0;       // [S] first atom of the tile holding structure s
   nep::DevBuf<float2> pnorm;     // [N] largest row 1-norm of the force rows, of the virial rows
-  nep::DevBuf<int> tile_deg;     // [T] most additions into one force component of the tile
+  nep::DevBuf<float2> tbound;    // [T] fixed-point bound factors of forces and virials
   int n_tiles = 0, tile_max = 0;
   int tile_kc = 0;               // individuals per contraction launch the tiles were sized for
   int pop_variant = 1;         // network kernel shape: 0, 1, 2 = 16, 32, 64 atoms per wave
@@ -300,8 +300,9 @@ struct nep_dataset_s {
   nep::DevBuf<float> fown;          // [3][N]
   nep::DevBuf<float> U;             // [pop][N]
   nep::DevBuf<float> dq;            // [pop][N][32] dU/dq of every individual
-  nep::DevBuf<float> dqmax;         // [N][pop] largest |dU/dq| of every atom and individual
-  nep::DevBuf<int2> tscale;         // [T][pop] fixed-point exponents of forces and virials
+  nep::DevBuf<float> dqbound;       // [pop] bound on |dU/dq| of every individual
+  nep::DevBuf<float4> wfrag;        // [pop][12][64] network weights in fragment order
+  nep::DevBuf<float> wb2;           // [pop] output biases
   nep::DevBuf<double> atom_terms;   // [10][N] per-atom U and W (forward)
   nep::DevBuf<double> struct_sq;    // [pop][S][3] squared errors per structure
   // backward workspace
@@ -322,7 +323,7 @@ struct nep_dataset_s {
     tile_order.release();
     stile0.release();
     pnorm.release();
-    tile_deg.release();
+    tbound.release();
   }
 };
 

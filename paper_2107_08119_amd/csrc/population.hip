@@ -182,11 +182,14 @@ __host__ __device__ constexpr int padded(int v) { return v < NR ? v : v + (kAng0
 
 // Fragment chunks (64 floats) per atom: the own-force/virial tile (8 K steps
 // over the padded descriptor), ns radial tiles of 16 pairs (3 K steps: the
-// nine g_n' and three zeros), na angular tiles of 16 pair components (5 K
-// steps over the angular part).
+// nine g_n' and three zeros), and per block of 16 angular pairs three
+// angular tiles, one per component x, y, z (5 K steps over the angular
+// part).  Row r of radial tile b and of the angular tiles of block b belong
+// to the same pair 16 b + r, so a lane holds both parts of a pair's partial
+// force and adds them before they go to LDS.
 constexpr int kGSteps = 8, kSSteps = 3, kASteps = 5;
 __host__ __device__ inline int radial_tiles(int pairs) { return (pairs + 15) / 16; }
-__host__ __device__ inline int angular_tiles(int ang) { return (3 * ang + 15) / 16; }
+__host__ __device__ inline int angular_tiles(int ang) { return 3 * ((ang + 15) / 16); }
 __host__ __device__ inline int atom_chunks(int pairs, int ang) {
   return kGSteps + kSSteps * radial_tiles(pairs) + kASteps * angular_tiles(ang);
 }
@@ -210,9 +213,10 @@ __global__ void k_pop_qpad(int N, const float* __restrict__ desc, float* __restr
 // One thread per (atom i, descriptor component nu < 29): D_ij[.][nu] for
 // every pair of i, written into i's radial or angular fragment chunks, and
 // row nu of G_i and V_i.  The thread of nu = 0 also writes the pair records
-// (r_ij/r_ij, receiver index within the tile).  pfrag must be zero before.
+// (r_ij/r_ij, offset 3 kcs j of the receiver's force accumulators in the
+// tile).  pfrag must be zero before.
 __global__ __launch_bounds__(kBlock) void k_pop_geo(
-    int N, const float4* __restrict__ rec, const int4* __restrict__ pmeta,
+    int N, int kcs, const float4* __restrict__ rec, const int4* __restrict__ pmeta,
     const float* __restrict__ desc, const int* __restrict__ struct_of,
     const int* __restrict__ stile0, float rc_r, float rc_a, float* __restrict__ pfrag,
     float4* __restrict__ ppair) {
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_pop_geo(
       if (v == 0) {
         const int j = (int)((unsigned)__float_as_int(e.w) % (unsigned)N);
         ppair[(size_t)m.y + p] =
-            make_float4(e.x * rinv, e.y * rinv, e.z * rinv, __int_as_float(j - t0));
+            make_float4(e.x * rinv, e.y * rinv, e.z * rinv, __int_as_float((j - t0) * 3 * kcs));
       }
     }
   } else {
@@ -290,10 +294,9 @@ __global__ __launch_bounds__(kBlock) void k_pop_geo(
       const int kap = v - NR;  // K index within the angular product
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const int row = 3 * a + b;
-        const size_t chunk =
-            dbase + kGSteps + (size_t)kSSteps * ns + (size_t)kASteps * (row / 16) + kap / 4;
-        pfrag[chunk * 64 + (kap % 4) * 16 + row % 16] = d[b];
+        const size_t chunk = dbase + kGSteps + (size_t)kSSteps * ns +
+                             (size_t)kASteps * (3 * (a / 16) + b) + kap / 4;
+        pfrag[chunk * 64 + (kap % 4) * 16 + a % 16] = d[b];
         G[b] += d[b];
 #pragma unroll
         for (int q = 0; q < 3; ++q) V[3 * q + b] -= rv[q] * d[b];
@@ -313,19 +316,70 @@ __global__ __launch_bounds__(kBlock) void k_pop_geo(
 // the bound and marks the individual).
 __device__ __forceinline__ float max_nan(float a, float b) { return (b > a || b != b) ? b : a; }
 
-// dU/dq of every individual on atoms [64 CT w, 64 CT w + 16 CT) for wave w:
+// The network weights of individual k = blockIdx.x in the lane order of the
+// network kernel's two products: wf[(k 12 + q) 64 + lane] (float4) holds for
+// lane (col, h) = (lane % 16, lane / 16)
+//   q 0..3:  W1[16 mt + col][nu(4 s + h)], the first product's A (mt, s),
+//   q 4..7:  W1[16 (s / 4) + 4 h + s % 4][nu(16 nt + col)], the second's B,
+//   q 8..11: b1 and w2 of the lane's neurons 16 mt + 4 h + r,
+// with nu(kappa) the descriptor component of padded index kappa and zeros for
+// padding; wb2[k] = b2; dqbound[k] bounds |dU/dq| of individual k.
+__global__ __launch_bounds__(64) void k_pop_wfrag(int n_par, const float* __restrict__ Z,
+                                                  float4* __restrict__ wf,
+                                                  float* __restrict__ wb2,
+                                                  float* __restrict__ dqbound) {
+  const int k = blockIdx.x, l = threadIdx.x, col = l & 15, h = l >> 4;
+  const float* z = Z + (size_t)k * n_par;
+  // |dU/dq_nu| = |sum_mu w2_mu sech^2(a_mu) W1[mu][nu]| <= sum_mu |w2_mu W1[mu][nu]|
+  // (sech^2 <= 1): a bound for every atom; NaN or infinite with the weights
+  float bnd = 0.f;
+  if (l < NDES)
+    for (int mu = 0; mu < NNEU; ++mu)
+      bnd += fabsf(z[NNEU * (NDES + 1) + mu] * z[mu * NDES + l]);
+  for (int d = 32; d > 0; d >>= 1) bnd = max_nan(bnd, __shfl_xor(bnd, d, 64));
+  if (l == 0) dqbound[k] = bnd;
+  auto w1 = [&](int mu, int kp) {
+    const int nu = kp < NR ? kp : kp - (kAng0 - NR);
+    return (mu < NNEU && (kp < NR || kp >= kAng0)) ? z[mu * NDES + nu] : 0.f;
+  };
+  float f[48];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int st = 0; st < 8; ++st) f[8 * mt + st] = w1(16 * mt + col, 4 * st + h);
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+    for (int st = 0; st < 8; ++st)
+      f[16 + 8 * nt + st] = w1(16 * (st / 4) + 4 * h + (st % 4), 16 * nt + col);
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int mu = 16 * mt + 4 * h + r;
+      f[32 + 4 * mt + r] = mu < NNEU ? z[NNEU * NDES + mu] : 0.f;
+      f[40 + 4 * mt + r] = mu < NNEU ? z[NNEU * (NDES + 1) + mu] : 0.f;
+    }
+#pragma unroll
+  for (int q = 0; q < 12; ++q)
+    wf[((size_t)k * 12 + q) * 64 + l] = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+  if (l == 0) wb2[k] = z[NNEU * (NDES + 2)];
+}
+
+// dU/dq of every individual on atoms [16 CT w', 16 CT (w' + 1)) for wave w':
 // act^T = W1_k Q^T (rows: neurons in two tiles of 16; columns: atoms), the
 // neurons' tanh, U_i, and dU/dq_i = sum_mu w2_mu sech^2(act_mu) W1_k[mu] as
 // a product whose K order (neurons) follows what each lane already holds,
-// so G = w2 sech^2 never moves between lanes.  dq [k][N][32] (padded order,
-// zeros at 9..11), U [k][N], dqmax [N][n_pop] = max_nu |dU/dq_nu|.
+// so G = w2 sech^2 never moves between lanes.  Each individual's weight
+// fragments are loaded while the previous individual is multiplied.
+// dq [N][n_pop][32] (padded order, zeros at 9..11), U [n_pop][N].
 template <int CT>
-__global__ __launch_bounds__(kBlock) void k_pop_net(int N, int n_pop, int n_par,
+__global__ __launch_bounds__(kBlock) void k_pop_net(int N, int n_pop,
                                                     const float* __restrict__ qpad,
-                                                    const float* __restrict__ Z,
+                                                    const float4* __restrict__ wf,
+                                                    const float* __restrict__ wb2,
                                                     float* __restrict__ dq,
-                                                    float* __restrict__ U,
-                                                    float* __restrict__ dqmax) {
+                                                    float* __restrict__ U) {
   const int l = threadIdx.x & 63, col = l & 15, h = l >> 4;
   const int a0 = (blockIdx.x * (kBlock / 64) + threadIdx.x / 64) * 16 * CT;
   if (a0 >= N) return;  // whole waves leave together
@@ -337,40 +391,22 @@ __global__ __launch_bounds__(kBlock) void k_pop_net(int N, int n_pop, int n_par,
 #pragma unroll
     for (int s = 0; s < 8; ++s) qb[ct][s] = a < N ? qpad[(size_t)a * kQ + 4 * s + h] : 0.f;
   }
+  float4 nxt[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) nxt[q] = wf[(size_t)q * 64 + l];
   for (int k = 0; k < n_pop; ++k) {
-    const float* z = Z + (size_t)k * n_par;
-    // W1 as the first product's A[mu = 16 mt + col][kappa = 4 s + h]
-    float wa[2][8];
+    float f[48];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int q = 0; q < 12; ++q) {
+      f[4 * q] = nxt[q].x;
+      f[4 * q + 1] = nxt[q].y;
+      f[4 * q + 2] = nxt[q].z;
+      f[4 * q + 3] = nxt[q].w;
+    }
+    const float b2 = wb2[k];
+    const int kn = k + 1 < n_pop ? k + 1 : k;
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int mu = 16 * mt + col, kp = 4 * s + h;
-        const int nu = kp < NR ? kp : kp - (kAng0 - NR);
-        wa[mt][s] = (mu < NNEU && (kp < NR || kp >= kAng0)) ? z[mu * NDES + nu] : 0.f;
-      }
-    // bias and output weight of the lane's neurons mu = 16 mt + 4 h + r
-    float b1[2][4], w2[2][4];
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int mu = 16 * mt + 4 * h + r;
-        b1[mt][r] = mu < NNEU ? z[NNEU * NDES + mu] : 0.f;
-        w2[mt][r] = mu < NNEU ? z[NNEU * (NDES + 1) + mu] : 0.f;
-      }
-    const float b2 = z[NNEU * (NDES + 2)];
-    // W1 as the second product's B[kappa][nu' = 16 nt + col]; K step s of
-    // lane group h holds neuron 16 (s / 4) + 4 h + s % 4
-    float wb[2][8];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int mu = 16 * (s / 4) + 4 * h + (s % 4), kp = 16 * nt + col;
-        const int nu = kp < NR ? kp : kp - (kAng0 - NR);
-        wb[nt][s] = (mu < NNEU && (kp < NR || kp >= kAng0)) ? z[mu * NDES + nu] : 0.f;
-      }
+    for (int q = 0; q < 12; ++q) nxt[q] = wf[((size_t)kn * 12 + q) * 64 + l];
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       f32x4 act[2];
@@ -378,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_pop_net(int N, int n_pop, int n_par,
       for (int mt = 0; mt < 2; ++mt) {
         act[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 8; ++s) act[mt] = mma(wa[mt][s], qb[ct][s], act[mt]);
+        for (int s = 0; s < 8; ++s) act[mt] = mma(f[8 * mt + s], qb[ct][s], act[mt]);
       }
       float gm[2][4];
       float u = 0.f;
@@ -386,13 +422,14 @@ __global__ __launch_bounds__(kBlock) void k_pop_net(int N, int n_pop, int n_par,
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float x = act[mt][r] - b1[mt][r];
+          const float x = act[mt][r] - f[32 + 4 * mt + r];
+          const float w2 = f[40 + 4 * mt + r];
           // tanh and 1 - tanh^2 from e = exp(-2|x|) (no cancellation)
           const float ea = __expf(-2.f * fabsf(x));
           const float inv = __builtin_amdgcn_rcpf(1.f + ea);
           const float th = copysignf((1.f - ea) * inv, x);
-          u += w2[mt][r] * th;
-          gm[mt][r] = w2[mt][r] * (4.f * ea * inv * inv);
+          u += w2 * th;
+          gm[mt][r] = w2 * (4.f * ea * inv * inv);
         }
       u += __shfl_xor(u, 16, 64);
       u += __shfl_xor(u, 32, 64);
@@ -403,27 +440,16 @@ __global__ __launch_bounds__(kBlock) void k_pop_net(int N, int n_pop, int n_par,
       for (int nt = 0; nt < 2; ++nt) {
         o[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 8; ++s) o[nt] = mma(gm[s / 4][s % 4], wb[nt][s], o[nt]);
+        for (int s = 0; s < 8; ++s) o[nt] = mma(gm[s / 4][s % 4], f[16 + 8 * nt + s], o[nt]);
       }
-      float mx[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int ar = a0 + 16 * ct + 4 * h + r;
         if (ar < N) {
-          dq[((size_t)k * N + ar) * kQ + col] = o[0][r];
-          dq[((size_t)k * N + ar) * kQ + 16 + col] = o[1][r];
+          float* d = dq + ((size_t)ar * n_pop + k) * kQ;
+          d[col] = o[0][r];
+          d[16 + col] = o[1][r];
         }
-        mx[r] = max_nan(fabsf(o[0][r]), fabsf(o[1][r]));
-      }
-      // largest |dU/dq| of each atom: over the 16 lanes of its row group
-#pragma unroll
-      for (int d = 1; d < 16; d <<= 1)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) mx[r] = max_nan(mx[r], __shfl_xor(mx[r], d, 64));
-      if (col < 4) {
-        const int ar = a0 + 16 * ct + 4 * h + col;
-        const float v = col == 0 ? mx[0] : col == 1 ? mx[1] : col == 2 ? mx[2] : mx[3];
-        if (ar < N) dqmax[(size_t)ar * n_pop + k] = v;
       }
     }
   }
@@ -462,22 +488,23 @@ __global__ void k_pop_norms(int N, const int4* __restrict__ pmeta, const float* 
   const float* fa = fs + 64 * kSSteps * ns;
 #pragma unroll 1
   for (int row = 0; row < 3 * A; ++row) {
+    const int a = row / 3, b = row % 3;
     float s = 0.f;
     for (int q = 0; q < kASteps; ++q)
       for (int hh = 0; hh < 4; ++hh)
-        s += fabsf(fa[64 * (kASteps * (row / 16) + q) + 16 * hh + row % 16]);
+        s += fabsf(fa[64 * (kASteps * (3 * (a / 16) + b) + q) + 16 * hh + a % 16]);
     fmax = fmaxf(fmax, s);
   }
   (void)na;
   pnorm[i] = make_float2(fmax, vmax);
 }
 
-// Fixed-point exponents of tile t = blockIdx.x for individuals k: a force
-// component of the tile receives at most tile_deg[t] contributions, each at
-// most max_i pnorm_i.x dqmax_i^k, and a structure's virial component at most
-// sum_i pnorm_i.y dqmax_i^k; values are stored as round(x 2^e) in 32 bits
-// with e chosen so that these bounds stay below 2^30.  A non-finite bound
-// (a non-finite dU/dq) gives e = kBadScale.
+// Fixed-point exponents of a tile for individual k: a force component of
+// the tile receives at most deg_t contributions of at most
+// max_i (largest force-row 1-norm of i) dqbound_k, a structure's virial
+// component at most sum_i (largest virial-row 1-norm of i) dqbound_k; values
+// are stored as round(x 2^e) in 32 bits with e chosen so that these bounds
+// stay below 2^30.  A non-finite bound gives e = kBadScale.
 constexpr int kBadScale = -1000;
 __device__ __forceinline__ int fixed_exponent(float bound) {
   if (!(bound <= 3.0e38f)) return kBadScale;  // NaN or infinite
@@ -488,56 +515,19 @@ __device__ __forceinline__ int fixed_exponent(float bound) {
   return s < -100 ? -100 : (s > 100 ? 100 : s);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pop_scale(int n_pop, const int* __restrict__ tile_off,
-                                                      const int* __restrict__ tile_deg,
-                                                      const float2* __restrict__ pnorm,
-                                                      const float* __restrict__ dqmax,
-                                                      int2* __restrict__ tscale) {
-  __shared__ float sf[kBlock], sv[kBlock];
-  const int t = blockIdx.x;
-  const int a0 = tile_off[t], a1 = tile_off[t + 1];
-  const int kl = threadIdx.x & 63, part = threadIdx.x >> 6;
-  for (int k0 = 0; k0 < n_pop; k0 += 64) {
-    const int k = k0 + kl;
-    float bf = 0.f, bv = 0.f;
-    if (k < n_pop) {
-#pragma unroll 8
-      for (int i = a0 + part; i < a1; i += kBlock / 64) {
-        const float2 pn = pnorm[i];
-        const float d = dqmax[(size_t)i * n_pop + k];
-        bf = max_nan(bf, pn.x * d);
-        bv += pn.y * d;
-      }
-    }
-    sf[threadIdx.x] = bf;
-    sv[threadIdx.x] = bv;
-    __syncthreads();
-    if (part == 0 && k < n_pop) {
-      for (int p = 1; p < kBlock / 64; ++p) {
-        bf = max_nan(bf, sf[64 * p + kl]);
-        bv += sv[64 * p + kl];
-      }
-      tscale[(size_t)t * n_pop + k] =
-          make_int2(fixed_exponent((float)tile_deg[t] * bf), fixed_exponent(bv));
-    }
-    __syncthreads();
-  }
-}
-
 // Operands of one owner atom in the contraction kernel, all requested
 // before the atom's first product.  Atoms with at most kFastPairs pairs and
-// kFastAng angular pairs (two radial and three angular tiles) are fetched
-// whole; others read their further tiles as they are used.
+// kFastAng angular pairs (two radial tiles, one block of angular tiles) are
+// fetched whole; others read their further tiles as they are used.
 constexpr int kFastPairs = 32, kFastAng = 16;
-constexpr int kFastS = 2, kFastA = 3;
+constexpr int kFastS = 2;
 constexpr int kCols = 4;  // column tiles of 16 individuals per wave
 struct AtomOps {
   float b[kCols][8];   // dU/dq of the lane's individuals, K index 4 q + h
   float g[kGSteps];    // own-force / virial tile
   float s[kFastS][kSSteps];
-  float a[kFastA][kASteps];
-  float4 ps[kFastS][4];  // pair records (unit vector, receiver) of the lane's radial rows
-  float pw[kFastA][4];   // receiver (record .w) of the pair of each angular row
+  float a[3][kASteps];   // angular tiles x, y, z of the first pair block
+  float4 ps[kFastS][4];  // pair records (unit vector, receiver) of the lane's rows
 };
 
 __device__ __forceinline__ bool fast_atom(int4 m) { return m.z <= kFastPairs && m.w <= kFastAng; }
@@ -547,13 +537,15 @@ __device__ __forceinline__ bool fast_atom(int4 m) { return m.z <= kFastPairs && 
 // atom's own reads a neighbour's data or padding) and masked at use: with no
 // branch between the loads, each operand waits only for itself.
 constexpr int kPadChunks = 64, kPadPairs = 64;
-__device__ __forceinline__ void fetch_atom(AtomOps& o, int4 m, int i, const float* const (&dqk)[kCols],
+__device__ __forceinline__ void fetch_atom(AtomOps& o, int4 m, int i, int n_pop,
+                                           const float* const (&dqk)[kCols],
                                            const float* pfrag, const float4* ppair, int l,
                                            int h) {
+  const size_t row = (size_t)i * n_pop * kQ;
 #pragma unroll
   for (int c = 0; c < kCols; ++c)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) o.b[c][q] = dqk[c][(size_t)i * kQ + 4 * q];
+    for (int q = 0; q < 8; ++q) o.b[c][q] = dqk[c][row + 4 * q];
   const float* fr = pfrag + (size_t)(unsigned)m.x * 64 + l;
   const int ns = radial_tiles(m.z);
 #pragma unroll
@@ -564,18 +556,14 @@ __device__ __forceinline__ void fetch_atom(AtomOps& o, int4 m, int i, const floa
     for (int q = 0; q < kSSteps; ++q) o.s[tt][q] = fr[64 * (kGSteps + kSSteps * tt + q)];
   const float* fa = fr + 64 * (kGSteps + kSSteps * ns);
 #pragma unroll
-  for (int tt = 0; tt < kFastA; ++tt)
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int q = 0; q < kASteps; ++q) o.a[tt][q] = fa[64 * (kASteps * tt + q)];
+    for (int q = 0; q < kASteps; ++q) o.a[c][q] = fa[64 * (kASteps * c + q)];
   const float4* pp = ppair + (size_t)m.y;
 #pragma unroll
   for (int tt = 0; tt < kFastS; ++tt)
 #pragma unroll
     for (int r = 0; r < 4; ++r) o.ps[tt][r] = pp[16 * tt + 4 * h + r];
-#pragma unroll
-  for (int tt = 0; tt < kFastA; ++tt)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) o.pw[tt][r] = pp[(16 * tt + 4 * h + r) / 3].w;
 }
 
 // Forces, energies, virials and squared errors of individuals k0 .. k0+KC-1
@@ -590,12 +578,13 @@ __device__ __forceinline__ void fetch_atom(AtomOps& o, int4 m, int i, const floa
 // the energy, force and virial errors in float64 in a fixed order.
 constexpr int kContractWaves = 8;
 __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
-    int N, int S, int k0, int KC, int n_pop, const int* __restrict__ tile_order,
+    int N, int S, int k0, int KC, int kcs, int n_pop, const int* __restrict__ tile_order,
     const int* __restrict__ tile_off, const int* __restrict__ tile_s0,
     const int* __restrict__ off, const int* __restrict__ struct_of,
     const int4* __restrict__ pmeta, const float* __restrict__ pfrag,
     const float4* __restrict__ ppair, const float* __restrict__ dq, const float* __restrict__ U,
-    const int2* __restrict__ tscale, const double* __restrict__ f_tar,
+    const float2* __restrict__ tbound, const float* __restrict__ dqbound,
+    const double* __restrict__ f_tar,
     const double* __restrict__ e_tar, const double* __restrict__ w_tar,
     const int* __restrict__ has_v, double* __restrict__ sq) {
   __shared__ int acc[kLdsInts];
@@ -603,108 +592,129 @@ __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
   const int t = tile_order[blockIdx.x];
   const int ta = tile_off[t], tb = tile_off[t + 1];
   const int s0 = tile_s0[t], s1 = tile_s0[t + 1];
-  int* Fq = acc;                         // [atom][3][KC]
-  int* Wq = acc + (tb - ta) * 3 * KC;    // [structure][9][KC]
-  const int n_acc = ((tb - ta) * 3 + (s1 - s0) * 9) * KC;
+  int* Fq = acc;                          // [atom][3][kcs]
+  int* Wq = acc + (tb - ta) * 3 * kcs;    // [structure][9][kcs]
+  const int n_acc = ((tb - ta) * 3 + (s1 - s0) * 9) * kcs;
   for (int x = threadIdx.x; x < n_acc; x += blockDim.x) acc[x] = 0;
   if (threadIdx.x < KC) {
-    const int2 e = tscale[(size_t)t * n_pop + k0 + threadIdx.x];
-    esc[0][threadIdx.x] = e.x;
-    esc[1][threadIdx.x] = e.y;
+    const float2 tb2 = tbound[t];
+    const float bk = dqbound[k0 + threadIdx.x];
+    esc[0][threadIdx.x] = fixed_exponent(tb2.x * bk);
+    esc[1][threadIdx.x] = fixed_exponent(tb2.y * bk);
   }
   __syncthreads();
   const int w = threadIdx.x / 64, l = threadIdx.x & 63, col = l & 15, h = l >> 4;
   const float* dqk[kCols];
-  float sF[kCols], sW[kCols];
+  float sF[kCols], rW[kCols];
   bool valid[kCols];
 #pragma unroll
   for (int c = 0; c < kCols; ++c) {
     const int kl = 16 * c + col;
     valid[c] = kl < KC;
     const int k = k0 + (valid[c] ? kl : 0);
-    dqk[c] = dq + (size_t)k * N * kQ + h;  // K index 4 q + h
+    dqk[c] = dq + (size_t)k * kQ + h;  // K index 4 q + h
     const int eF = valid[c] ? esc[0][kl] : kBadScale, eW = valid[c] ? esc[1][kl] : kBadScale;
-    // a non-finite bound: every contribution 0 (the loss is set to NaN below)
-    sF[c] = eF == kBadScale ? 0.f : ldexpf(1.f, eF);
-    sW[c] = eW == kBadScale ? 0.f : ldexpf(1.f, eW);
+    // the force scale goes into dU/dq, so the products come out scaled; the
+    // virial rows are rescaled by 2^(eW - eF).  A non-finite bound: every
+    // contribution 0 (the loss is set to NaN below).
+    const bool ok = eF != kBadScale && eW != kBadScale;
+    sF[c] = ok ? ldexpf(1.f, eF) : 0.f;
+    rW[c] = ok ? ldexpf(1.f, eW - eF) : 0.f;
   }
   auto add_q = [&](int* p, float x) { atomicAdd(p, __float2int_rn(x)); };
 
-  auto process = [&](const AtomOps& o, int4 m, int i) {
-    const int il = i - ta, sl = struct_of[i] - s0;
-    const int P = m.z, A = m.w;
-    const int ns = radial_tiles(P), na = angular_tiles(A);
+  // the pair block pb of atom i: radial tile v (rows: pairs) and, when the
+  // block holds angular pairs, angular tiles ax, ay, az (same rows);
+  // F_j -= u_ij v + (ax, ay, az) for the receiver j of each row.  Rows past
+  // the atom's pairs have zero operands (their products are 0) and go to the
+  // tile's first accumulator, so no lane branches.
+  auto scatter_block = [&](const f32x4& v, const f32x4* va, bool ang, const float4 (&e)[4],
+                           int pb, int P, int kl) {
 #pragma unroll
-    for (int c = 0; c < kCols; ++c) {  // own force (rows 0..2) and virial (rows 3..11)
+    for (int r = 0; r < 4; ++r) {
+      const int dst = 16 * pb + 4 * h + r < P ? __float_as_int(e[r].w) : 0;
+      int* fj = &Fq[dst + kl];
+      float x = -e[r].x * v[r], y = -e[r].y * v[r], z = -e[r].z * v[r];
+      if (ang) {
+        x -= va[0][r];
+        y -= va[1][r];
+        z -= va[2][r];
+      }
+      add_q(fj, x);
+      add_q(fj + kcs, y);
+      add_q(fj + 2 * kcs, z);
+    }
+  };
+
+  auto process = [&](AtomOps& o, int4 m, int i, int sl) {
+    const int il = i - ta;
+    const int P = m.z, A = m.w;
+    const int ns = radial_tiles(P), nab = (A + 15) / 16;
+#pragma unroll
+    for (int c = 0; c < kCols; ++c)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) o.b[c][q] *= sF[c];
+    // the lane's rows 4 h + r of the own-force / virial tile: rows 0..2 the
+    // own force, 3..11 the virial (row-major ab), 12..15 zero
+    int gdst[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 4 * h + r;
+      gdst[r] = row < 3 ? (il * 3 + row) * kcs
+                        : (row < 12 ? (int)(Wq - Fq) + (sl * 9 + row - 3) * kcs : il * 3 * kcs);
+    }
+#pragma unroll
+    for (int c = 0; c < kCols; ++c) {
       f32x4 g = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int q = 0; q < kGSteps; ++q) g = mma(o.g[q], o.b[c][q], g);
       if (!valid[c]) continue;
       const int kl = 16 * c + col;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 4 * h + r;
-        if (row < 3)
-          add_q(&Fq[(il * 3 + row) * KC + kl], g[r] * sF[c]);
-        else if (row < 12)
-          add_q(&Wq[(sl * 9 + row - 3) * KC + kl], g[r] * sW[c]);
-      }
+      for (int r = 0; r < 4; ++r)
+        add_q(&Fq[gdst[r] + kl], 4 * h + r < 3 ? g[r] : g[r] * rW[c]);
     }
     if (fast_atom(m)) {
 #pragma unroll
-      for (int tt = 0; tt < kFastS; ++tt) {
-        if (tt >= ns) break;
+      for (int pb = 0; pb < kFastS; ++pb) {
+        if (pb >= ns) break;
+        const bool ang = pb < nab;
 #pragma unroll
         for (int c = 0; c < kCols; ++c) {
           f32x4 v = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int q = 0; q < kSSteps; ++q) v = mma(o.s[tt][q], o.b[c][q], v);
-          if (!valid[c]) continue;
-          const int kl = 16 * c + col;
+          for (int q = 0; q < kSSteps; ++q) v = mma(o.s[pb][q], o.b[c][q], v);
+          f32x4 va[3];
+          if (ang) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            if (16 * tt + 4 * h + r >= P) continue;
-            const float4 e = o.ps[tt][r];
-            int* fj = &Fq[__float_as_int(e.w) * 3 * KC + kl];
-            const float x = -v[r] * sF[c];
-            add_q(fj, e.x * x);
-            add_q(fj + KC, e.y * x);
-            add_q(fj + 2 * KC, e.z * x);
+            for (int d = 0; d < 3; ++d) {
+              va[d] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+              for (int q = 0; q < kASteps; ++q) va[d] = mma(o.a[d][q], o.b[c][3 + q], va[d]);
+            }
           }
-        }
-      }
-#pragma unroll
-      for (int tt = 0; tt < kFastA; ++tt) {
-        if (tt >= na) break;
-#pragma unroll
-        for (int c = 0; c < kCols; ++c) {
-          f32x4 v = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int q = 0; q < kASteps; ++q) v = mma(o.a[tt][q], o.b[c][3 + q], v);
-          if (!valid[c]) continue;
-          const int kl = 16 * c + col;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = 16 * tt + 4 * h + r;
-            if (row >= 3 * A) continue;
-            add_q(&Fq[(__float_as_int(o.pw[tt][r]) * 3 + row - 3 * (row / 3)) * KC + kl],
-                  -v[r] * sF[c]);
-          }
+          if (valid[c]) scatter_block(v, va, ang, o.ps[pb], pb, P, 16 * c + col);
         }
       }
       return;
     }
     // atoms with more pairs: the further operands read as they are used
     const float* fs = pfrag + (size_t)(unsigned)m.x * 64 + l + 64 * kGSteps;
-    for (int tt = 0; tt < ns; ++tt) {
-      float d[kSSteps];
+    const float* fa = fs + 64 * kSSteps * ns;
+    for (int pb = 0; pb < ns; ++pb) {
+      float d[kSSteps], da[3][kASteps];
 #pragma unroll
-      for (int q = 0; q < kSSteps; ++q) d[q] = fs[64 * q];
-      fs += 64 * kSSteps;
+      for (int q = 0; q < kSSteps; ++q) d[q] = fs[64 * (kSSteps * pb + q)];
+      const bool ang = pb < nab;
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int q = 0; q < kASteps; ++q)
+          da[x][q] = ang ? fa[64 * (kASteps * (3 * pb + x) + q)] : 0.f;
       float4 e[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int p = 16 * tt + 4 * h + r;
+        const int p = 16 * pb + 4 * h + r;
         e[r] = ppair[(size_t)m.y + (p < P ? p : 0)];
       }
 #pragma unroll
@@ -712,41 +722,16 @@ __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
         f32x4 v = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < kSSteps; ++q) v = mma(d[q], o.b[c][q], v);
-        if (!valid[c]) continue;
-        const int kl = 16 * c + col;
+        f32x4 va[3];
+        if (ang) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (16 * tt + 4 * h + r >= P) continue;
-          int* fj = &Fq[__float_as_int(e[r].w) * 3 * KC + kl];
-          const float x = -v[r] * sF[c];
-          add_q(fj, e[r].x * x);
-          add_q(fj + KC, e[r].y * x);
-          add_q(fj + 2 * KC, e[r].z * x);
+          for (int x = 0; x < 3; ++x) {
+            va[x] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < kASteps; ++q) va[x] = mma(da[x][q], o.b[c][3 + q], va[x]);
+          }
         }
-      }
-    }
-    for (int tt = 0; tt < na; ++tt) {
-      float d[kASteps];
-#pragma unroll
-      for (int q = 0; q < kASteps; ++q) d[q] = fs[64 * q];
-      fs += 64 * kASteps;
-      int dst[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * tt + 4 * h + r;
-        const int p = row / 3;
-        dst[r] = row < 3 * A ? __float_as_int(ppair[(size_t)m.y + p].w) * 3 + row - 3 * p : -1;
-      }
-#pragma unroll
-      for (int c = 0; c < kCols; ++c) {
-        f32x4 v = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int q = 0; q < kASteps; ++q) v = mma(d[q], o.b[c][3 + q], v);
-        if (!valid[c]) continue;
-        const int kl = 16 * c + col;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (dst[r] >= 0) add_q(&Fq[dst[r] * KC + kl], -v[r] * sF[c]);
+        if (valid[c]) scatter_block(v, va, ang, e, pb, P, 16 * c + col);
       }
     }
   };
@@ -754,11 +739,18 @@ __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
   // Phase 1: atoms ta + w, ta + w + 8, ...; all operands of an atom are
   // requested before its first product (the other wave on the SIMD covers
   // the wait)
+  // (the atom records are read with vector loads, threadIdx.y being 0: a
+  // scalar load would have to wait for every LDS addition in flight)
   for (int i = ta + w; i < tb; i += kContractWaves) {
-    const int4 m = pmeta[i];
+    int4 m = pmeta[i + threadIdx.y];
+    m.x = __builtin_amdgcn_readfirstlane(m.x);
+    m.y = __builtin_amdgcn_readfirstlane(m.y);
+    m.z = __builtin_amdgcn_readfirstlane(m.z);
+    m.w = __builtin_amdgcn_readfirstlane(m.w);
+    const int sl = __builtin_amdgcn_readfirstlane(struct_of[i + threadIdx.y] - s0);
     AtomOps o;
-    fetch_atom(o, m, i, dqk, pfrag, ppair, l, h);
-    process(o, m, i);
+    fetch_atom(o, m, i, n_pop, dqk, pfrag, ppair, l, h);
+    process(o, m, i, sl);
   }
   __syncthreads();
   // Phase 2: unit (structure s, individual kl), lanes over atoms
@@ -775,7 +767,7 @@ __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
       const int il = i - ta;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double d = (double)Fq[(il * 3 + c) * KC + kl] * iF - f_tar[(size_t)c * N + i];
+        const double d = (double)Fq[(il * 3 + c) * kcs + kl] * iF - f_tar[(size_t)c * N + i];
         ef += d * d;
       }
     }
@@ -791,7 +783,7 @@ __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
         const int comp[6] = {0, 4, 8, 1, 5, 6};
         for (int c = 0; c < 6; ++c) {
           const double d =
-              ((double)Wq[((s - s0) * 9 + comp[c]) * KC + kl] * iW - w_tar[6 * (size_t)s + c]) *
+              ((double)Wq[((s - s0) * 9 + comp[c]) * kcs + kl] * iW - w_tar[6 * (size_t)s + c]) *
               ns_inv;
           ev += d * d;
         }
@@ -811,10 +803,12 @@ __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
 
 template <int CT>
 void launch_net(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z, bool first) {
+  launch_kernel(ctx, first, false, k_pop_wfrag, dim3(n_pop), dim3(64), ctx->n_par, Z,
+                ds->wfrag.ptr, ds->wb2.ptr, ds->dqbound.ptr);
   const int per_block = 16 * CT * (kBlock / 64);
-  launch_kernel(ctx, first, false, k_pop_net<CT>, dim3(blocks_for(ds->N, per_block)),
-                dim3(kBlock), ds->N, n_pop, ctx->n_par, (const float*)ds->qpad.ptr, Z,
-                ds->dq.ptr, ds->U.ptr, ds->dqmax.ptr);
+  launch_kernel(ctx, false, false, k_pop_net<CT>, dim3(blocks_for(ds->N, per_block)),
+                dim3(kBlock), ds->N, n_pop, (const float*)ds->qpad.ptr,
+                (const float4*)ds->wfrag.ptr, (const float*)ds->wb2.ptr, ds->dq.ptr, ds->U.ptr);
 }
 
 }  // namespace
@@ -908,7 +902,7 @@ hipError_t prepare_dataset_geometry(nep_ctx ctx, nep_dataset ds) {
       (e = ds->tile_off.ensure(T + 1)) != hipSuccess ||
       (e = ds->tile_s0.ensure(T + 1)) != hipSuccess ||
       (e = ds->tile_order.ensure(T)) != hipSuccess ||
-      (e = ds->tile_deg.ensure(T)) != hipSuccess || (e = ds->pnorm.ensure(N)) != hipSuccess)
+      (e = ds->tbound.ensure(T)) != hipSuccess || (e = ds->pnorm.ensure(N)) != hipSuccess)
     return e;
   auto up = [&](void* dst, const void* src, size_t bytes) {
     if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
@@ -918,17 +912,35 @@ hipError_t prepare_dataset_geometry(nep_ctx ctx, nep_dataset ds) {
   up(ds->tile_s0.ptr, ts0.data(), sizeof(int) * (T + 1));
   up(ds->tile_order.ptr, order.data(), sizeof(int) * T);
   up(ds->stile0.ptr, st0.data(), sizeof(int) * S);
-  up(ds->tile_deg.ptr, deg.data(), sizeof(int) * T);
   if (e == hipSuccess)
     e = hipMemsetAsync(ds->pfrag.ptr, 0, sizeof(float) * (chunks + kPadChunks) * 64, st);
   if (e == hipSuccess)
     e = hipMemsetAsync(ds->ppair.ptr + pairs, 0, sizeof(float4) * kPadPairs, st);
   if (e != hipSuccess) return e;
   k_pop_geo<<<blocks_for((size_t)N * 32, kBlock), kBlock, 0, st>>>(
-      N, ds->prec.ptr, ds->pmeta.ptr, ds->desc.ptr, ds->struct_of.ptr, ds->stile0.ptr, rcr, rca,
+      N, tile_kc, ds->prec.ptr, ds->pmeta.ptr, ds->desc.ptr, ds->struct_of.ptr, ds->stile0.ptr, rcr, rca,
       ds->pfrag.ptr, ds->ppair.ptr);
   k_pop_norms<<<blocks_for(N, 64), 64, 0, st>>>(N, ds->pmeta.ptr, ds->pfrag.ptr, ds->pnorm.ptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  // per tile: deg_t max_i (force-row norm) and sum_i (virial-row norm), the
+  // factors of the fixed-point bounds (times the bound on |dU/dq|)
+  std::vector<float2> pn(N), tb(T);
+  if ((e = hipMemcpyAsync(pn.data(), ds->pnorm.ptr, sizeof(float2) * N, hipMemcpyDeviceToHost,
+                          st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return e;
+  for (int t = 0; t < T; ++t) {
+    float fm = 0.f;
+    double vs = 0.0;
+    for (int i = toff[t]; i < toff[t + 1]; ++i) {
+      fm = std::max(fm, pn[i].x);
+      vs += pn[i].y;
+    }
+    // rounded up a little: the products formed on the device round
+    tb[t] = make_float2((float)deg[t] * fm * 1.001f, (float)vs * 1.001f);
+  }
+  up(ds->tbound.ptr, tb.data(), sizeof(float2) * T);
+  if (e != hipSuccess) return e;
   // the host vectors above are read by the copies
   return hipStreamSynchronize(st);
 }
@@ -951,18 +963,16 @@ hipError_t launch_population(nep_ctx ctx, nep_dataset ds, int n_pop, const float
     default:
       launch_net<2>(ctx, ds, n_pop, Z, first);
   }
-  launch_kernel(ctx, false, false, k_pop_scale, dim3(ds->n_tiles), dim3(kBlock), n_pop,
-                (const int*)ds->tile_off.ptr, (const int*)ds->tile_deg.ptr,
-                (const float2*)ds->pnorm.ptr, (const float*)ds->dqmax.ptr, ds->tscale.ptr);
   for (int k0 = 0; k0 < n_pop; k0 += KC)
     launch_kernel(ctx, false, false, k_pop_contract, dim3(ds->n_tiles),
-                  dim3(64 * kContractWaves), ds->N, ds->S, k0, std::min(KC, n_pop - k0), n_pop,
+                  dim3(64 * kContractWaves), ds->N, ds->S, k0, std::min(KC, n_pop - k0), KC, n_pop,
                   (const int*)ds->tile_order.ptr, (const int*)ds->tile_off.ptr,
                   (const int*)ds->tile_s0.ptr, (const int*)ds->off.ptr,
                   (const int*)ds->struct_of.ptr, (const int4*)ds->pmeta.ptr,
                   (const float*)ds->pfrag.ptr, (const float4*)ds->ppair.ptr,
                   (const float*)ds->dq.ptr, (const float*)ds->U.ptr,
-                  (const int2*)ds->tscale.ptr, (const double*)ds->f_tar.ptr,
+                  (const float2*)ds->tbound.ptr, (const float*)ds->dqbound.ptr,
+                  (const double*)ds->f_tar.ptr,
                   (const double*)ds->e_tar.ptr, (const double*)ds->w_tar.ptr,
                   (const int*)ds->has_v.ptr, ds->struct_sq.ptr);
   return hipGetLastError();

@@ -403,8 +403,9 @@ nep_status check_dataset(nep_ctx ctx, nep_dataset ds) {
 hipError_t ensure_population(nep_dataset ds, int n_pop) {
   const int N = ds->N, S = ds->S;
   hipError_t e = ds->dq.ensure((size_t)n_pop * N * 32);
-  if (e == hipSuccess) e = ds->dqmax.ensure((size_t)n_pop * N);
-  if (e == hipSuccess) e = ds->tscale.ensure((size_t)n_pop * (ds->n_tiles > 0 ? ds->n_tiles : 1));
+  if (e == hipSuccess) e = ds->dqbound.ensure((size_t)n_pop);
+  if (e == hipSuccess) e = ds->wfrag.ensure((size_t)n_pop * 12 * 64);
+  if (e == hipSuccess) e = ds->wb2.ensure((size_t)n_pop);
   if (e == hipSuccess) e = ds->U.ensure((size_t)n_pop * N);
   if (e == hipSuccess) e = ds->struct_sq.ensure((size_t)n_pop * 3 * S);
   return e;
@@ -569,8 +570,9 @@ void nep_dataset_destroy(nep_dataset ds) {
   ds->fown.release();
   ds->U.release();
   ds->dq.release();
-  ds->dqmax.release();
-  ds->tscale.release();
+  ds->dqbound.release();
+  ds->wfrag.release();
+  ds->wb2.release();
   ds->atom_terms.release();
   ds->struct_sq.release();
   ds->grad_rec.release();
@@ -789,8 +791,9 @@ nep_status snes_run(nep_ctx ctx, nep_dataset ds, int n_par, int n_pop, float* m_
   SnesGraph& G = ctx->snes_graph;
   const std::vector<const void*> pk = {ds, m_dev, s_dev, r_dev, Z_dev, loss_dev, best_dev,
                                        ds->dq.ptr, ds->U.ptr, ds->struct_sq.ptr, ds->pfrag.ptr,
-                                       ds->ppair.ptr, ds->qpad.ptr, ds->dqmax.ptr,
-                                       ds->tscale.ptr, ctx->gen_counter.ptr, ctx->stream};
+                                       ds->ppair.ptr, ds->qpad.ptr, ds->dqbound.ptr,
+                                       ds->tbound.ptr, ds->wfrag.ptr, ds->wb2.ptr,
+                                       ctx->gen_counter.ptr, ctx->stream};
   const std::vector<double> vk = {(double)ds->serial, (double)n_par, (double)n_pop,
                                   (double)(seed & 0xFFFFFFFFull), (double)(seed >> 32),
                                   lambda_host[0], lambda_host[1], lambda_host[2], lambda_host[3],
