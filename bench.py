@@ -109,32 +109,52 @@ def parse():
 
 def disordered_rate(args, nep, I, torch, z):
     """512,000-atom random Si cube at 2.33 g/cm^3: NVE steps that write the
-    per-atom virial and heat current every step."""
+    per-atom virial and heat current every step.  The random packing relaxes
+    violently (atoms move up to about 0.6 A in 10 fs under the trained model),
+    so the lists use a 1 A skin and are rebuilt every 5 steps; synchronize
+    raises if any step saw an atom farther than skin/2 from its list-build
+    position."""
     pos, box = I.disordered_cell(512000, seed=3)
     vel = I.maxwell_boltzmann(len(pos), 300.0, seed=2)
+    skin, rebuild, cap = 1.0, 5, 128
     ctx = nep.Context(0)
     ctx.load_params(nep.hyper(), z)
     p, v = nep.soa(pos), nep.soa(vel)
-    ctx.build_neighbors(p, box, skin=0.5, max_neighbors=96)
+    ctx.build_neighbors(p, box, skin=skin, max_neighbors=cap)
     n = len(pos)
     W = torch.empty((9, n), dtype=torch.float32, device="cuda")
     J = torch.empty((3, n), dtype=torch.float32, device="cuda")
     K = args.disordered_steps
     thermo = torch.empty((max(K, 20), 5), dtype=torch.float64, device="cuda")
-    ctx.md_step(20, 1.0, 10, I.MASS_SI, p, v, thermo, W, J)
+    ctx.md_step(20, 1.0, rebuild, I.MASS_SI, p, v, thermo, W, J)
     lanes, _ = ctx.autotune(p, reps=5)
     ctx.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.md_step(K, 1.0, 10, I.MASS_SI, p, v, thermo, W, J)
+    ctx.md_step(K, 1.0, rebuild, I.MASS_SI, p, v, thermo, W, J)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     ctx.synchronize()
     ms = nep.time_partials(ctx, p, reps=50)
+    h = nep.hyper()
+    mean_slots = float(ctx.get_neighbors()["cnt_radial"].double().mean())
+    pos_end = nep.aos(p)
+    nr = pair_counts(pos_end, box, h.rc_radial)
+    na = pair_counts(pos_end, box, h.rc_angular)
+    flop_atom = FLOP_SLOT * mean_slots + FLOP_RADIAL * nr + FLOP_ANGULAR * na + FLOP_ATOM
+    achieved = flop_atom * n / (ms / 1e3) / 1e12
     return {"workload": "NVE MD of a 512,000-atom random Si cube (2.33 g/cm^3, 2.0 A minimum "
                         "distance), per-atom W and J written every step, dt 1 fs, rebuild every "
-                        "10 steps", "atom_steps_per_s": n * K / t, "ms_per_step": t / K * 1e3,
-            "steps": K, "k_partials_us": ms * 1e3, "tile_lanes_per_atom": lanes}
+                        "%d steps, skin %.1f A" % (rebuild, skin),
+            "atom_steps_per_s": n * K / t, "ms_per_step": t / K * 1e3,
+            "steps": K, "k_partials_us": ms * 1e3, "tile_lanes_per_atom": lanes,
+            "roofline": {"kernel": "k_partials", "bound": "alu", "achieved": achieved,
+                         "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_FP32_TFLOPS, "flop_per_atom": flop_atom,
+                         "neighbours_radial": nr, "neighbours_angular": na,
+                         "list_slots": mean_slots,
+                         "algorithmic_GBps": (BYTE_ATOM + BYTE_SLOT * mean_slots) * n
+                         / (ms / 1e3) / 1e9}}
 
 
 def spectral_rate(ctx, nep, torch, p, v, n, box, dt, rebuild, mass, fe, n_lags=250,
@@ -294,6 +314,21 @@ def snes_rate(args, ctx, nep, I, torch):
     t_gen = (time.perf_counter() - t0) / G
     ctx.synchronize()
     best = float(loss[:, 0].min())
+    # algorithmic flops of one generation (population pass only; sampling,
+    # sort and update are O(n_pop N_par)):
+    #   network, per (individual, atom): the hidden layer and dU/dq, two
+    #     N_neu x N_des products, plus output and sech^2 terms: 4 N_neu N_des + 4 N_neu;
+    #   contraction, per (individual, pair): p_ij from the radial rows,
+    #     2 * 3 (n_R + 1), and for angular pairs from the angular rows,
+    #     2 * 3 (n_A + 1) l_max; then F_i += p_ij, F_j -= p_ij (6) and the
+    #     structure virial r_ij (x) p_ij (18)
+    n_r, n_a = ds.pairs()
+    n_des, n_neu = nep.num_descriptors(h), h.n_neuron
+    nr1, na1 = h.n_max_radial + 1, h.n_max_angular + 1
+    f_net = n_pop * ds.n_atoms * (4 * n_neu * n_des + 4 * n_neu)
+    f_con = n_pop * (n_r * (6 * nr1 + 24) + n_a * 6 * na1 * h.l_max)
+    peak = 157.3e12  # MI355X dense FP32 matrix-core peak
+    achieved = (f_net + f_con) / t_gen
     # plain path: per individual, per structure nep_build_neighbors + nep_compute,
     # loss assembled on the host; timed on two individuals, scaled to the population
     Zh = Z.cpu().numpy()
@@ -330,6 +365,13 @@ def snes_rate(args, ctx, nep, I, torch):
         "plain_path": "host loop of nep_build_neighbors + nep_compute per (structure, "
                       "individual), timed on %d individuals and scaled to %d" % (n_plain, n_pop),
         "speedup_vs_plain": t_plain / t_gen,
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "gflop_per_gen": (f_net + f_con) / 1e9,
+                     "gflop_network": f_net / 1e9, "gflop_contraction": f_con / 1e9,
+                     "pairs_radial": n_r, "pairs_angular": n_a,
+                     "note": "algorithmic FP32 flops of the population pass per generation "
+                             "over the generation's wall time"},
     }
 
 

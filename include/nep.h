@@ -52,7 +52,8 @@ typedef enum {
   NEP_ENONFINITE = 5,  /* a non-finite energy or force was produced           */
   NEP_EDEVICE = 6,     /* a HIP runtime call failed                           */
   NEP_ENOTIMPL = 7,    /* hyperparameters without a compiled kernel variant   */
-  NEP_EIMAGE = 8       /* a pair needs a lattice image beyond +-3 cells       */
+  NEP_EIMAGE = 8,      /* a pair needs a lattice image beyond +-3 cells       */
+  NEP_ESKIN = 9        /* an atom moved more than skin/2 since its list build */
 } nep_status;
 
 /* Hyperparameters of Table nep-hyper (Sec. III B): radial and angular cutoffs
@@ -87,7 +88,8 @@ const char* nep_last_error(nep_ctx ctx);
 nep_status nep_set_stream(nep_ctx ctx, void* hip_stream);
 
 /* Wait for all enqueued work; return the first latched device error
- * (NEP_EOVERFLOW, NEP_EIMAGE, NEP_ENONFINITE) and clear it, else NEP_OK. */
+ * (NEP_EOVERFLOW, NEP_EIMAGE, NEP_ENONFINITE, NEP_ESKIN) and clear it, else
+ * NEP_OK. */
 nep_status nep_synchronize(nep_ctx ctx);
 
 /* N_des and N_par of a hyperparameter set (Eqs. N_des, N_par); 0 if invalid. */
@@ -155,7 +157,10 @@ nep_status nep_set_species(nep_ctx ctx, int n, const int* atomic_numbers_host,
 /* ------------------------------------------------------------ evaluation */
 
 /* One force evaluation of the system last passed to nep_build_neighbors
- * (same n_atoms and box; positions may have moved by less than skin/2).
+ * (same n_atoms and box; positions may have moved by at most skin/2: an
+ * evaluation that finds an atom farther than skin/2 from its position at the
+ * list build, compared in float32, latches NEP_ESKIN, since the list may then
+ * miss pairs inside the cutoff).
  * Computes, per Sec. II A-D:
  *   U_i (site energy), F_i = sum_j (dU_i/dr_ij - dU_j/dr_ji),
  *   W_i = sum_j r_ij (x) dU_j/dr_ji (full 3x3, Eq. Wi), J_i = W_i . v_i,
@@ -206,10 +211,14 @@ size_t nep_static_workspace_bytes(void);
  * [n_steps][5] float64 receives per step (E_pot, E_kin, sum J_x, J_y, J_z)
  * evaluated with the end-of-step velocities.  W_dev [9][N] / J_dev [3][N]
  * (float32, may be NULL) receive the per-atom virial and heat current at
- * every step (so they hold the last step's on return).  Requires a prior nep_build_neighbors for this system (its skin
- * and max_neighbors are reused).  Forces of the starting positions are
- * computed first unless the previous call was nep_md_step on the same
- * buffers. */
+ * every step (so they hold the last step's on return).  Requires a prior
+ * nep_build_neighbors for this system (its skin and max_neighbors are
+ * reused).  Forces of the starting positions are computed first unless the
+ * previous call was nep_md_step on the same buffers.  Every step checks that
+ * no atom has moved more than skin/2 since the list in use was built; a
+ * violation (rebuild_every too long for the skin and the dynamics) latches
+ * NEP_ESKIN, reported by nep_synchronize: the trajectory may then have missed
+ * pairs and should be rerun with a shorter interval or a larger skin. */
 nep_status nep_md_step(nep_ctx ctx, int n_steps, double dt_fs, int rebuild_every,
                        double mass_amu, double* pos_dev, double* vel_dev, double* thermo_dev,
                        float* W_dev, float* J_dev);
@@ -282,6 +291,12 @@ nep_status nep_dataset_create(nep_ctx ctx, int n_struct, const int* n_atoms_host
                               const double* energy_host, const double* forces_host,
                               const double* virial_host, const unsigned char* has_virial_host,
                               int max_neighbors, nep_dataset* out);
+
+/* Ordered pairs (i, j) of the dataset with r_ij inside the radial cutoff,
+ * and inside the angular cutoff, counted when the dataset's geometry was
+ * last prepared (creation or nep_dataset_set_positions).  Host only: makes
+ * no device call.  NEP_EINVAL on a NULL argument. */
+nep_status nep_dataset_pairs(nep_dataset ds, long long* radial_pairs, long long* angular_pairs);
 
 /* Free a dataset (waits for its context's stream).  NULL is ok. */
 void nep_dataset_destroy(nep_dataset ds);

@@ -297,6 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     double ekin_factor, double dt,
     double* __restrict__ pos_next, float fe0, float fe1, float fe2,
     const double* __restrict__ mass_c, const int* __restrict__ perm, double mref,
+    const float* __restrict__ pos_ref, float half_skin2, int* __restrict__ flags,
     double* __restrict__ partials) {
   const unsigned bx = xcd_block(blockIdx.x, gridDim.x);
   const int gid = (int)bx * blockDim.x + threadIdx.x;
@@ -380,6 +381,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(
 #pragma unroll
   for (int q = 0; q < NQ; ++q) v[q] = 0.0;
   if (active && lane == 0) {
+    // the list holds every pair within the cutoff only while no atom has
+    // moved more than skin/2 since it was built (compared in float32, so an
+    // unmoved atom gives exactly zero)
+    const float ex = (float)xi - pos_ref[i], ey = (float)yi - pos_ref[n + i],
+                ez = (float)zi - pos_ref[2 * n + i];
+    if (ex * ex + ey * ey + ez * ez > half_skin2) flags[kFlagSkin] = 1;
     F[i] = f0;
     F[n + i] = f1;
     F[2 * n + i] = f2;
@@ -545,11 +552,12 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
   const float* U = ctx->U.ptr;
   const bool per_atom = ctx->species_on() && ctx->have_masses;
   const double* mass_c = per_atom ? (const double*)ctx->masses.ptr : (const double*)nullptr;
+  const float half_skin = (float)(0.5 * s.skin);
   auto go = [&](auto kernel) {
     launch_kernel(ctx, true, last, kernel, dim3(nb), dim3(kBlock), s.n, pos, vel, nl, geo, cnt, p,
                   fown, U, s.box, U_out, F_out, W_out, J_out, kick, ekin_factor, dt, pos_next,
                   (float)fe[0], (float)fe[1], (float)fe[2], mass_c, (const int*)s.perm.ptr, mass,
-                  block_out);
+                  (const float*)s.pos_ref.ptr, half_skin * half_skin, ctx->flags.ptr, block_out);
   };
   if (use_geo && gather_lanes(s.n) == 2) {
     if (mode == 0)

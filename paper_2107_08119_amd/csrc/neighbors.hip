@@ -35,7 +35,8 @@ __global__ void k_zero(int* __restrict__ a, int m) {
 // positions into the cell first) and, on the cell path, the cell index.
 __global__ void k_bin(int n, double* __restrict__ pos, Box box, int nc0, int nc1, int nc2,
                       int use_cells, int wrap_in_place, int* __restrict__ wrap,
-                      int* __restrict__ cell_of, int* __restrict__ cell_cnt) {
+                      int* __restrict__ cell_of, int* __restrict__ cell_cnt,
+                      float* __restrict__ pos_ref) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double r[3] = {pos[i], pos[n + i], pos[2 * n + i]};
@@ -52,6 +53,8 @@ __global__ void k_bin(int n, double* __restrict__ pos, Box box, int nc0, int nc1
     for (int a = 0; a < 3; ++a) w[a] = (int)floor(s[a]);
   }
   for (int a = 0; a < 3; ++a) wrap[a * n + i] = w[a];
+  if (pos_ref)  // the positions this list is built for (no re-sort on this path)
+    for (int c = 0; c < 3; ++c) pos_ref[c * n + i] = (float)r[c];
   if (use_cells) {
     const int nc[3] = {nc0, nc1, nc2};
     int c[3];
@@ -175,7 +178,8 @@ __global__ void k_permute(int n, const int* __restrict__ members, const double* 
                           int* __restrict__ wrap_out, const int* __restrict__ perm,
                           int* __restrict__ perm_out, const int* __restrict__ cell_of,
                           int* __restrict__ cell_out, CellRec* __restrict__ rec,
-                          int* __restrict__ iperm_out, int* __restrict__ flags) {
+                          int* __restrict__ iperm_out, float* __restrict__ pos_ref,
+                          int* __restrict__ flags) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int o = members[k];
@@ -186,6 +190,9 @@ __global__ void k_permute(int n, const int* __restrict__ members, const double* 
   pos_out[k] = r.x;
   pos_out[n + k] = r.y;
   pos_out[2 * n + k] = r.z;
+  pos_ref[k] = (float)r.x;
+  pos_ref[n + k] = (float)r.y;
+  pos_ref[2 * n + k] = (float)r.z;
   if (vel) {
     vel_out[k] = vel[o];
     vel_out[n + k] = vel[n + o];
@@ -688,7 +695,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
   const size_t ncap = (size_t)n * s.cap;
   if ((e = s.nl.ensure(ncap)) != hipSuccess || (e = s.rev.ensure(ncap)) != hipSuccess ||
       (e = s.cnt_r.ensure(n)) != hipSuccess || (e = s.cnt_a.ensure(n)) != hipSuccess ||
-      (e = s.iperm.ensure(n)) != hipSuccess ||
+      (e = s.iperm.ensure(n)) != hipSuccess || (e = s.pos_ref.ensure((size_t)3 * n)) != hipSuccess ||
       (e = s.wrap.ensure((size_t)3 * n)) != hipSuccess)
     return check_hip(ctx, e, "allocating neighbour lists");
   const double rc2_r = s.rc_list_r * s.rc_list_r;
@@ -715,7 +722,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
                     s.cell_cnt.ptr, ncell);
     launch_kernel(ctx, !zero, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, s.pos_s.ptr,
                   s.box, s.nc[0], s.nc[1], s.nc[2], 1, wrap_in_place ? 1 : 0, s.wrap.ptr,
-                  s.cell_of.ptr, s.cell_cnt.ptr);
+                  s.cell_of.ptr, s.cell_cnt.ptr, (float*)nullptr);
     const int nsb = (ncell + 1023) / 1024;
     if (ncell > 16384 && nsb <= 1024) {
       launch_kernel(ctx, false, false, k_scan_blocks, dim3(nsb), dim3(1024), ncell,
@@ -741,7 +748,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
                   have_vel ? (const double*)s.vel_s.ptr : (const double*)nullptr,
                   have_vel ? s.vel_t.ptr : (double*)nullptr, (const int*)s.wrap.ptr, s.wrap_t.ptr,
                   (const int*)s.perm.ptr, s.perm_t.ptr, (const int*)s.cell_of.ptr, s.cell_t.ptr,
-                  s.cell_rec.ptr, s.iperm.ptr, ctx->flags.ptr);
+                  s.cell_rec.ptr, s.iperm.ptr, s.pos_ref.ptr, ctx->flags.ptr);
     s.pos_s.swap(s.pos_t);
     if (have_vel) s.vel_s.swap(s.vel_t);
     s.wrap.swap(s.wrap_t);
@@ -754,7 +761,8 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
                   s.cnt_a.ptr, ctx->flags.ptr);
   } else {
     launch_kernel(ctx, true, false, k_bin, dim3(blocks_for(n, kBlock)), blk, n, s.pos_s.ptr, s.box,
-                  1, 1, 1, 0, wrap_in_place ? 1 : 0, s.wrap.ptr, (int*)nullptr, (int*)nullptr);
+                  1, 1, 1, 0, wrap_in_place ? 1 : 0, s.wrap.ptr, (int*)nullptr, (int*)nullptr,
+                  s.pos_ref.ptr);
     launch_kernel(ctx, false, false, k_build_all_pairs, dim3(blocks_for(n, 4)), dim3(256), n,
                   s.cap, (const double*)s.pos_s.ptr, s.box, s.kimg[0], s.kimg[1], s.kimg[2],
                   (const int*)s.wrap.ptr, rc2_r, rc2_a, s.nl.ptr, s.cnt_r.ptr, s.cnt_a.ptr,

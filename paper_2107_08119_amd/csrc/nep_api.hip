@@ -159,7 +159,9 @@ nep_status nep_synchronize(nep_ctx ctx) {
   st = check_hip(ctx, hipMemcpy(h, ctx->flags.ptr, sizeof(h), hipMemcpyDeviceToHost),
                  "reading device flags");
   if (st != NEP_OK) return st;
-  if (h[0] | h[1] | h[2] | h[3]) {
+  int any = 0;
+  for (int k = 0; k < kNumFlags; ++k) any |= h[k];
+  if (any) {
     st = check_hip(ctx, hipMemset(ctx->flags.ptr, 0, sizeof(h)), "clearing device flags");
     if (st != NEP_OK) return st;
   }
@@ -167,6 +169,10 @@ nep_status nep_synchronize(nep_ctx ctx) {
   if (h[kFlagImage]) return fail(ctx, NEP_EIMAGE, "a neighbour needs a lattice image beyond +-3 cells");
   if (h[kFlagReverse]) return fail(ctx, NEP_EDEVICE, "neighbour list is not symmetric");
   if (h[kFlagNonFinite]) return fail(ctx, NEP_ENONFINITE, "non-finite energy, virial or heat current");
+  if (h[kFlagSkin])
+    return fail(ctx, NEP_ESKIN,
+                "an atom moved more than skin/2 since its neighbour list was built (rebuild "
+                "more often or use a larger skin)");
   return NEP_OK;
 }
 

@@ -92,7 +92,14 @@ struct DevBuf {
 };
 
 // Device error flags latched by kernels.
-enum Flag { kFlagOverflow = 0, kFlagImage = 1, kFlagNonFinite = 2, kFlagReverse = 3, kNumFlags = 4 };
+enum Flag {
+  kFlagOverflow = 0,
+  kFlagImage = 1,
+  kFlagNonFinite = 2,
+  kFlagReverse = 3,
+  kFlagSkin = 4,  // an evaluation saw an atom more than skin/2 from its list-build position
+  kNumFlags = 5
+};
 
 // 1 eV/A acting on 1 amu, in A/fs^2; and 1 amu A^2/fs^2 in eV.
 constexpr double kAccel = 1.602176634e-19 / 1.66053906660e-27 * 1.0e-10;
@@ -136,6 +143,7 @@ struct System {
   DevBuf<int> cell_atoms;  // [n] members of each cell, in arrival order
   DevBuf<int> cell_sorted;  // [n] members of each cell, by atom index
   DevBuf<CellRec> cell_rec;  // [n] positions and offsets in cell order
+  DevBuf<float> pos_ref;     // [3][n] positions at the last list build (float32, internal order)
   // The library works on its own copies of positions and velocities in cell
   // order (re-sorted at every rebuild); perm[k] is the caller's index of the
   // atom at internal index k, iperm[c] the internal index of caller atom c.
@@ -291,6 +299,7 @@ struct nep_dataset_s {
   nep::DevBuf<float2> pnorm;     // [N] largest row 1-norm of the force rows, of the virial rows
   nep::DevBuf<float2> tbound;    // [T] fixed-point bound factors of forces and virials
   int n_tiles = 0, tile_max = 0;
+  long long pairs_r = 0, pairs_a = 0;  // pairs inside r_c^R, inside r_c^A (geometry cache)
   int tile_kc = 0;               // individuals per contraction launch the tiles were sized for
   int pop_variant = 1;         // network kernel shape: 0, 1, 2 = 16, 32, 64 atoms per wave
   unsigned long long serial = 0;  // unique per dataset created by the process

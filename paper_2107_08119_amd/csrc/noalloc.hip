@@ -56,6 +56,7 @@ bool carve(char* base, const System& geo, int n, int cap, System& s, nep_ctx_s& 
   k.take(s.pos_t, n3);
   k.take(s.vel_s, n3);
   k.take(s.perm, n);
+  k.take(s.pos_ref, n3);
   if (geo.use_cells) {
     const size_t ncell = (size_t)geo.nc[0] * geo.nc[1] * geo.nc[2];
     k.take(s.nl_rm, ncap);

@@ -848,12 +848,15 @@ hipError_t prepare_dataset_geometry(nep_ctx ctx, nep_dataset ds) {
       (e = hipStreamSynchronize(st)) != hipSuccess)
     return e;
   std::vector<int4> meta(N);
-  size_t chunks = 0, pairs = 0;
+  size_t chunks = 0, pairs = 0, pairs_a = 0;
   for (int i = 0; i < N; ++i) {
     meta[i] = make_int4((int)chunks, (int)pairs, n_in[i], n_ang[i]);
     chunks += atom_chunks(n_in[i], n_ang[i]);
     pairs += n_in[i];
+    pairs_a += n_ang[i];
   }
+  ds->pairs_r = (long long)pairs;
+  ds->pairs_a = (long long)pairs_a;
   if (chunks >= (1ull << 31) || pairs >= (1ull << 31)) return hipErrorInvalidValue;
   // Tiles: consecutive whole structures whose accumulators fit the LDS for
   // tile_kc individuals: 3 KC (atoms + 3 structures) 32-bit values.

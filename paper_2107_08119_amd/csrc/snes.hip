@@ -547,6 +547,13 @@ nep_status nep_dataset_create(nep_ctx ctx, int n_struct, const int* n_atoms_host
   return NEP_OK;
 }
 
+nep_status nep_dataset_pairs(nep_dataset ds, long long* radial_pairs, long long* angular_pairs) {
+  if (!ds || !radial_pairs || !angular_pairs) return NEP_EINVAL;
+  *radial_pairs = ds->pairs_r;
+  *angular_pairs = ds->pairs_a;
+  return NEP_OK;
+}
+
 void nep_dataset_destroy(nep_dataset ds) {
   if (!ds) return;
   DeviceGuard guard(ds->ctx->device);

@@ -16,10 +16,10 @@ import torch
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnep.so")
 
 NEP_OK, NEP_EINVAL, NEP_ESTATE, NEP_ENOMEM, NEP_EOVERFLOW = 0, 1, 2, 3, 4
-NEP_ENONFINITE, NEP_EDEVICE, NEP_ENOTIMPL, NEP_EIMAGE = 5, 6, 7, 8
+NEP_ENONFINITE, NEP_EDEVICE, NEP_ENOTIMPL, NEP_EIMAGE, NEP_ESKIN = 5, 6, 7, 8, 9
 STATUS_NAMES = {0: "NEP_OK", 1: "NEP_EINVAL", 2: "NEP_ESTATE", 3: "NEP_ENOMEM",
                 4: "NEP_EOVERFLOW", 5: "NEP_ENONFINITE", 6: "NEP_EDEVICE", 7: "NEP_ENOTIMPL",
-                8: "NEP_EIMAGE"}
+                8: "NEP_EIMAGE", 9: "NEP_ESKIN"}
 
 EXPORTED = [
     "nep_create", "nep_destroy", "nep_last_error", "nep_set_stream", "nep_synchronize",
@@ -28,7 +28,8 @@ EXPORTED = [
     "nep_time_partials", "nep_dataset_create", "nep_dataset_destroy", "snes_eval_population",
     "snes_sample", "snes_update", "nep_dataset_set_positions", "nep_dataset_get_positions",
     "nep_dataset_compute", "nep_dataset_backward", "snes_autotune", "snes_run",
-    "snes_set_tile", "nep_autotune", "nep_set_tile", "nep_md_step_driven", "nep_set_species",
+    "snes_set_tile", "nep_dataset_pairs", "nep_autotune", "nep_set_tile", "nep_md_step_driven",
+    "nep_set_species",
     "nep_vvcf_create", "nep_vvcf_destroy", "nep_vvcf_sample", "nep_vvcf_get", "nep_vvcf_spectrum",
     "nep_evaluate_static", "nep_static_workspace_bytes",
 ]
@@ -92,6 +93,7 @@ def lib() -> C.CDLL:
         L.nep_dataset_create.argtypes = [vp, ip, vp, vp, vp, vp, vp, vp, vp, ip, C.POINTER(vp)]
         L.nep_dataset_destroy.argtypes = [vp]
         L.nep_dataset_destroy.restype = None
+        L.nep_dataset_pairs.argtypes = [vp, vp, vp]
         L.snes_eval_population.argtypes = [vp, vp, ip, vp, vp, vp]
         L.snes_sample.argtypes = [vp, ip, ip, vp, vp, C.c_ulonglong, ip, vp, vp]
         L.snes_update.argtypes = [vp, ip, ip, vp, vp, vp, vp, dp, dp]
@@ -477,6 +479,12 @@ class Dataset:
     def __init__(self, ctx: Context, handle, n_struct: int, n_atoms: int):
         self.ctx, self._h, self.n_struct, self.n_atoms = ctx, handle, n_struct, n_atoms
         self._pos_key = None  # (data pointer, version) of the positions last uploaded
+
+    def pairs(self) -> tuple[int, int]:
+        """Ordered pairs inside the radial and inside the angular cutoff."""
+        r, a = C.c_longlong(), C.c_longlong()
+        self.ctx._check(self.ctx._lib.nep_dataset_pairs(self._h, C.byref(r), C.byref(a)))
+        return r.value, a.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -111,3 +111,50 @@ def test_ragged_cluster_matches_oracle():
     for k, got in (("U", out["U"].cpu().numpy()), ("F", nep.aos(out["F"])),
                    ("W", nep.aos(out["W"]).reshape(-1, 3, 3)), ("J", nep.aos(out["J"]))):
         assert rel(got, ref[k]) < TOL, k
+
+
+def test_skin_latch_on_evaluation():
+    """A list built with skin s holds every pair inside the cutoff only while
+    no atom has moved more than s/2 since the build: an evaluation past that
+    latches NEP_ESKIN (reported once by synchronize, then cleared); one within
+    it, or after a rebuild at the new positions, does not."""
+    z = I.random_parameters(931, 1)
+    nep, ctx = context(z)
+    pos, box = I.parity_cell(0)
+    ctx.build_neighbors(nep.soa(pos), box, skin=0.5, max_neighbors=64)
+    q = pos.copy()
+    q[5] += [0.2, 0.0, 0.1]  # 0.224 A < skin/2
+    ctx.compute(nep.soa(q))
+    ctx.synchronize()
+    q[5] = pos[5] + [0.0, -0.26, 0.0]
+    ctx.compute(nep.soa(q))
+    with pytest.raises(nep.NepError) as err:
+        ctx.synchronize()
+    assert err.value.status == nep.NEP_ESKIN
+    ctx.synchronize()  # the latch was cleared
+    ctx.build_neighbors(nep.soa(q), box, skin=0.5, max_neighbors=64)
+    out = ctx.compute(nep.soa(q))
+    ctx.synchronize()
+    ref = O.nep_eval(O.hyper(), z, q, box)
+    assert rel(nep.aos(out["F"]), ref["F"]) < TOL
+
+
+def test_skin_latch_in_md():
+    """Velocity-Verlet at 600 K with a 0.1 A skin: rebuilding every 2 steps
+    keeps every atom within skin/2 of its list-build position (about 0.015 A
+    per step at most here), a 1,000-step interval over 200 steps does not."""
+    from paper_2107_08119_amd import train as T
+    z, _ = T.load_model(T.MODEL_SI_SW)
+    nep, ctx = context(z)
+    pos, box = I.diamond_supercell(3, 3, 3)
+    vel = I.maxwell_boltzmann(len(pos), 600.0, seed=2)
+    p, v = nep.soa(pos), nep.soa(vel)
+    ctx.build_neighbors(p, box, skin=0.1, max_neighbors=64)
+    ctx.md_step(200, 1.0, 2, I.MASS_SI, p, v)
+    ctx.synchronize()
+    p, v = nep.soa(pos), nep.soa(vel)
+    ctx.build_neighbors(p, box, skin=0.1, max_neighbors=64)
+    ctx.md_step(200, 1.0, 1000, I.MASS_SI, p, v)
+    with pytest.raises(nep.NepError) as err:
+        ctx.synchronize()
+    assert err.value.status == nep.NEP_ESKIN

@@ -45,8 +45,8 @@ def gpu_eval(pos, box, z, vel=None, skin=0.5, cap=64, ctx=None):
     return res, ctx
 
 
-def list_keys_oracle(pos, box, rc):
-    cnt, jl, img = O.neighbor_arrays(pos, box, rc, cap=96)
+def list_keys_oracle(pos, box, rc, cap=96):
+    cnt, jl, img = O.neighbor_arrays(pos, box, rc, cap=cap)
     i = np.repeat(np.arange(len(cnt)), cnt)
     mask = np.arange(jl.shape[1])[None, :] < cnt[:, None]
     j = jl[mask]
