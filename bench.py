@@ -256,10 +256,10 @@ def pbte_rate(nep, I, torch, steps=100):
     """A two-species system (Sec. II C, multicomponent weighting sqrt(Z_i Z_j)):
     64,000-atom rock-salt PbTe with the PbTe-like model sizes of Table I
     (r_c 8/4 A, n_max 12/6, l_max 4, 40 neurons: 41-40-1, 1721 parameters),
-    random parameters, per-atom masses; NVE, dt 1 fs, rebuild every 10 steps."""
+    random parameters N(0, 0.05^2), per-atom masses; NVE, dt 1 fs, rebuild every
+    10 steps.  Multicomponent systems take the float64-descriptor kernel."""
     h = nep.hyper(8.0, 4.0, 12, 6, 4, 40)
     z = I.random_parameters(nep.num_params(h), seed=1, std=0.05)
-    z[:40 * 41] *= np.float32(1.0 / 300.0)  # input weights: O(1) activations
     pos, box, Z, masses = I.rocksalt_supercell(20, 20, 20)
     vel = I.maxwell_boltzmann(len(pos), 300.0, seed=2, mass=masses)
     ctx = nep.Context(0)

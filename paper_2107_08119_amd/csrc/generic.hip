@@ -16,6 +16,16 @@
 //     stores the pair vector r_ij in the atom's own slot for pass 2 (systems
 //     of up to kPairVectorMaxAtoms atoms).
 // Every sum has a fixed order, so results are reproducible bit for bit.
+//
+// Multicomponent systems take the descriptor and the hidden layer's input in
+// float64 (pair geometry, basis, harmonics, the sums q and c_nlm, and the
+// pre-activations with tanh and sech^2): the pair weights sqrt(Z_i Z_j) (up to
+// 82) scale the descriptor up by about two orders, unscaled input weights then
+// put pre-activations in the hundreds, and sech^2 there changes relatively by
+// twice any absolute error of the pre-activation, which float32 sums make about
+// 1e-5.  The partial forces stay float32.
+#include <type_traits>
+
 #include "nep_terms.h"
 
 namespace nep {
@@ -48,6 +58,92 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Fixed-order sum over the 64 lanes in float64 (butterfly: each step adds the
+// same two values on both partners, so every lane gets the same bits).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// r_ij of list entry e in float64, rounded exactly as the float32
+// displacement is before its final rounding (so the two agree to float32).
+__device__ __forceinline__ void displacement_d(uint32_t e, const double* __restrict__ pos, int n,
+                                               double xi, double yi, double zi, const double* h,
+                                               int& j, double& dx, double& dy, double& dz) {
+  j = (int)(e & kAtomMask);
+  int n0, n1, n2;
+  unpack_image(e, n0, n1, n2);
+  const double a0 = (double)n0, a1 = (double)n1, a2 = (double)n2;
+  dx = (pos[j] - xi) + (a0 * h[0] + a1 * h[3] + a2 * h[6]);
+  dy = (pos[n + j] - yi) + (a0 * h[1] + a1 * h[4] + a2 * h[7]);
+  dz = (pos[2 * n + j] - zi) + (a0 * h[2] + a1 * h[5] + a2 * h[8]);
+}
+
+constexpr double kPiD = 3.14159265358979323846;
+
+// f_c(r) = (1 + cos(pi r/r_c))/2 and T_n(x), x = 2 (r/r_c - 1)^2 - 1, n < NB,
+// in float64: the factors of g_n = f_c (T_n + 1)/2 (Eq. g_n).
+template <int NB>
+__device__ __forceinline__ void chebyshev_values_d(double r, double rc_inv, double& fc, double* T) {
+  const double t = r * rc_inv;
+  fc = 0.5 * (1.0 + cos(kPiD * t));
+  const double tm1 = t - 1.0;
+  const double x = 2.0 * tm1 * tm1 - 1.0;
+  T[0] = 1.0;
+  if constexpr (NB > 1) T[1] = x;
+#pragma unroll
+  for (int k = 2; k < NB; ++k) T[k] = 2.0 * x * T[k - 1] - T[k - 2];
+}
+
+// g_n(r), n < nb (<= MB), zero beyond, in float64.
+template <int MB>
+__device__ __forceinline__ void radial_basis_d(double r, double rc_inv, int nb, double* g) {
+  double fc, T[MB];
+  chebyshev_values_d<MB>(r, rc_inv, fc, T);
+#pragma unroll
+  for (int k = 0; k < MB; ++k) g[k] = k < nb ? 0.5 * (T[k] + 1.0) * fc : 0.0;
+}
+
+// The 24 harmonics Yhat_lm (l = 1..4) in float64: the same polynomials, with
+// the square roots in their float64 values.
+#pragma push_macro("NEP_S3")
+#pragma push_macro("NEP_S5")
+#pragma push_macro("NEP_S6")
+#pragma push_macro("NEP_S10")
+#pragma push_macro("NEP_S15")
+#pragma push_macro("NEP_S35")
+#pragma push_macro("NEP_S70")
+#undef NEP_S3
+#undef NEP_S5
+#undef NEP_S6
+#undef NEP_S10
+#undef NEP_S15
+#undef NEP_S35
+#undef NEP_S70
+#define NEP_S3 1.7320508075688772935
+#define NEP_S5 2.2360679774997896964
+#define NEP_S6 2.4494897427831780982
+#define NEP_S10 3.1622776601683793320
+#define NEP_S15 3.8729833462074168852
+#define NEP_S35 5.9160797830996160426
+#define NEP_S70 8.3666002653407554798
+__device__ __forceinline__ void harmonics_d(double x, double y, double z, double (&out)[24]) {
+  const double xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+  const double xyz = xy * z;
+  (void)xyz;
+#define NEP_Y(idx, YV, GX, GY, GZ) out[idx] = (YV);
+  NEP_YLM_TABLE(NEP_Y)
+#undef NEP_Y
+}
+#pragma pop_macro("NEP_S70")
+#pragma pop_macro("NEP_S35")
+#pragma pop_macro("NEP_S15")
+#pragma pop_macro("NEP_S10")
+#pragma pop_macro("NEP_S6")
+#pragma pop_macro("NEP_S5")
+#pragma pop_macro("NEP_S3")
+
 // Radial basis g_n, n < nb (<= MB), and optionally g_n'.
 template <int MB>
 __device__ __forceinline__ void radial_basis_n(float r, float rc_inv, int nb, float* g, float* dg) {
@@ -60,15 +156,20 @@ __device__ __forceinline__ void radial_basis_n(float r, float rc_inv, int nb, fl
   }
 }
 
-template <int TR, int TA, int TL, int TNEU>
+// F64: the float64 descriptor and hidden-layer input of multicomponent
+// systems (wspd = sqrt(Z) in float64 beside wsp).
+template <int TR, int TA, int TL, int TNEU, bool F64>
 __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
     int n, const double* __restrict__ pos, const uint32_t* __restrict__ nl,
     const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, const int* __restrict__ rev,
     Box box, const float* __restrict__ z, int nr_rt, int na_rt, int lmax_rt, int nneu_rt,
-    float rc_r, float rc_a, const float* __restrict__ wsp, const int* __restrict__ perm,
+    double rc_rd, double rc_ad, const float* __restrict__ wsp,
+    const double* __restrict__ wspd, const int* __restrict__ perm,
     Partial3* __restrict__ pin, float* __restrict__ fown, float* __restrict__ U,
     Partial3* __restrict__ geo) {
   using S = Shape<TR, TA, TL, TNEU>;
+  using DT = typename std::conditional<F64, double, float>::type;
+  const float rc_r = (float)rc_rd, rc_a = (float)rc_ad;
   constexpr int kMaxR = S::MR, kMaxA = S::MA, kMaxLM = S::MLM, kMaxNeu = S::MNEU;
   constexpr int kMaxDes = S::MDES;
   const int NR = S::kFixed ? TR : nr_rt;
@@ -80,7 +181,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
   // Compiled shapes with l_max = 4 read LDS four floats at a time: the
   // network rows, the descriptor and the neurons' w2 sech^2 are padded with
   // zeros to multiples of 4, and the harmonics rows hold 24 floats.
-  constexpr bool kVec = S::kFixed && TL == 4;
+  constexpr bool kVec = S::kFixed && TL == 4 && !F64;
   constexpr int kDes4 = ((kMaxDes + 3) / 4) * 4;
   constexpr int kRS = kVec ? kDes4 + (kDes4 % 32 == 0 ? 4 : 0) : kMaxDes + 1;
   constexpr int kNeuRows = kVec ? ((kMaxNeu + 3) / 4) * 4 : kMaxNeu;
@@ -88,11 +189,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
   const int RS = kVec ? kRS : NDES + 1;  // LDS row of neuron mu: w1[mu][:] (padded)
   __shared__ __align__(16) float s_w1[kNeuRows * kRS];
   __shared__ float s_b1[kMaxNeu], s_w2[kMaxNeu];
-  __shared__ float s_g[kWaves][64][kMaxA + 1];           // angular g_n of each lane's pair
-  __shared__ __align__(16) float s_y[kWaves][64][kYS];   // Yhat_lm of each lane's pair
-  __shared__ __align__(16) float s_q[kWaves][kDes4];
+  __shared__ DT s_g[kWaves][64][kMaxA + 1];           // angular g_n of each lane's pair
+  __shared__ __align__(16) DT s_y[kWaves][64][kYS];   // Yhat_lm of each lane's pair
+  __shared__ __align__(16) DT s_q[kWaves][kDes4];
   __shared__ float s_dq[kWaves][kMaxDes];
-  __shared__ float s_c[kWaves][kMaxA * kMaxLM];  // c_nlm, then a_nlm
+  __shared__ float s_c[kWaves][kMaxA * kMaxLM];  // c_nlm (float32 path), then a_nlm
+  __shared__ double s_cd[F64 ? kWaves : 1][F64 ? kMaxA * kMaxLM : 1];  // c_nlm in float64
   __shared__ __align__(16) float s_gmu[kWaves][kNeuRows];
   if constexpr (kVec) {
     for (int t = threadIdx.x; t < kNeuRows * kRS; t += blockDim.x) {
@@ -120,14 +222,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
   const float rcr_inv = 1.f / rc_r, rca_inv = 1.f / rc_a;
   const float rcr2 = rc_r * rc_r, rca2 = rc_a * rc_a;
   const int nout = NA * NLM;  // angular moments, lane k owns k, k + 64, ...
-  float qr[kMaxR];
+  DT qr[kMaxR];
   constexpr int kR4 = (kMaxA * 6 + 63) / 64;  // rounds of the four-output groups
-  float cacc[kVec ? 1 : (kMaxA * kMaxLM + 63) / 64];
+  DT cacc[kVec ? 1 : (kMaxA * kMaxLM + 63) / 64];
   float4 cacc4[kVec ? kR4 : 1];
 #pragma unroll
-  for (int a = 0; a < kMaxR; ++a) qr[a] = 0.f;
+  for (int a = 0; a < kMaxR; ++a) qr[a] = 0;
 #pragma unroll
-  for (int r = 0; r < (kVec ? 1 : (kMaxA * kMaxLM + 63) / 64); ++r) cacc[r] = 0.f;
+  for (int r = 0; r < (kVec ? 1 : (kMaxA * kMaxLM + 63) / 64); ++r) cacc[r] = 0;
 #pragma unroll
   for (int r = 0; r < (kVec ? kR4 : 1); ++r) cacc4[r] = make_float4(0.f, 0.f, 0.f, 0.f);
   auto wave_lds_sync = [] {
@@ -139,32 +241,59 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
   // ---- descriptor
   for (int base = 0; base < cr; base += 64) {
     const int s = base + lane;
-    float g[kMaxA], yh[kMaxLM];
+    DT g[kMaxA], yh[kMaxLM];
 #pragma unroll
-    for (int a = 0; a < kMaxA; ++a) g[a] = 0.f;
+    for (int a = 0; a < kMaxA; ++a) g[a] = 0;
 #pragma unroll
-    for (int m = 0; m < kMaxLM; ++m) yh[m] = 0.f;
+    for (int m = 0; m < kMaxLM; ++m) yh[m] = 0;
     if (s < cr) {
       int j;
       float dx, dy, dz;
-      displacement(nl[(size_t)s * n + i], pos, n, xi, yi, zi, box.h, j, dx, dy, dz);
-      const float wij = wsp ? wi * wsp[perm[j]] : 1.f;
-      const float r2 = pair_r2(dx, dy, dz);
-      const float rinv = __builtin_amdgcn_rsqf(r2);
-      const float r = r2 * rinv;
-      if (r2 < rcr2) {  // entries a >= NR are never read
-        float fc, T[kMaxR];
-        chebyshev_values<kMaxR>(r, rcr_inv, fc, T);
-        const float wf = wij * fc;
-        qr[0] += wf;
+      if constexpr (F64) {
+        double ex, ey, ez;
+        displacement_d(nl[(size_t)s * n + i], pos, n, xi, yi, zi, box.h, j, ex, ey, ez);
+        dx = (float)ex;
+        dy = (float)ey;
+        dz = (float)ez;
+        // in or out of a cutoff exactly as the float32 partial-force loop decides
+        const float r2 = pair_r2(dx, dy, dz);
+        const double wij = wspd[perm[i]] * wspd[perm[j]];
+        const double r = sqrt(ex * ex + ey * ey + ez * ez);
+        if (r2 < rcr2) {
+          double fc, T[kMaxR];
+          chebyshev_values_d<kMaxR>(r, 1.0 / rc_rd, fc, T);
+          const double wf = wij * fc;
+          qr[0] += wf;
 #pragma unroll
-        for (int a = 1; a < kMaxR; ++a) qr[a] += wf * T[a];
-      }
-      if (s < ca && r2 < rca2) {
-        radial_basis_n<kMaxA>(r, rca_inv, NA, g, nullptr);
+          for (int a = 1; a < kMaxR; ++a) qr[a] += wf * T[a];
+        }
+        if (s < ca && r2 < rca2) {
+          radial_basis_d<kMaxA>(r, 1.0 / rc_ad, NA, g);
 #pragma unroll
-        for (int a = 0; a < kMaxA; ++a) g[a] *= wij;
-        harmonics(dx * rinv, dy * rinv, dz * rinv, yh);
+          for (int a = 0; a < kMaxA; ++a) g[a] *= wij;
+          const double rinv = 1.0 / r;
+          harmonics_d(ex * rinv, ey * rinv, ez * rinv, yh);
+        }
+      } else {
+        displacement(nl[(size_t)s * n + i], pos, n, xi, yi, zi, box.h, j, dx, dy, dz);
+        const float wij = wsp ? wi * wsp[perm[j]] : 1.f;
+        const float r2 = pair_r2(dx, dy, dz);
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float r = r2 * rinv;
+        if (r2 < rcr2) {  // entries a >= NR are never read
+          float fc, T[kMaxR];
+          chebyshev_values<kMaxR>(r, rcr_inv, fc, T);
+          const float wf = wij * fc;
+          qr[0] += wf;
+#pragma unroll
+          for (int a = 1; a < kMaxR; ++a) qr[a] += wf * T[a];
+        }
+        if (s < ca && r2 < rca2) {
+          radial_basis_n<kMaxA>(r, rca_inv, NA, g, nullptr);
+#pragma unroll
+          for (int a = 0; a < kMaxA; ++a) g[a] *= wij;
+          harmonics(dx * rinv, dy * rinv, dz * rinv, yh);
+        }
       }
     }
 #pragma unroll
@@ -198,7 +327,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
         const int k = lane + 64 * r;
         if (k < nout) {
           const int a = k / NLM, m = k % NLM;
-          float acc = cacc[r];
+          DT acc = cacc[r];
           for (int p = 0; p < np; ++p) acc += s_g[wave][p][a] * s_y[wave][p][m];
           cacc[r] = acc;
         }
@@ -207,12 +336,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
     wave_lds_sync();
   }
   // radial components q_0 = R_0, q_n = (R_n + R_0)/2, and angular moments to LDS
-  const float r0 = wave_sum(qr[0]);
+  const DT r0 = wave_sum(qr[0]);
   if (lane == 0) s_q[wave][0] = r0;
 #pragma unroll
   for (int a = 1; a < kMaxR; ++a) {
-    const float v = wave_sum(qr[a]);
-    if (lane == 0 && a < NR) s_q[wave][a] = 0.5f * (v + r0);
+    const DT v = wave_sum(qr[a]);
+    if (lane == 0 && a < NR) s_q[wave][a] = (DT)0.5 * (v + r0);
   }
   if constexpr (kVec) {
 #pragma unroll
@@ -230,16 +359,22 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
 #pragma unroll
     for (int r = 0; r < (kMaxA * kMaxLM + 63) / 64; ++r) {
       const int k = lane + 64 * r;
-      if (k < nout) s_c[wave][k] = cacc[r];
+      if (k < nout) {
+        if constexpr (F64)
+          s_cd[wave][k] = cacc[r];
+        else
+          s_c[wave][k] = cacc[r];
+      }
     }
   }
   wave_lds_sync();
   // angular components q_nl = sum_m c_nlm^2
   if (lane < NA * LMAX) {
     const int a = lane / LMAX, l = lane % LMAX + 1;
-    float s2 = 0.f;
+    DT s2 = 0;
     for (int m = 0; m < 2 * l + 1; ++m) {
-      const float v = s_c[wave][a * NLM + l * l - 1 + m];
+      const int k = a * NLM + l * l - 1 + m;
+      const DT v = F64 ? (DT)s_cd[F64 ? wave : 0][F64 ? k : 0] : (DT)s_c[wave][k];
       s2 += v * v;
     }
     s_q[wave][NR + a * LMAX + (l - 1)] = s2;
@@ -247,9 +382,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
   wave_lds_sync();
 
   // ---- network (Eqs. nn1, nn2): lane mu is neuron mu
-  float u = 0.f;
+  DT u = 0;
   if (lane < NNEU) {
-    float act = -s_b1[lane];
+    DT act = -(DT)s_b1[lane];
     if constexpr (kVec) {
 #pragma unroll 4
       for (int v4 = 0; v4 < kDes4 / 4; ++v4) {
@@ -261,18 +396,26 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
         act += w4.w * q4.w;
       }
     } else {
-      for (int v = 0; v < NDES; ++v) act += s_w1[lane * RS + v] * s_q[wave][v];
+      for (int v = 0; v < NDES; ++v) act += (DT)s_w1[lane * RS + v] * s_q[wave][v];
     }
-    const float ea = __expf(-2.f * fabsf(act));
-    const float inv = __builtin_amdgcn_rcpf(1.f + ea);
-    const float th = copysignf((1.f - ea) * inv, act);
-    u = s_w2[lane] * th;
-    s_gmu[wave][lane] = s_w2[lane] * (4.f * ea * inv * inv);
+    if constexpr (F64) {
+      const double ea = exp(-2.0 * fabs(act));
+      const double inv = 1.0 / (1.0 + ea);
+      const double th = copysign((1.0 - ea) * inv, act);
+      u = (double)s_w2[lane] * th;
+      s_gmu[wave][lane] = (float)((double)s_w2[lane] * (4.0 * ea * inv * inv));
+    } else {
+      const float ea = __expf(-2.f * fabsf(act));
+      const float inv = __builtin_amdgcn_rcpf(1.f + ea);
+      const float th = copysignf((1.f - ea) * inv, act);
+      u = s_w2[lane] * th;
+      s_gmu[wave][lane] = s_w2[lane] * (4.f * ea * inv * inv);
+    }
   } else if (kVec && lane < kNeuRows) {
     s_gmu[wave][lane] = 0.f;  // padding (its w1 row is zero too)
   }
-  u = wave_sum(u) - b2;
-  if (lane == 0) U[i] = u;
+  u = wave_sum(u) - (DT)b2;
+  if (lane == 0) U[i] = (float)u;
   wave_lds_sync();
   // dU/dq_v: lane v (two rounds for up to 128 descriptor components)
   for (int v = lane; v < NDES; v += 64) {
@@ -300,7 +443,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
       const int a = k / NLM, m = k % NLM;
       int l = 1;
       while ((l + 1) * (l + 1) - 1 <= m) ++l;
-      s_c[wave][k] = 2.f * s_dq[wave][NR + a * LMAX + (l - 1)] * s_c[wave][k];
+      if constexpr (F64)
+        s_c[wave][k] = (float)(2.0 * (double)s_dq[wave][NR + a * LMAX + (l - 1)] *
+                               s_cd[F64 ? wave : 0][F64 ? k : 0]);
+      else
+        s_c[wave][k] = 2.f * s_dq[wave][NR + a * LMAX + (l - 1)] * s_c[wave][k];
     }
   }
   wave_lds_sync();
@@ -418,17 +565,18 @@ bool generic_supports(const nep_hyper& h) {
 
 namespace {
 
-template <int TR, int TA, int TL, int TNEU>
+template <int TR, int TA, int TL, int TNEU, bool F64>
 void launch_shape(nep_ctx ctx, const double* pos) {
   const System& s = ctx->sys;
   const nep_hyper& h = ctx->hyper;
-  launch_kernel(ctx, true, true, k_partials_generic<TR, TA, TL, TNEU>,
+  const bool species = ctx->species_on();
+  launch_kernel(ctx, true, true, k_partials_generic<TR, TA, TL, TNEU, F64>,
                 dim3(blocks_for(s.n, kWaves)), dim3(64 * kWaves), s.n, pos,
                 (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr, (const int*)s.cnt_a.ptr,
                 (const int*)s.rev.ptr, s.box, (const float*)ctx->z.ptr, h.n_max_radial + 1,
-                h.n_max_angular + 1, h.l_max, h.n_neuron, (float)h.rc_radial,
-                (float)h.rc_angular,
-                ctx->species_on() ? (const float*)ctx->species_w.ptr : (const float*)nullptr,
+                h.n_max_angular + 1, h.l_max, h.n_neuron, h.rc_radial, h.rc_angular,
+                species ? (const float*)ctx->species_w.ptr : (const float*)nullptr,
+                species ? (const double*)ctx->species_wd.ptr : (const double*)nullptr,
                 (const int*)s.perm.ptr, ctx->p.ptr, ctx->fown.ptr, ctx->U.ptr,
                 s.n <= kPairVectorMaxAtoms ? ctx->geo.ptr : (Partial3*)nullptr);
 }
@@ -442,19 +590,29 @@ bool is_shape(const nep_hyper& h, int nr, int na, int lmax, int nneu) {
 
 // Compile-time sizes for the models of Table I (general Si, silicene, PbTe)
 // and the default model; every other size takes the runtime-sized kernel.
+// Multicomponent systems take the float64-descriptor kernels (compiled sizes
+// for the PbTe and default models).
 hipError_t launch_partials_generic(nep_ctx ctx, const double* pos) {
   if (ctx->sys.n == 0) return hipSuccess;
   const nep_hyper& h = ctx->hyper;
-  if (is_shape(h, 16, 16, 4, 50))
-    launch_shape<16, 16, 4, 50>(ctx, pos);
-  else if (is_shape(h, 13, 13, 4, 40))
-    launch_shape<13, 13, 4, 40>(ctx, pos);
-  else if (is_shape(h, 13, 7, 4, 40))
-    launch_shape<13, 7, 4, 40>(ctx, pos);
-  else if (is_shape(h, 9, 5, 4, 30))
-    launch_shape<9, 5, 4, 30>(ctx, pos);
-  else
-    launch_shape<0, 0, 0, 0>(ctx, pos);
+  if (ctx->species_on()) {
+    if (is_shape(h, 13, 7, 4, 40))
+      launch_shape<13, 7, 4, 40, true>(ctx, pos);
+    else if (is_shape(h, 9, 5, 4, 30))
+      launch_shape<9, 5, 4, 30, true>(ctx, pos);
+    else
+      launch_shape<0, 0, 0, 0, true>(ctx, pos);
+  } else if (is_shape(h, 16, 16, 4, 50)) {
+    launch_shape<16, 16, 4, 50, false>(ctx, pos);
+  } else if (is_shape(h, 13, 13, 4, 40)) {
+    launch_shape<13, 13, 4, 40, false>(ctx, pos);
+  } else if (is_shape(h, 13, 7, 4, 40)) {
+    launch_shape<13, 7, 4, 40, false>(ctx, pos);
+  } else if (is_shape(h, 9, 5, 4, 30)) {
+    launch_shape<9, 5, 4, 30, false>(ctx, pos);
+  } else {
+    launch_shape<0, 0, 0, 0, false>(ctx, pos);
+  }
   return hipGetLastError();
 }
 

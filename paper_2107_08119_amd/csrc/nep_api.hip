@@ -128,6 +128,7 @@ void nep_destroy(nep_ctx ctx) {
   ctx->p.release();
   ctx->geo.release();
   ctx->species_w.release();
+  ctx->species_wd.release();
   ctx->masses.release();
   ctx->fown.release();
   ctx->U.release();
@@ -277,10 +278,12 @@ nep_status nep_set_species(nep_ctx ctx, int n, const int* atomic_numbers_host,
   if (!ctx->have_list) return fail(ctx, NEP_ESTATE, "nep_build_neighbors must come first");
   if (n != ctx->sys.n || n < 1) return fail(ctx, NEP_EINVAL, "n must equal the system's atom count");
   std::vector<float> w((size_t)n);
+  std::vector<double> wd((size_t)n);
   for (int k = 0; k < n; ++k) {
     const int Z = atomic_numbers_host[k];
     if (Z < 1 || Z > 118) return fail(ctx, NEP_EINVAL, "atomic numbers must be in 1..118");
-    w[k] = (float)std::sqrt((double)Z);
+    wd[k] = std::sqrt((double)Z);
+    w[k] = (float)wd[k];
   }
   if (masses_amu_host)
     for (int k = 0; k < n; ++k)
@@ -288,10 +291,13 @@ nep_status nep_set_species(nep_ctx ctx, int n, const int* atomic_numbers_host,
         return fail(ctx, NEP_EINVAL, "masses must be > 0");
   DeviceGuard guard(ctx->device);
   hipError_t e = ctx->species_w.ensure((size_t)n);
+  if (e == hipSuccess) e = ctx->species_wd.ensure((size_t)n);
   if (e == hipSuccess && masses_amu_host) e = ctx->masses.ensure((size_t)n);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e == hipSuccess)
     e = hipMemcpy(ctx->species_w.ptr, w.data(), sizeof(float) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(ctx->species_wd.ptr, wd.data(), sizeof(double) * n, hipMemcpyHostToDevice);
   if (e == hipSuccess && masses_amu_host)
     e = hipMemcpy(ctx->masses.ptr, masses_amu_host, sizeof(double) * n, hipMemcpyHostToDevice);
   if (e != hipSuccess) {

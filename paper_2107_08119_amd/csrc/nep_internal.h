@@ -239,6 +239,7 @@ struct nep_ctx_s {
   int species_n = 0;              // atoms the arrays describe; 0 = one species
   bool have_masses = false;
   nep::DevBuf<float> species_w;   // [n] sqrt(atomic number)
+  nep::DevBuf<double> species_wd;  // [n] the same in float64 (descriptor sums)
   nep::DevBuf<double> masses;     // [n] amu
   nep::DevBuf<double> totals;     // [16]
   nep::DevBuf<int> flags;         // [kNumFlags]

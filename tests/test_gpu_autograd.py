@@ -101,7 +101,7 @@ def test_autograd_function_energy_force_loss():
     gE = 2.0 * (E_ref - ls.energy) / ls.n_atoms ** 2
     gF = 2.0 * (F_ref - ls.forces) / F_ref.size
     ref = O.grad_params(OH, z, ls, gE, gF)
-    assert rel(zt.grad.double().cpu().numpy(), ref) < 1e-4
+    assert rel(zt.grad.double().cpu().numpy(), ref) < 1e-5
 
 
 def test_energy_position_gradient_is_minus_force():
@@ -119,6 +119,29 @@ def test_energy_position_gradient_is_minus_force():
         pos.grad = None
         E2, F2 = nep.NEPEnergy.apply(pos, zt, ctx, ds)
         (F2 ** 2).sum().backward()
+
+
+def test_trained_model_gradient_on_the_differentiation_set():
+    """The 256-structure set under the shipped SNES-trained silicon model:
+    energies, forces and the parameter gradient of an energy + force
+    objective against the oracle."""
+    import torch
+    from paper_2107_08119_amd import train as T
+    ls = I.labelled_set(256, 64, 512, seed=6)
+    z, _ = T.load_model(T.MODEL_SI_SW)
+    ctx, ds, zt = setup(ls, z, cap=96)
+    out = ctx.dataset_compute(ds, zt)
+    rng = np.random.default_rng(13)
+    gE = rng.standard_normal(len(ls.n_atoms))
+    gF = rng.standard_normal((int(ls.n_atoms.sum()), 3)).astype(np.float32)
+    g = ctx.dataset_backward(ds, zt, torch.from_numpy(gE).cuda(),
+                             torch.from_numpy(np.ascontiguousarray(gF.T)).cuda())
+    ctx.synchronize()
+    E_ref, F_ref = oracle_forward(z, ls)
+    assert rel(out["E"].cpu().numpy(), E_ref) < 1e-5
+    assert rel(out["F"].cpu().numpy().T, F_ref) < 1e-5
+    ref = O.grad_params(OH, z, ls, gE, gF.astype(np.float64), cap=96)
+    assert rel(g["z"].cpu().numpy(), ref) < 1e-5
 
 
 def test_full_size_differentiation_set():

@@ -216,7 +216,7 @@ def test_md_full_size_64k_matches_oracle():
     th_ref, p_ref, v_ref = O.md_nve(OH, z, pos, box, vel, I.MASS_SI, 1.0, 4)
     assert rel(th[:, 0], th_ref[:, 0]) < TOL
     assert rel(th[:, 1], th_ref[:, 1]) < TOL
-    assert rel(th[:, 2:], th_ref[:, 2:]) < 1e-4  # sum of J: cancellations
+    assert rel(th[:, 2:], th_ref[:, 2:]) < TOL  # summed J (measured at most 5e-6)
     assert rel(nep.aos(v), v_ref) < TOL
     d = nep.aos(p) - p_ref
     frac = d @ np.linalg.inv(box)
@@ -246,7 +246,7 @@ def test_hnemd_full_size_64k_matches_oracle():
     th_ref, p_ref, v_ref = O.md_nve(OH, z, pos, box, vel, I.MASS_SI, 1.0, 4, fe=fe)
     assert rel(th[:, 0], th_ref[:, 0]) < TOL
     assert rel(th[:, 1], th_ref[:, 1]) < TOL
-    assert rel(th[:, 2:], th_ref[:, 2:]) < 1e-4
+    assert rel(th[:, 2:], th_ref[:, 2:]) < TOL  # summed J (measured at most 5e-6)
     assert rel(nep.aos(v), v_ref) < TOL
     d = nep.aos(p) - p_ref
     frac = d @ np.linalg.inv(box)
@@ -267,7 +267,7 @@ def test_md_short_trajectory_matches_oracle(parity_case):
     th = thermo.cpu().numpy()
     assert rel(th[:, 0], th_ref[:, 0]) < TOL
     assert rel(th[:, 1], th_ref[:, 1]) < TOL
-    assert rel(th[:, 2:], th_ref[:, 2:]) < 1e-4
+    assert rel(th[:, 2:], th_ref[:, 2:]) < TOL  # summed J (measured at most 5e-6)
     # positions were wrapped at rebuilds: compare modulo the box
     d = nep.aos(p) - p_ref
     frac = d @ np.linalg.inv(box)
@@ -369,7 +369,7 @@ def test_driven_md_matches_oracle(parity_case):
     th = thermo.cpu().numpy()
     assert rel(th[:, 0], th_ref[:, 0]) < TOL
     assert rel(th[:, 1], th_ref[:, 1]) < TOL
-    assert rel(th[:, 2:], th_ref[:, 2:]) < 1e-4
+    assert rel(th[:, 2:], th_ref[:, 2:]) < TOL  # summed J (measured at most 5e-6)
     d = nep.aos(p) - p_ref
     frac = d @ np.linalg.inv(box)
     d = (frac - np.round(frac)) @ box

@@ -3,7 +3,12 @@ the cutoff function of pair (i, j) carries sqrt(Z_i Z_j)) against the FP64
 oracle: rock-salt PbTe with the PbTe-like model (r_c 8/4 A, n_max 12/6,
 l_max 4, 40 neurons: 41-40-1), on the all-pairs and the cell-list paths, in
 MD with per-atom masses, and the default 29-30-1 model on a two-species
-diamond cell.  Tolerance 1e-5 relative (norm over all components)."""
+diamond cell.  Tolerance 1e-5 relative (norm over all components).
+
+The weights are the paper's random initialisation N(0, 0.05^2) as drawn
+(pre-activations in the hundreds: the pair weights sqrt(Z_i Z_j) reach 82),
+and also with the input weights scaled down to O(1) activations, as in a
+trained model."""
 import numpy as np
 import pytest
 
@@ -39,12 +44,14 @@ def pbte_hyper():
     return nep.hyper(8.0, 4.0, 12, 6, 4, 40), O.hyper(8.0, 4.0, 12, 6, 4, 40)
 
 
-def pbte_case(cells, seed):
+def pbte_case(cells, seed, damp=False):
     pos, box, Z, masses = I.rocksalt_supercell(cells, cells, cells)
     rng = np.random.default_rng(seed)
     pos = I.wrap_positions(pos + rng.normal(0.0, 0.08, pos.shape), box)
     vel = I.maxwell_boltzmann(len(pos), 300.0, seed + 1, masses)
-    z = damp_input_weights(I.random_parameters(1721, seed + 2, std=0.05), 40, 41, 1.0 / 300.0)
+    z = I.random_parameters(1721, seed + 2, std=0.05)
+    if damp:
+        z = damp_input_weights(z, 40, 41, 1.0 / 300.0)
     return pos, box, Z, masses, vel, z
 
 
@@ -63,17 +70,24 @@ def evaluate(h, z, pos, box, vel, Z, cap=128, lanes=None):
             "W": nep.aos(out["W"]).reshape(-1, 3, 3), "J": nep.aos(out["J"])}, ctx
 
 
+@pytest.mark.parametrize("damp", [False, True])
 @pytest.mark.parametrize("cells", [2, 4])  # 64 atoms: all-pairs path; 512: cell lists
-def test_pbte_matches_oracle(cells):
+def test_pbte_matches_oracle(cells, damp):
     h, oh = pbte_hyper()
     assert O.n_par(oh) == 1721 and O.n_des(oh) == 41
-    pos, box, Z, _, vel, z = pbte_case(cells, 30 + cells)
+    pos, box, Z, _, vel, z = pbte_case(cells, 30 + cells, damp)
     out, _ = evaluate(h, z, pos, box, vel, Z)
     sel = None if cells == 2 else np.arange(0, len(pos), 3)
     ref = O.nep_eval(oh, z, pos, box, vel=vel, Z=Z, sel=sel)
+    errs = {}
     for k in ("U", "F", "W", "J"):
         got = out[k] if sel is None else out[k][sel]
-        assert rel(got, ref[k]) < TOL, k
+        errs[k] = rel(got, ref[k])
+    print("PbTe %d cells, %s weights: relative errors %s" % (
+        cells, "damped" if damp else "unscaled N(0, 0.05^2)",
+        ", ".join("%s %.1e" % kv for kv in errs.items())))
+    for k, e in errs.items():
+        assert e < TOL, (k, e)
 
 
 def test_pbte_md_with_per_atom_masses_matches_oracle():
@@ -90,7 +104,7 @@ def test_pbte_md_with_per_atom_masses_matches_oracle():
     th_ref, p_ref, v_ref = O.md_nve(oh, z, pos, box, vel, masses, 1.0, 12, Z=Z)
     assert rel(th[:, 0], th_ref[:, 0]) < TOL
     assert rel(th[:, 1], th_ref[:, 1]) < TOL
-    assert rel(th[:, 2:], th_ref[:, 2:]) < 1e-4  # sum of J: cancellations
+    assert rel(th[:, 2:], th_ref[:, 2:]) < TOL  # summed J (measured at most 5e-6)
     assert rel(nep.aos(v), v_ref) < TOL
     d = I.wrap_positions(nep.aos(p) - p_ref + 0.5 * np.diag(box), box) - 0.5 * np.diag(box)
     assert np.abs(d).max() < 1e-6
@@ -104,7 +118,7 @@ def test_default_model_two_species_through_generic_kernel():
     rng = np.random.default_rng(5)
     Z = np.where(rng.random(len(pos)) < 0.5, 14, 32).astype(np.int32)
     vel = I.maxwell_boltzmann(len(pos), 300.0, 6)
-    z = damp_input_weights(I.random_parameters(931, 1, std=0.02), 30, 29, 1.0 / 30.0)
+    z = I.random_parameters(931, 1, std=0.05)
     out, ctx = evaluate(nep.hyper(), z, pos, box, vel, Z, cap=96)
     lanes, _ = ctx.autotune(nep.soa(pos), reps=2)
     assert lanes == 64
@@ -153,8 +167,7 @@ def test_pbte_full_size_64k_sampled():
     rng = np.random.default_rng(11)
     pos = I.wrap_positions(pos + rng.normal(0.0, 0.05, pos.shape), box)
     vel = I.maxwell_boltzmann(len(pos), 300.0, 2, masses)
-    z = damp_input_weights(I.random_parameters(nep.num_params(h), 1, std=0.05), 40, 41,
-                           1.0 / 300.0)
+    z = I.random_parameters(nep.num_params(h), 1, std=0.05)
     out, _ = evaluate(h, z, pos, box, vel, Z)
     sel = np.sort(rng.choice(len(pos), 300, replace=False))
     ref = O.nep_eval(oh, z, pos, box, vel=vel, Z=Z, sel=sel)
@@ -172,8 +185,7 @@ def test_pbte_md_full_size_64k_matches_oracle():
     rng = np.random.default_rng(12)
     pos = I.wrap_positions(pos + rng.normal(0.0, 0.05, pos.shape), box)
     vel = I.maxwell_boltzmann(len(pos), 300.0, 2, masses)
-    z = damp_input_weights(I.random_parameters(nep.num_params(h), 1, std=0.05), 40, 41,
-                           1.0 / 300.0)
+    z = I.random_parameters(nep.num_params(h), 1, std=0.05)
     ctx = nep.Context(0)
     ctx.load_params(h, z)
     p, v = nep.soa(pos), nep.soa(vel)
