@@ -96,6 +96,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-snes", action="store_true", help="skip the SNES generation rate")
+    ap.add_argument("--snes-only", action="store_true",
+                    help="run only the SNES generation rate and print its entry (profiling)")
     ap.add_argument("--no-disordered", action="store_true",
                     help="skip the 512,000-atom disordered heat-current run")
     ap.add_argument("--disordered-steps", type=int, default=500)
@@ -424,6 +426,17 @@ def autograd_rate(nep, I, torch, z, reps=20, n_plain=32):
         c()
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / n_plain * len(ls.n_atoms)
+    # algorithmic flops of one call: the forward pass (descriptor, network,
+    # partial forces per pair, as counted for the MD kernel with the dataset's
+    # own pair counts, no skin) and the backward, which forms q and the
+    # directional derivative of q along dL/dF (the same per-pair work) and
+    # contracts per atom 4 N_neu N_des terms into the parameter gradient
+    n_at = int(ls.n_atoms.sum())
+    n_r, n_a = ds.pairs()
+    h = nep.hyper()
+    f_fwd = FLOP_SLOT * n_r + FLOP_RADIAL * n_r + FLOP_ANGULAR * n_a + FLOP_ATOM * n_at
+    f_call = 2 * f_fwd + 4 * h.n_neuron * nep.num_descriptors(h) * n_at
+    achieved = f_call / t_call / 1e12
     return {"workload": "NEPEnergy autograd over 256 SW-labelled Si structures of 64-512 atoms "
                         "(%d atoms), NEP 29-30-1: forward E, F and backward dL/dz of an "
                         "energy + force loss" % int(ls.n_atoms.sum()),
@@ -431,7 +444,12 @@ def autograd_rate(nep, I, torch, z, reps=20, n_plain=32):
             "plain_per_structure_structures_per_s": len(ls.n_atoms) / t_plain,
             "plain_path": "the same call per structure on single-structure datasets, timed on "
                           "%d structures and scaled to 256" % n_plain,
-            "speedup_vs_plain": t_plain / t_call}
+            "speedup_vs_plain": t_plain / t_call,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                         "gflop_per_call": f_call / 1e9,
+                         "note": "algorithmic float32 flops of forward + backward over the "
+                                 "whole call (host-side autograd and launches included)"}}
 
 
 def pair_counts(pos, box, rc):
@@ -442,8 +460,38 @@ def pair_counts(pos, box, rc):
     return 2.0 * len(tree.query_pairs(rc, output_type="ndarray")) / len(pos)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# The one-core leg runs in a child process so that OpenMP starts with one thread.
+_ONE_CORE = """
+import json, sys, time
+import numpy as np
+sys.path.insert(0, {root!r})
+import oracle as O
+d = np.load({path!r})
+h = O.hyper({hyper})
+pos, box, vel, z = d["pos"], d["box"], d["vel"], d["z"]
+t0 = time.perf_counter()
+O.md_nve(h, z, pos, box, vel, {mass!r}, {dt!r}, {steps})
+print(json.dumps({{"seconds": time.perf_counter() - t0}}))
+"""
+
+
 def cpu_baseline(h_np, z, pos, box, vel, mass, dt, target_s):
-    """The FP64 oracle as it stands: velocity-Verlet steps of the same system."""
+    """The FP64 oracle as it stands: velocity-Verlet steps of the same system,
+    on every host thread, then on one core (a child process with
+    OMP_NUM_THREADS=1)."""
+    import subprocess
+    import tempfile
     import oracle as O
     h = O.hyper(h_np.rc_radial, h_np.rc_angular, h_np.n_max_radial, h_np.n_max_angular,
                 h_np.l_max, h_np.n_neuron)
@@ -457,11 +505,43 @@ def cpu_baseline(h_np, z, pos, box, vel, mass, dt, target_s):
     O.md_nve(h, z, pos, box, vel, mass, dt, steps)
     t = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": len(pos) * steps / t, "unit": "atom-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d velocity-Verlet steps of the same %d-atom system by the FP64 oracle "
-                      "(plain C, literal angular double sum, OpenMP %d threads), %.1f s"
-                      % (steps, len(pos), threads, t)}
+    out = {"value": len(pos) * steps / t, "unit": "atom-steps/s", "cores": threads,
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": "%d velocity-Verlet steps of the same %d-atom system by the FP64 oracle "
+                     "(plain C, literal angular double sum, OpenMP %d threads), %.1f s"
+                     % (steps, len(pos), threads, t)}
+    # one core: a sample sized from the threaded rate (about target_s / 2)
+    per_step_1 = t / (steps + 1) * threads
+    steps1 = int(max(1, min(20, 0.5 * target_s / max(per_step_1, 1e-9) - 1)))
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "system.npz")
+        np.savez(path, pos=pos, box=box, vel=vel, z=np.asarray(z, np.float32))
+        code = _ONE_CORE.format(
+            root=ROOT, path=path, mass=float(mass), dt=float(dt), steps=steps1,
+            hyper="%r, %r, %d, %d, %d, %d" % (h_np.rc_radial, h_np.rc_angular, h_np.n_max_radial,
+                                              h_np.n_max_angular, h_np.l_max, h_np.n_neuron))
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=600)
+    if r.returncode == 0:
+        t1 = json.loads(r.stdout.strip().splitlines()[-1])["seconds"]
+        out["one_core"] = {"value": len(pos) * steps1 / t1, "unit": "atom-steps/s", "cores": 1,
+                           "sample": "%d velocity-Verlet steps of the same system, OpenMP 1 "
+                                     "thread, %.1f s" % (steps1, t1)}
+    else:
+        out["one_core"] = {"value": None, "error": r.stderr[-300:]}
+    return out
+
+
+def copy_probe(torch, mib):
+    """Five plain device copies of mib MiB: a kernel of known traffic that
+    scales the HBM byte counters of a profiler run."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return src.numel() * 4
 
 
 def main():
@@ -474,6 +554,15 @@ def main():
 
     from paper_2107_08119_amd import inputs as I
     from paper_2107_08119_amd import nep
+
+    if args.snes_only:
+        ctx = nep.Context(0)
+        ctx.load_params(nep.hyper(), I.random_parameters(931, seed=1))
+        line = {"snes": snes_rate(args, ctx, nep, I, torch)}
+        if args.copy_probe_mib:
+            line["copy_probe_bytes"] = copy_probe(torch, args.copy_probe_mib)
+        print(json.dumps(line), flush=True)
+        return
 
     n_cells = args.cells
     pos, box = I.diamond_supercell(n_cells, n_cells, n_cells)
@@ -601,12 +690,7 @@ def main():
         line["cpu_baseline"] = cpu_baseline(h, z_random, pos, box, vel, mass, dt,
                                             args.cpu_seconds)
     if args.copy_probe_mib:
-        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        line["copy_probe_bytes"] = src.numel() * 4
+        line["copy_probe_bytes"] = copy_probe(torch, args.copy_probe_mib)
     print(json.dumps(line), flush=True)
 
 

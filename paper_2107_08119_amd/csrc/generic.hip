@@ -82,12 +82,32 @@ __device__ __forceinline__ void displacement_d(uint32_t e, const double* __restr
 
 constexpr double kPiD = 3.14159265358979323846;
 
+// cos(pi t) for t near [0, 1] as -sin(y), y = pi (t - 1/2), from the Taylor
+// series of sin through y^21 (for |y| <= pi/2 the first omitted term is below
+// 2e-18, under float64 rounding).
+__device__ __forceinline__ double cos_pi_unit(double t) {
+  const double y = kPiD * (t - 0.5);
+  const double y2 = y * y;
+  double p = 1.0 / 51090942171709440000.0;  // 1/21!
+  p = p * y2 - 1.0 / 121645100408832000.0;  // 1/19!
+  p = p * y2 + 1.0 / 355687428096000.0;     // 1/17!
+  p = p * y2 - 1.0 / 1307674368000.0;       // 1/15!
+  p = p * y2 + 1.0 / 6227020800.0;          // 1/13!
+  p = p * y2 - 1.0 / 39916800.0;            // 1/11!
+  p = p * y2 + 1.0 / 362880.0;              // 1/9!
+  p = p * y2 - 1.0 / 5040.0;                // 1/7!
+  p = p * y2 + 1.0 / 120.0;                 // 1/5!
+  p = p * y2 - 1.0 / 6.0;                   // 1/3!
+  p = p * y2 + 1.0;
+  return -y * p;
+}
+
 // f_c(r) = (1 + cos(pi r/r_c))/2 and T_n(x), x = 2 (r/r_c - 1)^2 - 1, n < NB,
 // in float64: the factors of g_n = f_c (T_n + 1)/2 (Eq. g_n).
 template <int NB>
 __device__ __forceinline__ void chebyshev_values_d(double r, double rc_inv, double& fc, double* T) {
   const double t = r * rc_inv;
-  fc = 0.5 * (1.0 + cos(kPiD * t));
+  fc = 0.5 * (1.0 + cos_pi_unit(t));
   const double tm1 = t - 1.0;
   const double x = 2.0 * tm1 * tm1 - 1.0;
   T[0] = 1.0;
@@ -189,8 +209,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
   const int RS = kVec ? kRS : NDES + 1;  // LDS row of neuron mu: w1[mu][:] (padded)
   __shared__ __align__(16) float s_w1[kNeuRows * kRS];
   __shared__ float s_b1[kMaxNeu], s_w2[kMaxNeu];
-  __shared__ DT s_g[kWaves][64][kMaxA + 1];           // angular g_n of each lane's pair
-  __shared__ __align__(16) DT s_y[kWaves][64][kYS];   // Yhat_lm of each lane's pair
+  // pairs staged per round: all 64 lanes' pairs, or in float64 two halves of
+  // 32 (half the LDS, so that more waves fit a CU; the sums keep pair order)
+  constexpr int kStage = F64 ? 32 : 64;
+  __shared__ DT s_g[kWaves][kStage][kMaxA + 1];           // angular g_n of the staged pairs
+  __shared__ __align__(16) DT s_y[kWaves][kStage][kYS];   // Yhat_lm of the staged pairs
   __shared__ __align__(16) DT s_q[kWaves][kDes4];
   __shared__ float s_dq[kWaves][kMaxDes];
   __shared__ float s_c[kWaves][kMaxA * kMaxLM];  // c_nlm (float32 path), then a_nlm
@@ -220,6 +243,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
   // multicomponent weight of pair (i, j): sqrt(Z_i) sqrt(Z_j), 1 for one species
   const float wi = wsp ? wsp[perm[i]] : 1.f;
   const float rcr_inv = 1.f / rc_r, rca_inv = 1.f / rc_a;
+  const double rcr_inv_d = 1.0 / rc_rd, rca_inv_d = 1.0 / rc_ad;
   const float rcr2 = rc_r * rc_r, rca2 = rc_a * rc_a;
   const int nout = NA * NLM;  // angular moments, lane k owns k, k + 64, ...
   DT qr[kMaxR];
@@ -261,14 +285,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
         const double r = sqrt(ex * ex + ey * ey + ez * ez);
         if (r2 < rcr2) {
           double fc, T[kMaxR];
-          chebyshev_values_d<kMaxR>(r, 1.0 / rc_rd, fc, T);
+          chebyshev_values_d<kMaxR>(r, rcr_inv_d, fc, T);
           const double wf = wij * fc;
           qr[0] += wf;
 #pragma unroll
           for (int a = 1; a < kMaxR; ++a) qr[a] += wf * T[a];
         }
         if (s < ca && r2 < rca2) {
-          radial_basis_d<kMaxA>(r, 1.0 / rc_ad, NA, g);
+          radial_basis_d<kMaxA>(r, rca_inv_d, NA, g);
 #pragma unroll
           for (int a = 0; a < kMaxA; ++a) g[a] *= wij;
           const double rinv = 1.0 / r;
@@ -296,13 +320,16 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
         }
       }
     }
+    for (int half = 0; half < 64 / kStage; ++half) {
+    if (lane / kStage == half) {
 #pragma unroll
-    for (int a = 0; a < kMaxA; ++a) s_g[wave][lane][a] = g[a];
+      for (int a = 0; a < kMaxA; ++a) s_g[wave][lane % kStage][a] = g[a];
 #pragma unroll
-    for (int m = 0; m < kMaxLM; ++m) s_y[wave][lane][m] = yh[m];
+      for (int m = 0; m < kMaxLM; ++m) s_y[wave][lane % kStage][m] = yh[m];
+    }
     wave_lds_sync();
     // pairs past the list's angular part have g = 0: skip them
-    const int np = max(0, min(64, min(cr, ca) - base));
+    const int np = max(0, min(kStage, min(cr, ca) - base - half * kStage));
     if constexpr (kVec) {  // lane k owns outputs (n, 4 m4 .. 4 m4 + 3), k = 6 n + m4
 #pragma unroll
       for (int r = 0; r < kR4; ++r) {
@@ -334,6 +361,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_partials_generic(
       }
     }
     wave_lds_sync();
+    }
   }
   // radial components q_0 = R_0, q_n = (R_n + R_0)/2, and angular moments to LDS
   const DT r0 = wave_sum(qr[0]);
