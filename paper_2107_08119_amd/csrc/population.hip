@@ -506,6 +506,14 @@ __global__ void k_pop_norms(int N, const int4* __restrict__ pmeta, const float* 
 // are stored as round(x 2^e) in 32 bits with e chosen so that these bounds
 // stay below 2^30.  A non-finite bound gives e = kBadScale.
 constexpr int kBadScale = -1000;
+
+// floor(x + 1/2) as a 32-bit integer in one instruction (round half up; the
+// fixed-point values stay below 2^30 in magnitude)
+__device__ __forceinline__ int round_to_int(float x) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
 __device__ __forceinline__ int fixed_exponent(float bound) {
   if (!(bound <= 3.0e38f)) return kBadScale;  // NaN or infinite
   if (bound <= 0.f) return 30;
@@ -621,7 +629,7 @@ __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
     sF[c] = ok ? ldexpf(1.f, eF) : 0.f;
     rW[c] = ok ? ldexpf(1.f, eW - eF) : 0.f;
   }
-  auto add_q = [&](int* p, float x) { atomicAdd(p, __float2int_rn(x)); };
+  auto add_q = [&](int* p, float x) { atomicAdd(p, round_to_int(x)); };
 
   // the pair block pb of atom i: radial tile v (rows: pairs) and, when the
   // block holds angular pairs, angular tiles ax, ay, az (same rows);

@@ -292,27 +292,33 @@ __global__ __launch_bounds__(kBlock) void k_snes_update(int n_par, int n_pop, fl
 #pragma clang fp contract(off)
   __shared__ int order[1024];
   __shared__ double util[1024];
+  __shared__ double key[1024];
+  __shared__ double tot_s;
+  // sort keys (NaN ranks last) and the unnormalised utilities of ranks 1..P
+  const double top = log(n_pop / 2.0 + 1.0);
   for (int k = threadIdx.x; k < n_pop; k += blockDim.x) {
     const double lk = loss[6 * k];
-    const double key = lk != lk ? INFINITY : lk;
+    key[k] = lk != lk ? INFINITY : lk;
+    const double v = top - log((double)(k + 1));
+    util[k] = v > 0.0 ? v : 0.0;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n_pop; k += blockDim.x) {
+    const double kk = key[k];
     int rank = 0;
     for (int j = 0; j < n_pop; ++j) {
-      const double lj = loss[6 * j];
-      const double kj = lj != lj ? INFINITY : lj;
-      rank += (kj < key || (kj == key && j < k)) ? 1 : 0;
+      const double kj = key[j];
+      rank += (kj < kk || (kj == kk && j < k)) ? 1 : 0;
     }
     order[rank] = k;
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0) {  // the normalising sum in rank order
     double tot = 0.0;
-    const double top = log(n_pop / 2.0 + 1.0);
-    for (int k = 1; k <= n_pop; ++k) {
-      const double v = top - log((double)k);
-      util[k - 1] = v > 0.0 ? v : 0.0;
-      tot += util[k - 1];
-    }
-    for (int k = 0; k < n_pop; ++k) util[k] = util[k] / tot - 1.0 / n_pop;
+    for (int k = 0; k < n_pop; ++k) tot += util[k];
+    tot_s = tot;
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n_pop; k += blockDim.x) util[k] = util[k] / tot_s - 1.0 / n_pop;
   __syncthreads();
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n_par) return;
@@ -327,26 +333,39 @@ __global__ __launch_bounds__(kBlock) void k_snes_update(int n_par, int n_pop, fl
   s[v] = (float)(sv * exp(0.5 * eta_s * gs));
 }
 
-// One thread: best[(g - g0) 6 + q] = loss terms of the best individual of
+// One wave: best[(g - g0) 6 + q] = loss terms of the best individual of
 // generation g = counter[0] (NaN ranks last, ties by index), g0 = counter[1];
 // then counter[0] = g + 1.
-__global__ void k_snes_record(int n_pop, const double* __restrict__ loss, int* __restrict__ counter,
-                              double* __restrict__ best) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(64) void k_snes_record(int n_pop, const double* __restrict__ loss,
+                                                    int* __restrict__ counter,
+                                                    double* __restrict__ best) {
+  if (blockIdx.x != 0) return;
+  const int l = threadIdx.x;
   const int g = counter[0];
   if (best) {
-    int b = 0;
-    double lb = loss[0] != loss[0] ? INFINITY : loss[0];
-    for (int k = 1; k < n_pop; ++k) {
+    // lane minima over k = l, l + 64, ..., then the wave's (loss, index) minimum
+    double lb = INFINITY;
+    int b = n_pop;
+    for (int k = l; k < n_pop; k += 64) {
       const double lk = loss[6 * k] != loss[6 * k] ? INFINITY : loss[6 * k];
-      if (lk < lb) {
+      if (lk < lb || (lk == lb && k < b)) {
         lb = lk;
         b = k;
       }
     }
-    for (int q = 0; q < 6; ++q) best[(size_t)(g - counter[1]) * 6 + q] = loss[6 * b + q];
+    for (int d = 32; d > 0; d >>= 1) {
+      const double lo = __shfl_xor(lb, d, 64);
+      const int bo = __shfl_xor(b, d, 64);
+      if (lo < lb || (lo == lb && bo < b)) {
+        lb = lo;
+        b = bo;
+      }
+    }
+    if (b >= n_pop) b = 0;  // every loss NaN: the first individual
+    if (l < 6) best[(size_t)(g - counter[1]) * 6 + l] = loss[6 * b + l];
   }
-  counter[0] = g + 1;
+  __syncthreads();  // every lane has read the counter
+  if (l == 0) counter[0] = g + 1;
 }
 
 __global__ void k_set_counter(int* __restrict__ counter, int g) {
