@@ -197,6 +197,18 @@ __host__ __device__ inline int atom_chunks(int pairs, int ang) {
 // Fixed-point accumulators of a tile in LDS (162,816 bytes): forces
 // [atom][3][KC] and structure virials [structure][9][KC], 32-bit integers.
 constexpr int kLdsInts = 40704;
+constexpr int kTileTarget = 64;
+
+// Memory order of dU/dq within an (atom, individual) row of 32: padded
+// index kappa is stored at dq_slot(kappa) = 8 (kappa % 4) + kappa / 4, so the
+// 8 values a contraction lane multiplies (kappa = 4 q + h, q = 0..7) are
+// contiguous, and the network kernel's lane writes the pair kappa, kappa + 4
+// (its two output tiles) as one 8-byte store.
+__host__ __device__ constexpr int dq_slot(int kappa) { return 8 * (kappa % 4) + kappa / 4; }
+// the padded index of output column col of the network's second product, tile nt
+__host__ __device__ constexpr int dq_kappa(int col, int nt) {
+  return 8 * (col / 4) + col % 4 + 4 * nt;
+}
 
 __global__ void k_pop_qpad(int N, const float* __restrict__ desc, float* __restrict__ qpad) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -351,7 +363,7 @@ __global__ __launch_bounds__(64) void k_pop_wfrag(int n_par, const float* __rest
   for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
     for (int st = 0; st < 8; ++st)
-      f[16 + 8 * nt + st] = w1(16 * (st / 4) + 4 * h + (st % 4), 16 * nt + col);
+      f[16 + 8 * nt + st] = w1(16 * (st / 4) + 4 * h + (st % 4), dq_kappa(col, nt));
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -446,9 +458,9 @@ __global__ __launch_bounds__(kBlock) void k_pop_net(int N, int n_pop,
       for (int r = 0; r < 4; ++r) {
         const int ar = a0 + 16 * ct + 4 * h + r;
         if (ar < N) {
-          float* d = dq + ((size_t)ar * n_pop + k) * kQ;
-          d[col] = o[0][r];
-          d[16 + col] = o[1][r];
+          // kappa = dq_kappa(col, 0) and dq_kappa(col, 1) = that + 4: adjacent slots
+          float* d = dq + ((size_t)ar * n_pop + k) * kQ + dq_slot(dq_kappa(col, 0));
+          *reinterpret_cast<float2*>(d) = make_float2(o[0][r], o[1][r]);
         }
       }
     }
@@ -551,9 +563,18 @@ __device__ __forceinline__ void fetch_atom(AtomOps& o, int4 m, int i, int n_pop,
                                            int h) {
   const size_t row = (size_t)i * n_pop * kQ;
 #pragma unroll
-  for (int c = 0; c < kCols; ++c)
-#pragma unroll
-    for (int q = 0; q < 8; ++q) o.b[c][q] = dqk[c][row + 4 * q];
+  for (int c = 0; c < kCols; ++c) {  // kappa = 4 q + h at slots 8 h + q
+    const float4 lo = *reinterpret_cast<const float4*>(dqk[c] + row);
+    const float4 hi = *reinterpret_cast<const float4*>(dqk[c] + row + 4);
+    o.b[c][0] = lo.x;
+    o.b[c][1] = lo.y;
+    o.b[c][2] = lo.z;
+    o.b[c][3] = lo.w;
+    o.b[c][4] = hi.x;
+    o.b[c][5] = hi.y;
+    o.b[c][6] = hi.z;
+    o.b[c][7] = hi.w;
+  }
   const float* fr = pfrag + (size_t)(unsigned)m.x * 64 + l;
   const int ns = radial_tiles(m.z);
 #pragma unroll
@@ -620,7 +641,7 @@ __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
     const int kl = 16 * c + col;
     valid[c] = kl < KC;
     const int k = k0 + (valid[c] ? kl : 0);
-    dqk[c] = dq + (size_t)k * kQ + h;  // K index 4 q + h
+    dqk[c] = dq + (size_t)k * kQ + 8 * h;  // K index 4 q + h at slot 8 h + q
     const int eF = valid[c] ? esc[0][kl] : kBadScale, eW = valid[c] ? esc[1][kl] : kBadScale;
     // the force scale goes into dU/dq, so the products come out scaled; the
     // virial rows are rescaled by 2^(eW - eF).  A non-finite bound: every
@@ -874,11 +895,14 @@ hipError_t prepare_dataset_geometry(nep_ctx ctx, nep_dataset ds) {
   const int tile_kc = std::min(64, kLdsInts / (3 * (largest + 3)));
   if (tile_kc < 1) return hipErrorInvalidValue;
   const int units = kLdsInts / (3 * tile_kc);
+  // tiles are filled to kTileTarget units (a larger structure takes a tile
+  // alone): many small tiles balance the blocks over the compute units
+  const int target = std::min(units, kTileTarget);
   std::vector<int> toff{0}, ts0{0}, st0(S);
   int cur = 0;
   for (int s = 0; s < S; ++s) {
     const int ns = off[s + 1] - off[s] + 3;
-    if (cur > 0 && cur + ns > units) {
+    if (cur > 0 && cur + ns > target) {
       toff.push_back(off[s]);
       ts0.push_back(s);
       cur = 0;
