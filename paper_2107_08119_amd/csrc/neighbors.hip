@@ -72,29 +72,44 @@ __global__ void k_bin(int n, double* __restrict__ pos, Box box, int nc0, int nc1
 // are cleared for the next build and the fill counters for k_fill.
 __global__ __launch_bounds__(1024) void k_scan(int m, int* __restrict__ cnt,
                                                int* __restrict__ start, int* __restrict__ fill) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x;
-  const int per = (m + 1023) / 1024;
-  const int b = t * per;
-  const int e = min(b + per, m);
-  int sum = 0;
-  for (int k = b; k < e; ++k) sum += cnt[k];
-  part[t] = sum;
+  // wave w owns a run of consecutive cells, read in chunks of 64 (coalesced);
+  // pass 1 sums the run, one barrier combines the 16 wave totals, pass 2
+  // reads the counts again and writes the exclusive prefix (lane shuffles
+  // within a chunk, a running carry across chunks) and zeroes the counts
+  __shared__ int wsum[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int chunks = (m + 1023) / 1024;  // chunks of 64 per wave
+  const int c0 = w * chunks * 64;
+  const int c1 = min(m, c0 + chunks * 64);
+  int part = 0;
+  for (int c = c0 + lane; c < c1; c += 64) part += cnt[c];
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) part += __shfl_xor(part, d, 64);
+  if (lane == 0) wsum[w] = part;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  int carry = 0;
+  for (int u = 0; u < w; ++u) carry += wsum[u];
+  for (int b = c0; b < c1; b += 64) {
+    const int c = b + lane;
+    const int own = c < c1 ? cnt[c] : 0;
+    int x = own;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (c < c1) {
+      start[c] = carry + x - own;
+      cnt[c] = 0;   // ready for the next build
+      fill[c] = 0;  // for k_fill, next
+    }
+    carry += __shfl(x, 63, 64);
   }
-  int run = t > 0 ? part[t - 1] : 0;
-  for (int k = b; k < e; ++k) {
-    start[k] = run;
-    run += cnt[k];
-    cnt[k] = 0;   // ready for the next build
-    fill[k] = 0;  // for k_fill, next
+  if (threadIdx.x == 1023) {
+    int tot = 0;
+    for (int u = 0; u < 16; ++u) tot += wsum[u];
+    start[m] = tot;
   }
-  if (t == 1023) start[m] = part[1023];
 }
 
 // The same scan for many cells in three launches: block b scans counts
