@@ -96,6 +96,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-snes", action="store_true", help="skip the SNES generation rate")
+    ap.add_argument("--md-only", action="store_true",
+                    help="run only the 64,000-atom MD line (no HNEMD, Table I models, "
+                         "autograd, PbTe, 512k or SNES entries; profiling)")
     ap.add_argument("--snes-only", action="store_true",
                     help="run only the SNES generation rate and print its entry (profiling)")
     ap.add_argument("--no-disordered", action="store_true",
@@ -661,6 +664,11 @@ def main():
             k: (val[0] * 1e3 / val[1] if val[1] else None) for k, val in kt.items()},
         "energy_drift_meV_per_atom": float((e_tot.max() - e_tot.min()) / n * 1e3),
     }
+    if args.md_only:
+        if args.copy_probe_mib:
+            line["copy_probe_bytes"] = copy_probe(torch, args.copy_probe_mib)
+        print(json.dumps(line), flush=True)
+        return
     # HNEMD (Sec. II B): the same system driven by F_e . W_i, F_e = 1 um^-1 along x
     fe = (1.0e-4, 0.0, 0.0)
     k_h = min(args.steps, 200)

@@ -385,6 +385,12 @@ __global__ __launch_bounds__(64) void k_pop_wfrag(int n_par, const float* __rest
 // so G = w2 sech^2 never moves between lanes.  Each individual's weight
 // fragments are loaded while the previous individual is multiplied.
 // dq [N][n_pop][32] (padded order, zeros at 9..11), U [n_pop][N].
+// Individuals per wave of the network kernel: the population is split into
+// chunks over blockIdx.y, so that the grid has many more waves than the
+// machine holds at once (whole waves of all individuals left the last round
+// of waves mostly empty).
+constexpr int kNetChunk = 10;
+
 template <int CT>
 __global__ __launch_bounds__(kBlock) void k_pop_net(int N, int n_pop,
                                                     const float* __restrict__ qpad,
@@ -403,10 +409,13 @@ __global__ __launch_bounds__(kBlock) void k_pop_net(int N, int n_pop,
 #pragma unroll
     for (int s = 0; s < 8; ++s) qb[ct][s] = a < N ? qpad[(size_t)a * kQ + 4 * s + h] : 0.f;
   }
+  // the individuals k_begin .. k_end - 1 of this wave (blockIdx.y chunk)
+  const int k_begin = blockIdx.y * kNetChunk;
+  const int k_end = min(n_pop, k_begin + kNetChunk);
   float4 nxt[12];
 #pragma unroll
-  for (int q = 0; q < 12; ++q) nxt[q] = wf[(size_t)q * 64 + l];
-  for (int k = 0; k < n_pop; ++k) {
+  for (int q = 0; q < 12; ++q) nxt[q] = wf[((size_t)k_begin * 12 + q) * 64 + l];
+  for (int k = k_begin; k < k_end; ++k) {
     float f[48];
 #pragma unroll
     for (int q = 0; q < 12; ++q) {
@@ -416,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_pop_net(int N, int n_pop,
       f[4 * q + 3] = nxt[q].w;
     }
     const float b2 = wb2[k];
-    const int kn = k + 1 < n_pop ? k + 1 : k;
+    const int kn = k + 1 < k_end ? k + 1 : k;
 #pragma unroll
     for (int q = 0; q < 12; ++q) nxt[q] = wf[((size_t)kn * 12 + q) * 64 + l];
 #pragma unroll
@@ -835,7 +844,8 @@ void launch_net(nep_ctx ctx, nep_dataset ds, int n_pop, const float* Z, bool fir
   launch_kernel(ctx, first, false, k_pop_wfrag, dim3(n_pop), dim3(64), ctx->n_par, Z,
                 ds->wfrag.ptr, ds->wb2.ptr, ds->dqbound.ptr);
   const int per_block = 16 * CT * (kBlock / 64);
-  launch_kernel(ctx, false, false, k_pop_net<CT>, dim3(blocks_for(ds->N, per_block)),
+  launch_kernel(ctx, false, false, k_pop_net<CT>,
+                dim3(blocks_for(ds->N, per_block), (n_pop + kNetChunk - 1) / kNetChunk),
                 dim3(kBlock), ds->N, n_pop, (const float*)ds->qpad.ptr,
                 (const float4*)ds->wfrag.ptr, (const float*)ds->wb2.ptr, ds->dq.ptr, ds->U.ptr);
 }

@@ -323,6 +323,9 @@ __global__ __launch_bounds__(kBlock) void k_snes_update(int n_par, int n_pop, fl
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n_par) return;
   double gm = 0.0, gs = 0.0;
+  // (unrolled so that the loads of several ranks are in flight together; the
+  // sums keep rank order)
+#pragma unroll 8
   for (int rank = 0; rank < n_pop; ++rank) {
     const double rv = (double)r[(size_t)order[rank] * n_par + v];
     gm += util[rank] * rv;
