@@ -522,17 +522,21 @@ __global__ __launch_bounds__(256) void k_build_all_pairs(
 // j > i also writes the reverse slot of the entry it finds, and entries with
 // j < i are left to that thread; after an overflow every entry searches for
 // itself, so that every reverse slot still names a slot inside j's list.
-__global__ void k_reverse(int n, int cap, int width, const uint32_t* __restrict__ nl,
+// One block per kReverseAtoms consecutive atoms (all their slots), blocks
+// spread over the XCDs in contiguous ranges: a pair's partner row is then
+// mostly a nearby atom's, already in the XCD's L2.
+constexpr int kReverseAtoms = 32;
+__global__ __launch_bounds__(kBlock) void k_reverse(int n, int cap, const uint32_t* __restrict__ nl,
                           const uint32_t* __restrict__ nl_rm, const int* __restrict__ cnt_r,
                           const int* __restrict__ cnt_a, int* __restrict__ rev,
                           int* __restrict__ flags) {
   // thread (s0, i) handles slots s0, s0 + width, ... of atom i
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)n * width) return;
-  const int i = (int)(t % (size_t)n);
+  constexpr int width = kBlock / kReverseAtoms;
+  const int i = (int)xcd_block(blockIdx.x, gridDim.x) * kReverseAtoms + threadIdx.x % kReverseAtoms;
+  if (i >= n) return;
   const int cr = cnt_r[i], ca = cnt_a[i];
   const bool symmetric = flags[kFlagOverflow] == 0;
-  for (int s = (int)(t / (size_t)n); s < cr; s += width) {
+  for (int s = threadIdx.x / kReverseAtoms; s < cr; s += width) {
     const size_t idx = (size_t)s * n + i;
     const uint32_t e = nl[idx];
     const int j = (int)(e & kAtomMask);
@@ -626,9 +630,8 @@ void launch_reverse(nep_ctx ctx, int n, int cap, const uint32_t* nl, const int* 
                     const int* cnt_a, int* rev) {
   const size_t ncap = (size_t)n * cap;
   if (ncap == 0) return;
-  const int width = cap < 40 ? cap : 40;
-  launch_kernel(ctx, false, false, k_reverse, dim3(blocks_for((size_t)n * width, kBlock)),
-                dim3(kBlock), n, cap, width, nl, (const uint32_t*)nullptr, cnt_r, cnt_a, rev,
+  launch_kernel(ctx, false, false, k_reverse, dim3(blocks_for((size_t)n, kReverseAtoms)),
+                dim3(kBlock), n, cap, nl, (const uint32_t*)nullptr, cnt_r, cnt_a, rev,
                 ctx->flags.ptr);
 }
 
@@ -788,9 +791,8 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
   if (n > 0 && !s.use_cells)
     launch_kernel(ctx, false, false, k_invert_perm, dim3(blocks_for(n, kBlock)), blk, n,
                   (const int*)s.perm.ptr, s.iperm.ptr);
-  const int width = s.cap < 40 ? s.cap : 40;
-  launch_kernel(ctx, false, true, k_reverse, dim3(blocks_for((size_t)n * width, kBlock)), blk, n,
-                s.cap, width, (const uint32_t*)s.nl.ptr,
+  launch_kernel(ctx, false, true, k_reverse, dim3(blocks_for((size_t)n, kReverseAtoms)), blk, n,
+                s.cap, (const uint32_t*)s.nl.ptr,
                 s.use_cells ? (const uint32_t*)s.nl_rm.ptr : (const uint32_t*)nullptr,
                 (const int*)s.cnt_r.ptr, (const int*)s.cnt_a.ptr, s.rev.ptr, ctx->flags.ptr);
   return check_hip(ctx, hipGetLastError(), "launching neighbour kernels");
