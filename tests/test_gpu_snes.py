@@ -78,6 +78,24 @@ def test_population_loss_deterministic():
     np.testing.assert_array_equal(c[0], a[2])
 
 
+@pytest.mark.parametrize("n_pop", [23, 70])
+def test_population_sizes_that_split_the_launches(n_pop):
+    """Populations that end in a partial chunk of the network kernel's
+    individuals (23) and that need a second contraction launch beyond the
+    tile's 64 individuals (70): sampled individuals against the oracle, and
+    each equal bit for bit to its own evaluation alone."""
+    import torch
+    ls = small_set()
+    Z = population(n_pop, 40 + n_pop)
+    got, ctx, ds = gpu_losses(ls, Z)
+    assert np.all(np.isfinite(got))
+    for k in (0, 9, 10, n_pop - 1) + ((63, 64) if n_pop > 64 else ()):
+        ref = O.loss(OH, Z[k], ls, LAM, cap=200)
+        np.testing.assert_allclose(got[k], ref, rtol=1e-5, err_msg="individual %d" % k)
+        alone = ctx.eval_population(ds, torch.from_numpy(Z[k:k + 1].copy()).cuda(), LAM)
+        np.testing.assert_array_equal(alone.cpu().numpy()[0], got[k])
+
+
 def test_dataset_overflow_is_reported():
     nep = nep_mod()
     ctx = nep.Context(0)
