@@ -172,32 +172,27 @@ __global__ void k_fill(int n, const int* __restrict__ cell_of, const int* __rest
 
 // Order every cell's members by atom index: each atom counts the members of
 // its cell with a smaller index and takes that place (cells are small).
-__global__ void k_rank_cells(int n, const int* __restrict__ cell_of, const int* __restrict__ start,
-                             const int* __restrict__ members, int* __restrict__ sorted) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = cell_of[i];
+// Re-sort atoms into cell order (cells in order, each cell's members by old
+// index): old atom o finds its rank among its cell's members and moves to
+// internal index k = start[cell] + rank.  Position, velocity (when given),
+// offsets, caller index and cell move with it, and a 32-byte record
+// (position, index, packed offsets) is written per atom.
+__global__ void k_rank_permute(int n, const int* __restrict__ start,
+                               const int* __restrict__ members, const double* __restrict__ pos,
+                               double* __restrict__ pos_out, const double* __restrict__ vel,
+                               double* __restrict__ vel_out, const int* __restrict__ wrap,
+                               int* __restrict__ wrap_out, const int* __restrict__ perm,
+                               int* __restrict__ perm_out, const int* __restrict__ cell_of,
+                               int* __restrict__ cell_out, CellRec* __restrict__ rec,
+                               int* __restrict__ iperm_out, float* __restrict__ pos_ref,
+                               int* __restrict__ flags) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  const int c = cell_of[o];
   const int b = start[c], e = start[c + 1];
   int rank = 0;
-  for (int k = b; k < e; ++k) rank += members[k] < i ? 1 : 0;
-  sorted[b + rank] = i;
-}
-
-// Re-sort atoms into cell order: internal index k takes the atom at old index
-// o = members[k] (cells in order, members by old index).  Positions,
-// velocities (when given), offsets, caller indices and cells move with it, and
-// a 32-byte record (position, index, packed offsets) is written per atom.
-__global__ void k_permute(int n, const int* __restrict__ members, const double* __restrict__ pos,
-                          double* __restrict__ pos_out, const double* __restrict__ vel,
-                          double* __restrict__ vel_out, const int* __restrict__ wrap,
-                          int* __restrict__ wrap_out, const int* __restrict__ perm,
-                          int* __restrict__ perm_out, const int* __restrict__ cell_of,
-                          int* __restrict__ cell_out, CellRec* __restrict__ rec,
-                          int* __restrict__ iperm_out, float* __restrict__ pos_ref,
-                          int* __restrict__ flags) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const int o = members[k];
+  for (int m = b; m < e; ++m) rank += members[m] < o ? 1 : 0;
+  const int k = b + rank;
   CellRec r;
   r.x = pos[o];
   r.y = pos[n + o];
@@ -220,7 +215,7 @@ __global__ void k_permute(int n, const int* __restrict__ members, const double* 
   const int caller = perm[o];
   perm_out[k] = caller;
   iperm_out[caller] = k;  // caller index -> new internal index
-  cell_out[k] = cell_of[o];
+  cell_out[k] = c;
   if (w0 < -127 || w0 > 127 || w1 < -127 || w1 > 127 || w2 < -127 || w2 > 127)
     flags[kFlagImage] = 1;
   r.j = k;
@@ -727,7 +722,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
         (e = s.scan_part.ensure(1024)) != hipSuccess ||
         (e = s.cell_start.ensure((size_t)ncell + 1)) != hipSuccess ||
         (e = s.cell_fill.ensure(ncell)) != hipSuccess ||
-        (e = s.cell_atoms.ensure(n)) != hipSuccess || (e = s.cell_sorted.ensure(n)) != hipSuccess ||
+        (e = s.cell_atoms.ensure(n)) != hipSuccess ||
         (e = s.cell_rec.ensure(n)) != hipSuccess ||
         (e = s.pos_t.ensure((size_t)3 * n)) != hipSuccess ||
         (e = s.vel_t.ensure((size_t)3 * n)) != hipSuccess ||
@@ -758,11 +753,9 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
     launch_kernel(ctx, false, false, k_fill, dim3(blocks_for(n, kBlock)), blk, n,
                   (const int*)s.cell_of.ptr, (const int*)s.cell_start.ptr, s.cell_fill.ptr,
                   s.cell_atoms.ptr);
-    launch_kernel(ctx, false, false, k_rank_cells, dim3(blocks_for(n, kBlock)), blk, n,
-                  (const int*)s.cell_of.ptr, (const int*)s.cell_start.ptr,
-                  (const int*)s.cell_atoms.ptr, s.cell_sorted.ptr);
-    launch_kernel(ctx, false, false, k_permute, dim3(blocks_for(n, kBlock)), blk, n,
-                  (const int*)s.cell_sorted.ptr, (const double*)s.pos_s.ptr, s.pos_t.ptr,
+    launch_kernel(ctx, false, false, k_rank_permute, dim3(blocks_for(n, kBlock)), blk, n,
+                  (const int*)s.cell_start.ptr, (const int*)s.cell_atoms.ptr,
+                  (const double*)s.pos_s.ptr, s.pos_t.ptr,
                   have_vel ? (const double*)s.vel_s.ptr : (const double*)nullptr,
                   have_vel ? s.vel_t.ptr : (double*)nullptr, (const int*)s.wrap.ptr, s.wrap_t.ptr,
                   (const int*)s.perm.ptr, s.perm_t.ptr, (const int*)s.cell_of.ptr, s.cell_t.ptr,
@@ -787,7 +780,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
                   ctx->flags.ptr);
   }
   // caller index -> internal index, for the coalesced copies back (the cell
-  // path's k_permute writes it)
+  // path's k_rank_permute writes it)
   if (n > 0 && !s.use_cells)
     launch_kernel(ctx, false, false, k_invert_perm, dim3(blocks_for(n, kBlock)), blk, n,
                   (const int*)s.perm.ptr, s.iperm.ptr);

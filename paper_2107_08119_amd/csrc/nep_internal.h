@@ -141,7 +141,6 @@ struct System {
   DevBuf<int> cell_fill;   // [ncell]
   DevBuf<int> scan_part;   // [1024] block totals of the multi-block cell scan
   DevBuf<int> cell_atoms;  // [n] members of each cell, in arrival order
-  DevBuf<int> cell_sorted;  // [n] members of each cell, by atom index
   DevBuf<CellRec> cell_rec;  // [n] positions and offsets in cell order
   DevBuf<float> pos_ref;     // [3][n] positions at the last list build (float32, internal order)
   // The library works on its own copies of positions and velocities in cell
@@ -165,7 +164,6 @@ struct System {
     cell_fill.release();
     scan_part.release();
     cell_atoms.release();
-    cell_sorted.release();
     cell_rec.release();
     pos_s.release();
     pos_t.release();

@@ -66,7 +66,6 @@ bool carve(char* base, const System& geo, int n, int cap, System& s, nep_ctx_s& 
     k.take(s.cell_start, ncell + 1);
     k.take(s.cell_fill, ncell);
     k.take(s.cell_atoms, n);
-    k.take(s.cell_sorted, n);
     k.take(s.cell_rec, n);
     k.take(s.vel_t, n3);
     k.take(s.perm_t, n);
