@@ -544,10 +544,13 @@ __device__ __forceinline__ int fixed_exponent(float bound) {
   return s < -100 ? -100 : (s > 100 ? 100 : s);
 }
 
-// Operands of one owner atom in the contraction kernel, all requested
-// before the atom's first product.  Atoms with at most kFastPairs pairs and
-// kFastAng angular pairs (two radial tiles, one block of angular tiles) are
-// fetched whole; others read their further tiles as they are used.
+// Fragment operands of one owner atom in the contraction kernel, all
+// requested before the atom's first product (the pair records are read just
+// before the products of their block: holding them from the start would cost
+// 32 registers, and with them a third wave per SIMD).  Atoms with at most
+// kFastPairs pairs and kFastAng angular pairs (two radial tiles, one block of
+// angular tiles) are fetched whole; others read their further tiles as they
+// are used.
 constexpr int kFastPairs = 32, kFastAng = 16;
 constexpr int kFastS = 2;
 constexpr int kCols = 4;  // column tiles of 16 individuals per wave
@@ -556,7 +559,6 @@ struct AtomOps {
   float g[kGSteps];    // own-force / virial tile
   float s[kFastS][kSSteps];
   float a[3][kASteps];   // angular tiles x, y, z of the first pair block
-  float4 ps[kFastS][4];  // pair records (unit vector, receiver) of the lane's rows
 };
 
 __device__ __forceinline__ bool fast_atom(int4 m) { return m.z <= kFastPairs && m.w <= kFastAng; }
@@ -597,11 +599,6 @@ __device__ __forceinline__ void fetch_atom(AtomOps& o, int4 m, int i, int n_pop,
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int q = 0; q < kASteps; ++q) o.a[c][q] = fa[64 * (kASteps * c + q)];
-  const float4* pp = ppair + (size_t)m.y;
-#pragma unroll
-  for (int tt = 0; tt < kFastS; ++tt)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) o.ps[tt][r] = pp[16 * tt + 4 * h + r];
 }
 
 // Forces, energies, virials and squared errors of individuals k0 .. k0+KC-1
@@ -614,7 +611,7 @@ __device__ __forceinline__ void fetch_atom(AtomOps& o, int4 m, int i, int n_pop,
 // their order, so results are the same for any schedule.
 // Phase 2: one unit per (structure, individual): lanes over the atoms form
 // the energy, force and virial errors in float64 in a fixed order.
-constexpr int kContractWaves = 8;
+constexpr int kContractWaves = 12;
 __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
     int N, int S, int k0, int KC, int kcs, int n_pop, const int* __restrict__ tile_order,
     const int* __restrict__ tile_off, const int* __restrict__ tile_s0,
@@ -717,6 +714,9 @@ __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
       for (int pb = 0; pb < kFastS; ++pb) {
         if (pb >= ns) break;
         const bool ang = pb < nab;
+        float4 e[4];  // the rows' pair records, read while the products run
+#pragma unroll
+        for (int r = 0; r < 4; ++r) e[r] = ppair[(size_t)m.y + 16 * pb + 4 * h + r];
 #pragma unroll
         for (int c = 0; c < kCols; ++c) {
           f32x4 v = {0.f, 0.f, 0.f, 0.f};
@@ -731,7 +731,7 @@ __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
               for (int q = 0; q < kASteps; ++q) va[d] = mma(o.a[d][q], o.b[c][3 + q], va[d]);
             }
           }
-          if (valid[c]) scatter_block(v, va, ang, o.ps[pb], pb, P, 16 * c + col);
+          if (valid[c]) scatter_block(v, va, ang, e, pb, P, 16 * c + col);
         }
       }
       return;
@@ -774,9 +774,10 @@ __global__ __launch_bounds__(64 * kContractWaves) void k_pop_contract(
     }
   };
 
-  // Phase 1: atoms ta + w, ta + w + 8, ...; all operands of an atom are
-  // requested before its first product (the other wave on the SIMD covers
-  // the wait)
+  // Phase 1: atoms ta + w, ta + w + kContractWaves, ...; all fragment
+  // operands of an atom are requested before its first product (the other
+  // waves on the SIMD cover the wait), its pair records just before the
+  // products that use them
   // (the atom records are read with vector loads, threadIdx.y being 0: a
   // scalar load would have to wait for every LDS addition in flight)
   for (int i = ta + w; i < tb; i += kContractWaves) {
