@@ -315,8 +315,13 @@ void nep_dataset_destroy(nep_dataset ds);
  * per tile of whole structures that contracts the descriptor derivatives
  * cached when the dataset's positions were set (Sec. II D) with every
  * individual's dU/dq, gathers the forces in LDS and forms the squared errors.
- * Sums are float64 in a fixed order; the result of an individual does not
- * depend on the rest of the population.  The network kernel uses the shape
+ * Forces and structure virials are summed as 32-bit fixed point, round(x 2^e)
+ * with e per (tile of structures, individual) chosen from a bound on
+ * |dU/dq| so that no sum reaches 2^30 (each term then carries an absolute
+ * error of at most 2^-e-1, 2^-31 of the bound); integer sums do not depend on
+ * their order.  The squared errors are float64 sums in a fixed order.  The
+ * result of an individual does not depend on the rest of the population, and
+ * a non-finite bound gives NaN losses.  The network kernel uses the shape
  * chosen by snes_autotune (32 atoms per wave until then).  The dataset must
  * belong to ctx and match its hyperparameters.  NEP_EINVAL if a structure has
  * more than 13,312 atoms (the forces of one individual on one structure must
