@@ -318,7 +318,7 @@ void nep_dataset_destroy(nep_dataset ds);
  * Forces and structure virials are summed as 32-bit fixed point, round(x 2^e)
  * with e per (tile of structures, individual) chosen from a bound on
  * |dU/dq| so that no sum reaches 2^30 (each term then carries an absolute
- * error of at most 2^-e-1, 2^-31 of the bound); integer sums do not depend on
+ * error of at most 2^-e-1, at most 2^-30 of the bound); integer sums do not depend on
  * their order.  The squared errors are float64 sums in a fixed order.  The
  * result of an individual does not depend on the rest of the population, and
  * a non-finite bound gives NaN losses.  The network kernel uses the shape
