@@ -465,6 +465,24 @@ __global__ void k_kick_drift(int n, double* __restrict__ pos, double* __restrict
   pos[t] += dt * v;
 }
 
+// k_kick_drift reading the caller's arrays: internal index k takes caller
+// row perm[k] (the same arithmetic, so the same bits as a gather followed by
+// k_kick_drift).
+__global__ void k_take_kick_drift(int n, const double* __restrict__ pos_c,
+                                  const double* __restrict__ vel_c, double* __restrict__ pos,
+                                  double* __restrict__ vel, const float* __restrict__ F,
+                                  double kick, double dt, const double* __restrict__ mass_c,
+                                  const int* __restrict__ perm, double mref) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * n) return;
+  const int k = t % n, r = t / n;
+  const int c = perm[k];
+  const double kk = mass_c ? kick * (mref / mass_c[c]) : kick;
+  const double v = vel_c[(size_t)r * n + c] + kk * (double)F[t];
+  vel[t] = v;
+  pos[t] = pos_c[(size_t)r * n + c] + dt * v;
+}
+
 __global__ void k_zero_d(double* __restrict__ a, int m) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < m) a[t] = 0.0;
@@ -594,6 +612,18 @@ hipError_t launch_finalize(nep_ctx ctx, int nq, int nsets, const double* block_s
   else
     launch_kernel(ctx, first, true, k_finalize<5>, dim3(nsets), dim3(kBlock), nb, block_sums, out,
                   ctx->flags.ptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_take_kick_drift(nep_ctx ctx, const double* pos_c, const double* vel_c,
+                                  double* pos, double* vel, double kick, double mass, double dt) {
+  const int n = ctx->sys.n;
+  if (n == 0) return hipSuccess;
+  const bool per_atom = ctx->species_on() && ctx->have_masses;
+  launch_kernel(ctx, true, true, k_take_kick_drift, dim3(blocks_for((size_t)3 * n, kBlock)),
+                dim3(kBlock), n, pos_c, vel_c, pos, vel, (const float*)ctx->F.ptr, kick, dt,
+                per_atom ? (const double*)ctx->masses.ptr : (const double*)nullptr,
+                (const int*)ctx->sys.perm.ptr, mass);
   return hipGetLastError();
 }
 

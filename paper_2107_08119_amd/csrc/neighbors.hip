@@ -241,6 +241,19 @@ __global__ void k_put_rows(int n, int rows, const T* __restrict__ src, const int
   for (int r = 0; r < rows; ++r) dst[(size_t)r * n + c] = src[(size_t)r * n + k];
 }
 
+// Two [3][n] arrays back to the caller's order in one pass.
+__global__ void k_put_rows2(int n, const double* __restrict__ a, double* __restrict__ a_dst,
+                            const double* __restrict__ b, double* __restrict__ b_dst,
+                            const int* __restrict__ iperm) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int k = iperm[c];
+  for (int r = 0; r < 3; ++r) {
+    a_dst[(size_t)r * n + c] = a[(size_t)r * n + k];
+    b_dst[(size_t)r * n + c] = b[(size_t)r * n + k];
+  }
+}
+
 // iperm[perm[k]] = k.
 __global__ void k_invert_perm(int n, const int* __restrict__ perm, int* __restrict__ iperm) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -650,6 +663,13 @@ void launch_put_rows(nep_ctx ctx, int n, int rows, const double* src, double* ds
   if (n == 0) return;
   launch_kernel(ctx, false, false, k_put_rows<double>, dim3(blocks_for(n, kBlock)), dim3(kBlock),
                 n, rows, src, (const int*)ctx->sys.iperm.ptr, dst);
+}
+
+void launch_put_rows2(nep_ctx ctx, int n, const double* a, double* a_dst, const double* b,
+                      double* b_dst) {
+  if (n == 0) return;
+  launch_kernel(ctx, false, false, k_put_rows2, dim3(blocks_for(n, kBlock)), dim3(kBlock), n, a,
+                a_dst, b, b_dst, (const int*)ctx->sys.iperm.ptr);
 }
 
 void launch_put_rows(nep_ctx ctx, int n, int rows, const float* src, float* dst) {

@@ -376,9 +376,6 @@ nep_status nep_md_step_driven(nep_ctx ctx, int n_steps, double dt_fs, int rebuil
   if (!thermo_dev) return fail(ctx, NEP_EINVAL, "thermo_dev is required");
   DeviceGuard guard(ctx->device);
   const double kick = 0.5 * dt_fs * kAccel / mass_amu;
-  // the caller's arrays in the internal (cell) order
-  launch_take_rows(ctx, n, 3, pos_dev, s.pos_s.ptr);
-  launch_take_rows(ctx, n, 3, vel_dev, s.vel_s.ptr);
   // Thermo block sums of up to `chunk` steps are kept and reduced together.
   const size_t nb = gather_blocks(n);
   const int chunk = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)4 << 20) / (nb * 5 + 1)));
@@ -386,21 +383,33 @@ nep_status nep_md_step_driven(nep_ctx ctx, int n_steps, double dt_fs, int rebuil
   if (e != hipSuccess) return check_hip(ctx, e, "allocating thermo sums");
   const bool same_field = ctx->md_fe[0] == fe_host[0] && ctx->md_fe[1] == fe_host[1] &&
                           ctx->md_fe[2] == fe_host[2];
-  if (!(ctx->md_forces_valid && ctx->md_pos == pos_dev && ctx->md_vel == vel_dev && same_field)) {
-    // forces of the starting positions (with the driving force: mode 1 with a
-    // zero kick computes F + F_e . W and leaves the velocities unchanged)
+  const bool forces_valid =
+      ctx->md_forces_valid && ctx->md_pos == pos_dev && ctx->md_vel == vel_dev && same_field;
+  ctx->md_forces_valid = false;
+  int pending = 0;
+  // The caller's arrays in the internal (cell) order and the first half-kick
+  // and drift of step 0 (later steps get theirs from the previous step's
+  // pass 2): one kernel when the kept forces belong to these positions,
+  // else the forces of the starting positions first (with the driving force:
+  // mode 1 with a zero kick computes F + F_e . W and leaves the velocities
+  // unchanged).
+  if (forces_valid) {
+    e = timed(ctx, 3, [&] {
+      return launch_take_kick_drift(ctx, pos_dev, vel_dev, s.pos_s.ptr, s.vel_s.ptr, kick,
+                                    mass_amu, dt_fs);
+    });
+    if (e != hipSuccess) return check_hip(ctx, e, "launching integrator");
+  } else {
+    launch_take_rows(ctx, n, 3, pos_dev, s.pos_s.ptr);
+    launch_take_rows(ctx, n, 3, vel_dev, s.vel_s.ptr);
     e = evaluate_internal(ctx, true, nullptr, 1, 0.0, mass_amu, false, false, ctx->partials.ptr,
                           0.0, nullptr, fe_host);
     if (e != hipSuccess) return check_hip(ctx, e, "launching force kernels");
+    e = timed(ctx, 3, [&] {
+      return launch_kick_drift(ctx, s.pos_s.ptr, s.vel_s.ptr, kick, mass_amu, dt_fs);
+    });
+    if (e != hipSuccess) return check_hip(ctx, e, "launching integrator");
   }
-  ctx->md_forces_valid = false;
-  int pending = 0;
-  // first half-kick and drift of step 0; later steps get theirs from the
-  // previous step's pass 2
-  e = timed(ctx, 3, [&] {
-    return launch_kick_drift(ctx, s.pos_s.ptr, s.vel_s.ptr, kick, mass_amu, dt_fs);
-  });
-  if (e != hipSuccess) return check_hip(ctx, e, "launching integrator");
   for (int step = 0; step < n_steps; ++step) {
     if (++ctx->steps_since_rebuild >= rebuild_every) {
       if (n > 0) {
@@ -434,8 +443,7 @@ nep_status nep_md_step_driven(nep_ctx ctx, int n_steps, double dt_fs, int rebuil
       pending = 0;
     }
   }
-  launch_put_rows(ctx, n, 3, s.pos_s.ptr, pos_dev);
-  launch_put_rows(ctx, n, 3, s.vel_s.ptr, vel_dev);
+  launch_put_rows2(ctx, n, s.pos_s.ptr, pos_dev, s.vel_s.ptr, vel_dev);
   e = hipGetLastError();
   if (e != hipSuccess) return check_hip(ctx, e, "copying the state back");
   ctx->md_forces_valid = true;

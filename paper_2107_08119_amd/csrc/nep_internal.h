@@ -361,6 +361,9 @@ void launch_take_rows(nep_ctx ctx, int n, int rows, const double* src, double* d
 // same as dst[r*n + perm[k]] = src[r*n + k], with coalesced stores).
 void launch_put_rows(nep_ctx ctx, int n, int rows, const double* src, double* dst);
 void launch_put_rows(nep_ctx ctx, int n, int rows, const float* src, float* dst);
+// both [3][n] arrays a (to a_dst) and b (to b_dst) in one launch
+void launch_put_rows2(nep_ctx ctx, int n, const double* a, double* a_dst, const double* b,
+                      double* b_dst);
 void launch_iota(nep_ctx ctx, int n, int* dst);
 void prepare_system_geometry(System& s, const double* box_host, double rc_r, double rc_a,
                              double skin);
@@ -395,6 +398,11 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
 hipError_t launch_finalize(nep_ctx ctx, int nq, int nsets, const double* block_sums, double* out,
                            bool first);
 size_t gather_blocks(int n);
+// The caller's positions and velocities (caller order) gathered into the
+// internal arrays with the first half-kick and drift applied (the forces kept
+// in the context belong to these positions).
+hipError_t launch_take_kick_drift(nep_ctx ctx, const double* pos_c, const double* vel_c,
+                                  double* pos, double* vel, double kick, double mass, double dt);
 hipError_t launch_kick_drift(nep_ctx ctx, double* pos, double* vel, double kick, double mass,
                              double dt);
 // pass 1 over a dataset for n_pop parameter vectors Z [n_pop][n_par].
