@@ -274,9 +274,12 @@ __global__ void k_iota(int n, int* __restrict__ a) {
 // depend on G.  Angular-range entries go to the list at once; the remaining
 // radial-range entries wait in LDS (up to RO per atom) and follow them when
 // the scan is done.  An atom with more than RO of them scans its cells a
-// second time for that part.  Atoms are in cell order, so a cell's atoms are
-// start[c] .. start[c+1]-1.
-template <int G, int RO, int MAXC, int NT>
+// second time for that part.  With staged records a cheaper first pass picks
+// the candidates that can be inside the larger cutoff (up to SC of them, their
+// numbers in scan order in LDS) and the exact test runs on those alone; the
+// lists are the same as those of the plain scan.  Atoms are in cell order, so
+// a cell's atoms are start[c] .. start[c+1]-1.
+template <int G, int RO, int SC, int MAXC, int NT>
 __global__ __launch_bounds__(NT) void k_build_cells(
     int n, int cap, const double* __restrict__ pos, Box box, int nc0, int nc1, int nc2,
     const int* __restrict__ wrap, const int* __restrict__ start,
@@ -292,6 +295,8 @@ __global__ __launch_bounds__(NT) void k_build_cells(
   __shared__ CellRec s_rec[MAXC];
   __shared__ uint8_t s_cell[MAXC];
   __shared__ uint32_t s_ro[NG][RO];  // radial-only entries in scan order
+  __shared__ uint16_t s_cand[NG][SC];  // candidates left by the first pass
+  static_assert(MAXC <= 65536, "candidate numbers in 16 bits");
   const int cell = (int)xcd_block(blockIdx.x, gridDim.x);
   const int c0 = cell % nc0, c1 = (cell / nc0) % nc1, c2 = cell / (nc0 * nc1);
   const int tid = threadIdx.x;
@@ -331,6 +336,7 @@ __global__ __launch_bounds__(NT) void k_build_cells(
   const unsigned long long below = (1ull << k) - 1ull;
   const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
   const int a1 = start[cell + 1];
+  const double rc2_max = fmax(rc2_r, rc2_a);
   // records from LDS when all candidates were staged, else all from global
   // memory (two instantiations, so that neither path uses generic addresses)
   auto scan = [&](auto staged) {
@@ -380,14 +386,55 @@ __global__ __launch_bounds__(NT) void k_build_cells(
         entry = pack_entry(j, n0, n1, n2);
       }
     };
+    // First pass over staged records.  A candidate with the atom's own wrap
+    // counts (d = 0 below) takes the same float64 distance as in the exact
+    // test and is left out only if it lies outside both cutoffs; every other
+    // candidate is left to the exact test.  So the exact test sees every
+    // candidate it would keep, in scan order.
+    int ncand = total;
+    bool listed = false;
+    if constexpr (decltype(staged)::value) {
+      const bool in_range = wi0 >= -128 && wi0 <= 127 && wi1 >= -128 && wi1 <= 127 &&
+                            wi2 >= -128 && wi2 <= 127;
+      const int wpack =
+          in_range ? (wi0 & 0xFF) | ((wi1 & 0xFF) << 8) | ((wi2 & 0xFF) << 16) : -1;
+      int nk = 0;
+      for (int base = 0; base < total; base += G) {
+        const int c = base + k;
+        bool pass = false;
+        if (c < total) {
+          const int q = s_cell[c];
+          const CellRec rc = s_rec[c];
+          const double r2 = list_r2_shifted(rc.x, rc.y, rc.z, xi, yi, zi, s_shift[q][0],
+                                            s_shift[q][1], s_shift[q][2]);
+          pass = (rc.w & 0xFFFFFF) != wpack || r2 < rc2_max;
+        }
+        const unsigned long long bp = (__ballot(pass) >> shift) & gmask;
+        if (pass) {
+          const int u = nk + __popcll(bp & below);
+          if (u < SC) s_cand[grp][u] = (uint16_t)c;
+        }
+        nk += __popcll(bp);
+      }
+      if (nk <= SC) {
+        ncand = nk;
+        listed = true;
+      }
+      // the list is read back by other lanes of the group below
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // the t-th candidate of the exact test
+    auto number = [&](int t) { return listed ? (int)s_cand[grp][t] : t; };
     int na = 0, nro = 0;
-    for (int base = 0; base < total; base += G) {
-      const int c = base + k;
+    for (int base = 0; base < ncand; base += G) {
+      const int t = base + k;
       bool keep_a = false, keep_r = false;
       uint32_t entry = 0;
-      if (c < total) {
+      if (t < ncand) {
         double r2;
-        candidate(c, entry, r2);
+        candidate(number(t), entry, r2);
         keep_a = r2 >= 0.0 && r2 < rc2_a;
         keep_r = r2 >= rc2_a && r2 < rc2_r;
       }
@@ -403,8 +450,8 @@ __global__ __launch_bounds__(NT) void k_build_cells(
         }
       }
       if (keep_r) {
-        const int t = nro + __popcll(br & below);
-        if (t < RO) s_ro[grp][t] = entry;
+        const int ro = nro + __popcll(br & below);
+        if (ro < RO) s_ro[grp][ro] = entry;
       }
       na += __popcll(ba);
       nro += __popcll(br);
@@ -425,13 +472,13 @@ __global__ __launch_bounds__(NT) void k_build_cells(
       }
     } else {
       int count = na;
-      for (int base = 0; base < total; base += G) {
-        const int c = base + k;
+      for (int base = 0; base < ncand; base += G) {
+        const int t = base + k;
         bool keep = false;
         uint32_t entry = 0;
-        if (c < total) {
+        if (t < ncand) {
           double r2;
-          candidate(c, entry, r2);
+          candidate(number(t), entry, r2);
           keep = r2 >= rc2_a && r2 < rc2_r;
         }
         const unsigned long long ball = (__ballot(keep) >> shift) & gmask;
@@ -785,7 +832,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
     s.wrap.swap(s.wrap_t);
     s.perm.swap(s.perm_t);
     s.cell_of.swap(s.cell_t);
-    launch_kernel(ctx, false, false, k_build_cells<32, 64, 640, 256>, dim3(ncell), dim3(256), n,
+    launch_kernel(ctx, false, false, k_build_cells<32, 64, 96, 640, 256>, dim3(ncell), dim3(256), n,
                   s.cap, (const double*)s.pos_s.ptr, s.box, s.nc[0], s.nc[1], s.nc[2],
                   (const int*)s.wrap.ptr, (const int*)s.cell_start.ptr,
                   (const CellRec*)s.cell_rec.ptr, rc2_r, rc2_a, s.nl.ptr, s.nl_rm.ptr, s.cnt_r.ptr,
