@@ -74,6 +74,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   __shared__ float4 sd[KS][APB];
   __shared__ unsigned long long smask[2][W][APB];  // [angular, radial-only][w][atom]
   __shared__ int scount[2][APB];
+  __shared__ __align__(16) float snet[kBlock / 64][net_rows(L) * kNetX];  // network_mfma
   const float rcr2 = rc_r * rc_r, rca2 = rc_a * rc_a;
   {
     const int a = threadIdx.x % APB, w = threadIdx.x / APB;
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 
   float dq[NDES];
   float u;
-  network<NDES, NNEU, L>(q, sw4, sb2, lane, dq, u);
+  network_mfma<NDES, NNEU, L>(q, sw4, sb2, snet[threadIdx.x >> 6], dq, u);
   if (active && lane == 0) U[i] = u;
   angular_coefficients<NR, NA, LMAX>(dq, c);
   const float dqs = radial_dq_sum<NR>(dq);

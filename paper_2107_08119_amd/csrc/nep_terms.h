@@ -215,6 +215,126 @@ __device__ __forceinline__ void network(const float* q, const float4* rows, floa
   for (int v = 0; v < NDES; ++v) dq[v] = group_sum<L>(dq[v]);
 }
 
+// LDS row of one atom in network_mfma: 32 descriptor slots (dU/dq on the
+// way back), U at column 32, padding to 36 floats (rows off a multiple of 32
+// banks, 16-byte aligned).
+constexpr int kNetX = 36;
+constexpr int net_rows(int lanes) { return 64 / lanes > 16 ? 64 / lanes : 16; }
+
+// The network (Eqs. nn1, nn2) and dU/dq for the 64 / L atoms of a wave on the
+// matrix cores.  x is the wave's LDS block of net_rows(L) rows of kNetX
+// floats; all 64 lanes of the wave take part; every lane ends with its
+// atom's U and dq.  With H = W1 Q^T (neurons x atoms) and
+// G = w2 (1 - tanh^2(H - b1)), dq = W1^T G: each product is a 16x16x4 MFMA
+// chain per 16-neuron (forward) or 16-descriptor (backward) tile and 16
+// atoms.  Forward K step s takes descriptor 8 (l/16) + s in lane l, so a lane
+// reads 8 consecutive descriptors; backward step (t, r) takes neuron
+// 16 t + 4 (l/16) + r, which is element r of the lane's forward tile t, so G
+// feeds the second product from the registers the first one left it in.
+template <int NDES, int NNEU, int L>
+__device__ __forceinline__ void network_mfma(const float* q, const float4* rows, float b2,
+                                             float* x, float* dq, float& u) {
+  static_assert(NDES <= 32 && NNEU <= 32 && NNEU >= 1, "two 16-wide tiles");
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int RS = NetRows<NDES, NNEU>::RS;
+  constexpr int AW = 64 / L;                  // atoms of the wave
+  constexpr int AT = AW >= 16 ? AW / 16 : 1;  // tiles of 16 atoms
+  const float* sw = reinterpret_cast<const float*>(rows);
+  const int wl = threadIdx.x & 63, g = wl >> 4, j = wl & 15;
+  const int aw = wl / L, sub = wl % L;
+  // descriptor in, zero-padded to 32, written by the atom's first lane
+  if (sub == 0) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = 4 * t + e < NDES ? q[4 * t + e] : 0.f;
+      *reinterpret_cast<float4*>(x + aw * kNetX + 4 * t) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // forward operands: W1[16 t + j][8 g + s] (rows past NNEU repeat the last
+  // row; their output weight is zero below), the lane's b1 and w2
+  float af[2][8];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int mu = min(16 * t + j, NNEU - 1);
+    const float4 r0 = rows[(mu * RS + 8 * g) / 4], r1 = rows[(mu * RS + 8 * g) / 4 + 1];
+    af[t][0] = r0.x, af[t][1] = r0.y, af[t][2] = r0.z, af[t][3] = r0.w;
+    af[t][4] = r1.x, af[t][5] = r1.y, af[t][6] = r1.z, af[t][7] = r1.w;
+  }
+  float gv[AT][2][4];
+  float us[AT];
+#pragma unroll
+  for (int at = 0; at < AT; ++at) {
+    const float* xr = x + (16 * at + j) * kNetX + 8 * g;
+    const float4 b0 = *reinterpret_cast<const float4*>(xr);
+    const float4 b1v = *reinterpret_cast<const float4*>(xr + 4);
+    const float bq[8] = {b0.x, b0.y, b0.z, b0.w, b1v.x, b1v.y, b1v.z, b1v.w};
+    float up = 0.f;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      f4 h = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 8; ++s) h = __builtin_amdgcn_mfma_f32_16x16x4f32(af[t][s], bq[s], h, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int mu = 16 * t + 4 * g + r;
+        const int mc = min(mu, NNEU - 1);
+        const float w2 = mu < NNEU ? sw[mc * RS + NDES + 1] : 0.f;
+        const float act = h[r] - sw[mc * RS + NDES];
+        // tanh and its derivative 1 - tanh^2 from e = exp(-2|a|) (no cancellation)
+        const float ea = __expf(-2.f * fabsf(act));
+        const float inv = __builtin_amdgcn_rcpf(1.f + ea);
+        const float th = copysignf((1.f - ea) * inv, act);
+        up += w2 * th;
+        gv[at][t][r] = w2 * (4.f * ea * inv * inv);
+      }
+    }
+    // sum over the four lane groups (neurons 4 g .. 4 g + 3 of each tile)
+    up += __shfl_xor(up, 16, 64);
+    up += __shfl_xor(up, 32, 64);
+    us[at] = up - b2;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // backward: dq^T[16 d + 4 g + r][atom] into the atom rows, U at column 32
+#pragma unroll
+  for (int at = 0; at < AT; ++at) {
+    float* xr = x + (16 * at + j) * kNetX;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int mc = min(16 * t + 4 * g + r, NNEU - 1);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(sw[mc * RS + 16 * d + j], gv[at][t][r], acc,
+                                                     0, 0, 0);
+        }
+      *reinterpret_cast<float4*>(xr + 16 * d + 4 * g) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    }
+    if (g == 0) xr[32] = us[at];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const float4* xo = reinterpret_cast<const float4*>(x + aw * kNetX);
+#pragma unroll
+  for (int t = 0; t < (NDES + 3) / 4; ++t) {
+    const float4 v = xo[t];
+    const float e4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (4 * t + e < NDES) dq[4 * t + e] = e4[e];
+  }
+  u = x[aw * kNetX + 32];
+}
+
 // a_nlm = 2 dU/dq_nl c_nlm in place of c, then row 0 replaced by
 // a'_0lm = 2 a_0lm + sum_{n>=1} a_nlm (the constant part of sum_n a_nlm (T_n + 1)).
 template <int NR, int NA, int LMAX>
