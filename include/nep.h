@@ -440,12 +440,14 @@ nep_status nep_time_partials(nep_ctx ctx, const double* pos_dev, int reps, doubl
 
 /* Tile-shape autotuner for the descriptor/network/partial-force kernel on
  * the current system at pos_dev (as for nep_compute): times the compiled
- * shapes (2, 4 and 8 lanes per atom; 128, 64 and 32 atoms per block) over
- * `reps` launches each (1..10000) with HIP events on the context's stream and
- * keeps the fastest for later nep_compute / nep_md_step calls.  Host outputs
- * (either may be NULL): *lanes_out = chosen lanes per atom; ms_out[3] = mean
- * ms per launch of each shape in the order above.  Needs loaded parameters
- * and a neighbour list; waits for the stream. */
+ * shapes (2, 4 and 8 lanes per atom; 128, 64 and 32 atoms per block) with
+ * HIP events on the context's stream in three interleaved rounds of `reps`
+ * launches per shape (1..10000), so that a clock that settles during the
+ * calls weighs on every shape alike, and keeps the shape with the fastest
+ * round for later nep_compute / nep_md_step calls.  Host outputs (either may
+ * be NULL): *lanes_out = chosen lanes per atom; ms_out[3] = mean ms per
+ * launch of each shape's fastest round, in the order above.  Needs loaded
+ * parameters and a neighbour list; waits for the stream. */
 nep_status nep_autotune(nep_ctx ctx, const double* pos_dev, int reps, int* lanes_out,
                         double* ms_out);
 

@@ -521,28 +521,30 @@ nep_status nep_autotune(nep_ctx ctx, const double* pos_dev, int reps, int* lanes
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
   int best = ctx->md_variant;
-  double best_ms = 0.0;
   // other model sizes have the one-wave-per-atom kernel only
   const int nv = have_training_variant(ctx->hyper) && !ctx->species_on() ? 3 : 1;
-  for (int v = 0; v < 3 && e == hipSuccess; ++v) {
-    if (v >= nv) {
-      if (ms_out) ms_out[v] = ms_out[0];
-      continue;
+  // shapes timed in interleaved rounds; each keeps its fastest round
+  constexpr int kRounds = 3;
+  double per[3] = {0.0, 0.0, 0.0};
+  for (int round = 0; round < kRounds && e == hipSuccess; ++round)
+    for (int v = 0; v < nv && e == hipSuccess; ++v) {
+      if (round == 0) e = launch_partials(ctx, ctx->sys.pos_s.ptr, v);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r)
+        e = launch_partials(ctx, ctx->sys.pos_s.ptr, v);
+      if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e == hipSuccess && (round == 0 || (double)ms / reps < per[v])) per[v] = (double)ms / reps;
     }
-    e = launch_partials(ctx, ctx->sys.pos_s.ptr, v);  // warm-up
-    if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_partials(ctx, ctx->sys.pos_s.ptr, v);
-    if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(b);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-    const double per = (double)ms / reps;
-    if (ms_out) ms_out[v] = per;
-    if (e == hipSuccess && (v == 0 || per < best_ms)) {
-      best = v;
-      best_ms = per;
-    }
+  if (e == hipSuccess) {
+    best = 0;
+    for (int v = 1; v < nv; ++v)
+      if (per[v] < per[best]) best = v;
   }
+  if (ms_out)
+    for (int v = 0; v < 3; ++v) ms_out[v] = per[v < nv ? v : 0];
   if (a) (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
   ctx->timer.on = timing;

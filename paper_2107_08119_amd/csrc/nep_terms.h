@@ -173,48 +173,6 @@ __device__ __forceinline__ void load_net_rows(const float* __restrict__ z, float
   if (threadIdx.x == 0) *b2_out = z[NNEU * (NDES + 2)];
 }
 
-// The network (Eqs. nn1, nn2) and dU/dq, neurons split over the L lanes of
-// the atom's group; every lane ends with the full U and dq.
-template <int NDES, int NNEU, int L>
-__device__ __forceinline__ void network(const float* q, const float4* rows, float b2, int lane,
-                                        float* dq, float& u) {
-  constexpr int RS = NetRows<NDES, NNEU>::RS;
-  static_assert(L <= NNEU, "every lane has a first neuron");
-  // the lane's first neuron (mu = lane) starts the sums u and dq
-  for (int mu = lane; mu < NNEU; mu += L) {
-    float w[RS];
-#pragma unroll
-    for (int t = 0; t < RS / 4; ++t) {
-      const float4 r4 = rows[mu * (RS / 4) + t];
-      w[4 * t] = r4.x;
-      w[4 * t + 1] = r4.y;
-      w[4 * t + 2] = r4.z;
-      w[4 * t + 3] = r4.w;
-    }
-    float act = -w[NDES];
-#pragma unroll
-    for (int v = 0; v < NDES; ++v) act += w[v] * q[v];
-    // tanh and its derivative 1 - tanh^2 from e = exp(-2|a|) (no cancellation)
-    const float ea = __expf(-2.f * fabsf(act));
-    const float inv = __builtin_amdgcn_rcpf(1.f + ea);
-    const float th = copysignf((1.f - ea) * inv, act);
-    const float sech2 = 4.f * ea * inv * inv;
-    const float gmu = w[NDES + 1] * sech2;
-    if (mu == lane) {
-      u = w[NDES + 1] * th;
-#pragma unroll
-      for (int v = 0; v < NDES; ++v) dq[v] = gmu * w[v];
-    } else {
-      u += w[NDES + 1] * th;
-#pragma unroll
-      for (int v = 0; v < NDES; ++v) dq[v] += gmu * w[v];
-    }
-  }
-  u = group_sum<L>(u) - b2;
-#pragma unroll
-  for (int v = 0; v < NDES; ++v) dq[v] = group_sum<L>(dq[v]);
-}
-
 // LDS row of one atom in network_mfma: 32 descriptor slots (dU/dq on the
 // way back), U at column 32, padding to 36 floats (rows off a multiple of 32
 // banks, 16-byte aligned).
