@@ -68,42 +68,53 @@ __global__ void k_bin(int n, double* __restrict__ pos, Box box, int nc0, int nc1
   }
 }
 
-// Exclusive prefix sum of m counts by one block of 1024 threads; the counts
-// are cleared for the next build and the fill counters for k_fill.
+// Exclusive prefix sum of m <= 1024 * kScanChunks counts by one block of
+// 1024 threads; the counts are cleared for the next build and the fill
+// counters for k_fill.
+constexpr int kScanChunks = 16;
 __global__ __launch_bounds__(1024) void k_scan(int m, int* __restrict__ cnt,
                                                int* __restrict__ start, int* __restrict__ fill) {
-  // wave w owns a run of consecutive cells, read in chunks of 64 (coalesced);
-  // pass 1 sums the run, one barrier combines the 16 wave totals, pass 2
-  // reads the counts again and writes the exclusive prefix (lane shuffles
-  // within a chunk, a running carry across chunks) and zeroes the counts
+  // wave w owns a run of `chunks` chunks of 64 consecutive cells (coalesced
+  // reads, all issued before any is used); each chunk is scanned across the
+  // lanes, the chunks of a wave in order, the 16 waves after one barrier
   __shared__ int wsum[16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int chunks = (m + 1023) / 1024;  // chunks of 64 per wave
+  const int chunks = (m + 1023) / 1024;
   const int c0 = w * chunks * 64;
-  const int c1 = min(m, c0 + chunks * 64);
-  int part = 0;
-  for (int c = c0 + lane; c < c1; c += 64) part += cnt[c];
+  int own[kScanChunks], x[kScanChunks];
 #pragma unroll
-  for (int d = 32; d > 0; d >>= 1) part += __shfl_xor(part, d, 64);
-  if (lane == 0) wsum[w] = part;
+  for (int t = 0; t < kScanChunks; ++t) {
+    const int c = c0 + 64 * t + lane;
+    own[t] = t < chunks && c < m ? cnt[c] : 0;
+    x[t] = own[t];
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+    for (int t = 0; t < kScanChunks; ++t)
+      if (t < chunks) {
+        const int y = __shfl_up(x[t], d, 64);
+        if (lane >= d) x[t] += y;
+      }
+  int run = 0;  // the wave's sum before chunk t
+  int before[kScanChunks];
+#pragma unroll
+  for (int t = 0; t < kScanChunks; ++t) {
+    before[t] = run;
+    if (t < chunks) run += __shfl(x[t], 63, 64);
+  }
+  if (lane == 0) wsum[w] = run;
   __syncthreads();
   int carry = 0;
   for (int u = 0; u < w; ++u) carry += wsum[u];
-  for (int b = c0; b < c1; b += 64) {
-    const int c = b + lane;
-    const int own = c < c1 ? cnt[c] : 0;
-    int x = own;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int y = __shfl_up(x, d, 64);
-      if (lane >= d) x += y;
-    }
-    if (c < c1) {
-      start[c] = carry + x - own;
+  for (int t = 0; t < kScanChunks; ++t) {
+    const int c = c0 + 64 * t + lane;
+    if (t < chunks && c < m) {
+      start[c] = carry + before[t] + x[t] - own[t];
       cnt[c] = 0;   // ready for the next build
       fill[c] = 0;  // for k_fill, next
     }
-    carry += __shfl(x, 63, 64);
   }
   if (threadIdx.x == 1023) {
     int tot = 0;
@@ -804,7 +815,7 @@ nep_status build_neighbors(nep_ctx ctx, bool wrap_in_place, bool have_vel) {
                   s.box, s.nc[0], s.nc[1], s.nc[2], 1, wrap_in_place ? 1 : 0, s.wrap.ptr,
                   s.cell_of.ptr, s.cell_cnt.ptr, (float*)nullptr);
     const int nsb = (ncell + 1023) / 1024;
-    if (ncell > 16384 && nsb <= 1024) {
+    if (ncell > 1024 * kScanChunks && nsb <= 1024) {
       launch_kernel(ctx, false, false, k_scan_blocks, dim3(nsb), dim3(1024), ncell,
                     (const int*)s.cell_cnt.ptr, s.cell_start.ptr, s.scan_part.ptr);
       launch_kernel(ctx, false, false, k_scan_totals, dim3(1), dim3(1024), nsb, ncell,
