@@ -285,13 +285,15 @@ __global__ void k_iota(int n, int* __restrict__ a) {
 // depend on G.  Angular-range entries go to the list at once; the remaining
 // radial-range entries wait in LDS (up to RO per atom) and follow them when
 // the scan is done.  An atom with more than RO of them scans its cells a
-// second time for that part.  With staged records a cheaper first pass picks
-// the candidates that can be inside the larger cutoff (up to SC of them, their
-// numbers in scan order in LDS) and the exact test runs on those alone; the
-// lists are the same as those of the plain scan.  Atoms are in cell order, so
-// a cell's atoms are start[c] .. start[c+1]-1.
+// second time for that part.  When all candidates fit in LDS (MAXC), LDS
+// holds each one's position relative to the cell centre in float32, a
+// float32 first pass picks the candidates that can be inside the larger
+// cutoff (up to SC of them, their numbers in scan order in LDS) and the exact
+// test runs on those alone, with their float64 records read from global
+// memory; the lists are the same as those of the plain scan.  Atoms are in
+// cell order, so a cell's atoms are start[c] .. start[c+1]-1.
 template <int G, int RO, int SC, int MAXC, int NT>
-__global__ __launch_bounds__(NT) void k_build_cells(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_build_cells(
     int n, int cap, const double* __restrict__ pos, Box box, int nc0, int nc1, int nc2,
     const int* __restrict__ wrap, const int* __restrict__ start,
     const CellRec* __restrict__ rec, double rc2_r, double rc2_a, uint32_t* __restrict__ nl,
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(NT) void k_build_cells(
   __shared__ int s_first[27];  // first member slot of each neighbour cell
   __shared__ int s_img[27];    // packed periodic image offset of each neighbour cell
   __shared__ double s_shift[27][3];  // its lattice shift (for atoms with equal offsets)
-  __shared__ CellRec s_rec[MAXC];
+  __shared__ float4 s_pf[MAXC];  // candidate position - cell centre (float32), wrap offsets
   __shared__ uint8_t s_cell[MAXC];
   __shared__ uint32_t s_ro[NG][RO];  // radial-only entries in scan order
   __shared__ uint16_t s_cand[NG][SC];  // candidates left by the first pass
@@ -334,10 +336,17 @@ __global__ __launch_bounds__(NT) void k_build_cells(
   if (tid < 27)
     for (int c = s_off[tid]; c < s_off[tid + 1] && c < MAXC; ++c) s_cell[c] = (uint8_t)tid;
   __syncthreads();
+  // the cell centre: the first pass works on coordinates relative to it
+  const double f0 = (c0 + 0.5) / nc0, f1 = (c1 + 0.5) / nc1, f2 = (c2 + 0.5) / nc2;
+  const double ox = f0 * box.h[0] + f1 * box.h[3] + f2 * box.h[6];
+  const double oy = f0 * box.h[1] + f1 * box.h[4] + f2 * box.h[7];
+  const double oz = f0 * box.h[2] + f1 * box.h[5] + f2 * box.h[8];
   if (total <= MAXC)
     for (int c = tid; c < total; c += NT) {
       const int q = s_cell[c];
-      s_rec[c] = rec[s_first[q] + (c - s_off[q])];
+      const CellRec r = rec[s_first[q] + (c - s_off[q])];
+      s_pf[c] = make_float4((float)((r.x + s_shift[q][0]) - ox), (float)((r.y + s_shift[q][1]) - oy),
+                            (float)((r.z + s_shift[q][2]) - oz), __int_as_float(r.w & 0xFFFFFF));
     }
   __syncthreads();
 
@@ -347,7 +356,16 @@ __global__ __launch_bounds__(NT) void k_build_cells(
   const unsigned long long below = (1ull << k) - 1ull;
   const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
   const int a1 = start[cell + 1];
-  const double rc2_max = fmax(rc2_r, rc2_a);
+  // First-pass bound.  For an atom within kNear of the cell centre (each
+  // component) and a candidate with its wrap offsets whose true displacement
+  // d has |d| < r_c (the larger cutoff), each float32 displacement component
+  // is off by at most eps = 2^-22 (kNear + r_c) (three roundings of values
+  // below kNear + r_c), so |d_f| < r_c + 2 eps and the float32 |d_f|^2 (three
+  // roundings) stays below thr: such a candidate always passes.
+  constexpr float kNear = 4096.f;
+  const double rcm = sqrt(fmax(rc2_r, rc2_a));
+  const double eps = 0x1p-22 * ((double)kNear + rcm);
+  const float thr = (float)((rcm + 2.0 * eps) * (rcm + 2.0 * eps) * (1.0 + 0x1p-20));
   // records from LDS when all candidates were staged, else all from global
   // memory (two instantiations, so that neither path uses generic addresses)
   auto scan = [&](auto staged) {
@@ -361,7 +379,7 @@ __global__ __launch_bounds__(NT) void k_build_cells(
       CellRec rc;
       if constexpr (decltype(staged)::value) {
         q = s_cell[c];
-        rc = s_rec[c];
+        rc = rec[s_first[q] + (c - s_off[q])];
       } else {
         int lo = 0, hi = 27;
         while (hi - lo > 1) {
@@ -397,28 +415,31 @@ __global__ __launch_bounds__(NT) void k_build_cells(
         entry = pack_entry(j, n0, n1, n2);
       }
     };
-    // First pass over staged records.  A candidate with the atom's own wrap
-    // counts (d = 0 below) takes the same float64 distance as in the exact
-    // test and is left out only if it lies outside both cutoffs; every other
-    // candidate is left to the exact test.  So the exact test sees every
-    // candidate it would keep, in scan order.
+    // First pass over the staged positions.  A candidate with the atom's own
+    // wrap counts (d = 0 below) is left out only if its float32 distance
+    // exceeds the bound thr above; every other candidate (and every
+    // candidate of an atom beyond kNear of the cell centre) is left to the
+    // exact test.  So the exact test sees every candidate it would keep, in
+    // scan order.
     int ncand = total;
     bool listed = false;
     if constexpr (decltype(staged)::value) {
       const bool in_range = wi0 >= -128 && wi0 <= 127 && wi1 >= -128 && wi1 <= 127 &&
                             wi2 >= -128 && wi2 <= 127;
-      const int wpack =
-          in_range ? (wi0 & 0xFF) | ((wi1 & 0xFF) << 8) | ((wi2 & 0xFF) << 16) : -1;
+      const float xf = (float)(xi - ox), yf = (float)(yi - oy), zf = (float)(zi - oz);
+      const bool near = fabsf(xf) <= kNear && fabsf(yf) <= kNear && fabsf(zf) <= kNear;
+      const int wpack = in_range && near
+                            ? (wi0 & 0xFF) | ((wi1 & 0xFF) << 8) | ((wi2 & 0xFF) << 16)
+                            : -1;
       int nk = 0;
       for (int base = 0; base < total; base += G) {
         const int c = base + k;
         bool pass = false;
         if (c < total) {
-          const int q = s_cell[c];
-          const CellRec rc = s_rec[c];
-          const double r2 = list_r2_shifted(rc.x, rc.y, rc.z, xi, yi, zi, s_shift[q][0],
-                                            s_shift[q][1], s_shift[q][2]);
-          pass = (rc.w & 0xFFFFFF) != wpack || r2 < rc2_max;
+          const float4 pf = s_pf[c];
+          const float ex = pf.x - xf, ey = pf.y - yf, ez = pf.z - zf;
+          const float r2f = __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex));
+          pass = __float_as_int(pf.w) != wpack || r2f < thr;
         }
         const unsigned long long bp = (__ballot(pass) >> shift) & gmask;
         if (pass) {
