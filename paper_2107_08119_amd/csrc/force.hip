@@ -309,6 +309,16 @@ __global__ __launch_bounds__(kBlock) void k_gather(
   const int cr = active ? cnt_r[i] : 0;
   const double xi = pos[ii], yi = pos[n + ii], zi = pos[2 * n + ii];
   const double* H = box.h;
+  // the atom's own loads of the epilogue, issued before the slot loop
+  const float fo0 = active ? fown[i] : 0.f, fo1 = active ? fown[n + i] : 0.f,
+              fo2 = active ? fown[2 * n + i] : 0.f;
+  const bool own = active && lane == 0;
+  const float ui = own ? U[i] : 0.f;
+  const float rx = own ? pos_ref[i] : 0.f, ry = own ? pos_ref[n + i] : 0.f,
+              rz = own ? pos_ref[2 * n + i] : 0.f;
+  const double vx0 = own && vel ? vel[i] : 0.0, vy0 = own && vel ? vel[n + i] : 0.0,
+               vz0 = own && vel ? vel[2 * n + i] : 0.0;
+  const double mi = own && mass_c ? mass_c[perm[i]] : mref;
   float f0 = 0.f, f1 = 0.f, f2 = 0.f;
   float w[9];
 #pragma unroll
@@ -366,9 +376,9 @@ __global__ __launch_bounds__(kBlock) void k_gather(
       w[8] += dz * pji.z;
     }
   }
-  f0 = group_sum<L>(f0) + (active ? fown[i] : 0.f);
-  f1 = group_sum<L>(f1) + (active ? fown[n + i] : 0.f);
-  f2 = group_sum<L>(f2) + (active ? fown[2 * n + i] : 0.f);
+  f0 = group_sum<L>(f0) + fo0;
+  f1 = group_sum<L>(f1) + fo1;
+  f2 = group_sum<L>(f2) + fo2;
 #pragma unroll
   for (int k = 0; k < 9; ++k) w[k] = group_sum<L>(w[k]);
   if constexpr (MODE >= 1) {  // HNEMD driving force F_e . W_i (zero without a field)
@@ -385,13 +395,11 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     // the list holds every pair within the cutoff only while no atom has
     // moved more than skin/2 since it was built (compared in float32, so an
     // unmoved atom gives exactly zero)
-    const float ex = (float)xi - pos_ref[i], ey = (float)yi - pos_ref[n + i],
-                ez = (float)zi - pos_ref[2 * n + i];
+    const float ex = (float)xi - rx, ey = (float)yi - ry, ez = (float)zi - rz;
     if (ex * ex + ey * ey + ez * ez > half_skin2) flags[kFlagSkin] = 1;
     F[i] = f0;
     F[n + i] = f1;
     F[2 * n + i] = f2;
-    const float ui = U[i];
     if (U_out) U_out[i] = ui;
     if (W)
 #pragma unroll
@@ -401,14 +409,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     // for mass mref
     double ki = kick, ekf = ekin_factor;
     if (mass_c) {
-      const double m = mass_c[perm[i]];
-      ki = kick * (mref / m);
-      ekf = ekin_factor * (m / mref);
+      ki = kick * (mref / mi);
+      ekf = ekin_factor * (mi / mref);
     }
     if (vel) {
-      vx = vel[i];
-      vy = vel[n + i];
-      vz = vel[2 * n + i];
+      vx = vx0;
+      vy = vy0;
+      vz = vz0;
       if constexpr (MODE >= 1) {
         vx += ki * (double)f0;
         vy += ki * (double)f1;
