@@ -623,60 +623,83 @@ __global__ __launch_bounds__(kBlock) void k_reverse(int n, int cap, const uint32
   if (i >= n) return;
   const int cr = cnt_r[i], ca = cnt_a[i];
   const bool symmetric = flags[kFlagOverflow] == 0;
-  for (int s = threadIdx.x / kReverseAtoms; s < cr; s += width) {
-    const size_t idx = (size_t)s * n + i;
-    const uint32_t e = nl[idx];
-    const int j = (int)(e & kAtomMask);
-    if (symmetric && j < i) continue;
-    int n0, n1, n2;
-    unpack_image(e, n0, n1, n2);
-    const uint32_t target = pack_entry(i, -n0, -n1, -n2);
-    const bool angular = s < ca;
-    const int t0 = angular ? 0 : cnt_a[j];
-    const int t1 = angular ? cnt_a[j] : cnt_r[j];
-    int found = -1;
-    if (nl_rm && (cap & 3) == 0) {  // j's entries are contiguous: 4 per load
-      // 16 entries per round, their four loads issued together (no load
-      // waits on the previous compare); loads stay below t1 <= cap
-      const uint4* row4 = reinterpret_cast<const uint4*>(nl_rm + (size_t)j * cap);
-      for (int u16 = t0 & ~3; u16 < t1 && found < 0; u16 += 16) {
-        uint4 v[4];
+  // kBatch slots of the thread at a time: their entries, then their
+  // partners' list counts, are read before the first search
+  constexpr int kBatch = 4;
+  for (int sb = threadIdx.x / kReverseAtoms; sb < cr; sb += width * kBatch) {
+    uint32_t eb[kBatch];
+    int pa[kBatch], pr[kBatch];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          v[q] = u16 + 4 * q < t1 ? row4[(u16 >> 2) + q] : make_uint4(0u, 0u, 0u, 0u);
+    for (int b = 0; b < kBatch; ++b) {
+      const int s = sb + b * width;
+      eb[b] = s < cr ? nl[(size_t)s * n + i] : 0u;
+    }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int u4 = u16 + 4 * q;
-          if (found >= 0 || u4 >= t1) continue;
-          if (v[q].x == target && u4 >= t0) found = u4;
-          else if (v[q].y == target && u4 + 1 >= t0 && u4 + 1 < t1) found = u4 + 1;
-          else if (v[q].z == target && u4 + 2 >= t0 && u4 + 2 < t1) found = u4 + 2;
-          else if (v[q].w == target && u4 + 3 >= t0 && u4 + 3 < t1) found = u4 + 3;
-        }
-      }
-    } else if (nl_rm) {
-      const uint32_t* row = nl_rm + (size_t)j * cap;
-      for (int u = t0; u < t1; ++u) {
-        if (row[u] == target) {
-          found = u;
-          break;
-        }
-      }
-    } else {
-      for (int u = t0; u < t1; ++u) {
-        if (nl[(size_t)u * n + j] == target) {
-          found = u;
-          break;
-        }
-      }
+    for (int b = 0; b < kBatch; ++b) {
+      const int s = sb + b * width;
+      const int j = (int)(eb[b] & kAtomMask);
+      const bool need = s < cr && !(symmetric && j < i);
+      pa[b] = need ? cnt_a[j] : 0;
+      pr[b] = need ? cnt_r[j] : 0;
     }
-    if (found < 0) {
-      flags[kFlagReverse] = 1;
-      found = 0;
-    } else if (symmetric && j != i) {
-      rev[(size_t)found * n + j] = s;
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const int s = sb + b * width;
+      if (s >= cr) break;
+      const size_t idx = (size_t)s * n + i;
+      const uint32_t e = eb[b];
+      const int j = (int)(e & kAtomMask);
+      if (symmetric && j < i) continue;
+      int n0, n1, n2;
+      unpack_image(e, n0, n1, n2);
+      const uint32_t target = pack_entry(i, -n0, -n1, -n2);
+      const bool angular = s < ca;
+      const int t0 = angular ? 0 : pa[b];
+      const int t1 = angular ? pa[b] : pr[b];
+      int found = -1;
+      if (nl_rm && (cap & 3) == 0) {  // j's entries are contiguous: 4 per load
+        // 16 entries per round, their four loads issued together (no load
+        // waits on the previous compare); loads stay below t1 <= cap
+        const uint4* row4 = reinterpret_cast<const uint4*>(nl_rm + (size_t)j * cap);
+        for (int u16 = t0 & ~3; u16 < t1 && found < 0; u16 += 16) {
+          uint4 v[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            v[q] = u16 + 4 * q < t1 ? row4[(u16 >> 2) + q] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int u4 = u16 + 4 * q;
+            if (found >= 0 || u4 >= t1) continue;
+            if (v[q].x == target && u4 >= t0) found = u4;
+            else if (v[q].y == target && u4 + 1 >= t0 && u4 + 1 < t1) found = u4 + 1;
+            else if (v[q].z == target && u4 + 2 >= t0 && u4 + 2 < t1) found = u4 + 2;
+            else if (v[q].w == target && u4 + 3 >= t0 && u4 + 3 < t1) found = u4 + 3;
+          }
+        }
+      } else if (nl_rm) {
+        const uint32_t* row = nl_rm + (size_t)j * cap;
+        for (int u = t0; u < t1; ++u) {
+          if (row[u] == target) {
+            found = u;
+            break;
+          }
+        }
+      } else {
+        for (int u = t0; u < t1; ++u) {
+          if (nl[(size_t)u * n + j] == target) {
+            found = u;
+            break;
+          }
+        }
+      }
+      if (found < 0) {
+        flags[kFlagReverse] = 1;
+        found = 0;
+      } else if (symmetric && j != i) {
+        rev[(size_t)found * n + j] = s;
+      }
+      rev[idx] = found;
     }
-    rev[idx] = found;
   }
 }
 
