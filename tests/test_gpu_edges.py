@@ -1,8 +1,9 @@
 """Degenerate inputs on the GPU path: an empty system, an isolated atom (no
 neighbour: the descriptor is zero and the site energy is the network at
-q = 0), a pair inside r_c^R but outside r_c^A (radial terms only), and a
-ragged cluster whose atoms have from zero to many neighbours, each against
-the FP64 oracle or its closed form."""
+q = 0), a pair inside r_c^R but outside r_c^A (radial terms only), a
+ragged cluster whose atoms have from zero to many neighbours, and positions
+given outside the box, each against the FP64 oracle or its closed form; and
+the skin/2 displacement latch."""
 import numpy as np
 import pytest
 
@@ -158,3 +159,39 @@ def test_skin_latch_in_md():
     with pytest.raises(nep.NepError) as err:
         ctx.synchronize()
     assert err.value.status == nep.NEP_ESKIN
+
+
+def test_positions_outside_the_box_match_the_wrapped_system():
+    """Positions given outside the box (atoms moved by whole box vectors, -1,
+    0 or +1 per axis) describe the same periodic system (Sec. II A: the site
+    environment runs over all lattice images).  The cell-list path keeps such
+    atoms where they are, with their offsets, so their pairs take images other
+    than the neighbour cell's own; U, F, W and J must be the wrapped system's:
+    against the oracle on the wrapped positions, and against the GPU's own
+    evaluation of them."""
+    nep = nep_mod()
+    pos, box = I.diamond_supercell(4, 4, 4)  # 512 atoms, 21.7 A: three cells per axis
+    rng = np.random.default_rng(21)
+    pos = I.wrap_positions(pos + rng.normal(0.0, 0.05, pos.shape), box)
+    vel = I.maxwell_boltzmann(len(pos), 300.0, 5)
+    z = I.random_parameters(931, 7)
+    shift = rng.integers(-1, 2, size=pos.shape)
+    shift[rng.random(len(pos)) < 0.3] = 0
+    pos_out = pos + shift.astype(np.float64) @ np.asarray(box, np.float64)
+    assert (np.abs(pos_out - pos) > 1.0).any(axis=1).mean() > 0.5
+    outs = []
+    for P in (pos, pos_out):
+        ctx = nep.Context(0)
+        ctx.load_params(nep.hyper(), z)
+        p = nep.soa(P)
+        ctx.build_neighbors(p, box, skin=0.5, max_neighbors=64)
+        o = ctx.compute(p, nep.soa(vel))
+        ctx.synchronize()  # raises on a latched image, overflow or reverse-slot error
+        outs.append({"U": o["U"].cpu().numpy(), "F": nep.aos(o["F"]),
+                     "W": nep.aos(o["W"]).reshape(-1, 3, 3), "J": nep.aos(o["J"])})
+    sel = np.arange(0, len(pos), 5)
+    ref = O.nep_eval(O.hyper(), z, pos, box, vel=vel, sel=sel)
+    for k in ("U", "F", "W", "J"):
+        print(k, rel(outs[1][k], outs[0][k]), rel(outs[1][k][sel], ref[k]), flush=True)
+        assert rel(outs[1][k], outs[0][k]) < TOL, k
+        assert rel(outs[1][k][sel], ref[k]) < TOL, k
