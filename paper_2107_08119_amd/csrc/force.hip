@@ -74,6 +74,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   __shared__ float4 sd[KS][APB];
   __shared__ unsigned long long smask[2][W][APB];  // [angular, radial-only][w][atom]
   __shared__ int scount[2][APB];
+  __shared__ int slist[2][APB];  // list counts (radial, angular part) of the block's atoms
   __shared__ __align__(16) float snet[kBlock / 64][net_rows(L) * kNetX];  // network_mfma
   const float rcr2 = rc_r * rc_r, rca2 = rc_a * rc_a;
   {
@@ -136,6 +137,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     if (w == 0) {
       scount[0][a] = na;
       scount[1][a] = __popcll(fr);
+      slist[0][a] = cra;
+      slist[1][a] = caa;
     }
 #pragma unroll
     for (int t = 0; t < T; ++t) {
@@ -155,8 +158,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   const int la = threadIdx.x / L;
   const bool active = i < n;
   const int ii = active ? i : 0;
-  const int cr = active ? cnt_r[i] : 0;
-  const int ca = active ? cnt_a[i] : 0;
+  const int cr = slist[0][la];  // zero for atoms past n
+  const int ca = slist[1][la];
   const int n_ang = scount[0][la];              // staged pairs inside r_c^A
   const int n_in = n_ang + scount[1][la];       // staged pairs inside r_c^R
   const double xi = pos[ii], yi = pos[n + ii], zi = pos[2 * n + ii];
