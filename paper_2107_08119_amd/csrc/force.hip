@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int nblocks, const double* 
 // from the list entry and the neighbour's position (the same float32 value).
 template <int L, int MODE, bool GEO>
 __global__ __launch_bounds__(kBlock) void k_gather(
-    int n, const double* __restrict__ pos, double* __restrict__ vel,
+    int n, int cap, const double* __restrict__ pos, double* __restrict__ vel,
     const uint32_t* __restrict__ nl, const Partial3* __restrict__ geo,
     const int* __restrict__ cnt_r, const Partial3* __restrict__ pin,
     const float* __restrict__ fown, const float* __restrict__ U, Box box,
@@ -330,13 +330,18 @@ __global__ __launch_bounds__(kBlock) void k_gather(
   // (measured best on the 64,000-atom step: 9 of 9, 13, 17 with pair vectors
   // and 2 lanes per atom; 5 of 3, 5, 7, 9 otherwise with 4 lanes)
   constexpr int B = GEO && L == 2 ? 9 : 5;
-  for (int s0 = lane; s0 < cr; s0 += B * L) {
+  // The first batch is requested before the atom's slot count arrives: its
+  // addresses need only the list capacity (every atom has cap rows; slots at
+  // or past the count are read and not used).  Later batches stop at the count.
+  int s0 = lane;
+  do {
+    const int bound = s0 == lane ? cap : cr;
     Partial3 rg[B], p[B];
     uint32_t e[B];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int s = s0 + u * L;
-      const size_t idx = s < cr ? (size_t)s * n + i : (size_t)i;  // slot 0 when past the end
+      const size_t idx = s < bound ? (size_t)s * n + ii : (size_t)ii;  // slot 0 past the end
       if constexpr (GEO)
         rg[u] = geo[idx];
       else
@@ -347,7 +352,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     if constexpr (!GEO) {
 #pragma unroll
       for (int u = 0; u < B; ++u) {
-        const int j = (int)(e[u] & kAtomMask);
+        // an entry past the count may be stale: its neighbour is not read
+        const int j = s0 + u * L < cr ? (int)(e[u] & kAtomMask) : ii;
         pj[u][0] = pos[j];
         pj[u][1] = pos[n + j];
         pj[u][2] = pos[2 * n + j];
@@ -378,7 +384,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(
       w[7] += dz * pji.y;
       w[8] += dz * pji.z;
     }
-  }
+    s0 += B * L;
+  } while (s0 < cr);
   f0 = group_sum<L>(f0) + fo0;
   f1 = group_sum<L>(f1) + fo1;
   f2 = group_sum<L>(f2) + fo2;
@@ -583,7 +590,8 @@ hipError_t launch_gather(nep_ctx ctx, const double* pos, double* vel, float* U_o
   const double* mass_c = per_atom ? (const double*)ctx->masses.ptr : (const double*)nullptr;
   const float half_skin = (float)(0.5 * s.skin);
   auto go = [&](auto kernel) {
-    launch_kernel(ctx, true, last, kernel, dim3(nb), dim3(kBlock), s.n, pos, vel, nl, geo, cnt, p,
+    launch_kernel(ctx, true, last, kernel, dim3(nb), dim3(kBlock), s.n, s.cap, pos, vel, nl, geo,
+                  cnt, p,
                   fown, U, s.box, U_out, F_out, W_out, J_out, kick, ekin_factor, dt, pos_next,
                   (float)fe[0], (float)fe[1], (float)fe[2], mass_c, (const int*)s.perm.ptr, mass,
                   (const float*)s.pos_ref.ptr, half_skin * half_skin, ctx->flags.ptr, block_out);
