@@ -39,7 +39,7 @@ constexpr int stage_slots(int atoms_per_block) {
 // its outputs at pin + k*pstride, fown + 3nk, U + nk.
 template <int NR, int NA, int LMAX, int NNEU, int L, bool MULTI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_partials(
-    int n, int cap, const double* __restrict__ pos, const uint32_t* __restrict__ nl,
+    int n, const double* __restrict__ pos, const uint32_t* __restrict__ nl,
     const int* __restrict__ cnt_r, const int* __restrict__ cnt_a, const int* __restrict__ rev,
     Box box, const double* __restrict__ boxes, const int* __restrict__ struct_of,
     const float* __restrict__ zpar, size_t zstride, float rc_r, float rc_a,
@@ -86,15 +86,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     const double xa = ia < n ? pos[ia] : 0.0, ya = ia < n ? pos[n + ia] : 0.0,
                  za = ia < n ? pos[2 * n + ia] : 0.0;
     // all loads first (clamped to valid addresses), so that the T slots'
-    // list and position reads are in flight together; the list reads do not
-    // wait for the atom's count (every atom has cap rows; slots at or past
-    // the count are read and not used)
+    // list and position reads are in flight together
     uint32_t e[T];
     int rv[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
       const int sl = w + t * W;
-      const size_t idx = ia < n && sl < cap ? (size_t)sl * n + ia : 0;
+      const size_t idx = sl < cra ? (size_t)sl * n + ia : 0;
       e[t] = nl[idx];
       rv[t] = rev[idx];
     }
@@ -535,7 +533,7 @@ void launch_partials_shape(nep_ctx ctx, const double* pos, bool first, bool last
   const System& s = ctx->sys;
   const unsigned nb = blocks_for((size_t)s.n * L, kBlock);
   launch_kernel(ctx, first, last, k_partials<9, 5, 4, 30, L, false>, dim3(nb), dim3(kBlock), s.n,
-                s.cap, pos, (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr, (const int*)s.cnt_a.ptr,
+                pos, (const uint32_t*)s.nl.ptr, (const int*)s.cnt_r.ptr, (const int*)s.cnt_a.ptr,
                 (const int*)s.rev.ptr, s.box, (const double*)nullptr, (const int*)nullptr,
                 (const float*)ctx->z.ptr, (size_t)0, (float)ctx->hyper.rc_radial,
                 (float)ctx->hyper.rc_angular, ctx->p.ptr, (size_t)0, ctx->fown.ptr, ctx->U.ptr,
@@ -565,7 +563,7 @@ hipError_t launch_partials_population(nep_ctx ctx, nep_dataset ds, int n_pop, co
   if (ds->N == 0 || n_pop == 0) return hipSuccess;
   const unsigned nb = blocks_for((size_t)ds->N * kLanes, kBlock);
   launch_kernel(ctx, true, true, k_partials<9, 5, 4, 30, kLanes, true>, dim3(nb, n_pop),
-                dim3(kBlock), ds->N, ds->cap, (const double*)ds->pos.ptr, (const uint32_t*)ds->nl.ptr,
+                dim3(kBlock), ds->N, (const double*)ds->pos.ptr, (const uint32_t*)ds->nl.ptr,
                 (const int*)ds->cnt_r.ptr, (const int*)ds->cnt_a.ptr, (const int*)ds->rev.ptr,
                 Box{}, (const double*)ds->boxes.ptr, (const int*)ds->struct_of.ptr, Z,
                 (size_t)ctx->n_par, (float)ctx->hyper.rc_radial, (float)ctx->hyper.rc_angular,
